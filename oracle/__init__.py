@@ -1,0 +1,36 @@
+"""FP64 CPU oracle of the OSOG forward model -- TEST INFRASTRUCTURE ONLY.
+
+A plain, slow, single-threaded statement of what the renderer computes, written
+from the paper (arXiv 2606.21381, Sec. III) and sharing no code with the GPU
+library.  Only the tests, the smoke check and the benchmark's CPU-baseline leg
+may import it; the product path never does.
+
+  binning.py  sorted (tile, particle) pairs (FP32-exact box recipe)
+  raster.py   OPD canvas: exact-area prisms, centre-sampled ellipsoids (C, FP64)
+  optics.py   exit wave, DFT, pupil/defocus, BF / DIC / oblique, |E|^2, direct DFT
+  noise.py    Philox4x32-10 and Poisson shot noise
+  grad.py     central finite-difference gradients, solver loss
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import binning, grad, noise, optics, raster
+from .optics import BRIGHTFIELD, DIC, OBLIQUE, Optics
+
+
+def render(soa, H: int, W: int, opt: Optics, globals4, with_noise: bool = False, frame: int = 0):
+    """OPD (um) and intensity of one frame, FP64 throughout.
+
+    ``globals4`` = (defocus_um, shear_px, bias_rad, unused); FP32 values are widened.
+    """
+    g = np.asarray(globals4, dtype=np.float32).astype(np.float64)
+    opd = raster.opd(np.asarray(soa, dtype=np.float32), H, W)
+    I = optics.intensity(opd, opt, g[0], g[1], g[2])
+    if with_noise and opt.photons_mean > 0:
+        I = noise.add_noise(I, opt.photons_mean, opt.seed, frame)
+    return opd, I
+
+
+__all__ = ["binning", "grad", "noise", "optics", "raster", "render", "Optics",
+           "BRIGHTFIELD", "DIC", "OBLIQUE"]

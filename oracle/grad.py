@@ -1,0 +1,78 @@
+"""Oracle gradients by FP64 central finite differences -- TEST INFRASTRUCTURE ONLY.
+
+The paper's forward model is differentiable end to end (Sec. III.C, after Eq. 7:
+the gradient of the image with respect to the state tensor is kept).  The oracle
+states that gradient by its definition: for a real loss L(I) = sum_ij g_ij I_ij,
+
+    dL/dp ~ (L(p + d) - L(p - d)) / (2 d),   d = 1e-5 in natural units (px, rad, um, 1),
+
+evaluated on an FP64 copy of the particle table and FP64 globals.  Each estimate
+is repeated at d/2; components whose two estimates disagree by more than 1e-6
+relative (and more than the rounding noise of the difference) are flagged (a prism vertex or edge crossing a pixel boundary inside the
+stencil makes the thickness only piecewise smooth there).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import optics as _optics
+from . import raster as _raster
+
+
+def image64(soa64: np.ndarray, H: int, W: int, optics, g64) -> np.ndarray:
+    opd = _raster.opd(np.asarray(soa64, dtype=np.float64), H, W)
+    return _optics.intensity(opd, optics, float(g64[0]), float(g64[1]), float(g64[2]))
+
+
+def loss(soa64, H, W, optics, g64, weights) -> float:
+    """L = sum_ij weights_ij * I_ij (a linear probe of the noiseless image)."""
+    return float(np.sum(weights * image64(soa64, H, W, optics, g64)))
+
+
+def _central(f, x0: float, d: float) -> float:
+    return (f(x0 + d) - f(x0 - d)) / (2.0 * d)
+
+
+def fd_gradients(soa, H, W, optics, globals4, weights, rows=(0, 1, 2, 3, 4, 5, 6),
+                 delta: float = 1e-5):
+    """FD gradients of sum(weights * I) w.r.t. SoA rows ``rows`` and globals 0..2.
+
+    Returns (grad_soa [8][n] FP64 with untouched rows zero, grad_globals [3],
+    flags_soa [8][n] bool, flags_globals [3] bool).
+    """
+    soa64 = np.array(soa, dtype=np.float64)
+    g64 = np.array(globals4, dtype=np.float64)
+    n = soa64.shape[1]
+    # rounding noise of a central difference is ~ eps |L| / d; never flag below it
+    floor = 1e-9 * max(abs(loss(soa64, H, W, optics, g64, weights)), 1.0)
+    gs = np.zeros((8, n))
+    fs = np.zeros((8, n), dtype=bool)
+    for r in rows:
+        for p in range(n):
+            def f(v, r=r, p=p):
+                s = soa64.copy()
+                s[r, p] = v
+                return loss(s, H, W, optics, g64, weights)
+            x0 = soa64[r, p]
+            e1 = _central(f, x0, delta)
+            e2 = _central(f, x0, delta / 2)
+            gs[r, p] = e2
+            fs[r, p] = abs(e1 - e2) > max(1e-6 * max(abs(e1), abs(e2)), floor)
+    gg = np.zeros(3)
+    fg = np.zeros(3, dtype=bool)
+    for k in range(3):
+        def f(v, k=k):
+            g = g64.copy()
+            g[k] = v
+            return loss(soa64, H, W, optics, g, weights)
+        e1 = _central(f, g64[k], delta)
+        e2 = _central(f, g64[k], delta / 2)
+        gg[k] = e2
+        fg[k] = abs(e1 - e2) > max(1e-6 * max(abs(e1), abs(e2)), floor)
+    return gs, gg, fs, fg
+
+
+def mse(I: np.ndarray, target: np.ndarray) -> float:
+    """Inverse-rendering loss: mean squared error against a pixel-aligned target."""
+    d = np.asarray(I, dtype=np.float64) - np.asarray(target, dtype=np.float64)
+    return float(np.mean(d * d))

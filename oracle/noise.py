@@ -1,0 +1,129 @@
+"""Oracle sensor shot noise -- TEST INFRASTRUCTURE ONLY.
+
+Paper Sec. III.C (last paragraph) adds Poisson photon shot noise to the
+composited image.  Reading used: the clean image is scaled to photon counts by
+s = photons_mean / mean(I) (mean over the frame), counts ~ Poisson(s I) per
+pixel, and the output is counts / s.
+
+Random numbers come from a counter-based generator implemented here from its
+published definition, Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), so the
+GPU implementation and this one draw the same stream:
+  counter = (pixel index, frame index, round, 0), key = (seed low 32, seed high 32),
+  uniform = ((x >> 9) + 0.5) * 2^-23 in FP32 (every value exact, never 0 or 1).
+Poisson variates: mean < 10 by inversion with sequential search on one uniform
+(at most 40 steps); mean >= 10 by Hoermann's transformed rejection with squeeze
+"PTRS" (Insurance: Math. and Econ. 12, 1993), two uniforms per attempt, two
+attempts per Philox call, at most 16 calls.  The decisions are taken in FP32,
+the precision of the GPU sampler.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+M0, M1 = 0xD2511F53, 0xCD9E8D57
+W0, W1 = 0x9E3779B9, 0xBB67AE85
+MASK = 0xFFFFFFFF
+
+
+def philox4x32_10(ctr, key):
+    """One Philox4x32 block with 10 rounds on plain Python integers."""
+    c0, c1, c2, c3 = (int(x) & MASK for x in ctr)
+    k0, k1 = (int(x) & MASK for x in key)
+    for r in range(10):
+        p0 = M0 * c0
+        p1 = M1 * c2
+        hi0, lo0 = (p0 >> 32) & MASK, p0 & MASK
+        hi1, lo1 = (p1 >> 32) & MASK, p1 & MASK
+        c0, c1, c2, c3 = hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0
+        if r < 9:
+            k0 = (k0 + W0) & MASK
+            k1 = (k1 + W1) & MASK
+    return c0, c1, c2, c3
+
+
+def philox4x32_10_np(c0, c1, c2, c3, k0, k1):
+    """Vectorised Philox4x32-10 over uint32 arrays (the same rounds as above)."""
+    c0 = np.asarray(c0, dtype=np.uint64)
+    c1 = np.asarray(c1, dtype=np.uint64)
+    c2 = np.asarray(c2, dtype=np.uint64)
+    c3 = np.asarray(c3, dtype=np.uint64)
+    k0 = np.uint64(k0 & MASK)
+    k1 = np.uint64(k1 & MASK)
+    m = np.uint64(MASK)
+    for r in range(10):
+        p0 = np.uint64(M0) * c0
+        p1 = np.uint64(M1) * c2
+        hi0, lo0 = p0 >> np.uint64(32), p0 & m
+        hi1, lo1 = p1 >> np.uint64(32), p1 & m
+        c0, c1, c2, c3 = hi1 ^ c1 ^ k0, lo1, hi0 ^ c3 ^ k1, lo0
+        if r < 9:
+            k0 = (k0 + np.uint64(W0)) & m
+            k1 = (k1 + np.uint64(W1)) & m
+    return tuple(x.astype(np.uint32) for x in (c0, c1, c2, c3))
+
+
+def uniform_f32(x: int) -> np.float32:
+    return np.float32(((int(x) >> 9) + 0.5) * 2.0 ** -23)
+
+
+def _f(x) -> np.float32:
+    return np.float32(x)
+
+
+def poisson_one(mu: float, pixel: int, frame: int, seed: int) -> int:
+    """One Poisson(mu) variate for one pixel (FP32 decisions, as on the GPU)."""
+    mu = _f(mu)
+    if not (mu > 0):
+        return 0
+    key = (seed & MASK, (seed >> 32) & MASK)
+    if mu < _f(10.0):
+        u = uniform_f32(philox4x32_10((pixel, frame, 0, 0), key)[0])
+        p = _f(np.exp(-mu))
+        F = p
+        k = 0
+        while u > F and k < 40:
+            k += 1
+            p = _f(p * _f(mu / _f(k)))
+            F = _f(F + p)
+        return k
+    smu = _f(np.sqrt(mu))
+    log_mu = _f(np.log(mu))
+    b = _f(_f(0.931) + _f(_f(2.53) * smu))
+    a = _f(_f(-0.059) + _f(_f(0.02483) * b))
+    inv_alpha = _f(_f(1.1239) + _f(_f(1.1328) / _f(b - _f(3.4))))
+    vr = _f(_f(0.9277) - _f(_f(3.6224) / _f(b - _f(2.0))))
+    k = int(math.floor(float(mu)))
+    for rnd in range(16):
+        r = philox4x32_10((pixel, frame, rnd, 0), key)
+        for t in range(2):
+            U = _f(uniform_f32(r[2 * t]) - _f(0.5))
+            V = uniform_f32(r[2 * t + 1])
+            us = _f(_f(0.5) - _f(abs(U)))
+            kf = np.floor(_f(_f(_f(_f(_f(_f(2.0) * a) / us) + b) * U) + _f(mu + _f(0.43))))
+            kf = _f(kf)
+            if us >= _f(0.07) and V <= vr:
+                return int(kf)
+            if kf < 0 or (us < _f(0.013) and V > us):
+                continue
+            lhs = _f(_f(np.log(V)) + _f(np.log(inv_alpha)) - _f(np.log(_f(_f(a / _f(us * us)) + b))))
+            rhs = _f(_f(-mu + _f(kf * log_mu)) - _f(math.lgamma(float(kf) + 1.0)))
+            if lhs <= rhs:
+                return int(kf)
+    return k
+
+
+def add_noise(I: np.ndarray, photons_mean: float, seed: int, frame: int = 0,
+              mean_I: float | None = None) -> np.ndarray:
+    """counts/s with counts ~ Poisson(s I), s = photons_mean / mean(I).  Slow: small frames."""
+    I = np.asarray(I, dtype=np.float64)
+    m = float(I.mean()) if mean_I is None else float(mean_I)
+    if not (photons_mean > 0) or not (m > 0):
+        return I.copy()
+    s = photons_mean / m
+    flat = I.reshape(-1)
+    out = np.empty_like(flat)
+    for p in range(flat.shape[0]):
+        out[p] = poisson_one(s * flat[p], p, frame, seed) / s
+    return out.reshape(I.shape)
