@@ -1,0 +1,172 @@
+"""Benchmark: frames/s of the full forward path on 2048x2048 DIC frames with
+40,000 particles (half prisms, half ellipsoids), Poisson noise at 1000 photons/px.
+
+One step = one complete frame through every stage (binning, rasterisation,
+row FFT, column FFT with the transfer function, row IFFT with |E|^2 and noise),
+with the particle table already resident in HBM.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "frames/s at 2048²×40k-particle DIC"
+
+
+def algorithmic_bytes(H, W, n, P, kx_n):
+    """Bytes each stage must move at minimum (one read of its inputs, one write
+    of its outputs), per frame."""
+    hw4 = 4.0 * H * W
+    band = 8.0 * H * kx_n
+    return {
+        # SoA table, per-particle counts and offsets, pairs emitted, sorted (2 passes
+        # of read + write of 8-byte pairs), tile offsets
+        "binning": 32.0 * n + 16.0 * n + 8.0 * P * (1 + 2 * 2) + 4.0 * (H * W / 256 + 1),
+        # pair list + the 8 attributes of each listed particle, OPD written once
+        "raster": 4.0 * P + 32.0 * P + hw4,
+        "pass1": hw4 + band,
+        "pass2": 2.0 * band,
+        "pass3": band + hw4,
+    }
+
+
+def cpu_baseline(fr, budget_s=20.0):
+    """The FP64 oracle on a bounded sample of the same workload, scaled to frames/s.
+
+    Sample: one full noiseless frame (binning is not part of the oracle's
+    definition; it rasterises every particle directly) plus the shot noise of a
+    contiguous run of pixels, extrapolated to the frame's 2048^2 pixels.
+    """
+    import oracle
+    t0 = time.perf_counter()
+    opd = oracle.raster.opd(fr.soa, fr.H, fr.W)
+    g = fr.globals4.astype(np.float64)
+    o = oracle.Optics(mode=fr.optics.mode, na=fr.optics.na, shear_angle_rad=fr.optics.shear_angle_rad,
+                      wavelength_um=fr.optics.wavelength_um, n_medium=fr.optics.n_medium,
+                      pixel_um=fr.optics.pixel_um)
+    I = oracle.optics.intensity(opd, o, g[0], g[1], g[2])
+    t_render = time.perf_counter() - t0
+    s = fr.optics.photons_mean / I.mean()
+    flat = I.reshape(-1)
+    t1 = time.perf_counter()
+    m = 0
+    while time.perf_counter() - t1 < max(1.0, budget_s - t_render) and m < flat.size:
+        for p in range(m, min(m + 4096, flat.size)):
+            oracle.noise.poisson_one(s * flat[p], p, 0, fr.optics.seed)
+        m = min(m + 4096, flat.size)
+    t_noise = (time.perf_counter() - t1) * flat.size / m
+    per_frame = t_render + t_noise
+    return {"value": 1.0 / per_frame, "unit": "frames/s", "cores": 1, "kind": "oracle",
+            "sample": "1 full noiseless 2048^2 x 40k DIC frame (%.2f s) + Poisson noise of %d pixels "
+                      "extrapolated to %d (%.1f s/frame)" % (t_render, m, flat.size, t_noise)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=50)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X with no sharding "
+              "or collectives (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2606_21381_amd import _lib, render, workloads
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    fr = workloads.config1()
+    H, W, n = fr.H, fr.W, fr.soa.shape[1]
+    soa = torch.from_numpy(fr.soa).to(dev)
+    g = torch.from_numpy(fr.globals4).to(dev)
+    out = torch.empty((H, W), dtype=torch.float32, device=dev)
+    ws = torch.empty(render.workspace_size(H, W, n), dtype=torch.uint8, device=dev)
+
+    def step():
+        render.render(soa, H, W, fr.optics, g, out=out, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+
+    # per-stage durations with HIP events on the launch stream (separate run)
+    lib = _lib.load()
+    ctx = render.context(dev)
+    _lib.check(lib.osog_profile_enable(ctx, 1), "profile_enable")
+    for _ in range(args.profile_steps):
+        step()
+    import ctypes
+    st_ms = (ctypes.c_double * 10)()
+    st_n = (ctypes.c_int64 * 10)()
+    _lib.check(lib.osog_profile_read(ctx, st_ms, st_n), "profile_read")
+    _lib.check(lib.osog_profile_enable(ctx, 0), "profile_disable")
+    stage_us = {_lib.STAGES[k]: 1000.0 * st_ms[k] / st_n[k] for k in range(10) if st_n[k]}
+
+    _, _, _, _, P = render.bin_pairs(soa, H, W)
+    from paper_2606_21381_amd.render import band_columns
+    kx_n = band_columns(H, W, fr.optics)
+    alg = algorithmic_bytes(H, W, n, P, kx_n)
+    dom = max((k for k in stage_us if k in alg), key=lambda k: stage_us[k])
+    achieved = alg[dom] / (stage_us[dom] * 1e-6) / 1e9
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes": alg[dom], "avg_us": round(stage_us[dom], 2)}
+    total_alg = sum(alg.values())
+    res = {
+        "metric": METRIC,
+        "value": round(1000.0 / ms, 2),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded particle tables)",
+        "config": {"workload": "dic2048_n40000", "height": H, "width": W, "particles": n,
+                   "prisms": int((fr.soa[7] < 0.5).sum()), "mode": "DIC", "na": fr.optics.na,
+                   "photons_mean": fr.optics.photons_mean, "pairs": P, "band_columns": kx_n},
+        "particles_per_s": round(n * 1000.0 / ms, 1),
+        "stage_us": {k: round(v, 2) for k, v in stage_us.items()},
+        "frame_alg_bytes": total_alg,
+        "frame_alg_gbs": round(total_alg / (ms * 1e-3) / 1e9, 1),
+        "roofline": roof,
+        "paper_context": "paper: 40,000 particles in under 50 ms on one NVIDIA A100 (1024^2 canvas)",
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(fr)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

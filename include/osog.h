@@ -1,0 +1,219 @@
+/*
+ * osog.h -- C ABI of libosog, an MI355X (gfx950) renderer of the OSOG forward
+ * model (arXiv 2606.21381): a Structure-of-Arrays particle table becomes an
+ * optical-path-difference (OPD) canvas, and the canvas becomes a microscope
+ * image through the wave-optics chain exp(i 2 pi/lambda OPD) -> FFT -> pupil and
+ * defocus -> DIC shear / oblique shift -> inverse FFT -> |E|^2 (-> shot noise).
+ *
+ * Conventions shared by every entry point
+ *   - Plain C types only.  "device" pointers are GPU memory of the context's
+ *     device; "host" pointers are CPU memory read before the call returns.
+ *   - The caller owns every buffer it passes; the library never frees them and
+ *     never keeps them after the call.  The context owns only its own tables.
+ *   - Work is enqueued on the caller's HIP stream (a hipStream_t passed as
+ *     void*, NULL = default stream) and is asynchronous: no entry point waits
+ *     for the GPU, and none copies device data to the host.
+ *   - Outputs are overwritten, never accumulated into.  Inputs are not modified.
+ *   - Arguments are checked on the host before anything is enqueued; a failed
+ *     check returns its status and enqueues nothing.  Device array contents are
+ *     not checked: NaNs propagate (a particle with a NaN centre or a
+ *     non-positive half-width contributes nothing).
+ *   - Results are bitwise reproducible for fixed inputs and tiling.
+ *   - No C++ exception crosses this boundary.  osog_last_error() returns the
+ *     calling thread's message for its last non-OK status.
+ */
+#ifndef OSOG_H
+#define OSOG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  OSOG_OK = 0,
+  OSOG_ERR_INVALID_ARGUMENT = 1, /* null pointer, bad size, bad optics            */
+  OSOG_ERR_UNSUPPORTED = 2,      /* canvas not a power of two in [32, 4096], ...  */
+  OSOG_ERR_WORKSPACE = 3,        /* workspace missing or smaller than required    */
+  OSOG_ERR_HIP = 4,              /* a HIP runtime call or kernel launch failed     */
+  OSOG_ERR_NOT_INITIALIZED = 5   /* null context                                  */
+} osog_status;
+
+/* Imaging modality (paper Sec. III.B): brightfield (Eq. 4's |U * h_obj|^2),
+ * differential interference contrast (Eq. 5), oblique illumination (the
+ * asymmetric Fourier pupil of the oblique modality). */
+typedef enum { OSOG_BRIGHTFIELD = 0, OSOG_DIC = 1, OSOG_OBLIQUE = 2 } osog_mode;
+
+/* The particle table is the SoA tensor S of paper Sec. III.A stored
+ * attribute-major: float soa[OSOG_D][ld], row r holding attribute r of
+ * particles 0..n-1 (ld >= n).  Pixel (i = row, j = column) covers
+ * [j, j+1] x [i, i+1] in pixel units; R(angle) maps local (u, v) to (x, y). */
+enum {
+  OSOG_CX = 0,     /* centre x [px]                                             */
+  OSOG_CY = 1,     /* centre y [px]                                             */
+  OSOG_ANGLE = 2,  /* in-plane rotation [rad]                                   */
+  OSOG_A = 3,      /* half-width along u [px] (prism) / semi-axis (ellipsoid)   */
+  OSOG_B = 4,      /* half-width along v [px] / semi-axis                       */
+  OSOG_HEIGHT = 5, /* prism height / ellipsoid full central thickness [um]      */
+  OSOG_DN = 6,     /* n_particle - n_medium                                     */
+  OSOG_SHAPE = 7,  /* < 0.5: prism (box-filtered exact area); else ellipsoid    */
+  OSOG_D = 8
+};
+
+/* Static optics of a frame (host memory).  Lengths in micrometres. */
+typedef struct {
+  int32_t mode;            /* osog_mode                                               */
+  double wavelength_um;    /* lambda > 0                                              */
+  double na;               /* numerical aperture, 0 < na < n_medium                   */
+  double n_medium;         /* n_m; axial wavenumber k0 = 2 pi n_m / lambda (Eq. 3)    */
+  double pixel_um;         /* canvas pixel pitch dx > 0                               */
+  double shear_angle_rad;  /* DIC shear direction psi (not differentiated)            */
+  double tilt_fx;          /* oblique illumination frequency [cycles/um]: H = P(f+ft) */
+  double tilt_fy;
+  double photons_mean;     /* > 0: Poisson shot noise at this mean photon count/px    */
+  uint64_t seed;           /* Philox4x32-10 key of the noise                           */
+  uint32_t noise_frame;    /* second Philox counter word (frame index)                 */
+} osog_optics;
+
+/* Differentiable per-frame globals live in DEVICE memory, float[4]:
+ *   [0] defocus dz [um]   (Eq. 3)
+ *   [1] total DIC shear 2|ds| [px] along shear_angle_rad   (Eq. 5)
+ *   [2] DIC bias phase theta [rad]                          (Eq. 5)
+ *   [3] unused (0)
+ * so that solver steps need no host round trip and calls can be captured. */
+#define OSOG_NGLOBALS 4
+
+typedef struct osog_context osog_context;
+
+/* Create a context on HIP device `device`: uploads the FFT twiddle table and
+ * sets the default tiling (16 x 16 pixel tiles).  Allocates device memory. */
+osog_status osog_context_create(osog_context** out, int device);
+osog_status osog_context_destroy(osog_context* ctx);
+
+/* Tiling used for binning and rasterisation: tile_h x tile_w pixels, both
+ * powers of two with tile_h * tile_w == 256.  Changing it changes the pair
+ * list but not the OPD (each pixel always sums its particles in ascending id). */
+osog_status osog_set_tiling(osog_context* ctx, int32_t tile_h, int32_t tile_w);
+osog_status osog_get_tiling(const osog_context* ctx, int32_t* tile_h, int32_t* tile_w);
+
+/* Bytes of device workspace needed by osog_render (with_backward = 0) or by
+ * osog_render_backward (with_backward = 1) for an H x W canvas and n particles.
+ * pairs_per_particle bounds the mean number of (tile, particle) pairs the
+ * workspace holds (0 selects 32).  If a frame needs more pairs than that, the
+ * render stays correct and bitwise identical but rasterises by a slow
+ * brute-force scan of all particles per tile. */
+osog_status osog_workspace_size(const osog_context* ctx, int32_t height, int32_t width, int64_t n,
+                                int32_t pairs_per_particle, int32_t with_backward, size_t* bytes);
+
+/* Forward render (paper Sec. III, f(Theta) = I):
+ *   soa           device float[OSOG_D][ld], ld >= n, n >= 0 (n = 0: empty canvas)
+ *   optics        host, static optics
+ *   globals       device float[4] (see above)
+ *   opd_out       device float[height][width] or NULL: OPD canvas [um] (Eq. 2's integral)
+ *   intensity_out device float[height][width]: |E|^2, with shot noise if photons_mean > 0
+ *   workspace     device, >= osog_workspace_size(..., with_backward = 0) bytes
+ * height, width: powers of two in [32, 4096], multiples of the tile sides. */
+osog_status osog_render(osog_context* ctx, void* stream, int32_t height, int32_t width,
+                        const float* soa, int64_t n, int64_t ld, const osog_optics* optics,
+                        const float* globals, float* opd_out, float* intensity_out,
+                        void* workspace, size_t workspace_bytes);
+
+/* Adjoint of the noiseless render (the gradient the paper keeps after Eq. 7):
+ * given dL/dI (and optionally dL/dOPD) of a real loss L, writes
+ *   grad_soa      device float[OSOG_D][ld] or NULL: dL/d(cx, cy, angle, a, b,
+ *                 height, dn); row OSOG_SHAPE is written as 0
+ *   grad_globals  device float[4] or NULL: dL/d(defocus, shear, bias), [3] = 0
+ * Forward intermediates are recomputed inside the call, not stored.  Shot
+ * noise is treated as a constant.  workspace: >= osog_workspace_size(...,
+ * with_backward = 1) bytes. */
+osog_status osog_render_backward(osog_context* ctx, void* stream, int32_t height, int32_t width,
+                                 const float* soa, int64_t n, int64_t ld,
+                                 const osog_optics* optics, const float* globals,
+                                 const float* grad_intensity, const float* grad_opd,
+                                 float* grad_soa, float* grad_globals,
+                                 void* workspace, size_t workspace_bytes);
+
+/* One frame of a batch (host array of these; pointers are device memory). */
+typedef struct {
+  int32_t height, width;
+  const float* soa;
+  int64_t n, ld;
+  osog_optics optics;
+  const float* globals;      /* device float[4]                               */
+  float* opd_out;            /* device float[height][width] or NULL           */
+  float* intensity_out;      /* device float[height][width]                   */
+} osog_frame;
+
+/* Bytes of device workspace for osog_batch_render over these frames. */
+osog_status osog_batch_workspace_size(osog_context* ctx, const osog_frame* frames,
+                                      int32_t n_frames, int32_t pairs_per_particle,
+                                      size_t* bytes);
+
+/* Render many frames of uneven size and particle count in one persistent
+ * kernel launch (a device work queue over (frame, stage, item) in dependency
+ * order), captured once per batch signature in a HIP graph owned by the context
+ * and replayed on later calls with the same signature.  Each frame's output is
+ * bitwise identical to osog_render of that frame with the same tiling.
+ *   frame_done_ns  device uint64[n_frames] or NULL: GPU timestamp (ns, the
+ *                  device's constant-rate clock) at which each frame finished,
+ *                  and [n_frames] = launch start, for latency percentiles. */
+osog_status osog_batch_render(osog_context* ctx, void* stream, const osog_frame* frames,
+                              int32_t n_frames, void* workspace, size_t workspace_bytes,
+                              uint64_t* frame_done_ns);
+
+/* Binning only (steps F1-F4 of the renderer), for inspection and testing:
+ * writes the pairs sorted by (tile key, particle id):
+ *   keys_out, pids_out  device int32[capacity]; pair_count_out device int32[1]
+ *   tile_start_out      device int32[n_tiles + 1]; counts_out device int32[n] or NULL
+ * n_tiles = (height / tile_h) * (width / tile_w).  If more than `capacity`
+ * pairs exist, *pair_count_out is set to the full count and the lists hold
+ * nothing meaningful. */
+osog_status osog_bin(osog_context* ctx, void* stream, int32_t height, int32_t width,
+                     const float* soa, int64_t n, int64_t ld, int32_t* keys_out,
+                     int32_t* pids_out, int64_t capacity, int32_t* pair_count_out,
+                     int32_t* tile_start_out, int32_t* counts_out, void* workspace,
+                     size_t workspace_bytes);
+
+/* The in-band spectrum columns the chain carries for these optics: signed kx in
+ * [*kx_lo, *kx_lo + *kx_n) are the columns with at least one DFT bin inside the
+ * (oblique: shifted) pupil disc (Eq. 3).  Host only, no device work. */
+osog_status osog_band_info(const osog_context* ctx, int32_t height, int32_t width,
+                           const osog_optics* optics, int32_t* kx_lo, int32_t* kx_n);
+
+/* The counter-based generator of the shot noise, Philox4x32-10 (Salmon et al.,
+ * SC'11), evaluated on the device: out[4k..4k+3] = philox(ctr[4k..4k+3], key). */
+osog_status osog_philox4x32_10(void* stream, const uint32_t* ctr, int64_t count, uint32_t key0,
+                               uint32_t key1, uint32_t* out);
+
+/* Per-stage timing with HIP events.  While enabled, every call records a pair
+ * of events around each stage on the caller's stream (this adds a little
+ * launch overhead).  osog_profile_read waits for the recorded events, adds
+ * their elapsed milliseconds into ms[OSOG_NSTAGES] and the number of timed
+ * launches into launches[OSOG_NSTAGES] (both host arrays, overwritten), and
+ * forgets them. */
+enum {
+  OSOG_STAGE_BINNING = 0,   /* F1-F4: boxes, scan, emit, radix sort, tile offsets */
+  OSOG_STAGE_RASTER = 1,    /* F5: per-tile OPD accumulation                      */
+  OSOG_STAGE_PASS1 = 2,     /* F6: exp(i phi), row FFT, band store                */
+  OSOG_STAGE_PASS2 = 3,     /* F7: column FFT, transfer function, column IFFT     */
+  OSOG_STAGE_PASS3 = 4,     /* F8: row IFFT, |E|^2, shot noise                    */
+  OSOG_STAGE_ADJ_PASS3 = 5,
+  OSOG_STAGE_ADJ_PASS2 = 6,
+  OSOG_STAGE_ADJ_PASS1 = 7,
+  OSOG_STAGE_ADJ_RASTER = 8,
+  OSOG_STAGE_BATCH = 9,     /* the persistent batch kernel                        */
+  OSOG_NSTAGES = 10
+};
+osog_status osog_profile_enable(osog_context* ctx, int32_t enable);
+osog_status osog_profile_read(osog_context* ctx, double* ms, int64_t* launches);
+
+const char* osog_status_string(osog_status s);
+const char* osog_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OSOG_H */

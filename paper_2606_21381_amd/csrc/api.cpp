@@ -1,0 +1,435 @@
+// Host side of libosog: context, argument checks, frame planning, workspace
+// carving and the C entry points declared in osog.h.
+// Built with -ffp-contract=off: the pupil band bounds below must round exactly
+// like the device predicate and the FP64 reference statement of the pupil.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "batch.h"
+#include "fft_common.h"
+#include "osog.h"
+#include "osog_internal.h"
+
+struct osog_context {
+  int device = 0;
+  float2* twiddle = nullptr;  // kTwN entries: (cos, sin)(2 pi m / kTwN)
+  int tile_h = 16, tile_w = 16;
+  osog::BatchCache* batch = nullptr;
+  osog::Profiler* prof = nullptr;
+};
+
+namespace osog {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+static osog_status fail(osog_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+static osog_status hip_fail(hipError_t e, const char* where) {
+  return fail(OSOG_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+static bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
+
+static int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+static size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+// ---- workspace ---------------------------------------------------------------
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off = align_up(off + count * sizeof(T));
+    return p;
+  }
+};
+
+static int64_t pair_capacity(int64_t n, int n_tiles, int ppp) {
+  int64_t cap = n * (int64_t)ppp + n_tiles;
+  return cap > INT_MAX - 1 ? INT_MAX - 1 : cap;
+}
+
+static FrameBufs carve_impl(Carver& c, int H, int W, int64_t n, int tile_h, int tile_w, int ppp,
+                            bool backward, int64_t* cap_out) {
+  const int n_tiles = (H / tile_h) * (W / tile_w);
+  const int64_t cap = pair_capacity(n, n_tiles, ppp);
+  const size_t hw = (size_t)H * W;
+  FrameBufs b{};
+  b.recs = c.take<PRec>(n > 0 ? n : 1);
+  b.boxes = c.take<int4>(n > 0 ? n : 1);
+  b.counts = c.take<int>(n > 0 ? n : 1);
+  b.emit_start = c.take<long long>(n + 1);
+  b.scal = c.take<int>(64);
+  b.keys_a = c.take<int>(cap);
+  b.vals_a = c.take<int>(cap);
+  b.keys_b = c.take<int>(cap);
+  b.vals_b = c.take<int>(cap);
+  b.hist = c.take<int>((1 << kRadixBits) * kRadixBlocks);
+  b.tile_start = c.take<int>(n_tiles + 1);
+  b.opd = c.take<float>(hw);
+  b.band = c.take<float2>(hw);
+  b.colsum = c.take<double>(W);
+  if (backward) {
+    b.band2 = c.take<float2>(hw);
+    b.gopd = c.take<float>(hw);
+    b.colgrad = c.take<double>(3 * (size_t)W);
+  }
+  if (cap_out) *cap_out = cap;
+  return b;
+}
+
+size_t frame_workspace_bytes(int H, int W, int64_t n, int tile_h, int tile_w, int ppp, bool backward) {
+  Carver c{nullptr};
+  carve_impl(c, H, W, n, tile_h, tile_w, ppp, backward, nullptr);
+  return c.off;
+}
+
+FrameBufs carve(void* ws, int H, int W, int64_t n, int tile_h, int tile_w, int ppp, bool backward,
+                int64_t* cap_out) {
+  Carver c{static_cast<char*>(ws)};
+  return carve_impl(c, H, W, n, tile_h, tile_w, ppp, backward, cap_out);
+}
+
+// ---- pupil band: signed kx columns with any bin inside the (shifted) disc ----
+static void band_range(int H, int W, const osog_optics& o, int* kx_lo, int* kx_n) {
+  const double vx = 1.0 / ((double)W * o.pixel_um), vy = 1.0 / ((double)H * o.pixel_um);
+  const double tx = o.mode == OSOG_OBLIQUE ? o.tilt_fx : 0.0;
+  const double ty = o.mode == OSOG_OBLIQUE ? o.tilt_fy : 0.0;
+  const double r = o.na / o.wavelength_um, r2 = r * r;
+  const int kmin = -(H / 2), kmax = H / 2 - 1;
+  const double cky = -ty / vy;
+  int c0 = (int)std::floor(cky);
+  c0 = c0 < kmin ? kmin : (c0 > kmax ? kmax : c0);
+  int c1 = c0 + 1 > kmax ? kmax : c0 + 1;
+  int lo = INT_MAX, hi = INT_MIN;
+  for (int kx = -(W / 2); kx < W / 2; ++kx) {
+    const double gx = (double)kx * vx + tx;
+    const double gx2 = gx * gx;
+    const double gy0 = (double)c0 * vy + ty, gy1 = (double)c1 * vy + ty;
+    if (gx2 + gy0 * gy0 <= r2 || gx2 + gy1 * gy1 <= r2) {
+      if (kx < lo) lo = kx;
+      if (kx > hi) hi = kx;
+    }
+  }
+  if (lo > hi) { *kx_lo = 0; *kx_n = 0; }
+  else { *kx_lo = lo; *kx_n = hi - lo + 1; }
+}
+
+static osog_status check_optics(const osog_optics* o) {
+  if (!o) return fail(OSOG_ERR_INVALID_ARGUMENT, "optics is NULL");
+  if (o->mode < OSOG_BRIGHTFIELD || o->mode > OSOG_OBLIQUE)
+    return fail(OSOG_ERR_INVALID_ARGUMENT, "optics.mode must be 0 (brightfield), 1 (DIC) or 2 (oblique)");
+  if (!(o->wavelength_um > 0.0) || !std::isfinite(o->wavelength_um))
+    return fail(OSOG_ERR_INVALID_ARGUMENT, "optics.wavelength_um must be finite and > 0");
+  if (!(o->pixel_um > 0.0) || !std::isfinite(o->pixel_um))
+    return fail(OSOG_ERR_INVALID_ARGUMENT, "optics.pixel_um must be finite and > 0");
+  if (!(o->n_medium > 0.0) || !std::isfinite(o->n_medium))
+    return fail(OSOG_ERR_INVALID_ARGUMENT, "optics.n_medium must be finite and > 0");
+  if (!(o->na > 0.0) || !(o->na < o->n_medium))
+    return fail(OSOG_ERR_INVALID_ARGUMENT, "optics.na must satisfy 0 < na < n_medium");
+  if (!std::isfinite(o->shear_angle_rad) || !std::isfinite(o->tilt_fx) || !std::isfinite(o->tilt_fy))
+    return fail(OSOG_ERR_INVALID_ARGUMENT, "optics shear angle and tilt must be finite");
+  if (!(o->photons_mean >= 0.0) || !std::isfinite(o->photons_mean))
+    return fail(OSOG_ERR_INVALID_ARGUMENT, "optics.photons_mean must be finite and >= 0");
+  return OSOG_OK;
+}
+
+static osog_status check_frame(const osog_context* ctx, int H, int W, const float* soa, int64_t n,
+                               int64_t ld, const osog_optics* optics, const float* globals) {
+  if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
+  if (n < 0 || n > INT_MAX) return fail(OSOG_ERR_INVALID_ARGUMENT, "n must be in [0, 2^31)");
+  if (ld < n) return fail(OSOG_ERR_INVALID_ARGUMENT, "ld must be >= n");
+  if (n > 0 && !soa) return fail(OSOG_ERR_INVALID_ARGUMENT, "soa is NULL");
+  if (!globals) return fail(OSOG_ERR_INVALID_ARGUMENT, "globals is NULL");
+  osog_status st = check_optics(optics);
+  if (st != OSOG_OK) return st;
+  if (!pow2_in(H, 32, 4096) || !pow2_in(W, 32, 4096))
+    return fail(OSOG_ERR_UNSUPPORTED, "height and width must be powers of two in [32, 4096]");
+  if (H % ctx->tile_h || W % ctx->tile_w)
+    return fail(OSOG_ERR_UNSUPPORTED, "canvas sides must be multiples of the tile sides");
+  return OSOG_OK;
+}
+
+FramePlan make_plan(const osog_context* ctx, int H, int W, int64_t n, int64_t ld,
+                    const osog_optics& o, int64_t cap) {
+  FramePlan p{};
+  p.H = H; p.W = W; p.logH = ilog2(H); p.logW = ilog2(W);
+  p.tile_h = ctx->tile_h; p.tile_w = ctx->tile_w;
+  p.ntx = W / p.tile_w; p.nty = H / p.tile_h; p.n_tiles = p.ntx * p.nty;
+  p.key_bits = ilog2(p.n_tiles);
+  band_range(H, W, o, &p.kx_lo, &p.kx_n);
+  p.rb = rows_per_block(W);
+  p.n = n; p.ld = ld; p.cap = cap;
+  p.mode = o.mode;
+  p.phase_k = (float)(2.0 * M_PI / o.wavelength_um);
+  p.inv_wdx = (float)(1.0 / ((double)W * o.pixel_um));
+  p.inv_hdx = (float)(1.0 / ((double)H * o.pixel_um));
+  p.kn = (float)(o.n_medium / o.wavelength_um);
+  p.tfx_d = o.mode == OSOG_OBLIQUE ? o.tilt_fx : 0.0;
+  p.tfy_d = o.mode == OSOG_OBLIQUE ? o.tilt_fy : 0.0;
+  p.tfx = (float)p.tfx_d; p.tfy = (float)p.tfy_d;
+  p.cos_psi = (float)std::cos(o.shear_angle_rad);
+  p.sin_psi = (float)std::sin(o.shear_angle_rad);
+  p.dx_um = (float)o.pixel_um;
+  p.dx_d = o.pixel_um;
+  p.na_over_lambda = o.na / o.wavelength_um;
+  p.photons = (float)o.photons_mean;
+  p.seed_lo = (uint32_t)(o.seed & 0xffffffffu);
+  p.seed_hi = (uint32_t)(o.seed >> 32);
+  p.frame = o.noise_frame;
+  return p;
+}
+
+static int effective_ppp(int ppp) { return ppp > 0 ? ppp : kDefaultPairsPerParticle; }
+
+// Forward chain of one frame on a carved workspace.
+hipError_t forward_frame(const osog_context* ctx, const FramePlan& p, const float* soa,
+                         const float* globals, FrameBufs& b, float* opd_out, float* intensity,
+                         hipStream_t s) {
+  float* opd = opd_out ? opd_out : b.opd;
+  Profiler* pr = ctx->prof;
+  hipError_t e;
+  profile_begin(pr, OSOG_STAGE_BINNING, s);
+  if ((e = launch_binning(p, soa, b, s)) != hipSuccess) return e;
+  profile_end(pr, OSOG_STAGE_BINNING, s);
+  profile_begin(pr, OSOG_STAGE_RASTER, s);
+  if ((e = launch_raster(p, b, opd, s)) != hipSuccess) return e;
+  profile_end(pr, OSOG_STAGE_RASTER, s);
+  profile_begin(pr, OSOG_STAGE_PASS1, s);
+  if ((e = launch_pass1(p, opd, b, ctx->twiddle, s)) != hipSuccess) return e;
+  profile_end(pr, OSOG_STAGE_PASS1, s);
+  if (p.kx_n > 0) {
+    profile_begin(pr, OSOG_STAGE_PASS2, s);
+    if ((e = launch_pass2(p, globals, b, ctx->twiddle, s)) != hipSuccess) return e;
+    profile_end(pr, OSOG_STAGE_PASS2, s);
+  }
+  profile_begin(pr, OSOG_STAGE_PASS3, s);
+  if ((e = launch_pass3(p, b, ctx->twiddle, intensity, s)) != hipSuccess) return e;
+  profile_end(pr, OSOG_STAGE_PASS3, s);
+  return hipSuccess;
+}
+
+}  // namespace osog
+
+using namespace osog;
+
+extern "C" {
+
+osog_status osog_context_create(osog_context** out, int device) {
+  if (!out) return fail(OSOG_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+  if (device < 0 || device >= count) return fail(OSOG_ERR_INVALID_ARGUMENT, "no such HIP device");
+  if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+  osog_context* ctx = new (std::nothrow) osog_context();
+  if (!ctx) return fail(OSOG_ERR_INVALID_ARGUMENT, "out of host memory");
+  ctx->device = device;
+  std::vector<float2> tw(kTwN);
+  for (int m = 0; m < kTwN; ++m) {
+    double a = 2.0 * M_PI * (double)m / (double)kTwN;
+    tw[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  if ((e = hipMalloc(&ctx->twiddle, sizeof(float2) * kTwN)) != hipSuccess) {
+    delete ctx;
+    return hip_fail(e, "hipMalloc(twiddle)");
+  }
+  if ((e = hipMemcpy(ctx->twiddle, tw.data(), sizeof(float2) * kTwN, hipMemcpyHostToDevice)) != hipSuccess) {
+    (void)hipFree(ctx->twiddle);
+    delete ctx;
+    return hip_fail(e, "hipMemcpy(twiddle)");
+  }
+  ctx->batch = batch_cache_create();
+  ctx->prof = profiler_create();
+  *out = ctx;
+  return OSOG_OK;
+}
+
+osog_status osog_context_destroy(osog_context* ctx) {
+  if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
+  (void)hipSetDevice(ctx->device);
+  batch_cache_destroy(ctx->batch);
+  profiler_destroy(ctx->prof);
+  if (ctx->twiddle) (void)hipFree(ctx->twiddle);
+  delete ctx;
+  return OSOG_OK;
+}
+
+osog_status osog_set_tiling(osog_context* ctx, int32_t tile_h, int32_t tile_w) {
+  if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
+  if (!pow2_in(tile_h, 1, 256) || !pow2_in(tile_w, 1, 256) || tile_h * tile_w != kThreads)
+    return fail(OSOG_ERR_UNSUPPORTED, "tile sides must be powers of two with tile_h * tile_w == 256");
+  ctx->tile_h = tile_h;
+  ctx->tile_w = tile_w;
+  return OSOG_OK;
+}
+
+osog_status osog_get_tiling(const osog_context* ctx, int32_t* tile_h, int32_t* tile_w) {
+  if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
+  if (!tile_h || !tile_w) return fail(OSOG_ERR_INVALID_ARGUMENT, "output pointer is NULL");
+  *tile_h = ctx->tile_h;
+  *tile_w = ctx->tile_w;
+  return OSOG_OK;
+}
+
+osog_status osog_workspace_size(const osog_context* ctx, int32_t height, int32_t width, int64_t n,
+                                int32_t pairs_per_particle, int32_t with_backward, size_t* bytes) {
+  if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
+  if (!bytes) return fail(OSOG_ERR_INVALID_ARGUMENT, "bytes is NULL");
+  if (n < 0 || n > INT_MAX) return fail(OSOG_ERR_INVALID_ARGUMENT, "n must be in [0, 2^31)");
+  if (pairs_per_particle < 0) return fail(OSOG_ERR_INVALID_ARGUMENT, "pairs_per_particle must be >= 0");
+  if (!pow2_in(height, 32, 4096) || !pow2_in(width, 32, 4096))
+    return fail(OSOG_ERR_UNSUPPORTED, "height and width must be powers of two in [32, 4096]");
+  if (height % ctx->tile_h || width % ctx->tile_w)
+    return fail(OSOG_ERR_UNSUPPORTED, "canvas sides must be multiples of the tile sides");
+  *bytes = frame_workspace_bytes(height, width, n, ctx->tile_h, ctx->tile_w,
+                                 effective_ppp(pairs_per_particle), with_backward != 0);
+  return OSOG_OK;
+}
+
+osog_status osog_render(osog_context* ctx, void* stream, int32_t height, int32_t width,
+                        const float* soa, int64_t n, int64_t ld, const osog_optics* optics,
+                        const float* globals, float* opd_out, float* intensity_out,
+                        void* workspace, size_t workspace_bytes) {
+  osog_status st = check_frame(ctx, height, width, soa, n, ld, optics, globals);
+  if (st != OSOG_OK) return st;
+  if (!intensity_out) return fail(OSOG_ERR_INVALID_ARGUMENT, "intensity_out is NULL");
+  if (!workspace) return fail(OSOG_ERR_WORKSPACE, "workspace is NULL");
+  // the largest pair capacity this workspace holds
+  int ppp = 0;
+  for (int cand = 1 << 20; cand >= 1; cand >>= 1)
+    if (frame_workspace_bytes(height, width, n, ctx->tile_h, ctx->tile_w, cand, false) <= workspace_bytes) {
+      ppp = cand;
+      break;
+    }
+  if (ppp == 0) return fail(OSOG_ERR_WORKSPACE, "workspace smaller than osog_workspace_size()");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  int64_t cap = 0;
+  FrameBufs b = carve(workspace, height, width, n, ctx->tile_h, ctx->tile_w, ppp, false, &cap);
+  FramePlan p = make_plan(ctx, height, width, n, ld, *optics, cap);
+  e = forward_frame(ctx, p, soa, globals, b, opd_out, intensity_out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "osog_render launch");
+  return OSOG_OK;
+}
+
+osog_status osog_bin(osog_context* ctx, void* stream, int32_t height, int32_t width,
+                     const float* soa, int64_t n, int64_t ld, int32_t* keys_out, int32_t* pids_out,
+                     int64_t capacity, int32_t* pair_count_out, int32_t* tile_start_out,
+                     int32_t* counts_out, void* workspace, size_t workspace_bytes) {
+  if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
+  if (n < 0 || n > INT_MAX || ld < n) return fail(OSOG_ERR_INVALID_ARGUMENT, "bad n or ld");
+  if (n > 0 && !soa) return fail(OSOG_ERR_INVALID_ARGUMENT, "soa is NULL");
+  if (!keys_out || !pids_out || !pair_count_out || !tile_start_out)
+    return fail(OSOG_ERR_INVALID_ARGUMENT, "output pointer is NULL");
+  if (capacity < 0 || capacity > INT_MAX - 1) return fail(OSOG_ERR_INVALID_ARGUMENT, "bad capacity");
+  if (!pow2_in(height, 32, 4096) || !pow2_in(width, 32, 4096))
+    return fail(OSOG_ERR_UNSUPPORTED, "height and width must be powers of two in [32, 4096]");
+  if (height % ctx->tile_h || width % ctx->tile_w)
+    return fail(OSOG_ERR_UNSUPPORTED, "canvas sides must be multiples of the tile sides");
+  size_t need = frame_workspace_bytes(height, width, n, ctx->tile_h, ctx->tile_w, 1, false);
+  if (!workspace || workspace_bytes < need) return fail(OSOG_ERR_WORKSPACE, "workspace too small");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  int ppp = 1;
+  for (int cand = 1 << 20; cand >= 1; cand >>= 1)
+    if (frame_workspace_bytes(height, width, n, ctx->tile_h, ctx->tile_w, cand, false) <= workspace_bytes) {
+      ppp = cand;
+      break;
+    }
+  int64_t cap = 0;
+  FrameBufs b = carve(workspace, height, width, n, ctx->tile_h, ctx->tile_w, ppp, false, &cap);
+  if (cap > capacity) cap = capacity;
+  osog_optics o{};
+  o.mode = OSOG_BRIGHTFIELD; o.wavelength_um = 0.55; o.na = 0.5; o.n_medium = 1.33; o.pixel_um = 0.1;
+  FramePlan p = make_plan(ctx, height, width, n, ld, o, cap);
+  hipStream_t s = (hipStream_t)stream;
+  if ((e = launch_binning(p, soa, b, s)) != hipSuccess) return hip_fail(e, "osog_bin launch");
+  if ((e = hipMemcpyAsync(pair_count_out, b.emit_start + n, sizeof(int32_t), hipMemcpyDeviceToDevice, s)) != hipSuccess)
+    return hip_fail(e, "copy pair count");
+  if (cap > 0) {
+    if ((e = hipMemcpyAsync(keys_out, b.keys_a, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+      return hip_fail(e, "copy keys");
+    if ((e = hipMemcpyAsync(pids_out, b.vals_a, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+      return hip_fail(e, "copy pids");
+  }
+  if ((e = hipMemcpyAsync(tile_start_out, b.tile_start, sizeof(int32_t) * (p.n_tiles + 1), hipMemcpyDeviceToDevice, s)) != hipSuccess)
+    return hip_fail(e, "copy tile_start");
+  if (counts_out && n > 0 &&
+      (e = hipMemcpyAsync(counts_out, b.counts, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+    return hip_fail(e, "copy counts");
+  return OSOG_OK;
+}
+
+osog_status osog_band_info(const osog_context* ctx, int32_t height, int32_t width,
+                           const osog_optics* optics, int32_t* kx_lo, int32_t* kx_n) {
+  if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
+  if (!kx_lo || !kx_n) return fail(OSOG_ERR_INVALID_ARGUMENT, "output pointer is NULL");
+  osog_status st = check_optics(optics);
+  if (st != OSOG_OK) return st;
+  if (!pow2_in(height, 32, 4096) || !pow2_in(width, 32, 4096))
+    return fail(OSOG_ERR_UNSUPPORTED, "height and width must be powers of two in [32, 4096]");
+  int lo = 0, nn = 0;
+  band_range(height, width, *optics, &lo, &nn);
+  *kx_lo = lo;
+  *kx_n = nn;
+  return OSOG_OK;
+}
+
+osog_status osog_philox4x32_10(void* stream, const uint32_t* ctr, int64_t count, uint32_t key0,
+                               uint32_t key1, uint32_t* out) {
+  if (count < 0) return fail(OSOG_ERR_INVALID_ARGUMENT, "count must be >= 0");
+  if (count > 0 && (!ctr || !out)) return fail(OSOG_ERR_INVALID_ARGUMENT, "NULL pointer");
+  if (count == 0) return OSOG_OK;
+  hipError_t e = launch_philox(ctr, count, key0, key1, out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "osog_philox4x32_10 launch");
+  return OSOG_OK;
+}
+
+osog_status osog_profile_enable(osog_context* ctx, int32_t enable) {
+  if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
+  profiler_set(ctx->prof, enable != 0);
+  return OSOG_OK;
+}
+
+osog_status osog_profile_read(osog_context* ctx, double* ms, int64_t* launches) {
+  if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
+  if (!ms || !launches) return fail(OSOG_ERR_INVALID_ARGUMENT, "output pointer is NULL");
+  hipError_t e = profiler_read(ctx->prof, ms, launches);
+  if (e != hipSuccess) return hip_fail(e, "osog_profile_read");
+  return OSOG_OK;
+}
+
+const char* osog_status_string(osog_status s) {
+  switch (s) {
+    case OSOG_OK: return "OSOG_OK";
+    case OSOG_ERR_INVALID_ARGUMENT: return "OSOG_ERR_INVALID_ARGUMENT";
+    case OSOG_ERR_UNSUPPORTED: return "OSOG_ERR_UNSUPPORTED";
+    case OSOG_ERR_WORKSPACE: return "OSOG_ERR_WORKSPACE";
+    case OSOG_ERR_HIP: return "OSOG_ERR_HIP";
+    case OSOG_ERR_NOT_INITIALIZED: return "OSOG_ERR_NOT_INITIALIZED";
+  }
+  return "unknown osog_status";
+}
+
+const char* osog_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

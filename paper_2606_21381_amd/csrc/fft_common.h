@@ -1,0 +1,266 @@
+// Device building blocks of the imaging chain: Stockham FFT stages in LDS, the
+// transfer function of each modality, the FP64 pupil-support predicate and the
+// Poisson sampler.  Shared by the forward and adjoint passes.
+#pragma once
+
+#include "osog_internal.h"
+
+namespace osog {
+
+// Rows of the blocked band layout (and rows per pass-1/pass-3 workgroup): keeps
+// one workgroup's LDS at <= 64 KB for W >= 1024.
+__host__ __device__ constexpr int rows_per_block(int W) { return W >= 1024 ? 8192 / W : 8; }
+
+// Kernel-argument copy of the optics a pass needs.
+struct OpticsArgs {
+  int H, W, kx_lo, kx_n, rb, mode;
+  float inv_wdx, inv_hdx, kn, tfx, tfy, dsx_per_px, dsy_per_px, inv_hw, photons;
+  double vx, vy, tfx_d, tfy_d, r2;  // FP64 band predicate: f = k * v, (fx+tx)^2 + (fy+ty)^2 <= r2
+  uint32_t seed_lo, seed_hi, frame;
+};
+
+inline OpticsArgs optics_args(const FramePlan& p) {
+  OpticsArgs o;
+  o.H = p.H; o.W = p.W; o.kx_lo = p.kx_lo; o.kx_n = p.kx_n; o.rb = p.rb; o.mode = p.mode;
+  o.inv_wdx = p.inv_wdx; o.inv_hdx = p.inv_hdx; o.kn = p.kn; o.tfx = p.tfx; o.tfy = p.tfy;
+  o.dsx_per_px = 0.5f * p.dx_um * p.cos_psi;  // ds = (shear/2) dx (cos psi, sin psi)
+  o.dsy_per_px = 0.5f * p.dx_um * p.sin_psi;
+  o.inv_hw = 1.0f / ((float)p.H * (float)p.W);
+  o.photons = p.photons;
+  o.vx = 1.0 / ((double)p.W * p.dx_d);
+  o.vy = 1.0 / ((double)p.H * p.dx_d);
+  o.tfx_d = p.tfx_d; o.tfy_d = p.tfy_d;
+  o.r2 = p.na_over_lambda * p.na_over_lambda;
+  o.seed_lo = p.seed_lo; o.seed_hi = p.seed_hi; o.frame = p.frame;
+  return o;
+}
+
+// ---- small DFTs in registers; DIR = -1 forward (e^{-i...}), +1 inverse --------
+template <int DIR>
+__device__ __forceinline__ float2 mul_i(float2 z) {  // z * (DIR i)
+  return DIR > 0 ? make_float2(-z.y, z.x) : make_float2(z.y, -z.x);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft4(float2& v0, float2& v1, float2& v2, float2& v3) {
+  float2 t0 = cadd(v0, v2), t1 = csub(v0, v2), t2 = cadd(v1, v3), t3 = mul_i<DIR>(csub(v1, v3));
+  v0 = cadd(t0, t2);
+  v2 = csub(t0, t2);
+  v1 = cadd(t1, t3);
+  v3 = csub(t1, t3);
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void dft(float2* v) {
+  if constexpr (R == 2) {
+    float2 a = v[0];
+    v[0] = cadd(a, v[1]);
+    v[1] = csub(a, v[1]);
+  } else if constexpr (R == 4) {
+    dft4<DIR>(v[0], v[1], v[2], v[3]);
+  } else {
+    float2 e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    float2 o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<DIR>(e0, e1, e2, e3);
+    dft4<DIR>(o0, o1, o2, o3);
+    const float s2 = 0.70710678118654752f;
+    o1 = cscale(cadd(o1, mul_i<DIR>(o1)), s2);       // * (1 + DIR i)/sqrt2
+    o2 = mul_i<DIR>(o2);                              // * DIR i
+    o3 = cscale(csub(mul_i<DIR>(o3), o3), s2);        // * (-1 + DIR i)/sqrt2
+    v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+  }
+}
+
+// One Stockham autosort stage over ROWS rows of N points held in LDS, then the
+// remaining stages.  NS = product of the radices done so far, REM = log2 of the
+// part still to transform.  Butterfly j of radix R reads x[j + r N/R],
+// twiddles by W^(r (j mod NS) N/(NS R)), and writes to (j/NS) NS R + (j mod NS) + r NS.
+template <int N, int ROWS, int DIR, int NS, int REM>
+struct Stages {
+  static __device__ __forceinline__ void run(float2* buf, const float2* __restrict__ tw) {
+    constexpr int R = REM >= 3 ? 8 : (REM == 2 ? 4 : 2);
+    constexpr int LR = REM >= 3 ? 3 : REM;
+    constexpr int NB = N / R, TOT = ROWS * NB, BPT = (TOT + kThreads - 1) / kThreads;
+    constexpr int TSTRIDE = kTwN / N;
+    float2 v[BPT][R];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) {
+      const int idx = t + q * kThreads;
+      if (TOT % kThreads == 0 || idx < TOT) {
+        const int row = idx / NB, j = idx % NB;
+        const float2* rb = buf + row * N;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[q][r] = rb[j + r * NB];
+        if constexpr (NS > 1) {
+          const int k = j & (NS - 1);
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            float2 w = tw[(r * k * (N / (NS * R))) * TSTRIDE];
+            if (DIR < 0) w.y = -w.y;
+            v[q][r] = cmul(v[q][r], w);
+          }
+        }
+        dft<R, DIR>(v[q]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < BPT; ++q) {
+      const int idx = t + q * kThreads;
+      if (TOT % kThreads == 0 || idx < TOT) {
+        const int row = idx / NB, j = idx % NB;
+        float2* rb = buf + row * N;
+        const int d = (j / NS) * NS * R + (j & (NS - 1));
+#pragma unroll
+        for (int r = 0; r < R; ++r) rb[d + r * NS] = v[q][r];
+      }
+    }
+    __syncthreads();
+    Stages<N, ROWS, DIR, NS * R, REM - LR>::run(buf, tw);
+  }
+};
+
+template <int N, int ROWS, int DIR, int NS>
+struct Stages<N, ROWS, DIR, NS, 0> {
+  static __device__ __forceinline__ void run(float2*, const float2* __restrict__) {}
+};
+
+// ---- transfer function ------------------------------------------------------
+// P(f) = exp(i dz (kz - k0)) inside the pupil (the piston exp(i dz k0) of Eq. 3 is
+// dropped: it multiplies the whole field by one phase and leaves |E|^2 unchanged);
+// kz - k0 = -2 pi |g|^2 / (kn + sqrt(kn^2 - |g|^2)) without cancellation, g = f + f_t.
+// DIC: P (e^{i th} e^{+2 pi i f.ds} - e^{-i th} e^{-2 pi i f.ds}) = 2 i sin(2 pi f.ds + th) P.
+__device__ __forceinline__ float2 transfer(const OpticsArgs& o, int kx, int ky, float dz,
+                                           float shear, float bias) {
+  const float two_pi = 6.283185307179586f;
+  const float fx = (float)kx * o.inv_wdx, fy = (float)ky * o.inv_hdx;
+  const float gx = fx + o.tfx, gy = fy + o.tfy;
+  const float g2 = gx * gx + gy * gy;
+  const float kzm = -two_pi * g2 / (o.kn + sqrtf(fmaxf(o.kn * o.kn - g2, 0.0f)));
+  float s, c;
+  sincosf(dz * kzm, &s, &c);
+  if (o.mode == OSOG_DIC) {
+    const float rho = two_pi * shear * (fx * o.dsx_per_px + fy * o.dsy_per_px);
+    const float sr = 2.0f * sinf(rho + bias);
+    return make_float2(-sr * s, sr * c);
+  }
+  return make_float2(c, s);
+}
+
+// Derivatives of the transfer function with respect to (dz, shear, bias).
+__device__ __forceinline__ void transfer_grads(const OpticsArgs& o, int kx, int ky, float dz,
+                                               float shear, float bias, float2* d_dz,
+                                               float2* d_shear, float2* d_bias) {
+  const float two_pi = 6.283185307179586f;
+  const float fx = (float)kx * o.inv_wdx, fy = (float)ky * o.inv_hdx;
+  const float gx = fx + o.tfx, gy = fy + o.tfy;
+  const float g2 = gx * gx + gy * gy;
+  const float kzm = -two_pi * g2 / (o.kn + sqrtf(fmaxf(o.kn * o.kn - g2, 0.0f)));
+  float s, c;
+  sincosf(dz * kzm, &s, &c);
+  const float2 P = make_float2(c, s);
+  const float2 dP = make_float2(-kzm * s, kzm * c);  // d/dz e^{i dz kzm} = i kzm P
+  if (o.mode == OSOG_DIC) {
+    const float fds = fx * o.dsx_per_px + fy * o.dsy_per_px;
+    const float rho = two_pi * shear * fds;
+    float sn, cs;
+    sincosf(rho + bias, &sn, &cs);
+    // H = 2 i sin(rho + bias) P
+    *d_dz = make_float2(-2.0f * sn * dP.y, 2.0f * sn * dP.x);
+    const float dsh = 2.0f * cs * two_pi * fds;          // d/dshear of 2 sin(rho+bias)
+    *d_shear = make_float2(-dsh * P.y, dsh * P.x);
+    const float db = 2.0f * cs;
+    *d_bias = make_float2(-db * P.y, db * P.x);
+  } else {
+    *d_dz = dP;
+    *d_shear = make_float2(0.0f, 0.0f);
+    *d_bias = make_float2(0.0f, 0.0f);
+  }
+}
+
+// Pupil support of column kx: the signed ky range where
+// (fx + tx)^2 + (fy + ty)^2 <= (NA/lambda)^2, f = k / (N dx), evaluated in FP64
+// with every operation separately rounded (the same expression as the host's
+// band bounds), so that no bin on the disc's edge can flip between passes.
+__device__ inline void band_chord(const OpticsArgs& o, int kx, int* lo_out, int* hi_out) {
+#pragma clang fp contract(off)
+  const double gx = (double)kx * o.vx + o.tfx_d;
+  const double gx2 = gx * gx;
+  const int kmin = -(o.H / 2), kmax = o.H / 2 - 1;
+  auto pred = [&](int ky) {
+    const double gy = (double)ky * o.vy + o.tfy_d;
+    return gx2 + gy * gy <= o.r2;
+  };
+  const double cky = -o.tfy_d / o.vy;
+  int c0 = (int)floor(cky);
+  c0 = c0 < kmin ? kmin : (c0 > kmax ? kmax : c0);
+  int c1 = c0 + 1 > kmax ? kmax : c0 + 1;
+  int c;
+  if (pred(c0)) c = c0;
+  else if (pred(c1)) c = c1;
+  else { *lo_out = 1; *hi_out = 0; return; }
+  const double rem = o.r2 - gx2;
+  const double hw = rem > 0.0 ? sqrt(rem) / o.vy : 0.0;
+  int l = (int)fmax((double)kmin, floor(cky - hw));
+  int h = (int)fmin((double)kmax, ceil(cky + hw));
+  if (l > c) l = c;
+  if (h < c) h = c;
+  while (l < c && !pred(l)) ++l;
+  while (l > kmin && pred(l - 1)) --l;
+  while (h > c && !pred(h)) --h;
+  while (h < kmax && pred(h + 1)) ++h;
+  *lo_out = l;
+  *hi_out = h;
+}
+
+// ---- Poisson sampler ---------------------------------------------------------
+// Philox4x32-10 stream per pixel: counter (pixel, frame, round, 0), key = seed.
+// mean < 10: inversion by sequential search on one uniform (at most 40 steps);
+// mean >= 10: transformed rejection with squeeze (Hoermann 1993, "PTRS"), two
+// uniforms per attempt, two attempts per Philox call, at most 16 calls.  Every
+// operation is a separately rounded FP32 operation.
+__device__ inline int poisson(float mu, uint32_t pixel, uint32_t frame, uint32_t k0, uint32_t k1) {
+#pragma clang fp contract(off)
+  if (!(mu > 0.0f)) return 0;
+  if (mu < 10.0f) {
+    uint4 r = philox4x32_10(make_uint4(pixel, frame, 0u, 0u), k0, k1);
+    const float u = u01(r.x);
+    float p = expf(-mu);
+    float F = p;
+    int k = 0;
+    while (u > F && k < 40) {
+      ++k;
+      p = p * (mu / (float)k);
+      F = F + p;
+    }
+    return k;
+  }
+  const float smu = sqrtf(mu), log_mu = logf(mu);
+  const float b = 0.931f + 2.53f * smu;
+  const float a = -0.059f + 0.02483f * b;
+  const float inv_alpha = 1.1239f + 1.1328f / (b - 3.4f);
+  const float vr = 0.9277f - 3.6224f / (b - 2.0f);
+  for (uint32_t rnd = 0; rnd < 16; ++rnd) {
+    const uint4 r = philox4x32_10(make_uint4(pixel, frame, rnd, 0u), k0, k1);
+    const uint32_t w[4] = {r.x, r.y, r.z, r.w};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const float U = u01(w[2 * q]) - 0.5f;
+      const float V = u01(w[2 * q + 1]);
+      const float us = 0.5f - fabsf(U);
+      const float kf = floorf((((2.0f * a) / us) + b) * U + (mu + 0.43f));
+      if (us >= 0.07f && V <= vr) return (int)kf;
+      if (kf < 0.0f || (us < 0.013f && V > us)) continue;
+      const float lhs = (logf(V) + logf(inv_alpha)) - logf(a / (us * us) + b);
+      const float rhs = (-mu + kf * log_mu) - lgammaf(kf + 1.0f);
+      if (lhs <= rhs) return (int)kf;
+    }
+  }
+  return (int)floorf(mu);
+}
+
+}  // namespace osog

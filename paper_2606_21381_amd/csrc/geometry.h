@@ -1,0 +1,85 @@
+// Per-pixel particle thickness (paper Sec. III.A, Eq. 1 with M = 4 vertical
+// side faces plus top and bottom for the prism; the ellipsoid height profile)
+// and its derivatives.  Included by the raster and adjoint kernels.
+#pragma once
+
+#include "osog_internal.h"
+
+namespace osog {
+
+// Average of clamp(y, 0, 1) over y running linearly from y1 to y2.
+// Written as (fraction of [lo,hi] inside [0,1]) * (mean inside) + (fraction
+// above 1) so that short or flat segments stay well conditioned.
+__device__ __forceinline__ float clamp_avg(float y1, float y2) {
+  float lo = fminf(y1, y2), hi = fmaxf(y1, y2);
+  float clo = fminf(fmaxf(lo, 0.0f), 1.0f), chi = fminf(fmaxf(hi, 0.0f), 1.0f);
+  float d = hi - lo;
+  if (!(d > 0.0f)) return clo;
+  float fin = (chi - clo) / d;
+  float above = fmaxf(0.0f, hi - fmaxf(lo, 1.0f)) / d;
+  return fin * ((clo + chi) * 0.5f) + above;
+}
+
+// Signed contribution of the directed edge P->Q of a counter-clockwise polygon
+// to its area inside the unit square [0,1]^2:  -integral over x in [0,1] of
+// clamp(y(x), 0, 1) dx along the edge (Green's theorem, area = -closed integral y dx,
+// with y clamped to the square).
+__device__ __forceinline__ float edge_area(float px, float py, float qx, float qy) {
+  float xl = fminf(px, qx), xr = fmaxf(px, qx);
+  float a = fmaxf(xl, 0.0f), b = fminf(xr, 1.0f);
+  if (!(b > a)) return 0.0f;
+  float sl = (qy - py) / (qx - px);
+  float ya = (a == px) ? py : ((a == qx) ? qy : py + (a - px) * sl);
+  float yb = (b == px) ? py : ((b == qx) ? qy : py + (b - px) * sl);
+  float w = (b - a) * clamp_avg(ya, yb);
+  return (qx > px) ? -w : w;
+}
+
+// Exact area of pixel (i, j) covered by the prism footprint of record r.
+// Pixel-corner offsets j - cx and i - cy are exact in FP32 for on-canvas
+// particles, so the clip runs in small local coordinates.
+__device__ __forceinline__ float prism_cover(const PRec& r, int i, int j) {
+  float cx = r.f[0], cy = r.f[1], c = r.f[4], s = r.f[5], a = r.f[6], b = r.f[7];
+  float dx = ((float)j + 0.5f) - cx, dy = ((float)i + 0.5f) - cy;
+  float u = c * dx + s * dy, v = -s * dx + c * dy;
+  const float hd = 0.70712f;  // > sqrt(2)/2: the pixel lies in this disc around its centre
+  if (fabsf(u) > a + hd || fabsf(v) > b + hd) return 0.0f;
+  if (fabsf(u) < a - hd && fabsf(v) < b - hd) return 1.0f;
+  float X0 = (float)j - cx, Y0 = (float)i - cy;
+  float x0 = r.f[8] - X0, y0 = r.f[9] - Y0, x1 = r.f[10] - X0, y1 = r.f[11] - Y0;
+  float x2 = r.f[12] - X0, y2 = r.f[13] - Y0, x3 = r.f[14] - X0, y3 = r.f[15] - Y0;
+  float area = edge_area(x0, y0, x1, y1);
+  area += edge_area(x1, y1, x2, y2);
+  area += edge_area(x2, y2, x3, y3);
+  area += edge_area(x3, y3, x0, y0);
+  return area;
+}
+
+// Ellipsoid thickness times dn at the centre of pixel (i, j).  Within 2e-3 of
+// the rim, where sqrt(1 - q) amplifies rounding, q is recomputed in FP64.
+__device__ __forceinline__ float ellipsoid_opd(const PRec& r, int i, int j) {
+  float cx = r.f[0], cy = r.f[1], c = r.f[4], s = r.f[5];
+  float dx = ((float)j + 0.5f) - cx, dy = ((float)i + 0.5f) - cy;
+  float u = (c * dx + s * dy) * r.f[8], v = (-s * dx + c * dy) * r.f[9];
+  float q = u * u + v * v;
+  if (q >= 1.002f) return 0.0f;
+  if (q > 0.998f) {
+    double cd = __hiloint2double(__float_as_int(r.f[11]), __float_as_int(r.f[10]));
+    double sd = __hiloint2double(__float_as_int(r.f[13]), __float_as_int(r.f[12]));
+    double ddx = ((double)j + 0.5) - (double)cx, ddy = ((double)i + 0.5) - (double)cy;
+    double uu = (cd * ddx + sd * ddy) / (double)r.f[6];
+    double vv = (-sd * ddx + cd * ddy) / (double)r.f[7];
+    double qq = uu * uu + vv * vv;
+    return qq < 1.0 ? (float)((double)r.f[14] * (double)r.f[15] * sqrt(1.0 - qq)) : 0.0f;
+  }
+  return r.f[2] * sqrtf(1.0f - q);
+}
+
+__device__ __forceinline__ float particle_opd(const PRec& r, int i, int j) {
+  float k = r.f[3];
+  if (k == 0.0f) return r.f[2] * prism_cover(r, i, j);
+  if (k == 1.0f) return ellipsoid_opd(r, i, j);
+  return 0.0f;
+}
+
+}  // namespace osog

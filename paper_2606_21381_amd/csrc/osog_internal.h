@@ -1,0 +1,135 @@
+// Internal declarations of libosog: device data structures, workspace plan and
+// the kernel launchers shared between translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "osog.h"
+
+namespace osog {
+
+constexpr int kThreads = 256;     // every kernel runs 256-thread workgroups (4 wave64)
+constexpr int kTwN = 4096;        // twiddle table length (largest FFT)
+constexpr int kRadixBits = 8;     // LSD radix digit width
+constexpr int kRadixBlocks = 256; // workgroups of each radix pass
+constexpr int kDefaultPairsPerParticle = 32;
+
+// Per-particle raster record, 64 bytes, written once by the prepare kernel.
+//   f[0] cx  f[1] cy  f[2] amp = dn*h (FP32)  f[3] kind (0 prism, 1 ellipsoid, -1 none)
+//   f[4] cos f[5] sin f[6] a   f[7] b
+//   prism     f[8..15] footprint corner offsets from the centre (x0,y0,...,x3,y3), CCW
+//   ellipsoid f[8] 1/a f[9] 1/b f[10..11] cos as double f[12..13] sin as double
+//             f[14] dn f[15] h     (the FP64 rim refinement uses these)
+struct __align__(16) PRec {
+  float f[16];
+};
+
+// Static per-call description of a frame, computed on the host.
+struct FramePlan {
+  int H, W, logH, logW;
+  int tile_h, tile_w, ntx, nty, n_tiles;
+  int key_bits;          // bits of the tile key (0 when one tile)
+  int kx_lo, kx_n;       // in-band signed kx range [kx_lo, kx_lo + kx_n)
+  int rb;                // rows per band block of the blocked spectrum layout
+  int64_t n, ld, cap;    // particles, leading dimension, pair capacity
+  // optics in the precision the kernels use
+  int mode;
+  float phase_k;         // 2 pi / lambda  [rad/um]
+  float inv_wdx, inv_hdx;// 1/(W dx), 1/(H dx)  [cycles/um per bin]
+  float kn;              // n_medium / lambda [cycles/um]
+  float tfx, tfy;        // oblique tilt [cycles/um] (0 unless oblique)
+  float cos_psi, sin_psi;// DIC shear direction
+  float dx_um;
+  double na_over_lambda; // pupil radius, FP64 (the band predicate is FP64)
+  double dx_d, tfx_d, tfy_d;
+  float photons;
+  uint32_t seed_lo, seed_hi, frame;
+};
+
+// Carved views into the caller's workspace for one frame.
+struct FrameBufs {
+  PRec* recs;
+  int4* boxes;
+  int* counts;
+  long long* emit_start;  // n + 1
+  int* scal;              // [0] pair count (clamped), [1] overflow flag
+  int* keys_a; int* vals_a; int* keys_b; int* vals_b;
+  int* hist;              // 2^kRadixBits * kRadixBlocks
+  int* tile_start;        // n_tiles + 1
+  float* opd;             // H*W (used when the caller passes no opd_out)
+  float2* band;           // H * W complex (blocked layout, kx_n used)
+  double* colsum;         // W
+  // backward only
+  float2* band2;          // H * W complex
+  float* gopd;            // H*W
+  double* colgrad;        // 3 * W
+};
+
+size_t frame_workspace_bytes(int H, int W, int64_t n, int tile_h, int tile_w, int ppp, bool backward);
+FrameBufs carve(void* ws, int H, int W, int64_t n, int tile_h, int tile_w, int ppp, bool backward, int64_t* cap_out);
+
+// launchers (return hipError_t of the last launch)
+hipError_t launch_binning(const FramePlan& p, const float* soa, FrameBufs& b, hipStream_t s);
+hipError_t launch_raster(const FramePlan& p, FrameBufs& b, float* opd, hipStream_t s);
+hipError_t launch_pass1(const FramePlan& p, const float* opd, FrameBufs& b, const float2* tw, hipStream_t s);
+hipError_t launch_pass2(const FramePlan& p, const float* globals, FrameBufs& b, const float2* tw, hipStream_t s);
+hipError_t launch_pass3(const FramePlan& p, FrameBufs& b, const float2* tw, float* intensity, hipStream_t s);
+hipError_t launch_philox(const uint32_t* ctr, int64_t count, uint32_t k0, uint32_t k1, uint32_t* out, hipStream_t s);
+
+// backward launchers
+hipError_t launch_adj_pass3(const FramePlan& p, FrameBufs& b, const float2* tw, const float* grad_i, hipStream_t s);
+hipError_t launch_adj_pass2(const FramePlan& p, const float* globals, FrameBufs& b, const float2* tw, hipStream_t s);
+hipError_t launch_adj_pass1(const FramePlan& p, const float* opd, const float* grad_opd, FrameBufs& b, const float2* tw, hipStream_t s);
+hipError_t launch_raster_adjoint(const FramePlan& p, const float* soa, FrameBufs& b, float* grad_soa, hipStream_t s);
+hipError_t launch_global_grads(const FramePlan& p, FrameBufs& b, float* grad_globals, hipStream_t s);
+
+void set_error(const std::string& msg);
+
+// Stage profiler owned by the context (HIP events around stage launches).
+struct Profiler;
+Profiler* profiler_create();
+void profiler_destroy(Profiler* p);
+// begin/end return without doing anything when profiling is off
+void profile_begin(Profiler* p, int stage, hipStream_t s);
+void profile_end(Profiler* p, int stage, hipStream_t s);
+void profiler_set(Profiler* p, bool on);
+hipError_t profiler_read(Profiler* p, double* ms, int64_t* launches);
+
+}  // namespace osog
+
+// ---------------------------------------------------------------------------
+// Device helpers shared by several kernels.
+// ---------------------------------------------------------------------------
+namespace osog {
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 10 rounds of two 32x32->64
+// multiplies with the Weyl-sequence key schedule.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    uint32_t hi0 = __umulhi(M0, c.x), lo0 = M0 * c.x;
+    uint32_t hi1 = __umulhi(M1, c.z), lo1 = M1 * c.z;
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    k0 += W0;
+    k1 += W1;
+  }
+  return c;
+}
+
+__device__ __forceinline__ float u01(uint32_t x) {
+  return ((float)(x >> 9) + 0.5f) * (1.0f / 8388608.0f);  // exact: 23-bit grid, never 0 or 1
+}
+
+}  // namespace osog

@@ -1,0 +1,199 @@
+"""Python face of libosog: render(), render_backward(), RenderFn, bin_pairs(), batch_render().
+
+PyTorch supplies device memory and the current stream; every computation runs
+in libosog's HIP kernels through the C ABI.  There is no CPU fallback: if the
+library or a GPU is missing these functions raise.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import torch
+
+from . import _lib
+
+_contexts = {}
+
+
+def context(device: Optional[torch.device] = None):
+    """The library context of a CUDA (HIP) device, created on first use."""
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    ctx = _contexts.get(idx)
+    if ctx is None:
+        lib = _lib.load()
+        p = ctypes.c_void_p()
+        _lib.check(lib.osog_context_create(ctypes.byref(p), idx), "osog_context_create")
+        ctx = p
+        _contexts[idx] = ctx
+    return ctx
+
+
+def set_tiling(tile_h: int, tile_w: int, device=None):
+    _lib.check(_lib.load().osog_set_tiling(context(device), tile_h, tile_w), "osog_set_tiling")
+
+
+def get_tiling(device=None):
+    h, w = ctypes.c_int32(), ctypes.c_int32()
+    _lib.check(_lib.load().osog_get_tiling(context(device), ctypes.byref(h), ctypes.byref(w)),
+               "osog_get_tiling")
+    return h.value, w.value
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _check_soa(soa: torch.Tensor):
+    if soa.dim() != 2 or soa.shape[0] != 8 or soa.dtype != torch.float32 or not soa.is_cuda:
+        raise ValueError("soa must be a CUDA float32 tensor of shape [8, n]")
+    if soa.shape[1] > 0 and soa.stride(1) != 1:
+        raise ValueError("soa rows must be contiguous")
+    n = soa.shape[1]
+    ld = soa.stride(0) if n > 0 else 0
+    return n, max(ld, n)
+
+
+def _check_globals(g: torch.Tensor, device):
+    if g.dtype != torch.float32 or g.numel() != 4 or not g.is_cuda or not g.is_contiguous():
+        raise ValueError("globals must be a contiguous CUDA float32 tensor of 4 values")
+    return g
+
+
+def workspace_size(H: int, W: int, n: int, with_backward: bool = False, pairs_per_particle: int = 0,
+                   device=None) -> int:
+    b = ctypes.c_size_t()
+    _lib.check(_lib.load().osog_workspace_size(context(device), H, W, n, pairs_per_particle,
+                                               1 if with_backward else 0, ctypes.byref(b)),
+               "osog_workspace_size")
+    return b.value
+
+
+_ws_cache = {}
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    """A device byte buffer of at least nbytes, reused across calls on a stream."""
+    key = (torch.device(device).index, torch.cuda.current_stream(device).cuda_stream)
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return buf
+
+
+def render(soa: torch.Tensor, H: int, W: int, optics, globals4: torch.Tensor, want_opd: bool = False,
+           out: Optional[torch.Tensor] = None, opd_out: Optional[torch.Tensor] = None,
+           workspace: Optional[torch.Tensor] = None, pairs_per_particle: int = 0):
+    """Render one frame.  Returns intensity [H, W] (and the OPD canvas if want_opd)."""
+    device = soa.device
+    n, ld = _check_soa(soa)
+    _check_globals(globals4, device)
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.float32, device=device)
+    if want_opd and opd_out is None:
+        opd_out = torch.empty((H, W), dtype=torch.float32, device=device)
+    nb = workspace_size(H, W, n, False, pairs_per_particle, device)
+    ws = workspace if workspace is not None else _workspace(nb, device)
+    o = _lib.make_optics(optics)
+    lib = _lib.load()
+    _lib.check(lib.osog_render(context(device), _stream(device), H, W, _ptr(soa) if n else None, n, ld,
+                               ctypes.byref(o), _ptr(globals4), _ptr(opd_out), _ptr(out), _ptr(ws),
+                               ws.numel()), "osog_render")
+    return (out, opd_out) if want_opd else out
+
+
+def render_backward(soa: torch.Tensor, H: int, W: int, optics, globals4: torch.Tensor,
+                    grad_intensity: torch.Tensor, grad_opd: Optional[torch.Tensor] = None,
+                    need_soa: bool = True, need_globals: bool = True,
+                    workspace: Optional[torch.Tensor] = None):
+    """Adjoint of the noiseless render: (grad_soa [8, n] or None, grad_globals [4] or None)."""
+    device = soa.device
+    n, ld = _check_soa(soa)
+    _check_globals(globals4, device)
+    gi = grad_intensity.contiguous()
+    go = grad_opd.contiguous() if grad_opd is not None else None
+    gs = torch.empty((8, ld), dtype=torch.float32, device=device) if (need_soa and n) else None
+    gg = torch.empty(4, dtype=torch.float32, device=device) if need_globals else None
+    nb = workspace_size(H, W, n, True, 0, device)
+    ws = workspace if workspace is not None else _workspace(nb, device)
+    o = _lib.make_optics(optics)
+    _lib.check(_lib.load().osog_render_backward(context(device), _stream(device), H, W,
+                                                 _ptr(soa) if n else None, n, ld, ctypes.byref(o),
+                                                 _ptr(globals4), _ptr(gi), _ptr(go), _ptr(gs), _ptr(gg),
+                                                 _ptr(ws), ws.numel()), "osog_render_backward")
+    if gs is not None and ld != n:
+        gs = gs[:, :n]
+    return gs, gg
+
+
+class RenderFn(torch.autograd.Function):
+    """I = render(soa, globals) with the library's hand-written adjoint as backward.
+
+    Only (soa, globals) are saved; the backward recomputes the forward
+    intermediates inside the library.  Shot noise is treated as a constant.
+    """
+
+    @staticmethod
+    def forward(ctx, soa, globals4, H, W, optics):
+        I = render(soa.detach(), H, W, optics, globals4.detach())
+        ctx.save_for_backward(soa, globals4)
+        ctx.H, ctx.W, ctx.optics = H, W, optics
+        return I
+
+    @staticmethod
+    def backward(ctx, grad_I):
+        soa, globals4 = ctx.saved_tensors
+        gs, gg = render_backward(soa.detach(), ctx.H, ctx.W, ctx.optics, globals4.detach(),
+                                 grad_I, None, ctx.needs_input_grad[0], ctx.needs_input_grad[1])
+        return gs, gg, None, None, None
+
+
+def render_diff(soa: torch.Tensor, globals4: torch.Tensor, H: int, W: int, optics) -> torch.Tensor:
+    """Differentiable render (autograd through the HIP adjoint)."""
+    return RenderFn.apply(soa, globals4, H, W, optics)
+
+
+def bin_pairs(soa: torch.Tensor, H: int, W: int, capacity: Optional[int] = None):
+    """Binning steps only: (keys, pids, tile_start, counts, pair_count) as CUDA int32 tensors."""
+    device = soa.device
+    n, ld = _check_soa(soa)
+    th, tw = get_tiling(device)
+    n_tiles = (H // th) * (W // tw)
+    if capacity is None:
+        capacity = 32 * max(n, 1) + n_tiles
+    keys = torch.empty(max(capacity, 1), dtype=torch.int32, device=device)
+    pids = torch.empty_like(keys)
+    ts = torch.empty(n_tiles + 1, dtype=torch.int32, device=device)
+    counts = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+    pc = torch.empty(1, dtype=torch.int32, device=device)
+    nb = workspace_size(H, W, n, False, max(1, (capacity + max(n, 1) - 1) // max(n, 1)), device)
+    ws = _workspace(nb, device)
+    _lib.check(_lib.load().osog_bin(context(device), _stream(device), H, W, _ptr(soa) if n else None, n, ld,
+                                     _ptr(keys), _ptr(pids), capacity, _ptr(pc), _ptr(ts), _ptr(counts),
+                                     _ptr(ws), ws.numel()), "osog_bin")
+    P = int(pc.item())
+    return keys[:P], pids[:P], ts, counts[:n], P
+
+
+def band_columns(H: int, W: int, optics, device=None) -> int:
+    """Number of in-band spectrum columns the chain carries for these optics."""
+    lo, nn = ctypes.c_int32(), ctypes.c_int32()
+    o = _lib.make_optics(optics)
+    _lib.check(_lib.load().osog_band_info(context(device), H, W, ctypes.byref(o), ctypes.byref(lo),
+                                           ctypes.byref(nn)), "osog_band_info")
+    return nn.value
+
+
+def philox(ctr: torch.Tensor, key0: int, key1: int) -> torch.Tensor:
+    """Philox4x32-10 of a CUDA int32/uint32 counter tensor [m, 4] (device)."""
+    c = ctr.contiguous()
+    out = torch.empty_like(c)
+    _lib.check(_lib.load().osog_philox4x32_10(_stream(c.device), _ptr(c), c.shape[0], key0 & 0xFFFFFFFF,
+                                               key1 & 0xFFFFFFFF, _ptr(out)), "osog_philox4x32_10")
+    return out
