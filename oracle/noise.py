@@ -13,8 +13,10 @@ GPU implementation and this one draw the same stream:
 Poisson variates: mean < 10 by inversion with sequential search on one uniform
 (at most 40 steps); mean >= 10 by Hoermann's transformed rejection with squeeze
 "PTRS" (Insurance: Math. and Econ. 12, 1993), two uniforms per attempt, two
-attempts per Philox call, at most 16 calls.  The decisions are taken in FP32,
-the precision of the GPU sampler.
+attempts per Philox call, at most 16 calls.  Its acceptance test compares
+log(V inv_alpha / (a/us^2 + b)) with -mu + k log(mu) - log(k!), where log(k!)
+is tabulated below k = 10 and taken from Stirling's series above.  The
+decisions are taken in FP32, the precision of the GPU sampler.
 """
 from __future__ import annotations
 
@@ -72,6 +74,18 @@ def _f(x) -> np.float32:
     return np.float32(x)
 
 
+def log_factorial_f32(k: float) -> np.float32:
+    """log(k!) in FP32: correctly rounded table below 10, Stirling's series
+    (x - 1/2) ln x - x + ln(2 pi)/2 + 1/(12 x) - 1/(360 x^3), x = k + 1, above."""
+    if k < 10:
+        return _f(math.lgamma(int(k) + 1.0))
+    x = _f(_f(k) + _f(1.0))
+    t = _f(_f(_f(x - _f(0.5)) * _f(np.log(x))) - x)
+    t = _f(t + _f(0.918938533))
+    t = _f(t + _f(_f(1.0) / _f(_f(12.0) * x)))
+    return _f(t - _f(_f(1.0) / _f(_f(_f(_f(360.0) * x) * x) * x)))
+
+
 def poisson_one(mu: float, pixel: int, frame: int, seed: int) -> int:
     """One Poisson(mu) variate for one pixel (FP32 decisions, as on the GPU)."""
     mu = _f(mu)
@@ -107,8 +121,8 @@ def poisson_one(mu: float, pixel: int, frame: int, seed: int) -> int:
                 return int(kf)
             if kf < 0 or (us < _f(0.013) and V > us):
                 continue
-            lhs = _f(_f(np.log(V)) + _f(np.log(inv_alpha)) - _f(np.log(_f(_f(a / _f(us * us)) + b))))
-            rhs = _f(_f(-mu + _f(kf * log_mu)) - _f(math.lgamma(float(kf) + 1.0)))
+            lhs = _f(np.log(_f(_f(V * inv_alpha) / _f(_f(a / _f(us * us)) + b))))
+            rhs = _f(_f(-mu + _f(kf * log_mu)) - log_factorial_f32(float(kf)))
             if lhs <= rhs:
                 return int(kf)
     return k

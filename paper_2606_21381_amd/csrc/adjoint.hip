@@ -1,0 +1,394 @@
+// Adjoint of the renderer (the end-to-end gradient the paper keeps, Sec. III.C
+// after Eq. 7), as hand-written kernels.  For a real loss L and the complex
+// gradient convention g_z = dL/dRe z + i dL/dIm z, a complex-linear map y = M x
+// has g_x = M^H g_y.  The forward chain and its adjoint, pass by pass:
+//
+//   pass 3   E = IDFT_x(B) / (HW), I = |E|^2      g_E = 2 g_I E;  g_B = DFT_x(g_E)/(HW) on the band
+//   pass 2   U~ = DFT_y(A), G = U~ H, B = IDFT_y(G) g_G = DFT_y(g_B);  g_U~ = conj(H) g_G;
+//                                                   dL/dpsi = Re sum conj(g_G) U~ dH/dpsi;
+//                                                   g_A = IDFT_y(g_U~)
+//   pass 1   A = band of DFT_x(U), U = e^{i phi}   g_U = IDFT_x(g_A zero-filled);
+//                                                   g_OPD = (2 pi/lambda) Im(conj(U) g_U)
+//   raster   OPD = sum_p dn_p t_p                  dL/dtheta_p = sum over p's pixels of g_OPD dOPD/dtheta_p
+//
+// (IDFT here is unnormalised.)  Forward intermediates are recomputed by the
+// caller before these kernels run; nothing of frame size is kept between calls.
+// The raster adjoint gathers, for each particle, g_OPD over the tiles its pixel
+// box covers -- the transpose of the tile scatter-add -- and reduces in a fixed
+// order, so gradients are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include "fft_common.h"
+#include "geometry.h"
+#include "osog_internal.h"
+
+namespace osog {
+
+// ---- forward pass 2 writing B out of place (A stays in band for the adjoint) --
+template <int LOGH>
+__global__ void __launch_bounds__(kThreads) k_pass2_keep(const float2* __restrict__ band,
+                                                         float2* __restrict__ band2, OpticsArgs o,
+                                                         const float* __restrict__ globals,
+                                                         const float2* __restrict__ tw) {
+  constexpr int H = 1 << LOGH;
+  __shared__ float2 buf[H];
+  __shared__ int chord[2];
+  const int t = threadIdx.x, b = blockIdx.x, kx = o.kx_lo + b, RB = o.rb;
+  for (int i = t; i < H; i += kThreads) buf[i] = band[((size_t)(i / RB) * o.kx_n + b) * RB + (i % RB)];
+  if (t == 0) band_chord(o, kx, &chord[0], &chord[1]);
+  __syncthreads();
+  Stages<H, 1, -1, 1, LOGH>::run(buf, tw);
+  const float dz = globals[0], shear = globals[1], bias = globals[2];
+  const int lo = chord[0], hi = chord[1];
+  for (int m = t; m < H; m += kThreads) {
+    const int ky = m < H / 2 ? m : m - H;
+    buf[m] = (ky >= lo && ky <= hi) ? cmul(buf[m], transfer(o, kx, ky, dz, shear, bias))
+                                    : make_float2(0.0f, 0.0f);
+  }
+  __syncthreads();
+  Stages<H, 1, 1, 1, LOGH>::run(buf, tw);
+  for (int i = t; i < H; i += kThreads) band2[((size_t)(i / RB) * o.kx_n + b) * RB + (i % RB)] = buf[i];
+}
+
+// ---- adjoint of pass 3 (rows): g_B = DFT_x(2 g_I E) / (HW) on the band --------
+template <int LOGW>
+__global__ void __launch_bounds__(kThreads) k_adj_pass3(float2* __restrict__ band2, OpticsArgs o,
+                                                        const float* __restrict__ grad_i,
+                                                        const float2* __restrict__ tw) {
+  constexpr int W = 1 << LOGW, RB = rows_per_block(W);
+  __shared__ float2 buf[RB * W];
+  const int t = threadIdx.x, rb = blockIdx.x;
+  for (int idx = t; idx < RB * W; idx += kThreads) buf[idx] = make_float2(0.0f, 0.0f);
+  __syncthreads();
+  float2* blk = band2 + (size_t)rb * o.kx_n * RB;
+  for (int idx = t; idx < o.kx_n * RB; idx += kThreads) {
+    const int b = idx / RB, r = idx - b * RB;
+    buf[r * W + ((o.kx_lo + b) & (W - 1))] = blk[idx];
+  }
+  __syncthreads();
+  Stages<W, RB, 1, 1, LOGW>::run(buf, tw);
+  const float inv = o.inv_hw;
+  const float* gi = grad_i + (size_t)rb * RB * W;
+  for (int idx = t; idx < RB * W; idx += kThreads) {
+    const float2 e = buf[idx];
+    const float g2 = 2.0f * gi[idx] * inv;
+    buf[idx] = make_float2(g2 * e.x * inv, g2 * e.y * inv);  // g_E / (HW), E = B~/(HW)
+  }
+  __syncthreads();
+  Stages<W, RB, -1, 1, LOGW>::run(buf, tw);
+  for (int idx = t; idx < o.kx_n * RB; idx += kThreads) {
+    const int b = idx / RB, r = idx - b * RB;
+    blk[idx] = buf[r * W + ((o.kx_lo + b) & (W - 1))];
+  }
+}
+
+// ---- adjoint of pass 2 (columns) ---------------------------------------------
+template <int LOGH>
+__global__ void __launch_bounds__(kThreads) k_adj_pass2(const float2* __restrict__ band,
+                                                        float2* __restrict__ band2, OpticsArgs o,
+                                                        const float* __restrict__ globals,
+                                                        const float2* __restrict__ tw,
+                                                        double* __restrict__ colgrad) {
+  constexpr int H = 1 << LOGH;
+  __shared__ float2 ua[H];
+  __shared__ float2 gb[H];
+  __shared__ int chord[2];
+  __shared__ double red[3][kThreads];
+  const int t = threadIdx.x, b = blockIdx.x, kx = o.kx_lo + b, RB = o.rb;
+  for (int i = t; i < H; i += kThreads) {
+    const size_t at = ((size_t)(i / RB) * o.kx_n + b) * RB + (i % RB);
+    ua[i] = band[at];
+    gb[i] = band2[at];
+  }
+  if (t == 0) band_chord(o, kx, &chord[0], &chord[1]);
+  __syncthreads();
+  Stages<H, 1, -1, 1, LOGH>::run(ua, tw);  // U~
+  Stages<H, 1, -1, 1, LOGH>::run(gb, tw);  // g_G
+  const float dz = globals[0], shear = globals[1], bias = globals[2];
+  const int lo = chord[0], hi = chord[1];
+  double p0 = 0.0, p1 = 0.0, p2 = 0.0;
+  for (int m = t; m < H; m += kThreads) {
+    const int ky = m < H / 2 ? m : m - H;
+    float2 out = make_float2(0.0f, 0.0f);
+    if (ky >= lo && ky <= hi) {
+      const float2 g = gb[m], u = ua[m];
+      float2 ddz, dsh, dbi;
+      transfer_grads(o, kx, ky, dz, shear, bias, &ddz, &dsh, &dbi);
+      const float2 cgu = cmul(cconj(g), u);  // conj(g_G) U~
+      p0 += (double)cmul(cgu, ddz).x;
+      p1 += (double)cmul(cgu, dsh).x;
+      p2 += (double)cmul(cgu, dbi).x;
+      out = cmul(cconj(transfer(o, kx, ky, dz, shear, bias)), g);
+    }
+    gb[m] = out;
+  }
+  red[0][t] = p0;
+  red[1][t] = p1;
+  red[2][t] = p2;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      red[0][t] += red[0][t + s];
+      red[1][t] += red[1][t + s];
+      red[2][t] += red[2][t + s];
+    }
+    __syncthreads();
+  }
+  if (t < 3) colgrad[(size_t)t * o.kx_n + b] = red[t][0];
+  Stages<H, 1, 1, 1, LOGH>::run(gb, tw);  // g_A
+  for (int i = t; i < H; i += kThreads) band2[((size_t)(i / RB) * o.kx_n + b) * RB + (i % RB)] = gb[i];
+}
+
+// ---- adjoint of pass 1 (rows): g_OPD ------------------------------------------
+template <int LOGW>
+__global__ void __launch_bounds__(kThreads) k_adj_pass1(const float2* __restrict__ band2, OpticsArgs o,
+                                                        const float* __restrict__ opd,
+                                                        const float* __restrict__ grad_opd,
+                                                        float phase_k, const float2* __restrict__ tw,
+                                                        float* __restrict__ gopd) {
+  constexpr int W = 1 << LOGW, RB = rows_per_block(W);
+  __shared__ float2 buf[RB * W];
+  const int t = threadIdx.x, rb = blockIdx.x;
+  for (int idx = t; idx < RB * W; idx += kThreads) buf[idx] = make_float2(0.0f, 0.0f);
+  __syncthreads();
+  const float2* blk = band2 + (size_t)rb * o.kx_n * RB;
+  for (int idx = t; idx < o.kx_n * RB; idx += kThreads) {
+    const int b = idx / RB, r = idx - b * RB;
+    buf[r * W + ((o.kx_lo + b) & (W - 1))] = blk[idx];
+  }
+  __syncthreads();
+  Stages<W, RB, 1, 1, LOGW>::run(buf, tw);  // g_U
+  const size_t off = (size_t)rb * RB * W;
+  for (int idx = t; idx < RB * W; idx += kThreads) {
+    float s, c;
+    sincosf(phase_k * opd[off + idx], &s, &c);
+    const float2 g = buf[idx];
+    // Im(conj(U) g_U) with U = c + i s
+    float go = phase_k * (c * g.y - s * g.x);
+    if (grad_opd) go += grad_opd[off + idx];
+    gopd[off + idx] = go;
+  }
+}
+
+// ---- adjoint of the rasteriser: per-particle gather over its tiles ------------
+// Prism: c = dn h cov; d cov / d theta is the boundary flux of the footprint's
+// velocity field through the part of its outline inside the pixel (each edge
+// clipped to the pixel square by Liang-Barsky).  Ellipsoid: c = dn h sqrt(1-q)
+// at the pixel centre, differentiated directly.
+struct EdgeClip {
+  float len, mid;  // clipped length and midpoint parameter along the edge (0..1)
+};
+
+__device__ __forceinline__ EdgeClip clip_edge(float px, float py, float qx, float qy) {
+  // segment P + t (Q - P), t in [0,1], against the unit square [0,1]^2
+  float t0 = 0.0f, t1 = 1.0f;
+  const float dx = qx - px, dy = qy - py;
+  const float pp[4] = {-dx, dx, -dy, dy};
+  const float qq[4] = {px, 1.0f - px, py, 1.0f - py};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (pp[k] == 0.0f) {
+      if (qq[k] < 0.0f) return {0.0f, 0.0f};
+    } else {
+      const float r = qq[k] / pp[k];
+      if (pp[k] < 0.0f) t0 = fmaxf(t0, r);
+      else t1 = fminf(t1, r);
+    }
+  }
+  if (!(t1 > t0)) return {0.0f, 0.0f};
+  return {(t1 - t0) * sqrtf(dx * dx + dy * dy), 0.5f * (t0 + t1)};
+}
+
+__global__ void __launch_bounds__(kThreads) k_adj_raster(const float* __restrict__ soa, int64_t n,
+                                                         int64_t ld, const PRec* __restrict__ recs,
+                                                         const int4* __restrict__ boxes, int W,
+                                                         int tile_h, int tile_w,
+                                                         const float* __restrict__ gopd,
+                                                         float* __restrict__ grad_soa) {
+  __shared__ float red[7][kThreads];
+  const int t = threadIdx.x;
+  const int64_t p = blockIdx.x;
+  const PRec r = recs[p];
+  const int4 box = boxes[p];
+  const float h = soa[5 * ld + p], dn = soa[6 * ld + p];
+  float acc[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (r.f[3] >= 0.0f && box.x <= box.y) {
+    const int tx0 = box.x / tile_w, tx1 = box.y / tile_w, ty0 = box.z / tile_h, ty1 = box.w / tile_h;
+    const int li = t / tile_w, lj = t - li * tile_w;
+    const bool prism = r.f[3] == 0.0f;
+    const float4 bb = prism ? prism_bounds(r) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float c = r.f[4], s = r.f[5], a = r.f[6], b = r.f[7];
+    for (int ty = ty0; ty <= ty1; ++ty)
+      for (int tx = tx0; tx <= tx1; ++tx) {
+        const int i = ty * tile_h + li, j = tx * tile_w + lj;
+        if (j < box.x || j > box.y || i < box.z || i > box.w) continue;
+        const float g = gopd[(int64_t)i * W + j];
+        if (g == 0.0f) continue;
+        if (prism) {
+          const float fj = (float)j, fi = (float)i;
+          if (bb.y <= fj || bb.x >= fj + 1.0f || bb.w <= fi || bb.z >= fi + 1.0f) continue;
+          const int cls = prism_classify(r, fj + 0.5f, fi + 0.5f, 0.0f);
+          if (cls < 0) continue;
+          if (cls > 0) {  // fully covered: only height and dn act
+            acc[5] += g * dn;
+            acc[6] += g * h;
+            continue;
+          }
+          const float cov = prism_cover(r, bb, i, j);
+          acc[5] += g * dn * cov;
+          acc[6] += g * h * cov;
+          // corners relative to the pixel corner, CCW: (-a,-b) (a,-b) (a,b) (-a,b)
+          const float X0 = fj - r.f[0], Y0 = fi - r.f[1];
+          float vx[4], vy[4];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            vx[k] = r.f[8 + 2 * k] - X0;
+            vy[k] = r.f[9 + 2 * k] - Y0;
+          }
+          // outward normals: bottom -e_v, right e_u, top e_v, left -e_u
+          const float nx[4] = {s, c, -s, -c}, ny[4] = {-c, s, c, -s};
+          float fx = 0.f, fy = 0.f, fang = 0.f, fa = 0.f, fb = 0.f;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            const EdgeClip e = clip_edge(vx[k], vy[k], vx[(k + 1) & 3], vy[(k + 1) & 3]);
+            if (e.len == 0.0f) continue;
+            fx += nx[k] * e.len;
+            fy += ny[k] * e.len;
+            // local coordinate along the edge at the clipped midpoint
+            if (k == 0) { fang -= e.len * (-a + 2.0f * a * e.mid); fb += e.len; }
+            else if (k == 1) { fang -= e.len * (-b + 2.0f * b * e.mid); fa += e.len; }
+            else if (k == 2) { fang += e.len * (a - 2.0f * a * e.mid); fb += e.len; }
+            else { fang += e.len * (b - 2.0f * b * e.mid); fa += e.len; }
+          }
+          const float amp = g * r.f[2];
+          acc[0] += amp * fx;
+          acc[1] += amp * fy;
+          acc[2] += amp * fang;
+          acc[3] += amp * fa;
+          acc[4] += amp * fb;
+        } else {
+          const float dx = ((float)j + 0.5f) - r.f[0], dy = ((float)i + 0.5f) - r.f[1];
+          const float u = c * dx + s * dy, v = -s * dx + c * dy;
+          const float ia = r.f[8], ib = r.f[9];
+          const float q = u * u * ia * ia + v * v * ib * ib;
+          if (!(q < 1.0f)) continue;
+          const float sq = sqrtf(1.0f - q);
+          acc[5] += g * dn * sq;
+          acc[6] += g * h * sq;
+          const float dcq = -g * r.f[2] * 0.5f / fmaxf(sq, 1e-20f);  // d c / d q
+          const float qu = 2.0f * u * ia * ia, qv = 2.0f * v * ib * ib;
+          acc[0] += dcq * (qu * -c + qv * s);
+          acc[1] += dcq * (qu * -s + qv * -c);
+          acc[2] += dcq * (qu * v + qv * -u);
+          acc[3] += dcq * (-2.0f * u * u * ia * ia * ia);
+          acc[4] += dcq * (-2.0f * v * v * ib * ib * ib);
+        }
+      }
+  }
+#pragma unroll
+  for (int k = 0; k < 7; ++k) red[k][t] = acc[k];
+  __syncthreads();
+  for (int st = kThreads / 2; st > 0; st >>= 1) {
+    if (t < st) {
+#pragma unroll
+      for (int k = 0; k < 7; ++k) red[k][t] += red[k][t + st];
+    }
+    __syncthreads();
+  }
+  if (t < 8) grad_soa[(int64_t)t * ld + p] = t < 7 ? red[t][0] : 0.0f;
+}
+
+// grad_globals[k] = sum over columns of colgrad[k][col], fixed order; [3] = 0
+__global__ void __launch_bounds__(kThreads) k_adj_global(const double* __restrict__ colgrad, int kx_n,
+                                                         float* __restrict__ grad_globals) {
+  __shared__ double red[3][kThreads];
+  const int t = threadIdx.x;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int b = t; b < kx_n; b += kThreads) {
+    s0 += colgrad[b];
+    s1 += colgrad[kx_n + b];
+    s2 += colgrad[2 * (size_t)kx_n + b];
+  }
+  red[0][t] = s0;
+  red[1][t] = s1;
+  red[2][t] = s2;
+  __syncthreads();
+  for (int st = kThreads / 2; st > 0; st >>= 1) {
+    if (t < st) {
+      red[0][t] += red[0][t + st];
+      red[1][t] += red[1][t + st];
+      red[2][t] += red[2][t + st];
+    }
+    __syncthreads();
+  }
+  if (t < 4) grad_globals[t] = t < 3 ? (float)red[t][0] : 0.0f;
+}
+
+// ------------------------------------------------------------ dispatch -------
+#define OSOG_SIZE_SWITCH(LOG, CALL) \
+  switch (LOG) {                    \
+    case 5: CALL(5); break;         \
+    case 6: CALL(6); break;         \
+    case 7: CALL(7); break;         \
+    case 8: CALL(8); break;         \
+    case 9: CALL(9); break;         \
+    case 10: CALL(10); break;       \
+    case 11: CALL(11); break;       \
+    case 12: CALL(12); break;       \
+    default: return hipErrorInvalidValue; \
+  }
+
+hipError_t launch_pass2_keep(const FramePlan& p, const float* globals, FrameBufs& b, const float2* tw,
+                             hipStream_t s) {
+  OpticsArgs o = optics_args(p);
+#define K(LG) hipLaunchKernelGGL(k_pass2_keep<LG>, dim3(p.kx_n), dim3(kThreads), 0, s, b.band, b.band2, o, \
+                                 globals, tw)
+  OSOG_SIZE_SWITCH(p.logH, K)
+#undef K
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_pass3(const FramePlan& p, FrameBufs& b, const float2* tw, const float* grad_i,
+                            hipStream_t s) {
+  OpticsArgs o = optics_args(p);
+#define K(LG) hipLaunchKernelGGL(k_adj_pass3<LG>, dim3(p.H / p.rb), dim3(kThreads), 0, s, b.band2, o, \
+                                 grad_i, tw)
+  OSOG_SIZE_SWITCH(p.logW, K)
+#undef K
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_pass2(const FramePlan& p, const float* globals, FrameBufs& b, const float2* tw,
+                            hipStream_t s) {
+  OpticsArgs o = optics_args(p);
+#define K(LG) hipLaunchKernelGGL(k_adj_pass2<LG>, dim3(p.kx_n), dim3(kThreads), 0, s, b.band, b.band2, o, \
+                                 globals, tw, b.colgrad)
+  OSOG_SIZE_SWITCH(p.logH, K)
+#undef K
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_pass1(const FramePlan& p, const float* opd, const float* grad_opd, FrameBufs& b,
+                            const float2* tw, hipStream_t s) {
+  OpticsArgs o = optics_args(p);
+#define K(LG) hipLaunchKernelGGL(k_adj_pass1<LG>, dim3(p.H / p.rb), dim3(kThreads), 0, s, b.band2, o, opd, \
+                                 grad_opd, p.phase_k, tw, b.gopd)
+  OSOG_SIZE_SWITCH(p.logW, K)
+#undef K
+  return hipGetLastError();
+}
+
+hipError_t launch_raster_adjoint(const FramePlan& p, const float* soa, FrameBufs& b, float* grad_soa,
+                                 hipStream_t s) {
+  if (p.n > 0)
+    hipLaunchKernelGGL(k_adj_raster, dim3((unsigned)p.n), dim3(kThreads), 0, s, soa, p.n, p.ld, b.recs,
+                       b.boxes, p.W, p.tile_h, p.tile_w, b.gopd, grad_soa);
+  return hipGetLastError();
+}
+
+hipError_t launch_global_grads(const FramePlan& p, FrameBufs& b, float* grad_globals, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_global, dim3(1), dim3(kThreads), 0, s, b.colgrad, p.kx_n, grad_globals);
+  return hipGetLastError();
+}
+
+}  // namespace osog

@@ -75,14 +75,19 @@ static FrameBufs carve_impl(Carver& c, int H, int W, int64_t n, int tile_h, int 
   b.recs = c.take<PRec>(n > 0 ? n : 1);
   b.boxes = c.take<int4>(n > 0 ? n : 1);
   b.counts = c.take<int>(n > 0 ? n : 1);
+  const int64_t nblk = (n + kThreads - 1) / kThreads;
+  b.blocksum = c.take<long long>(nblk > 0 ? nblk : 1);
   b.emit_start = c.take<long long>(n + 1);
   b.scal = c.take<int>(64);
   b.keys_a = c.take<int>(cap);
   b.vals_a = c.take<int>(cap);
   b.keys_b = c.take<int>(cap);
   b.vals_b = c.take<int>(cap);
-  b.hist = c.take<int>((1 << kRadixBits) * kRadixBlocks);
-  b.tile_start = c.take<int>(n_tiles + 1);
+  b.hist1 = c.take<int>(256 * (size_t)(nblk > 0 ? nblk : 1));
+  b.hist2 = c.take<int>(256 * 256);
+  b.dtot = c.take<int>(512);
+  b.tile_first = c.take<int>(n_tiles);
+  b.tile_count = c.take<int>(n_tiles);
   b.opd = c.take<float>(hw);
   b.band = c.take<float2>(hw);
   b.colsum = c.take<double>(W);
@@ -331,6 +336,64 @@ osog_status osog_render(osog_context* ctx, void* stream, int32_t height, int32_t
   return OSOG_OK;
 }
 
+osog_status osog_render_backward(osog_context* ctx, void* stream, int32_t height, int32_t width,
+                                 const float* soa, int64_t n, int64_t ld, const osog_optics* optics,
+                                 const float* globals, const float* grad_intensity,
+                                 const float* grad_opd, float* grad_soa, float* grad_globals,
+                                 void* workspace, size_t workspace_bytes) {
+  osog_status st = check_frame(ctx, height, width, soa, n, ld, optics, globals);
+  if (st != OSOG_OK) return st;
+  if (!grad_intensity) return fail(OSOG_ERR_INVALID_ARGUMENT, "grad_intensity is NULL");
+  if (!workspace) return fail(OSOG_ERR_WORKSPACE, "workspace is NULL");
+  int ppp = 0;
+  for (int cand = 1 << 20; cand >= 1; cand >>= 1)
+    if (frame_workspace_bytes(height, width, n, ctx->tile_h, ctx->tile_w, cand, true) <= workspace_bytes) {
+      ppp = cand;
+      break;
+    }
+  if (ppp == 0) return fail(OSOG_ERR_WORKSPACE, "workspace smaller than osog_workspace_size(with_backward=1)");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  int64_t cap = 0;
+  FrameBufs b = carve(workspace, height, width, n, ctx->tile_h, ctx->tile_w, ppp, true, &cap);
+  FramePlan p = make_plan(ctx, height, width, n, ld, *optics, cap);
+  hipStream_t s = (hipStream_t)stream;
+  Profiler* pr = ctx->prof;
+  const float2* tw = ctx->twiddle;
+  // recompute the forward intermediates: OPD, row spectra A (band), B = IDFT_y(U~ H) (band2)
+  profile_begin(pr, OSOG_STAGE_BINNING, s);
+  if ((e = launch_binning(p, soa, b, s)) != hipSuccess) return hip_fail(e, "backward: binning");
+  profile_end(pr, OSOG_STAGE_BINNING, s);
+  profile_begin(pr, OSOG_STAGE_RASTER, s);
+  if ((e = launch_raster(p, b, b.opd, s)) != hipSuccess) return hip_fail(e, "backward: raster");
+  profile_end(pr, OSOG_STAGE_RASTER, s);
+  profile_begin(pr, OSOG_STAGE_PASS1, s);
+  if ((e = launch_pass1(p, b.opd, b, tw, s)) != hipSuccess) return hip_fail(e, "backward: pass 1");
+  profile_end(pr, OSOG_STAGE_PASS1, s);
+  if (p.kx_n > 0) {
+    profile_begin(pr, OSOG_STAGE_PASS2, s);
+    if ((e = launch_pass2_keep(p, globals, b, tw, s)) != hipSuccess) return hip_fail(e, "backward: pass 2");
+    profile_end(pr, OSOG_STAGE_PASS2, s);
+    profile_begin(pr, OSOG_STAGE_ADJ_PASS3, s);
+    if ((e = launch_adj_pass3(p, b, tw, grad_intensity, s)) != hipSuccess) return hip_fail(e, "backward: adj pass 3");
+    profile_end(pr, OSOG_STAGE_ADJ_PASS3, s);
+    profile_begin(pr, OSOG_STAGE_ADJ_PASS2, s);
+    if ((e = launch_adj_pass2(p, globals, b, tw, s)) != hipSuccess) return hip_fail(e, "backward: adj pass 2");
+    profile_end(pr, OSOG_STAGE_ADJ_PASS2, s);
+  }
+  profile_begin(pr, OSOG_STAGE_ADJ_PASS1, s);
+  if ((e = launch_adj_pass1(p, b.opd, grad_opd, b, tw, s)) != hipSuccess) return hip_fail(e, "backward: adj pass 1");
+  profile_end(pr, OSOG_STAGE_ADJ_PASS1, s);
+  if (grad_soa) {
+    profile_begin(pr, OSOG_STAGE_ADJ_RASTER, s);
+    if ((e = launch_raster_adjoint(p, soa, b, grad_soa, s)) != hipSuccess) return hip_fail(e, "backward: raster adjoint");
+    profile_end(pr, OSOG_STAGE_ADJ_RASTER, s);
+  }
+  if (grad_globals && (e = launch_global_grads(p, b, grad_globals, s)) != hipSuccess)
+    return hip_fail(e, "backward: global gradients");
+  return OSOG_OK;
+}
+
 osog_status osog_bin(osog_context* ctx, void* stream, int32_t height, int32_t width,
                      const float* soa, int64_t n, int64_t ld, int32_t* keys_out, int32_t* pids_out,
                      int64_t capacity, int32_t* pair_count_out, int32_t* tile_start_out,
@@ -366,13 +429,12 @@ osog_status osog_bin(osog_context* ctx, void* stream, int32_t height, int32_t wi
   if ((e = hipMemcpyAsync(pair_count_out, b.emit_start + n, sizeof(int32_t), hipMemcpyDeviceToDevice, s)) != hipSuccess)
     return hip_fail(e, "copy pair count");
   if (cap > 0) {
-    if ((e = hipMemcpyAsync(keys_out, b.keys_a, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+    if ((e = hipMemcpyAsync(keys_out, b.sorted_keys, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s)) != hipSuccess)
       return hip_fail(e, "copy keys");
-    if ((e = hipMemcpyAsync(pids_out, b.vals_a, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+    if ((e = hipMemcpyAsync(pids_out, b.sorted_vals, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s)) != hipSuccess)
       return hip_fail(e, "copy pids");
   }
-  if ((e = hipMemcpyAsync(tile_start_out, b.tile_start, sizeof(int32_t) * (p.n_tiles + 1), hipMemcpyDeviceToDevice, s)) != hipSuccess)
-    return hip_fail(e, "copy tile_start");
+  if ((e = launch_tile_start(p, b, tile_start_out, s)) != hipSuccess) return hip_fail(e, "tile offsets");
   if (counts_out && n > 0 &&
       (e = hipMemcpyAsync(counts_out, b.counts, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s)) != hipSuccess)
     return hip_fail(e, "copy counts");

@@ -1,0 +1,65 @@
+// Per-particle pixel box and raster record, shared by the forward binning and
+// the adjoint (which re-derives each particle's tile range from the same box).
+#pragma once
+
+#include "osog_internal.h"
+
+namespace osog {
+
+// Conservative pixel box of a particle.  Only exactly rounded FP32 operations
+// with no contraction, so every correct implementation reproduces it bit for bit:
+//   ext = max(a,b) * 1.41421366f + 1 (prism; 1.41421366f is the float just above
+//   sqrt 2, so ext covers the footprint's circumradius plus a pixel) or max(a,b) + 1
+//   (ellipsoid); box = [floor(c - ext), floor(c + ext)] clamped to the canvas.
+// Returns false (no pairs) for a non-positive or NaN half-width, a NaN bound or
+// a box that misses the canvas.
+__device__ __forceinline__ bool pixel_box(float cx, float cy, float a, float b, float shape, int H,
+                                          int W, int4* box) {
+#pragma clang fp contract(off)
+  if (!(a > 0.0f) || !(b > 0.0f)) return false;
+  float m = fmaxf(a, b);
+  float ext = (shape < 0.5f) ? (m * 1.41421366f + 1.0f) : (m + 1.0f);
+  float fx0 = floorf(cx - ext), fx1 = floorf(cx + ext);
+  float fy0 = floorf(cy - ext), fy1 = floorf(cy + ext);
+  if (!(fx0 <= fx1) || !(fy0 <= fy1)) return false;
+  if (!(fx1 >= 0.0f) || !(fy1 >= 0.0f)) return false;
+  if (!(fx0 <= (float)(W - 1)) || !(fy0 <= (float)(H - 1))) return false;
+  box->x = (int)fmaxf(fx0, 0.0f);
+  box->y = (int)fminf(fx1, (float)(W - 1));
+  box->z = (int)fmaxf(fy0, 0.0f);
+  box->w = (int)fminf(fy1, (float)(H - 1));
+  return true;
+}
+
+// Raster record of a valid particle (layout documented with PRec).
+__device__ __forceinline__ void make_record(float cx, float cy, float ang, float a, float b, float h,
+                                            float dn, float shape, PRec* out) {
+  PRec& r = *out;
+  double cd, sd;
+  sincos((double)ang, &sd, &cd);
+  const float c = (float)cd, s = (float)sd;
+  r.f[0] = cx; r.f[1] = cy; r.f[2] = dn * h;
+  r.f[4] = c; r.f[5] = s; r.f[6] = a; r.f[7] = b;
+  if (shape < 0.5f) {
+    r.f[3] = 0.0f;
+    const float su[4] = {-1.f, 1.f, 1.f, -1.f}, sv[4] = {-1.f, -1.f, 1.f, 1.f};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float u = su[k] * a, v = sv[k] * b;
+      r.f[8 + 2 * k] = c * u - s * v;
+      r.f[9 + 2 * k] = s * u + c * v;
+    }
+  } else {
+    r.f[3] = 1.0f;
+    r.f[8] = 1.0f / a;
+    r.f[9] = 1.0f / b;
+    r.f[10] = __int_as_float(__double2loint(cd));
+    r.f[11] = __int_as_float(__double2hiint(cd));
+    r.f[12] = __int_as_float(__double2loint(sd));
+    r.f[13] = __int_as_float(__double2hiint(sd));
+    r.f[14] = dn;
+    r.f[15] = h;
+  }
+}
+
+}  // namespace osog

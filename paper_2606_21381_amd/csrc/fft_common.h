@@ -221,9 +221,22 @@ __device__ inline void band_chord(const OpticsArgs& o, int kx, int* lo_out, int*
 // Philox4x32-10 stream per pixel: counter (pixel, frame, round, 0), key = seed.
 // mean < 10: inversion by sequential search on one uniform (at most 40 steps);
 // mean >= 10: transformed rejection with squeeze (Hoermann 1993, "PTRS"), two
-// uniforms per attempt, two attempts per Philox call, at most 16 calls.  Every
-// operation is a separately rounded FP32 operation.
-__device__ inline int poisson(float mu, uint32_t pixel, uint32_t frame, uint32_t k0, uint32_t k1) {
+// uniforms per attempt, two attempts per Philox call, at most 16 calls.  The
+// acceptance test compares log(V inv_alpha / (a/us^2 + b)) with
+// -mu + k log(mu) - log(k!), log(k!) from a table for k < 10 and from Stirling's
+// series (x - 1/2) ln x - x + ln(2 pi)/2 + 1/(12x) - 1/(360 x^3), x = k + 1, above.
+// Every operation is a separately rounded FP32 operation.
+__device__ __forceinline__ float log_factorial(float k) {
+#pragma clang fp contract(off)
+  const float table[10] = {0.000000000e+00f, 0.000000000e+00f, 6.931471825e-01f, 1.791759491e+00f,
+                           3.178053856e+00f, 4.787491798e+00f, 6.579251289e+00f, 8.525161743e+00f,
+                           1.060460281e+01f, 1.280182743e+01f};
+  if (k < 10.0f) return table[(int)k];
+  const float x = k + 1.0f;
+  return (x - 0.5f) * logf(x) - x + 0.918938533f + 1.0f / (12.0f * x) - 1.0f / (360.0f * x * x * x);
+}
+
+__device__ __forceinline__ int poisson(float mu, uint32_t pixel, uint32_t frame, uint32_t k0, uint32_t k1) {
 #pragma clang fp contract(off)
   if (!(mu > 0.0f)) return 0;
   if (mu < 10.0f) {
@@ -255,8 +268,8 @@ __device__ inline int poisson(float mu, uint32_t pixel, uint32_t frame, uint32_t
       const float kf = floorf((((2.0f * a) / us) + b) * U + (mu + 0.43f));
       if (us >= 0.07f && V <= vr) return (int)kf;
       if (kf < 0.0f || (us < 0.013f && V > us)) continue;
-      const float lhs = (logf(V) + logf(inv_alpha)) - logf(a / (us * us) + b);
-      const float rhs = (-mu + kf * log_mu) - lgammaf(kf + 1.0f);
+      const float lhs = logf(V * inv_alpha / (a / (us * us) + b));
+      const float rhs = (-mu + kf * log_mu) - log_factorial(kf);
       if (lhs <= rhs) return (int)kf;
     }
   }

@@ -35,19 +35,43 @@ __device__ __forceinline__ float edge_area(float px, float py, float qx, float q
   return (qx > px) ? -w : w;
 }
 
-// Exact area of pixel (i, j) covered by the prism footprint of record r.
+// Axis-aligned bounds of a prism footprint in canvas pixels (xmin, xmax, ymin, ymax),
+// rounded the same way wherever they are used.
+__device__ __forceinline__ float4 prism_bounds(const PRec& r) {
+  const float xlo = fminf(fminf(r.f[8], r.f[10]), fminf(r.f[12], r.f[14]));
+  const float xhi = fmaxf(fmaxf(r.f[8], r.f[10]), fmaxf(r.f[12], r.f[14]));
+  const float ylo = fminf(fminf(r.f[9], r.f[11]), fminf(r.f[13], r.f[15]));
+  const float yhi = fmaxf(fmaxf(r.f[9], r.f[11]), fmaxf(r.f[13], r.f[15]));
+  return make_float4(r.f[0] + xlo, r.f[0] + xhi, r.f[1] + ylo, r.f[1] + yhi);
+}
+
+// Centre-sample test of a pixel against the prism slabs: +1 when the whole pixel
+// is inside (coverage exactly 1), -1 when it is certainly outside, 0 otherwise.
+// The pixel lies in the disc of radius sqrt(2)/2 about its centre.
+__device__ __forceinline__ int prism_classify(const PRec& r, float px, float py, float margin) {
+  const float c = r.f[4], s = r.f[5], a = r.f[6], b = r.f[7];
+  const float dx = px - r.f[0], dy = py - r.f[1];
+  const float u = c * dx + s * dy, v = -s * dx + c * dy;
+  const float hd = 0.70712f;
+  if (fabsf(u) > a + hd || fabsf(v) > b + hd) return -1;
+  if (fabsf(u) < a - hd - margin && fabsf(v) < b - hd - margin) return 1;
+  return 0;
+}
+
+// Exact area of pixel (i, j) covered by the prism footprint of record r (bounds
+// bb from prism_bounds).  Exactly 0 for a pixel outside the bounds and exactly 1
+// for a pixel whose disc is inside both slabs; otherwise the clipped area.
 // Pixel-corner offsets j - cx and i - cy are exact in FP32 for on-canvas
 // particles, so the clip runs in small local coordinates.
-__device__ __forceinline__ float prism_cover(const PRec& r, int i, int j) {
-  float cx = r.f[0], cy = r.f[1], c = r.f[4], s = r.f[5], a = r.f[6], b = r.f[7];
-  float dx = ((float)j + 0.5f) - cx, dy = ((float)i + 0.5f) - cy;
-  float u = c * dx + s * dy, v = -s * dx + c * dy;
-  const float hd = 0.70712f;  // > sqrt(2)/2: the pixel lies in this disc around its centre
-  if (fabsf(u) > a + hd || fabsf(v) > b + hd) return 0.0f;
-  if (fabsf(u) < a - hd && fabsf(v) < b - hd) return 1.0f;
-  float X0 = (float)j - cx, Y0 = (float)i - cy;
-  float x0 = r.f[8] - X0, y0 = r.f[9] - Y0, x1 = r.f[10] - X0, y1 = r.f[11] - Y0;
-  float x2 = r.f[12] - X0, y2 = r.f[13] - Y0, x3 = r.f[14] - X0, y3 = r.f[15] - Y0;
+__device__ __forceinline__ float prism_cover(const PRec& r, const float4& bb, int i, int j) {
+  const float fj = (float)j, fi = (float)i;
+  if (bb.y <= fj || bb.x >= fj + 1.0f || bb.w <= fi || bb.z >= fi + 1.0f) return 0.0f;
+  const int cls = prism_classify(r, fj + 0.5f, fi + 0.5f, 0.0f);
+  if (cls < 0) return 0.0f;
+  if (cls > 0) return 1.0f;
+  const float X0 = fj - r.f[0], Y0 = fi - r.f[1];
+  const float x0 = r.f[8] - X0, y0 = r.f[9] - Y0, x1 = r.f[10] - X0, y1 = r.f[11] - Y0;
+  const float x2 = r.f[12] - X0, y2 = r.f[13] - Y0, x3 = r.f[14] - X0, y3 = r.f[15] - Y0;
   float area = edge_area(x0, y0, x1, y1);
   area += edge_area(x1, y1, x2, y2);
   area += edge_area(x2, y2, x3, y3);
@@ -75,11 +99,12 @@ __device__ __forceinline__ float ellipsoid_opd(const PRec& r, int i, int j) {
   return r.f[2] * sqrtf(1.0f - q);
 }
 
-__device__ __forceinline__ float particle_opd(const PRec& r, int i, int j) {
-  float k = r.f[3];
-  if (k == 0.0f) return r.f[2] * prism_cover(r, i, j);
-  if (k == 1.0f) return ellipsoid_opd(r, i, j);
-  return 0.0f;
+// Half extents of an ellipse's axis-aligned bounding box, enlarged so that every
+// pixel centre outside them has q >= 1.002 after FP32 rounding.
+__device__ __forceinline__ float2 ellipse_extent(const PRec& r) {
+  const float c = r.f[4], s = r.f[5], a = r.f[6], b = r.f[7];
+  const float ex = sqrtf(a * a * c * c + b * b * s * s), ey = sqrtf(a * a * s * s + b * b * c * c);
+  return make_float2(ex * 1.0011f + 1e-3f, ey * 1.0011f + 1e-3f);
 }
 
 }  // namespace osog

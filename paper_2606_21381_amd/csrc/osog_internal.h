@@ -13,8 +13,6 @@ namespace osog {
 
 constexpr int kThreads = 256;     // every kernel runs 256-thread workgroups (4 wave64)
 constexpr int kTwN = 4096;        // twiddle table length (largest FFT)
-constexpr int kRadixBits = 8;     // LSD radix digit width
-constexpr int kRadixBlocks = 256; // workgroups of each radix pass
 constexpr int kDefaultPairsPerParticle = 32;
 
 // Per-particle raster record, 64 bytes, written once by the prepare kernel.
@@ -54,11 +52,17 @@ struct FrameBufs {
   PRec* recs;
   int4* boxes;
   int* counts;
+  long long* blocksum;    // one per 256-particle block
   long long* emit_start;  // n + 1
-  int* scal;              // [0] pair count (clamped), [1] overflow flag
+  int* scal;              // [0] pair count (0 on overflow), [1] overflow flag
   int* keys_a; int* vals_a; int* keys_b; int* vals_b;
-  int* hist;              // 2^kRadixBits * kRadixBlocks
-  int* tile_start;        // n_tiles + 1
+  int* hist1;             // 256 digits x particle blocks
+  int* hist2;             // 256 digits x 256 slices
+  int* dtot;              // 2 x 256 digit totals
+  int* tile_first;        // n_tiles: first sorted pair of the tile (INT_MAX if none)
+  int* tile_count;        // n_tiles: pairs of the tile
+  int* sorted_keys;       // set by launch_binning: where the sorted pairs ended
+  int* sorted_vals;
   float* opd;             // H*W (used when the caller passes no opd_out)
   float2* band;           // H * W complex (blocked layout, kx_n used)
   double* colsum;         // W
@@ -73,6 +77,7 @@ FrameBufs carve(void* ws, int H, int W, int64_t n, int tile_h, int tile_w, int p
 
 // launchers (return hipError_t of the last launch)
 hipError_t launch_binning(const FramePlan& p, const float* soa, FrameBufs& b, hipStream_t s);
+hipError_t launch_tile_start(const FramePlan& p, FrameBufs& b, int* tile_start, hipStream_t s);
 hipError_t launch_raster(const FramePlan& p, FrameBufs& b, float* opd, hipStream_t s);
 hipError_t launch_pass1(const FramePlan& p, const float* opd, FrameBufs& b, const float2* tw, hipStream_t s);
 hipError_t launch_pass2(const FramePlan& p, const float* globals, FrameBufs& b, const float2* tw, hipStream_t s);
@@ -80,6 +85,7 @@ hipError_t launch_pass3(const FramePlan& p, FrameBufs& b, const float2* tw, floa
 hipError_t launch_philox(const uint32_t* ctr, int64_t count, uint32_t k0, uint32_t k1, uint32_t* out, hipStream_t s);
 
 // backward launchers
+hipError_t launch_pass2_keep(const FramePlan& p, const float* globals, FrameBufs& b, const float2* tw, hipStream_t s);
 hipError_t launch_adj_pass3(const FramePlan& p, FrameBufs& b, const float2* tw, const float* grad_i, hipStream_t s);
 hipError_t launch_adj_pass2(const FramePlan& p, const float* globals, FrameBufs& b, const float2* tw, hipStream_t s);
 hipError_t launch_adj_pass1(const FramePlan& p, const float* opd, const float* grad_opd, FrameBufs& b, const float2* tw, hipStream_t s);
@@ -87,6 +93,14 @@ hipError_t launch_raster_adjoint(const FramePlan& p, const float* soa, FrameBufs
 hipError_t launch_global_grads(const FramePlan& p, FrameBufs& b, float* grad_globals, hipStream_t s);
 
 void set_error(const std::string& msg);
+
+struct Profiler;
+// host helpers shared by the entry points (api.cpp)
+FramePlan make_plan(const osog_context* ctx, int H, int W, int64_t n, int64_t ld, const osog_optics& o,
+                    int64_t cap);
+hipError_t forward_frame(const osog_context* ctx, const FramePlan& p, const float* soa,
+                         const float* globals, FrameBufs& b, float* opd_out, float* intensity,
+                         hipStream_t s);
 
 // Stage profiler owned by the context (HIP events around stage launches).
 struct Profiler;

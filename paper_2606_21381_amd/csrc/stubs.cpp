@@ -12,13 +12,6 @@ void batch_cache_destroy(BatchCache* c) { delete c; }
 }  // namespace osog
 
 extern "C" {
-osog_status osog_render_backward(osog_context* ctx, void*, int32_t, int32_t, const float*, int64_t,
-                                 int64_t, const osog_optics*, const float*, const float*,
-                                 const float*, float*, float*, void*, size_t) {
-  if (!ctx) { osog::set_error("context is NULL"); return OSOG_ERR_NOT_INITIALIZED; }
-  osog::set_error("osog_render_backward: not built");
-  return OSOG_ERR_UNSUPPORTED;
-}
 osog_status osog_batch_workspace_size(osog_context*, const osog_frame*, int32_t, int32_t, size_t*) {
   osog::set_error("osog_batch_workspace_size: not built");
   return OSOG_ERR_UNSUPPORTED;

@@ -52,3 +52,11 @@ def test_add_noise_scaling_and_seed():
     assert np.array_equal(a, b) and not np.array_equal(a, c)
     z = (a * 250.0 - 1000.0) / np.sqrt(1000.0)       # s = 1000 / 4
     assert abs(z.mean()) < 4.5 / 20 and abs(z.var() - 1) < 0.35
+
+
+def test_log_factorial_matches_lgamma():
+    import math
+    for k in list(range(0, 40)) + [57, 99, 512, 1000, 1003, 4096, 20000]:
+        ref = math.lgamma(k + 1.0)
+        got = float(noise.log_factorial_f32(float(k)))
+        assert abs(got - ref) <= 2e-7 * max(1.0, abs(ref)) + 1e-6, k
