@@ -7,13 +7,17 @@ pixel, and the output is counts / s.
 
 Random numbers come from a counter-based generator implemented here from its
 published definition, Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), so the
-GPU implementation and this one draw the same stream:
-  counter = (pixel index, frame index, round, 0), key = (seed low 32, seed high 32),
-  uniform = ((x >> 9) + 0.5) * 2^-23 in FP32 (every value exact, never 0 or 1).
-Poisson variates: mean < 10 by inversion with sequential search on one uniform
-(at most 40 steps); mean >= 10 by Hoermann's transformed rejection with squeeze
-"PTRS" (Insurance: Math. and Econ. 12, 1993), two uniforms per attempt, two
-attempts per Philox call, at most 16 calls.  Its acceptance test compares
+GPU implementation and this one draw the same stream.  Key = (seed low 32, seed
+high 32).  Pixels 2m and 2m+1 share the block at counter (m, frame, 0, 0):
+words 0,1 belong to the even pixel, words 2,3 to the odd one; any further words
+of pixel p come from its own blocks at counter (p, frame, round, 1), round =
+1, 2, ...  uniform = ((x >> 9) + 0.5) * 2^-23 in FP32 (every value exact, never
+0 or 1).
+Poisson variates: mean < 10 by inversion with sequential search on the pixel's
+first word (at most 40 steps); mean >= 10 by Hoermann's transformed rejection
+with squeeze "PTRS" (Insurance: Math. and Econ. 12, 1993), two uniforms per
+attempt: the first attempt from the shared block, then two per own block, at
+most 15 own blocks.  Its acceptance test compares
 log(V inv_alpha / (a/us^2 + b)) with -mu + k log(mu) - log(k!), where log(k!)
 is tabulated below k = 10 and taken from Stirling's series above.  The
 decisions are taken in FP32, the precision of the GPU sampler.
@@ -86,14 +90,31 @@ def log_factorial_f32(k: float) -> np.float32:
     return _f(t - _f(_f(1.0) / _f(_f(_f(_f(360.0) * x) * x) * x)))
 
 
+def _ptrs_attempt(wu, wv, mu, log_mu, a, b, inv_alpha, vr):
+    """One PTRS attempt from two words: k >= 0 if accepted, -1 if rejected."""
+    U = _f(uniform_f32(wu) - _f(0.5))
+    V = uniform_f32(wv)
+    us = _f(_f(0.5) - _f(abs(U)))
+    kf = _f(np.floor(_f(_f(_f(_f(_f(_f(2.0) * a) / us) + b) * U) + _f(mu + _f(0.43)))))
+    if us >= _f(0.07) and V <= vr:
+        return int(kf)
+    if kf < 0 or (us < _f(0.013) and V > us):
+        return -1
+    lhs = _f(np.log(_f(_f(V * inv_alpha) / _f(_f(a / _f(us * us)) + b))))
+    rhs = _f(_f(-mu + _f(kf * log_mu)) - log_factorial_f32(float(kf)))
+    return int(kf) if lhs <= rhs else -1
+
+
 def poisson_one(mu: float, pixel: int, frame: int, seed: int) -> int:
     """One Poisson(mu) variate for one pixel (FP32 decisions, as on the GPU)."""
     mu = _f(mu)
     if not (mu > 0):
         return 0
     key = (seed & MASK, (seed >> 32) & MASK)
+    shared = philox4x32_10((pixel >> 1, frame, 0, 0), key)
+    w0, w1 = shared[2 * (pixel & 1)], shared[2 * (pixel & 1) + 1]
     if mu < _f(10.0):
-        u = uniform_f32(philox4x32_10((pixel, frame, 0, 0), key)[0])
+        u = uniform_f32(w0)
         p = _f(np.exp(-mu))
         F = p
         k = 0
@@ -108,24 +129,16 @@ def poisson_one(mu: float, pixel: int, frame: int, seed: int) -> int:
     a = _f(_f(-0.059) + _f(_f(0.02483) * b))
     inv_alpha = _f(_f(1.1239) + _f(_f(1.1328) / _f(b - _f(3.4))))
     vr = _f(_f(0.9277) - _f(_f(3.6224) / _f(b - _f(2.0))))
-    k = int(math.floor(float(mu)))
-    for rnd in range(16):
-        r = philox4x32_10((pixel, frame, rnd, 0), key)
+    k = _ptrs_attempt(w0, w1, mu, log_mu, a, b, inv_alpha, vr)
+    if k >= 0:
+        return k
+    for rnd in range(1, 16):
+        r = philox4x32_10((pixel, frame, rnd, 1), key)
         for t in range(2):
-            U = _f(uniform_f32(r[2 * t]) - _f(0.5))
-            V = uniform_f32(r[2 * t + 1])
-            us = _f(_f(0.5) - _f(abs(U)))
-            kf = np.floor(_f(_f(_f(_f(_f(_f(2.0) * a) / us) + b) * U) + _f(mu + _f(0.43))))
-            kf = _f(kf)
-            if us >= _f(0.07) and V <= vr:
-                return int(kf)
-            if kf < 0 or (us < _f(0.013) and V > us):
-                continue
-            lhs = _f(np.log(_f(_f(V * inv_alpha) / _f(_f(a / _f(us * us)) + b))))
-            rhs = _f(_f(-mu + _f(kf * log_mu)) - log_factorial_f32(float(kf)))
-            if lhs <= rhs:
-                return int(kf)
-    return k
+            k = _ptrs_attempt(r[2 * t], r[2 * t + 1], mu, log_mu, a, b, inv_alpha, vr)
+            if k >= 0:
+                return k
+    return int(math.floor(float(mu)))
 
 
 def add_noise(I: np.ndarray, photons_mean: float, seed: int, frame: int = 0,

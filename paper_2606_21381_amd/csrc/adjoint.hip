@@ -190,7 +190,7 @@ __device__ __forceinline__ EdgeClip clip_edge(float px, float py, float qx, floa
     if (pp[k] == 0.0f) {
       if (qq[k] < 0.0f) return {0.0f, 0.0f};
     } else {
-      const float r = qq[k] / pp[k];
+      const float r = qq[k] * __builtin_amdgcn_rcpf(pp[k]);
       if (pp[k] < 0.0f) t0 = fmaxf(t0, r);
       else t1 = fminf(t1, r);
     }

@@ -83,11 +83,12 @@ static FrameBufs carve_impl(Carver& c, int H, int W, int64_t n, int tile_h, int 
   b.vals_a = c.take<int>(cap);
   b.keys_b = c.take<int>(cap);
   b.vals_b = c.take<int>(cap);
-  b.hist1 = c.take<int>(256 * (size_t)(nblk > 0 ? nblk : 1));
-  b.hist2 = c.take<int>(256 * 256);
+  const size_t nsl = (size_t)((cap + kThreads - 1) / kThreads);
+  b.hist1 = c.take<int>(256 * (nsl > 0 ? nsl : 1));
+  b.hist2 = c.take<int>(256 * (nsl > 0 ? nsl : 1));
   b.dtot = c.take<int>(512);
   b.tile_first = c.take<int>(n_tiles);
-  b.tile_count = c.take<int>(n_tiles);
+  b.tile_end = c.take<int>(n_tiles);
   b.opd = c.take<float>(hw);
   b.band = c.take<float2>(hw);
   b.colsum = c.take<double>(W);

@@ -35,6 +35,8 @@ __device__ __forceinline__ bool pixel_box(float cx, float cy, float a, float b, 
 __device__ __forceinline__ void make_record(float cx, float cy, float ang, float a, float b, float h,
                                             float dn, float shape, PRec* out) {
   PRec& r = *out;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) r.f[k] = 0.0f;
   double cd, sd;
   sincos((double)ang, &sd, &cd);
   const float c = (float)cd, s = (float)sd;
@@ -49,6 +51,15 @@ __device__ __forceinline__ void make_record(float cx, float cy, float ang, float
       r.f[8 + 2 * k] = c * u - s * v;
       r.f[9 + 2 * k] = s * u + c * v;
     }
+    float xlo = r.f[8], xhi = r.f[8], ylo = r.f[9], yhi = r.f[9];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int q = (k + 1) & 3;
+      r.f[16 + k] = (r.f[9 + 2 * q] - r.f[9 + 2 * k]) / (r.f[8 + 2 * q] - r.f[8 + 2 * k]);
+      xlo = fminf(xlo, r.f[8 + 2 * k]); xhi = fmaxf(xhi, r.f[8 + 2 * k]);
+      ylo = fminf(ylo, r.f[9 + 2 * k]); yhi = fmaxf(yhi, r.f[9 + 2 * k]);
+    }
+    r.f[20] = cx + xlo; r.f[21] = cx + xhi; r.f[22] = cy + ylo; r.f[23] = cy + yhi;
   } else {
     r.f[3] = 1.0f;
     r.f[8] = 1.0f / a;
@@ -59,6 +70,11 @@ __device__ __forceinline__ void make_record(float cx, float cy, float ang, float
     r.f[13] = __int_as_float(__double2hiint(sd));
     r.f[14] = dn;
     r.f[15] = h;
+    // bounding-box half extents of the ellipse, enlarged so that every pixel centre
+    // outside them has q >= 1.002 after FP32 rounding
+    const float ex = sqrtf(a * a * c * c + b * b * s * s), ey = sqrtf(a * a * s * s + b * b * c * c);
+    r.f[16] = ex * 1.0011f + 1e-3f;
+    r.f[17] = ey * 1.0011f + 1e-3f;
   }
 }
 

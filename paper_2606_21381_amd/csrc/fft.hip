@@ -88,7 +88,8 @@ template <int LOGW>
 __global__ void __launch_bounds__(kThreads) k_pass3(const float2* __restrict__ band, OpticsArgs o,
                                                     const double* __restrict__ colsum,
                                                     const float2* __restrict__ tw,
-                                                    float* __restrict__ out) {
+                                                    float* __restrict__ out,
+                                                    float* __restrict__ noise_scale) {
   constexpr int W = 1 << LOGW, RB = rows_per_block(W);
   __shared__ float2 buf[RB * W];
   __shared__ double red[kThreads];
@@ -100,34 +101,50 @@ __global__ void __launch_bounds__(kThreads) k_pass3(const float2* __restrict__ b
     const int b = idx / RB, r = idx - b * RB;
     buf[r * W + ((o.kx_lo + b) & (W - 1))] = src[idx];
   }
-  // image mean from the per-column Parseval sums, fixed summation order
-  float scale = 0.0f;
-  if (o.photons > 0.0f) {
+  // block 0: photon scale s = photons / mean(I), the mean from the per-column
+  // Parseval sums in a fixed summation order (read by the noise kernel)
+  if (o.photons > 0.0f && rb == 0) {
     double s = 0.0;
     for (int b = t; b < o.kx_n; b += kThreads) s += colsum[b];
     red[t] = s;
   }
   __syncthreads();
-  if (o.photons > 0.0f) {
+  if (o.photons > 0.0f && rb == 0) {
     for (int s = kThreads / 2; s > 0; s >>= 1) {
       if (t < s) red[t] += red[t + s];
       __syncthreads();
     }
-    const double hw = (double)o.H * (double)W;
-    const double mean = red[0] / (hw * hw);
-    scale = mean > 0.0 ? (float)((double)o.photons / mean) : 0.0f;
+    if (t == 0) {
+      const double hw = (double)o.H * (double)W;
+      const double mean = red[0] / (hw * hw);
+      *noise_scale = mean > 0.0 ? (float)((double)o.photons / mean) : 0.0f;
+    }
   }
   Stages<W, RB, 1, 1, LOGW>::run(buf, tw);
   const float inv = o.inv_hw;
   float* dst = out + (size_t)rb * RB * W;
-  const uint32_t pix0 = (uint32_t)rb * RB * W;
   for (int idx = t; idx < RB * W; idx += kThreads) {
     const float2 e = buf[idx];
     const float er = e.x * inv, ei = e.y * inv;
-    float I = er * er + ei * ei;
-    if (scale > 0.0f) I = (float)poisson(scale * I, pix0 + idx, o.frame, o.seed_lo, o.seed_hi) / scale;
-    dst[idx] = I;
+    dst[idx] = er * er + ei * ei;
   }
+}
+
+// Shot noise in place: I <- Poisson(s I) / s, one pixel pair per thread (its
+// own kernel so the sampler runs at full occupancy, not under pass 3's LDS
+// budget).  The pair's shared Philox block feeds both first attempts.
+__global__ void __launch_bounds__(kThreads) k_noise(float* __restrict__ img, int64_t npix,
+                                                    const float* __restrict__ noise_scale,
+                                                    uint32_t frame, uint32_t k0, uint32_t k1) {
+  const int64_t m = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  const float scale = *noise_scale;
+  if (2 * m >= npix || !(scale > 0.0f)) return;
+  const float2 I = reinterpret_cast<const float2*>(img)[m];
+  const uint4 r = philox4x32_10(make_uint4((uint32_t)m, frame, 0u, 0u), k0, k1);
+  float2 out;
+  out.x = (float)poisson(scale * I.x, r.x, r.y, (uint32_t)(2 * m), frame, k0, k1) / scale;
+  out.y = (float)poisson(scale * I.y, r.z, r.w, (uint32_t)(2 * m + 1), frame, k0, k1) / scale;
+  reinterpret_cast<float2*>(img)[m] = out;
 }
 
 // ------------------------------------------------------------ dispatch -------
@@ -169,9 +186,14 @@ hipError_t launch_pass3(const FramePlan& p, FrameBufs& b, const float2* tw, floa
   OpticsArgs o = optics_args(p);
   const int rbn = p.H / p.rb;
 #define L3(LG) hipLaunchKernelGGL(k_pass3<LG>, dim3(rbn), dim3(kThreads), 0, s, b.band, o, \
-                                  b.colsum, tw, intensity)
+                                  b.colsum, tw, intensity, (float*)(b.scal + 2))
   OSOG_SIZE_SWITCH(p.logW, L3)
 #undef L3
+  if (p.photons > 0.0f && p.kx_n > 0) {
+    const int64_t npix = (int64_t)p.H * p.W;
+    hipLaunchKernelGGL(k_noise, dim3((unsigned)((npix / 2 + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                       intensity, npix, (const float*)(b.scal + 2), p.frame, p.seed_lo, p.seed_hi);
+  }
   return hipGetLastError();
 }
 

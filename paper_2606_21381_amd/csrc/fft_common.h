@@ -218,13 +218,17 @@ __device__ inline void band_chord(const OpticsArgs& o, int kx, int* lo_out, int*
 }
 
 // ---- Poisson sampler ---------------------------------------------------------
-// Philox4x32-10 stream per pixel: counter (pixel, frame, round, 0), key = seed.
-// mean < 10: inversion by sequential search on one uniform (at most 40 steps);
-// mean >= 10: transformed rejection with squeeze (Hoermann 1993, "PTRS"), two
-// uniforms per attempt, two attempts per Philox call, at most 16 calls.  The
-// acceptance test compares log(V inv_alpha / (a/us^2 + b)) with
-// -mu + k log(mu) - log(k!), log(k!) from a table for k < 10 and from Stirling's
-// series (x - 1/2) ln x - x + ln(2 pi)/2 + 1/(12x) - 1/(360 x^3), x = k + 1, above.
+// Random words per frame from Philox4x32-10 (key = seed): pixels 2m and 2m+1
+// share the block at counter (m, frame, 0, 0) -- words 0,1 belong to the even
+// pixel, 2,3 to the odd one -- and draw any further words from their own blocks
+// at counter (pixel, frame, round, 1), round = 1, 2, ...
+// mean < 10: inversion by sequential search on the pixel's first word (at most
+// 40 steps); mean >= 10: transformed rejection with squeeze (Hoermann 1993,
+// "PTRS"), one attempt from the shared block, then two attempts per own block,
+// at most 15 own blocks.  The acceptance test compares
+// log(V inv_alpha / (a/us^2 + b)) with -mu + k log(mu) - log(k!), log(k!) from a
+// table for k < 10 and from Stirling's series
+// (x - 1/2) ln x - x + ln(2 pi)/2 + 1/(12x) - 1/(360 x^3), x = k + 1, above.
 // Every operation is a separately rounded FP32 operation.
 __device__ __forceinline__ float log_factorial(float k) {
 #pragma clang fp contract(off)
@@ -236,12 +240,28 @@ __device__ __forceinline__ float log_factorial(float k) {
   return (x - 0.5f) * logf(x) - x + 0.918938533f + 1.0f / (12.0f * x) - 1.0f / (360.0f * x * x * x);
 }
 
-__device__ __forceinline__ int poisson(float mu, uint32_t pixel, uint32_t frame, uint32_t k0, uint32_t k1) {
+// One PTRS attempt from two words; returns k >= 0 when accepted, -1 when rejected.
+__device__ __forceinline__ int ptrs_attempt(uint32_t wu, uint32_t wv, float mu, float log_mu, float a,
+                                            float b, float inv_alpha, float vr) {
+#pragma clang fp contract(off)
+  const float U = u01(wu) - 0.5f;
+  const float V = u01(wv);
+  const float us = 0.5f - fabsf(U);
+  const float kf = floorf((((2.0f * a) / us) + b) * U + (mu + 0.43f));
+  if (us >= 0.07f && V <= vr) return (int)kf;
+  if (kf < 0.0f || (us < 0.013f && V > us)) return -1;
+  const float lhs = logf(V * inv_alpha / (a / (us * us) + b));
+  const float rhs = (-mu + kf * log_mu) - log_factorial(kf);
+  return lhs <= rhs ? (int)kf : -1;
+}
+
+// Poisson(mu) for one pixel; (w0, w1) are its two words of the shared block.
+__device__ __forceinline__ int poisson(float mu, uint32_t w0, uint32_t w1, uint32_t pixel,
+                                       uint32_t frame, uint32_t k0, uint32_t k1) {
 #pragma clang fp contract(off)
   if (!(mu > 0.0f)) return 0;
   if (mu < 10.0f) {
-    uint4 r = philox4x32_10(make_uint4(pixel, frame, 0u, 0u), k0, k1);
-    const float u = u01(r.x);
+    const float u = u01(w0);
     float p = expf(-mu);
     float F = p;
     int k = 0;
@@ -257,21 +277,14 @@ __device__ __forceinline__ int poisson(float mu, uint32_t pixel, uint32_t frame,
   const float a = -0.059f + 0.02483f * b;
   const float inv_alpha = 1.1239f + 1.1328f / (b - 3.4f);
   const float vr = 0.9277f - 3.6224f / (b - 2.0f);
-  for (uint32_t rnd = 0; rnd < 16; ++rnd) {
-    const uint4 r = philox4x32_10(make_uint4(pixel, frame, rnd, 0u), k0, k1);
-    const uint32_t w[4] = {r.x, r.y, r.z, r.w};
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const float U = u01(w[2 * q]) - 0.5f;
-      const float V = u01(w[2 * q + 1]);
-      const float us = 0.5f - fabsf(U);
-      const float kf = floorf((((2.0f * a) / us) + b) * U + (mu + 0.43f));
-      if (us >= 0.07f && V <= vr) return (int)kf;
-      if (kf < 0.0f || (us < 0.013f && V > us)) continue;
-      const float lhs = logf(V * inv_alpha / (a / (us * us) + b));
-      const float rhs = (-mu + kf * log_mu) - log_factorial(kf);
-      if (lhs <= rhs) return (int)kf;
-    }
+  int k = ptrs_attempt(w0, w1, mu, log_mu, a, b, inv_alpha, vr);
+  if (k >= 0) return k;
+  for (uint32_t rnd = 1; rnd < 16; ++rnd) {
+    const uint4 r = philox4x32_10(make_uint4(pixel, frame, rnd, 1u), k0, k1);
+    k = ptrs_attempt(r.x, r.y, mu, log_mu, a, b, inv_alpha, vr);
+    if (k >= 0) return k;
+    k = ptrs_attempt(r.z, r.w, mu, log_mu, a, b, inv_alpha, vr);
+    if (k >= 0) return k;
   }
   return (int)floorf(mu);
 }

@@ -14,21 +14,21 @@ __device__ __forceinline__ float clamp_avg(float y1, float y2) {
   float lo = fminf(y1, y2), hi = fmaxf(y1, y2);
   float clo = fminf(fmaxf(lo, 0.0f), 1.0f), chi = fminf(fmaxf(hi, 0.0f), 1.0f);
   float d = hi - lo;
-  if (!(d > 0.0f)) return clo;
-  float fin = (chi - clo) / d;
-  float above = fmaxf(0.0f, hi - fmaxf(lo, 1.0f)) / d;
+  if (!(d > 1e-30f)) return clo;
+  const float inv = __builtin_amdgcn_rcpf(d);  // hardware reciprocal (1 ulp)
+  float fin = fminf((chi - clo) * inv, 1.0f);
+  float above = fmaxf(0.0f, hi - fmaxf(lo, 1.0f)) * inv;
   return fin * ((clo + chi) * 0.5f) + above;
 }
 
-// Signed contribution of the directed edge P->Q of a counter-clockwise polygon
-// to its area inside the unit square [0,1]^2:  -integral over x in [0,1] of
-// clamp(y(x), 0, 1) dx along the edge (Green's theorem, area = -closed integral y dx,
-// with y clamped to the square).
-__device__ __forceinline__ float edge_area(float px, float py, float qx, float qy) {
+// Signed contribution of the directed edge P->Q (slope sl = dy/dx) of a
+// counter-clockwise polygon to its area inside the unit square [0,1]^2:
+// -integral over x in [0,1] of clamp(y(x), 0, 1) dx along the edge (Green's
+// theorem, area = -closed integral y dx, with y clamped to the square).
+__device__ __forceinline__ float edge_area(float px, float py, float qx, float qy, float sl) {
   float xl = fminf(px, qx), xr = fmaxf(px, qx);
   float a = fmaxf(xl, 0.0f), b = fminf(xr, 1.0f);
   if (!(b > a)) return 0.0f;
-  float sl = (qy - py) / (qx - px);
   float ya = (a == px) ? py : ((a == qx) ? qy : py + (a - px) * sl);
   float yb = (b == px) ? py : ((b == qx) ? qy : py + (b - px) * sl);
   float w = (b - a) * clamp_avg(ya, yb);
@@ -38,11 +38,7 @@ __device__ __forceinline__ float edge_area(float px, float py, float qx, float q
 // Axis-aligned bounds of a prism footprint in canvas pixels (xmin, xmax, ymin, ymax),
 // rounded the same way wherever they are used.
 __device__ __forceinline__ float4 prism_bounds(const PRec& r) {
-  const float xlo = fminf(fminf(r.f[8], r.f[10]), fminf(r.f[12], r.f[14]));
-  const float xhi = fmaxf(fmaxf(r.f[8], r.f[10]), fmaxf(r.f[12], r.f[14]));
-  const float ylo = fminf(fminf(r.f[9], r.f[11]), fminf(r.f[13], r.f[15]));
-  const float yhi = fmaxf(fmaxf(r.f[9], r.f[11]), fmaxf(r.f[13], r.f[15]));
-  return make_float4(r.f[0] + xlo, r.f[0] + xhi, r.f[1] + ylo, r.f[1] + yhi);
+  return make_float4(r.f[20], r.f[21], r.f[22], r.f[23]);
 }
 
 // Centre-sample test of a pixel against the prism slabs: +1 when the whole pixel
@@ -58,24 +54,49 @@ __device__ __forceinline__ int prism_classify(const PRec& r, float px, float py,
   return 0;
 }
 
+// Area of the unit pixel on the inner side of one straight edge: the pixel's
+// box filter of a half-plane.  t = signed distance from the pixel centre to the
+// edge line (positive inside), (nx, ny) = the line's unit normal.  With
+// p = max(|nx|,|ny|), q = min: 0 for t <= -(p+q)/2, 1 for t >= (p+q)/2, linear
+// 1/2 + t/p for |t| <= (p-q)/2 and quadratic in between.
+__device__ __forceinline__ float halfplane_cover(float t, float nx, float ny) {
+  const float p = fmaxf(fabsf(nx), fabsf(ny)), q = fminf(fabsf(nx), fabsf(ny));
+  const float h = 0.5f * (p + q), l = 0.5f * (p - q);
+  if (t >= h) return 1.0f;
+  if (t <= -h) return 0.0f;
+  if (fabsf(t) <= l) return 0.5f + t * __builtin_amdgcn_rcpf(p);
+  const float e = h - fabsf(t);
+  const float tri = e * e * __builtin_amdgcn_rcpf(2.0f * p * q);
+  return t > 0.0f ? 1.0f - tri : tri;
+}
+
 // Exact area of pixel (i, j) covered by the prism footprint of record r (bounds
 // bb from prism_bounds).  Exactly 0 for a pixel outside the bounds and exactly 1
-// for a pixel whose disc is inside both slabs; otherwise the clipped area.
+// for a pixel whose disc is inside both slabs; a single half-plane's box filter
+// where only one edge reaches the pixel; otherwise the clipped polygon area.
 // Pixel-corner offsets j - cx and i - cy are exact in FP32 for on-canvas
 // particles, so the clip runs in small local coordinates.
 __device__ __forceinline__ float prism_cover(const PRec& r, const float4& bb, int i, int j) {
   const float fj = (float)j, fi = (float)i;
   if (bb.y <= fj || bb.x >= fj + 1.0f || bb.w <= fi || bb.z >= fi + 1.0f) return 0.0f;
-  const int cls = prism_classify(r, fj + 0.5f, fi + 0.5f, 0.0f);
-  if (cls < 0) return 0.0f;
-  if (cls > 0) return 1.0f;
+  const float c = r.f[4], s = r.f[5], a = r.f[6], b = r.f[7];
+  const float dx = (fj + 0.5f) - r.f[0], dy = (fi + 0.5f) - r.f[1];
+  const float u = c * dx + s * dy, v = -s * dx + c * dy;
+  const float hd = 0.70712f;  // > sqrt(2)/2: the pixel lies in this disc around its centre
+  const float du = fabsf(u) - a, dv = fabsf(v) - b;  // signed distances to the nearer edges
+  if (du > hd || dv > hd) return 0.0f;
+  if (du < -hd && dv < -hd) return 1.0f;
+  // only one pair of edges reaches the pixel, and only its nearer edge (the far
+  // one is >= 2a - hd away): the pixel meets a single half-plane
+  if (dv < -hd && a >= hd) return halfplane_cover(-du, c, s);
+  if (du < -hd && b >= hd) return halfplane_cover(-dv, s, c);
   const float X0 = fj - r.f[0], Y0 = fi - r.f[1];
   const float x0 = r.f[8] - X0, y0 = r.f[9] - Y0, x1 = r.f[10] - X0, y1 = r.f[11] - Y0;
   const float x2 = r.f[12] - X0, y2 = r.f[13] - Y0, x3 = r.f[14] - X0, y3 = r.f[15] - Y0;
-  float area = edge_area(x0, y0, x1, y1);
-  area += edge_area(x1, y1, x2, y2);
-  area += edge_area(x2, y2, x3, y3);
-  area += edge_area(x3, y3, x0, y0);
+  float area = edge_area(x0, y0, x1, y1, r.f[16]);
+  area += edge_area(x1, y1, x2, y2, r.f[17]);
+  area += edge_area(x2, y2, x3, y3, r.f[18]);
+  area += edge_area(x3, y3, x0, y0, r.f[19]);
   return area;
 }
 
@@ -101,10 +122,6 @@ __device__ __forceinline__ float ellipsoid_opd(const PRec& r, int i, int j) {
 
 // Half extents of an ellipse's axis-aligned bounding box, enlarged so that every
 // pixel centre outside them has q >= 1.002 after FP32 rounding.
-__device__ __forceinline__ float2 ellipse_extent(const PRec& r) {
-  const float c = r.f[4], s = r.f[5], a = r.f[6], b = r.f[7];
-  const float ex = sqrtf(a * a * c * c + b * b * s * s), ey = sqrtf(a * a * s * s + b * b * c * c);
-  return make_float2(ex * 1.0011f + 1e-3f, ey * 1.0011f + 1e-3f);
-}
+__device__ __forceinline__ float2 ellipse_extent(const PRec& r) { return make_float2(r.f[16], r.f[17]); }
 
 }  // namespace osog

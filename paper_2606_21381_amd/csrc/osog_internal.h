@@ -15,14 +15,18 @@ constexpr int kThreads = 256;     // every kernel runs 256-thread workgroups (4 
 constexpr int kTwN = 4096;        // twiddle table length (largest FFT)
 constexpr int kDefaultPairsPerParticle = 32;
 
-// Per-particle raster record, 64 bytes, written once by the prepare kernel.
+// Per-particle raster record, 128 bytes, written once by the prepare kernel and
+// read by the raster through the scalar cache.
 //   f[0] cx  f[1] cy  f[2] amp = dn*h (FP32)  f[3] kind (0 prism, 1 ellipsoid, -1 none)
 //   f[4] cos f[5] sin f[6] a   f[7] b
-//   prism     f[8..15] footprint corner offsets from the centre (x0,y0,...,x3,y3), CCW
+//   prism     f[8..15]  footprint corner offsets from the centre (x0,y0,...,x3,y3), CCW
+//             f[16..19] edge slopes dy/dx of edges 0-1, 1-2, 2-3, 3-0
+//             f[20..23] footprint bounds xmin, xmax, ymin, ymax in canvas pixels
 //   ellipsoid f[8] 1/a f[9] 1/b f[10..11] cos as double f[12..13] sin as double
 //             f[14] dn f[15] h     (the FP64 rim refinement uses these)
+//             f[16], f[17] half extents of the bounding box, enlarged (see ellipse_extent)
 struct __align__(16) PRec {
-  float f[16];
+  float f[32];
 };
 
 // Static per-call description of a frame, computed on the host.
@@ -56,11 +60,11 @@ struct FrameBufs {
   long long* emit_start;  // n + 1
   int* scal;              // [0] pair count (0 on overflow), [1] overflow flag
   int* keys_a; int* vals_a; int* keys_b; int* vals_b;
-  int* hist1;             // 256 digits x particle blocks
-  int* hist2;             // 256 digits x 256 slices
+  int* hist1;             // low-digit counts: 2^d1 digits x (capacity / 256) slices
+  int* hist2;             // high-digit counts: 2^d2 digits x (capacity / 256) slices
   int* dtot;              // 2 x 256 digit totals
   int* tile_first;        // n_tiles: first sorted pair of the tile (INT_MAX if none)
-  int* tile_count;        // n_tiles: pairs of the tile
+  int* tile_end;          // n_tiles: one past its last sorted pair (0 if none)
   int* sorted_keys;       // set by launch_binning: where the sorted pairs ended
   int* sorted_vals;
   float* opd;             // H*W (used when the caller passes no opd_out)
