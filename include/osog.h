@@ -163,6 +163,20 @@ osog_status osog_batch_render(osog_context* ctx, void* stream, const osog_frame*
                               int32_t n_frames, void* workspace, size_t workspace_bytes,
                               uint64_t* frame_done_ns);
 
+/* Nonzero *flag (host) if a workgroup of the last batch launch on this
+ * workspace gave up waiting for a dependency (its outputs are then invalid).
+ * Waits for the device. */
+osog_status osog_batch_error(osog_context* ctx, void* workspace, int32_t* flag);
+
+/* Batch scheduling: frames are queued in groups of `group` consecutive frames,
+ * stage-major inside a group (0: one group).  Default 16. */
+osog_status osog_set_batch_group(osog_context* ctx, int32_t group);
+
+/* Tiling used for frames of one canvas size in batches (the autotuner's
+ * choice); other sizes use osog_set_tiling's. */
+osog_status osog_set_size_tiling(osog_context* ctx, int32_t height, int32_t width, int32_t tile_h,
+                                 int32_t tile_w);
+
 /* Binning only (steps F1-F4 of the renderer), for inspection and testing:
  * writes the pairs sorted by (tile key, particle id):
  *   keys_out, pids_out  device int32[capacity]; pair_count_out device int32[1]
@@ -175,6 +189,45 @@ osog_status osog_bin(osog_context* ctx, void* stream, int32_t height, int32_t wi
                      int32_t* pids_out, int64_t capacity, int32_t* pair_count_out,
                      int32_t* tile_start_out, int32_t* counts_out, void* workspace,
                      size_t workspace_bytes);
+
+/* ---- Learned initializer (a BF16 CNN on the MFMA matrix cores) ----------------
+ * Six 3x3 convolutions (padding 1, bias + ReLU, channels 1->32/2, 32->32,
+ * 32->64/2, 64->64, 64->128/2, 128->128/2), global average pooling, dense
+ * 128->64 (ReLU) and 64->4.  Input images enter as I / 4 - 1 (the empty DIC
+ * background at bias pi/2 maps to 0); the four outputs are the caller's
+ * normalised targets.
+ * Parameters are one FP32 vector (layout: for each convolution W[3][3][Ci][Co]
+ * then b[Co]; then W[128][64], b[64], W[64][4], b[4]); convolutions run in
+ * BF16 with FP32 accumulation; training is deterministic. */
+osog_status osog_cnn_param_count(int64_t* count);
+/* Workspace for a batch of `batch` images of height x width (multiples of 16). */
+osog_status osog_cnn_workspace_size(int32_t batch, int32_t height, int32_t width, size_t* bytes);
+/* pred (device float[batch][4]) = network(images (device float[batch][height][width])). */
+osog_status osog_cnn_forward(osog_context* ctx, void* stream, int32_t batch, int32_t height, int32_t width,
+                             const float* images, const float* params, float* pred, void* workspace,
+                             size_t workspace_bytes);
+/* One training step on a batch: forward, mean squared error against targets
+ * (device float[batch][4]) into *loss (device float[1], or NULL), backward
+ * through every layer, and, when step >= 1, an Adam update (beta1 0.9, beta2
+ * 0.999, eps 1e-8, bias correction for `step`) of params with moments m, v
+ * (device float[count] each).  grads_out (device float[count] or NULL)
+ * receives the gradient.  step = 0 computes the gradient only. */
+osog_status osog_cnn_train_step(osog_context* ctx, void* stream, int32_t batch, int32_t height, int32_t width,
+                                const float* images, const float* targets, float* params, float* m, float* v,
+                                int32_t step, float lr, float* loss, float* grads_out, void* workspace,
+                                size_t workspace_bytes);
+/* One 3x3 convolution (padding 1, stride 1 or 2) on the MFMA kernels, NHWC BF16
+ * (uint16 bit patterns):
+ *   mode 0  out_bf16[B][Ho][Wo][Co] = relu(conv(x, w) + bias)
+ *   mode 1  out_bf16[B][Hi][Wi][Ci] = dL/dx given grad_y and the layer output y (ReLU mask)
+ *   mode 2  out_f32[3][3][Ci][Co]   = dL/dw given x, grad_y and y
+ * w is [3][3][Ci][Co] BF16.  workspace: osog_conv3x3_workspace_size bytes. */
+osog_status osog_conv3x3_workspace_size(int32_t mode, int32_t batch, int32_t height, int32_t width,
+                                        int32_t c_in, int32_t c_out, int32_t stride, size_t* bytes);
+osog_status osog_conv3x3(osog_context* ctx, void* stream, int32_t mode, int32_t batch, int32_t height,
+                         int32_t width, int32_t c_in, int32_t c_out, int32_t stride, const uint16_t* x,
+                         const uint16_t* y, const uint16_t* grad_y, const uint16_t* w, const float* bias,
+                         uint16_t* out_bf16, float* out_f32, void* workspace, size_t workspace_bytes);
 
 /* The in-band spectrum columns the chain carries for these optics: signed kx in
  * [*kx_lo, *kx_lo + *kx_n) are the columns with at least one DFT bin inside the

@@ -1,0 +1,173 @@
+"""Learned initializer for inverse rendering: a BF16 CNN on MFMA (libosog).
+
+The network regresses the global optical parameters (dn, defocus, DIC shear,
+DIC bias) of a DIC frame.  It is trained on crops the renderer itself produces
+(one persistent batch launch per training batch) with the library's own
+forward, backward and Adam kernels; PyTorch only holds the buffers.
+
+Target normalisation (zero-centred, about unit range over the training draw):
+  dn: (dn - 0.03) / 0.02     dz: dz / 2     shear: (s - 1) / 0.2
+  bias: (theta / (pi/2) - 1) / 0.2
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import time
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib, workloads
+from .render import Batch, _ptr, _stream, context
+
+
+def normalize(g: np.ndarray) -> np.ndarray:
+    g = np.asarray(g, dtype=np.float64)
+    return np.stack([(g[..., 0] - 0.03) / 0.02, g[..., 1] / 2.0, (g[..., 2] - 1.0) / 0.2,
+                     (g[..., 3] / (math.pi / 2) - 1.0) / 0.2], axis=-1)
+
+
+def denormalize(z: np.ndarray) -> np.ndarray:
+    z = np.asarray(z, dtype=np.float64)
+    return np.stack([0.03 + 0.02 * z[..., 0], 2.0 * z[..., 1], 1.0 + 0.2 * z[..., 2],
+                     (math.pi / 2) * (1.0 + 0.2 * z[..., 3])], axis=-1)
+
+
+def param_count() -> int:
+    c = ctypes.c_int64()
+    _lib.check(_lib.load().osog_cnn_param_count(ctypes.byref(c)), "osog_cnn_param_count")
+    return c.value
+
+
+LAYERS = [(1, 32), (32, 32), (32, 64), (64, 64), (64, 128), (128, 128)]
+
+
+def init_params(seed: int = 4) -> torch.Tensor:
+    """He-normal convolutions, zero biases; Glorot-uniform dense layers (CPU, FP32)."""
+    g = torch.Generator().manual_seed(seed)
+    parts = []
+    for ci, co in LAYERS:
+        parts.append(torch.randn(9 * ci * co, generator=g) * math.sqrt(2.0 / (9 * ci)))
+        parts.append(torch.zeros(co))
+    for fi, fo in [(128, 64), (64, 4)]:
+        lim = math.sqrt(6.0 / (fi + fo))
+        parts.append((torch.rand(fi * fo, generator=g) * 2 - 1) * lim)
+        parts.append(torch.zeros(fo))
+    p = torch.cat(parts).float()
+    assert p.numel() == param_count()
+    return p
+
+
+class LearnedInit:
+    def __init__(self, device="cuda", seed: int = 4, batch: int = 256, crop: int = 256, n_max: int = 64):
+        self.device = torch.device(device)
+        self.lib = _lib.load()
+        self.ctx = context(self.device)
+        self.params = init_params(seed).to(self.device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step_count = 0
+        self.batch, self.crop, self.n_max = batch, crop, n_max
+        self.seed = seed
+        self._ws = {}
+
+    # -- workspace --------------------------------------------------------------
+    def _workspace(self, B, H, W):
+        key = (B, H, W)
+        if key not in self._ws:
+            b = ctypes.c_size_t()
+            _lib.check(self.lib.osog_cnn_workspace_size(B, H, W, ctypes.byref(b)), "osog_cnn_workspace_size")
+            self._ws[key] = torch.empty(b.value, dtype=torch.uint8, device=self.device)
+        return self._ws[key]
+
+    # -- network ------------------------------------------------------------------
+    def forward(self, images: torch.Tensor) -> torch.Tensor:
+        """Normalised predictions [B, 4] for images [B, H, W] (CUDA float32)."""
+        images = images.contiguous()
+        B, H, W = images.shape
+        ws = self._workspace(B, H, W)
+        pred = torch.empty((B, 4), dtype=torch.float32, device=self.device)
+        _lib.check(self.lib.osog_cnn_forward(self.ctx, _stream(self.device), B, H, W, _ptr(images),
+                                             _ptr(self.params), _ptr(pred), _ptr(ws), ws.numel()),
+                   "osog_cnn_forward")
+        return pred
+
+    def train_step(self, images, targets, lr: float, grads_out: Optional[torch.Tensor] = None,
+                   update: bool = True) -> torch.Tensor:
+        images = images.contiguous()
+        B, H, W = images.shape
+        ws = self._workspace(B, H, W)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        step = self.step_count + 1 if update else 0
+        _lib.check(self.lib.osog_cnn_train_step(self.ctx, _stream(self.device), B, H, W, _ptr(images),
+                                                _ptr(targets.contiguous()), _ptr(self.params), _ptr(self.m),
+                                                _ptr(self.v), step, lr, _ptr(loss), _ptr(grads_out),
+                                                _ptr(ws), ws.numel()), "osog_cnn_train_step")
+        if update:
+            self.step_count += 1
+        return loss
+
+    def predict(self, image: torch.Tensor) -> np.ndarray:
+        """(dn, dz, shear, bias) for one frame [H, W] (fully convolutional + global pool)."""
+        z = self.forward(image[None]).double().cpu().numpy()[0]
+        return denormalize(z)
+
+    # -- training data rendered by the engine -------------------------------------
+    def _crop_source(self):
+        """Fixed-shape batch of crops (padded particle tables) rendered by one persistent launch."""
+        B, S, N = self.batch, self.crop, self.n_max
+        self.soa_dev = torch.zeros((B, 8, N), dtype=torch.float32, device=self.device)
+        self.g_dev = torch.zeros((B, 4), dtype=torch.float32, device=self.device)
+        self.images = torch.empty((B, S, S), dtype=torch.float32, device=self.device)
+        opt = workloads.dic_optics(0.0)
+        frames = [(self.soa_dev[b], S, S, opt, self.g_dev[b]) for b in range(B)]
+        self.batch_renderer = Batch(frames, out=[self.images[b] for b in range(B)])
+
+    def render_crops(self, rng: np.random.Generator):
+        B, N = self.batch, self.n_max
+        soa = np.zeros((B, 8, N), dtype=np.float32)
+        g = np.zeros((B, 4), dtype=np.float32)
+        tgt = np.zeros((B, 4), dtype=np.float64)
+        for b in range(B):
+            t, gl, truth = workloads.crop(rng, self.crop)
+            n = min(N, t.shape[1])
+            soa[b, :, :n] = t[:, :n]
+            g[b] = gl
+            tgt[b] = truth
+        self.soa_dev.copy_(torch.from_numpy(soa))
+        self.g_dev.copy_(torch.from_numpy(g))
+        self.batch_renderer.run()
+        return torch.from_numpy(normalize(tgt).astype(np.float32)).to(self.device)
+
+    def train(self, samples: int = 200_000, lr: float = 1e-3, seed: Optional[int] = None, log=None):
+        """Train on `samples` freshly rendered crops; returns (losses, seconds)."""
+        if not hasattr(self, "batch_renderer"):
+            self._crop_source()
+        rng = np.random.Generator(np.random.PCG64(self.seed if seed is None else seed))
+        steps = max(1, samples // self.batch)
+        losses = []
+        t0 = time.perf_counter()
+        for k in range(steps):
+            # cosine learning-rate schedule over the run
+            lr_k = lr * 0.5 * (1 + math.cos(math.pi * k / steps))
+            tgt = self.render_crops(rng)
+            loss = self.train_step(self.images, tgt, lr_k)
+            losses.append(loss)
+            if log and (k % 50 == 0 or k == steps - 1):
+                log(k, float(loss.item()))
+        torch.cuda.synchronize(self.device)
+        return torch.cat(losses).cpu().numpy(), time.perf_counter() - t0
+
+    def evaluate(self, n: int = 1000, seed: int = 5):
+        """Mean absolute error per global on n held-out crops (physical units)."""
+        if not hasattr(self, "batch_renderer"):
+            self._crop_source()
+        rng = np.random.Generator(np.random.PCG64(seed))
+        errs = []
+        for _ in range(max(1, n // self.batch)):
+            tgt = self.render_crops(rng)
+            pred = self.forward(self.images)
+            errs.append(np.abs(denormalize(pred.double().cpu().numpy()) - denormalize(tgt.double().cpu().numpy())))
+        return np.concatenate(errs).mean(axis=0)

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -20,6 +22,8 @@ struct osog_context {
   int device = 0;
   float2* twiddle = nullptr;  // kTwN entries: (cos, sin)(2 pi m / kTwN)
   int tile_h = 16, tile_w = 16;
+  std::map<std::pair<int, int>, std::pair<int, int>> size_tiling;  // per canvas size (autotuner)
+  int batch_group = 16;
   osog::BatchCache* batch = nullptr;
   osog::Profiler* prof = nullptr;
 };
@@ -202,6 +206,15 @@ FramePlan make_plan(const osog_context* ctx, int H, int W, int64_t n, int64_t ld
   p.frame = o.noise_frame;
   return p;
 }
+
+void context_tiling(const osog_context* ctx, int H, int W, int* th, int* tw) {
+  auto it = ctx->size_tiling.find({H, W});
+  if (it != ctx->size_tiling.end()) { *th = it->second.first; *tw = it->second.second; }
+  else { *th = ctx->tile_h; *tw = ctx->tile_w; }
+}
+const float2* context_twiddle(const osog_context* ctx) { return ctx->twiddle; }
+int context_device(const osog_context* ctx) { return ctx->device; }
+BatchCache* context_batch(osog_context* ctx) { return ctx->batch; }
 
 static int effective_ppp(int ppp) { return ppp > 0 ? ppp : kDefaultPairsPerParticle; }
 
@@ -454,6 +467,175 @@ osog_status osog_band_info(const osog_context* ctx, int32_t height, int32_t widt
   band_range(height, width, *optics, &lo, &nn);
   *kx_lo = lo;
   *kx_n = nn;
+  return OSOG_OK;
+}
+
+static osog_status check_batch(osog_context* ctx, const osog_frame* frames, int32_t n_frames) {
+  if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
+  if (n_frames <= 0 || !frames) return fail(OSOG_ERR_INVALID_ARGUMENT, "need n_frames >= 1 and a frame array");
+  for (int f = 0; f < n_frames; ++f) {
+    const osog_frame& fr = frames[f];
+    int th, tw;
+    context_tiling(ctx, fr.height, fr.width, &th, &tw);
+    osog_status st = check_optics(&fr.optics);
+    if (st != OSOG_OK) return fail(st, "frame " + std::to_string(f) + ": " + g_last_error);
+    if (fr.n < 0 || fr.n > INT_MAX || fr.ld < fr.n || (fr.n > 0 && !fr.soa) || !fr.globals || !fr.intensity_out)
+      return fail(OSOG_ERR_INVALID_ARGUMENT, "frame " + std::to_string(f) + ": bad n/ld or NULL pointer");
+    if (!pow2_in(fr.height, 32, 4096) || !pow2_in(fr.width, 32, 4096) || fr.height % th || fr.width % tw)
+      return fail(OSOG_ERR_UNSUPPORTED, "frame " + std::to_string(f) + ": canvas size not supported");
+  }
+  return OSOG_OK;
+}
+
+osog_status osog_batch_workspace_size(osog_context* ctx, const osog_frame* frames, int32_t n_frames,
+                                      int32_t pairs_per_particle, size_t* bytes) {
+  osog_status st = check_batch(ctx, frames, n_frames);
+  if (st != OSOG_OK) return st;
+  if (!bytes) return fail(OSOG_ERR_INVALID_ARGUMENT, "bytes is NULL");
+  if (pairs_per_particle < 0) return fail(OSOG_ERR_INVALID_ARGUMENT, "pairs_per_particle must be >= 0");
+  *bytes = batch_workspace_bytes(ctx, frames, n_frames, effective_ppp(pairs_per_particle));
+  return OSOG_OK;
+}
+
+osog_status osog_batch_render(osog_context* ctx, void* stream, const osog_frame* frames, int32_t n_frames,
+                              void* workspace, size_t workspace_bytes, uint64_t* frame_done_ns) {
+  osog_status st = check_batch(ctx, frames, n_frames);
+  if (st != OSOG_OK) return st;
+  if (!workspace) return fail(OSOG_ERR_WORKSPACE, "workspace is NULL");
+  int ppp = 0;
+  for (int cand = 1 << 20; cand >= 1; cand >>= 1)
+    if (batch_workspace_bytes(ctx, frames, n_frames, cand) <= workspace_bytes) { ppp = cand; break; }
+  if (ppp == 0) return fail(OSOG_ERR_WORKSPACE, "workspace smaller than osog_batch_workspace_size()");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  std::string err;
+  Profiler* pr = ctx->prof;
+  profile_begin(pr, OSOG_STAGE_BATCH, (hipStream_t)stream);
+  e = batch_render(ctx, (hipStream_t)stream, frames, n_frames, ppp, ctx->batch_group, workspace,
+                   workspace_bytes, frame_done_ns, &err);
+  profile_end(pr, OSOG_STAGE_BATCH, (hipStream_t)stream);
+  if (e != hipSuccess) return err.empty() ? hip_fail(e, "osog_batch_render") : fail(OSOG_ERR_WORKSPACE, err);
+  return OSOG_OK;
+}
+
+osog_status osog_batch_error(osog_context* ctx, void* workspace, int32_t* flag) {
+  if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
+  if (!workspace || !flag) return fail(OSOG_ERR_INVALID_ARGUMENT, "NULL pointer");
+  hipError_t e = batch_error_flag(workspace, flag);
+  if (e != hipSuccess) return hip_fail(e, "osog_batch_error");
+  return OSOG_OK;
+}
+
+osog_status osog_set_batch_group(osog_context* ctx, int32_t group) {
+  if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
+  if (group < 0) return fail(OSOG_ERR_INVALID_ARGUMENT, "group must be >= 0 (0: all frames in one group)");
+  ctx->batch_group = group;
+  return OSOG_OK;
+}
+
+osog_status osog_set_size_tiling(osog_context* ctx, int32_t height, int32_t width, int32_t tile_h, int32_t tile_w) {
+  if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
+  if (!pow2_in(tile_h, 1, 256) || !pow2_in(tile_w, 1, 256) || tile_h * tile_w != kThreads ||
+      !pow2_in(height, 32, 4096) || !pow2_in(width, 32, 4096) || height % tile_h || width % tile_w)
+    return fail(OSOG_ERR_UNSUPPORTED, "tiling must divide the canvas, powers of two, tile_h * tile_w == 256");
+  ctx->size_tiling[{height, width}] = {tile_h, tile_w};
+  return OSOG_OK;
+}
+
+osog_status osog_cnn_param_count(int64_t* count) {
+  if (!count) return fail(OSOG_ERR_INVALID_ARGUMENT, "count is NULL");
+  *count = cnn_param_count();
+  return OSOG_OK;
+}
+
+static osog_status check_cnn_shape(int32_t batch, int32_t height, int32_t width) {
+  if (batch < 1 || height < 16 || width < 16 || height % 16 || width % 16 || height > 8192 || width > 8192)
+    return fail(OSOG_ERR_UNSUPPORTED, "batch >= 1 and height, width multiples of 16 in [16, 8192]");
+  if ((int64_t)batch * height * width > (int64_t)1 << 31)
+    return fail(OSOG_ERR_UNSUPPORTED, "batch * height * width must stay below 2^31");
+  return OSOG_OK;
+}
+
+osog_status osog_cnn_workspace_size(int32_t batch, int32_t height, int32_t width, size_t* bytes) {
+  if (!bytes) return fail(OSOG_ERR_INVALID_ARGUMENT, "bytes is NULL");
+  osog_status st = check_cnn_shape(batch, height, width);
+  if (st != OSOG_OK) return st;
+  *bytes = cnn_workspace_bytes(batch, height, width);
+  return OSOG_OK;
+}
+
+osog_status osog_cnn_forward(osog_context* ctx, void* stream, int32_t batch, int32_t height, int32_t width,
+                             const float* images, const float* params, float* pred, void* workspace,
+                             size_t workspace_bytes) {
+  if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
+  osog_status st = check_cnn_shape(batch, height, width);
+  if (st != OSOG_OK) return st;
+  if (!images || !params || !pred) return fail(OSOG_ERR_INVALID_ARGUMENT, "NULL pointer");
+  if (!workspace || workspace_bytes < cnn_workspace_bytes(batch, height, width))
+    return fail(OSOG_ERR_WORKSPACE, "workspace smaller than osog_cnn_workspace_size()");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = cnn_forward(batch, height, width, images, params, pred, workspace, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "osog_cnn_forward");
+  return OSOG_OK;
+}
+
+osog_status osog_cnn_train_step(osog_context* ctx, void* stream, int32_t batch, int32_t height, int32_t width,
+                                const float* images, const float* targets, float* params, float* m, float* v,
+                                int32_t step, float lr, float* loss, float* grads_out, void* workspace,
+                                size_t workspace_bytes) {
+  if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
+  osog_status st = check_cnn_shape(batch, height, width);
+  if (st != OSOG_OK) return st;
+  if (!images || !targets || !params) return fail(OSOG_ERR_INVALID_ARGUMENT, "NULL pointer");
+  if (step < 0 || (step > 0 && (!m || !v)) || !std::isfinite(lr))
+    return fail(OSOG_ERR_INVALID_ARGUMENT, "step >= 0 (with m, v when step > 0) and a finite lr");
+  if (!workspace || workspace_bytes < cnn_workspace_bytes(batch, height, width))
+    return fail(OSOG_ERR_WORKSPACE, "workspace smaller than osog_cnn_workspace_size()");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess)
+    e = cnn_train_step(batch, height, width, images, targets, params, m, v, step, lr, loss, grads_out, workspace,
+                       (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "osog_cnn_train_step");
+  return OSOG_OK;
+}
+
+static osog_status check_conv(int32_t mode, int32_t batch, int32_t height, int32_t width, int32_t c_in,
+                              int32_t c_out, int32_t stride) {
+  if (mode < 0 || mode > 2) return fail(OSOG_ERR_INVALID_ARGUMENT, "mode must be 0, 1 or 2");
+  if (batch < 1 || height < 2 || width < 2 || c_in < 1 || c_out < 1 || (stride != 1 && stride != 2) ||
+      (stride == 2 && (height % 2 || width % 2)))
+    return fail(OSOG_ERR_INVALID_ARGUMENT, "bad convolution shape");
+  if ((int64_t)batch * height * width * std::max(c_in, c_out) > (int64_t)1 << 31)
+    return fail(OSOG_ERR_UNSUPPORTED, "convolution too large");
+  return OSOG_OK;
+}
+
+osog_status osog_conv3x3_workspace_size(int32_t mode, int32_t batch, int32_t height, int32_t width,
+                                        int32_t c_in, int32_t c_out, int32_t stride, size_t* bytes) {
+  if (!bytes) return fail(OSOG_ERR_INVALID_ARGUMENT, "bytes is NULL");
+  osog_status st = check_conv(mode, batch, height, width, c_in, c_out, stride);
+  if (st != OSOG_OK) return st;
+  *bytes = conv3x3_workspace_bytes(mode, batch, height, width, c_in, c_out, stride);
+  return OSOG_OK;
+}
+
+osog_status osog_conv3x3(osog_context* ctx, void* stream, int32_t mode, int32_t batch, int32_t height,
+                         int32_t width, int32_t c_in, int32_t c_out, int32_t stride, const uint16_t* x,
+                         const uint16_t* y, const uint16_t* grad_y, const uint16_t* w, const float* bias,
+                         uint16_t* out_bf16, float* out_f32, void* workspace, size_t workspace_bytes) {
+  if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
+  osog_status st = check_conv(mode, batch, height, width, c_in, c_out, stride);
+  if (st != OSOG_OK) return st;
+  const bool ok = mode == 0 ? (x && w && bias && out_bf16)
+                : mode == 1 ? (y && grad_y && w && out_bf16) : (x && y && grad_y && out_f32);
+  if (!ok) return fail(OSOG_ERR_INVALID_ARGUMENT, "NULL pointer");
+  if (!workspace || workspace_bytes < conv3x3_workspace_bytes(mode, batch, height, width, c_in, c_out, stride))
+    return fail(OSOG_ERR_WORKSPACE, "workspace smaller than osog_conv3x3_workspace_size()");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess)
+    e = conv3x3(mode, batch, height, width, c_in, c_out, stride, x, y, grad_y, w, bias, out_bf16, out_f32, workspace,
+                (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "osog_conv3x3");
   return OSOG_OK;
 }
 

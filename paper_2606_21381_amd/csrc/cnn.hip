@@ -1,0 +1,605 @@
+// Learned initializer: a small BF16 convolutional network on the MFMA matrix
+// cores with FP32 accumulation, trained on frames the renderer itself
+// produces, that regresses the global optical parameters (dn, defocus, DIC
+// shear, bias) from a DIC image.
+//
+// Network (3x3 convolutions, padding 1, bias + ReLU, activations NHWC BF16):
+//   1 -> 32 /2, 32 -> 32, 32 -> 64 /2, 64 -> 64, 64 -> 128 /2, 128 -> 128 /2,
+//   global average pool, dense 128 -> 64 (ReLU), dense 64 -> 4.
+// Every convolution -- forward, input gradient (dgrad) and weight gradient
+// (wgrad) -- is an implicit GEMM whose operand tiles are gathered from the
+// activations into LDS as BF16 and multiplied with v_mfma_f32_16x16x16_bf16:
+//   forward  C[pix][co]  = sum_k  im2col(x)[pix][k]            W[k][co],  k = (ky,kx,ci)
+//   dgrad    C[pix][ci]  = sum_k  col(gz)[pix][k]              W^T[k][ci], k = (ky,kx,co)
+//   wgrad    C[k][co]    = sum_pix im2col(x)[pix][k]^T         gz[pix][co]  (split over pix)
+// with gz = dL/d(output) masked by ReLU (output > 0).  The wgrad's split-K
+// partial sums are reduced in a fixed order, so training is deterministic.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "osog_internal.h"
+
+namespace osog {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7F800000u) == 0x7F800000u) return (uint16_t)((u >> 16) | ((u & 0xFFFFu) ? 0x40u : 0u));
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+struct ConvGeom {
+  int B, Hi, Wi, Ci, Ho, Wo, Co, stride;
+};
+
+enum ConvMode { CONV_FWD = 0, CONV_DGRAD = 1, CONV_WGRAD = 2 };
+
+// Gathers for the three GEMM views.  Activations / gradients are NHWC BF16;
+// weights are [ky][kx][ci][co] BF16.
+struct ConvArgs {
+  ConvGeom g;
+  const uint16_t* x;      // layer input activations   [B][Hi][Wi][Ci]
+  const uint16_t* y;      // layer output activations  [B][Ho][Wo][Co] (ReLU mask for dgrad/wgrad)
+  const uint16_t* gy;     // dL/d(output)               [B][Ho][Wo][Co]
+  const uint16_t* w;      // weights                    [3][3][Ci][Co]
+  const float* bias;      // [Co] (forward)
+  uint16_t* out_bf16;     // forward: activations; dgrad: dL/d(input) [B][Hi][Wi][Ci]
+  float* out_f32;         // wgrad: partials [split][9 Ci][Co]
+  int M, N, K;            // GEMM sizes
+  int k_chunk;            // wgrad: pixels per split
+};
+
+__device__ __forceinline__ float relu_mask_grad(const ConvArgs& a, int64_t pix, int co) {
+  const int64_t at = pix * a.g.Co + co;
+  return a.y[at] != 0 && !(a.y[at] & 0x8000u) ? bf2f(a.gy[at]) : 0.0f;
+}
+
+// A operand element (row m, column k) of the GEMM.
+template <int MODE>
+__device__ __forceinline__ uint16_t gather_a(const ConvArgs& a, int m, int k) {
+  const ConvGeom& g = a.g;
+  if (MODE == CONV_FWD) {
+    if (k >= 9 * g.Ci) return 0;
+    const int hw = g.Ho * g.Wo, b = m / hw, r = m - b * hw, oy = r / g.Wo, ox = r - oy * g.Wo;
+    const int tap = k / g.Ci, ci = k - tap * g.Ci, ky = tap / 3, kx = tap - ky * 3;
+    const int iy = oy * g.stride - 1 + ky, ix = ox * g.stride - 1 + kx;
+    if (iy < 0 || iy >= g.Hi || ix < 0 || ix >= g.Wi) return 0;
+    return a.x[(((int64_t)b * g.Hi + iy) * g.Wi + ix) * g.Ci + ci];
+  } else if (MODE == CONV_DGRAD) {
+    // dL/dx[b,y,x,ci] = sum over (ky,kx,co) of gz[b,oy,ox,co] W[ky,kx,ci,co], y = oy*s - 1 + ky
+    const int hw = g.Hi * g.Wi, b = m / hw, r = m - b * hw, y = r / g.Wi, x = r - y * g.Wi;
+    const int tap = k / g.Co, co = k - tap * g.Co, ky = tap / 3, kx = tap - ky * 3;
+    const int ny = y + 1 - ky, nx = x + 1 - kx;
+    if (ny < 0 || nx < 0 || ny % g.stride || nx % g.stride) return 0;
+    const int oy = ny / g.stride, ox = nx / g.stride;
+    if (oy >= g.Ho || ox >= g.Wo) return 0;
+    return f2bf(relu_mask_grad(a, ((int64_t)b * g.Ho + oy) * g.Wo + ox, co));
+  } else {
+    // wgrad: A[m = tap-channel k'][k = pixel] = im2col(x)[pixel][k']
+    const int kk = m;
+    if (kk >= 9 * g.Ci) return 0;
+    const int tap = kk / g.Ci, ci = kk - tap * g.Ci, ky = tap / 3, kx = tap - ky * 3;
+    const int hw = g.Ho * g.Wo, b = k / hw, r = k - b * hw, oy = r / g.Wo, ox = r - oy * g.Wo;
+    if (b >= g.B) return 0;
+    const int iy = oy * g.stride - 1 + ky, ix = ox * g.stride - 1 + kx;
+    if (iy < 0 || iy >= g.Hi || ix < 0 || ix >= g.Wi) return 0;
+    return a.x[(((int64_t)b * g.Hi + iy) * g.Wi + ix) * g.Ci + ci];
+  }
+}
+
+// B operand element (row k, column n).
+template <int MODE>
+__device__ __forceinline__ uint16_t gather_b(const ConvArgs& a, int k, int n) {
+  const ConvGeom& g = a.g;
+  if (MODE == CONV_FWD) {
+    if (k >= 9 * g.Ci) return 0;
+    return a.w[(int64_t)k * g.Co + n];
+  } else if (MODE == CONV_DGRAD) {
+    const int tap = k / g.Co, co = k - tap * g.Co;
+    return a.w[((int64_t)tap * g.Ci + n) * g.Co + co];
+  } else {
+    const int hw = g.Ho * g.Wo;
+    if (k >= g.B * hw) return 0;
+    return f2bf(relu_mask_grad(a, k, n));
+  }
+}
+
+// One workgroup computes a BM x BN tile of C with 4 waves (2 x 2), each wave a
+// (BM/2) x (BN/2) block of 16 x 16 MFMA tiles.  K advances 16 at a time through
+// LDS tiles stored [row][16] so every MFMA operand is one 8-byte LDS read:
+// A lane l reads row l%16, k 4(l/16)..+3; B lane l reads column l%16 likewise;
+// C lane l holds rows 4(l/16)..+3 of column l%16 (v_mfma_f32_16x16x16_bf16).
+template <int MODE, int BM, int BN>
+__global__ void __launch_bounds__(256) k_conv_gemm(ConvArgs a) {
+  constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
+  __shared__ __align__(16) uint16_t As[BM][16];
+  __shared__ __align__(16) uint16_t Bs[BN][16];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  int kbeg = 0, kend = a.K;
+  if (MODE == CONV_WGRAD) {
+    kbeg = blockIdx.z * a.k_chunk;
+    kend = min(a.K, kbeg + a.k_chunk);
+  }
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = kbeg; k0 < kend; k0 += 16) {
+    for (int e = t; e < BM * 16; e += 256) {
+      const int r = e >> 4, kk = e & 15, m = m0 + r, k = k0 + kk;
+      As[r][kk] = (m < a.M && k < kend) ? gather_a<MODE>(a, m, k) : (uint16_t)0;
+    }
+    for (int e = t; e < BN * 16; e += 256) {
+      const int c = e >> 4, kk = e & 15, n = n0 + c, k = k0 + kk;
+      Bs[c][kk] = (n < a.N && k < kend) ? gather_b<MODE>(a, k, n) : (uint16_t)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const bf16x4 av = *reinterpret_cast<const bf16x4*>(&As[wm * WM + i * 16 + (lane & 15)][4 * (lane >> 4)]);
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const bf16x4 bv = *reinterpret_cast<const bf16x4*>(&Bs[wn * WN + j * 16 + (lane & 15)][4 * (lane >> 4)]);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[i][j], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // epilogue
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + r;
+        const int n = n0 + wn * WN + j * 16 + (lane & 15);
+        if (m >= a.M || n >= a.N) continue;
+        const float v = acc[i][j][r];
+        if (MODE == CONV_FWD) {
+          a.out_bf16[(int64_t)m * a.N + n] = f2bf(fmaxf(v + a.bias[n], 0.0f));
+        } else if (MODE == CONV_DGRAD) {
+          a.out_bf16[(int64_t)m * a.N + n] = f2bf(v);
+        } else {
+          a.out_f32[((int64_t)blockIdx.z * a.M + m) * a.N + n] = v;
+        }
+      }
+}
+
+}  // namespace osog
+
+namespace osog {
+
+// ---- small VALU kernels ----------------------------------------------------------
+// Input: x = I / 4 - 1 (BF16, one channel): the empty DIC background at bias
+// pi/2 (|2i sin(theta)|^2 = 4) maps to 0; absolute brightness is kept because
+// it carries the bias.
+__global__ void __launch_bounds__(256) k_cnn_input(const float* __restrict__ img, int64_t n,
+                                                   uint16_t* __restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) x[i] = f2bf(img[i] * 0.25f - 1.0f);
+}
+
+// Global average pool of the last activations [B][hw][C] -> p [B][C].
+__global__ void __launch_bounds__(256) k_cnn_pool(const uint16_t* __restrict__ a, int hw, int C,
+                                                  float* __restrict__ p) {
+  const int b = blockIdx.x, c = threadIdx.x;
+  if (c >= C) return;
+  float s = 0.0f;
+  for (int i = 0; i < hw; ++i) s += bf2f(a[((int64_t)b * hw + i) * C + c]);
+  p[b * C + c] = s / (float)hw;
+}
+
+// Dense head, one workgroup over the whole batch (fixed order):
+//   h = relu(W7^T p + b7) [64], out = W8^T h + b8 [4];
+//   with targets: loss = mean (out - t)^2 and the gradients of the head's
+//   parameters (written into grads) and of p (gp [B][128]).
+__global__ void __launch_bounds__(256) k_cnn_head(const float* __restrict__ p, int B,
+                                                  const float* __restrict__ W7, const float* __restrict__ b7,
+                                                  const float* __restrict__ W8, const float* __restrict__ b8,
+                                                  float* __restrict__ pred, const float* __restrict__ targets,
+                                                  float* __restrict__ gW7, float* __restrict__ gb7,
+                                                  float* __restrict__ gW8, float* __restrict__ gb8,
+                                                  float* __restrict__ gp, float* __restrict__ loss) {
+  __shared__ float h[64], go[4], gh[64], pp[128];
+  __shared__ float acc_loss;
+  const int t = threadIdx.x;
+  // zero the head gradients (each thread owns a strided subset)
+  if (targets) {
+    for (int i = t; i < 128 * 64; i += 256) gW7[i] = 0.0f;
+    for (int i = t; i < 64; i += 256) gb7[i] = 0.0f;
+    for (int i = t; i < 64 * 4; i += 256) gW8[i] = 0.0f;
+    if (t < 4) gb8[t] = 0.0f;
+    if (t == 0) acc_loss = 0.0f;
+  }
+  __syncthreads();
+  for (int b = 0; b < B; ++b) {
+    if (t < 128) pp[t] = p[b * 128 + t];
+    __syncthreads();
+    if (t < 64) {
+      float s = b7[t];
+      for (int i = 0; i < 128; ++i) s += W7[i * 64 + t] * pp[i];
+      h[t] = fmaxf(s, 0.0f);
+    }
+    __syncthreads();
+    if (t < 4) {
+      float s = b8[t];
+      for (int i = 0; i < 64; ++i) s += W8[i * 4 + t] * h[i];
+      pred[b * 4 + t] = s;
+      if (targets) go[t] = 2.0f * (s - targets[b * 4 + t]) / (float)(4 * B);
+    }
+    __syncthreads();
+    if (!targets) continue;
+    if (t == 0) {
+      float l = 0.0f;
+      for (int k = 0; k < 4; ++k) {
+        const float d = pred[b * 4 + k] - targets[b * 4 + k];
+        l += d * d;
+      }
+      acc_loss += l / (float)(4 * B);
+    }
+    if (t < 4) gb8[t] += go[t];
+    for (int i = t; i < 64 * 4; i += 256) gW8[i] += h[i / 4] * go[i % 4];
+    if (t < 64) {
+      float s = 0.0f;
+      for (int k = 0; k < 4; ++k) s += W8[t * 4 + k] * go[k];
+      gh[t] = h[t] > 0.0f ? s : 0.0f;
+    }
+    __syncthreads();
+    if (t < 64) gb7[t] += gh[t];
+    for (int i = t; i < 128 * 64; i += 256) gW7[i] += pp[i / 64] * gh[i % 64];
+    if (t < 128) {
+      float s = 0.0f;
+      for (int k = 0; k < 64; ++k) s += W7[t * 64 + k] * gh[k];
+      gp[b * 128 + t] = s;
+    }
+    __syncthreads();
+  }
+  if (targets && t == 0) *loss = acc_loss;
+}
+
+// dL/d(last activations) from the pooled gradient: gy[b][i][c] = gp[b][c] / hw.
+__global__ void __launch_bounds__(256) k_cnn_unpool(const float* __restrict__ gp, int B, int hw, int C,
+                                                    uint16_t* __restrict__ gy) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)B * hw * C) return;
+  const int c = (int)(e % C);
+  const int b = (int)(e / ((int64_t)hw * C));
+  gy[e] = f2bf(gp[b * C + c] / (float)hw);
+}
+
+// Bias-gradient partials: part[chunk][c] = sum over the chunk's pixels of the
+// ReLU-masked output gradient.
+__global__ void __launch_bounds__(256) k_cnn_bias_partials(const uint16_t* __restrict__ y,
+                                                           const uint16_t* __restrict__ gy, int64_t npix,
+                                                           int C, int64_t chunk, float* __restrict__ part) {
+  const int c = threadIdx.x;
+  if (c >= C) return;
+  const int64_t p0 = (int64_t)blockIdx.x * chunk, p1 = min(npix, p0 + chunk);
+  float s = 0.0f;
+  for (int64_t p = p0; p < p1; ++p) {
+    const uint16_t yv = y[p * C + c];
+    if (yv != 0 && !(yv & 0x8000u)) s += bf2f(gy[p * C + c]);
+  }
+  part[(int64_t)blockIdx.x * C + c] = s;
+}
+
+// out[i] = sum over s of part[s][i], in order of s.
+__global__ void __launch_bounds__(256) k_cnn_reduce(const float* __restrict__ part, int nsplit, int64_t n,
+                                                    float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.0f;
+  for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * n + i];
+  out[i] = s;
+}
+
+__global__ void __launch_bounds__(256) k_cnn_to_bf16(const float* __restrict__ src, int64_t n,
+                                                     uint16_t* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) dst[i] = f2bf(src[i]);
+}
+
+// Adam (Kingma & Ba 2015) with bias correction, elementwise over all parameters.
+__global__ void __launch_bounds__(256) k_cnn_adam(float* __restrict__ p, float* __restrict__ m,
+                                                  float* __restrict__ v, const float* __restrict__ g,
+                                                  int64_t n, float lr, float b1, float b2, float eps,
+                                                  float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ---- host --------------------------------------------------------------------------
+struct CnnLayer {
+  int Ci, Co, stride;
+};
+static const CnnLayer kLayers[6] = {{1, 32, 2}, {32, 32, 1}, {32, 64, 2}, {64, 64, 1}, {64, 128, 2}, {128, 128, 2}};
+constexpr int kHead1 = 64, kOut = 4;
+
+struct CnnOffsets {
+  int64_t w[6], b[6], w7, b7, w8, b8, total;
+};
+
+static CnnOffsets cnn_offsets() {
+  CnnOffsets o;
+  int64_t off = 0;
+  for (int l = 0; l < 6; ++l) {
+    o.w[l] = off;
+    off += 9LL * kLayers[l].Ci * kLayers[l].Co;
+    o.b[l] = off;
+    off += kLayers[l].Co;
+  }
+  o.w7 = off; off += 128LL * kHead1;
+  o.b7 = off; off += kHead1;
+  o.w8 = off; off += (int64_t)kHead1 * kOut;
+  o.b8 = off; off += kOut;
+  o.total = off;
+  return o;
+}
+
+int64_t cnn_param_count() { return cnn_offsets().total; }
+
+struct CnnPlan {
+  int B, H, W;
+  int hs[7], ws[7];  // spatial size of activation l (0 = input)
+  size_t x_off[7];   // activation l offsets (bf16 elements)
+  size_t act_elems, ga_elems, wbf_off[6], wbf_elems, part_elems;
+  int split[6];
+};
+
+static int64_t wgrad_chunk(const CnnPlan& P, int l) {
+  const int64_t K = (int64_t)P.B * P.hs[l + 1] * P.ws[l + 1];
+  return (K + P.split[l] - 1) / P.split[l];
+}
+
+static CnnPlan cnn_plan(int B, int H, int W) {
+  CnnPlan P{};
+  P.B = B; P.H = H; P.W = W;
+  P.hs[0] = H; P.ws[0] = W;
+  size_t off = 0;
+  P.x_off[0] = 0;
+  off += (size_t)B * H * W;
+  for (int l = 0; l < 6; ++l) {
+    P.hs[l + 1] = kLayers[l].stride == 2 ? P.hs[l] / 2 : P.hs[l];
+    P.ws[l + 1] = kLayers[l].stride == 2 ? P.ws[l] / 2 : P.ws[l];
+    P.x_off[l + 1] = off;
+    off += (size_t)B * P.hs[l + 1] * P.ws[l + 1] * kLayers[l].Co;
+  }
+  P.act_elems = off;
+  size_t ga = 0;
+  for (int l = 0; l <= 6; ++l) {
+    const int C = l == 0 ? 1 : kLayers[l - 1].Co;
+    ga = std::max(ga, (size_t)B * P.hs[l] * P.ws[l] * C);
+  }
+  P.ga_elems = ga;
+  size_t wb = 0;
+  for (int l = 0; l < 6; ++l) { P.wbf_off[l] = wb; wb += 9ull * kLayers[l].Ci * kLayers[l].Co; }
+  P.wbf_elems = wb;
+  size_t part = 0;
+  for (int l = 0; l < 6; ++l) {
+    const int64_t K = (int64_t)B * P.hs[l + 1] * P.ws[l + 1];
+    // split the pixel reduction so each split holds ~16K pixels (at most 512 splits)
+    int s = (int)std::min<int64_t>(512, std::max<int64_t>(1, K / 16384));
+    P.split[l] = s;
+    part = std::max(part, (size_t)s * 9 * kLayers[l].Ci * kLayers[l].Co);
+    part = std::max(part, (size_t)s * kLayers[l].Co);
+  }
+  P.part_elems = part;
+  return P;
+}
+
+struct CnnBufs {
+  uint16_t* act;      // all activations (input + 6 layers)
+  uint16_t* ga0;      // gradient ping
+  uint16_t* ga1;      // gradient pong
+  uint16_t* wbf;      // bf16 weights
+  float* part;        // split partial sums
+  float* grads;       // all parameter gradients
+  float* pool;        // [B][128]
+  float* gpool;       // [B][128]
+  float* pred;        // [B][4]
+  float* loss;        // [1]
+  size_t total;
+};
+
+static CnnBufs cnn_carve(void* ws, const CnnPlan& P) {
+  char* base = static_cast<char*>(ws);
+  size_t off = 0;
+  auto take = [&](size_t bytes) { void* p = base ? base + off : nullptr; off += (bytes + 255) & ~size_t(255); return p; };
+  CnnBufs b;
+  b.act = (uint16_t*)take(P.act_elems * 2);
+  b.ga0 = (uint16_t*)take(P.ga_elems * 2);
+  b.ga1 = (uint16_t*)take(P.ga_elems * 2);
+  b.wbf = (uint16_t*)take(P.wbf_elems * 2);
+  b.part = (float*)take(P.part_elems * 4);
+  b.grads = (float*)take((size_t)cnn_param_count() * 4);
+  b.pool = (float*)take((size_t)P.B * 128 * 4);
+  b.gpool = (float*)take((size_t)P.B * 128 * 4);
+  b.pred = (float*)take((size_t)P.B * 4 * 4);
+  b.loss = (float*)take(256);
+  b.total = off;
+  return b;
+}
+
+size_t cnn_workspace_bytes(int B, int H, int W) { return cnn_carve(nullptr, cnn_plan(B, H, W)).total; }
+
+static unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+template <int MODE>
+static hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
+  if (a.N <= 32) {
+    dim3 grid((a.M + 127) / 128, (a.N + 31) / 32, MODE == CONV_WGRAD ? (a.K + a.k_chunk - 1) / a.k_chunk : 1);
+    hipLaunchKernelGGL((k_conv_gemm<MODE, 128, 32>), grid, dim3(256), 0, s, a);
+  } else {
+    dim3 grid((a.M + 63) / 64, (a.N + 63) / 64, MODE == CONV_WGRAD ? (a.K + a.k_chunk - 1) / a.k_chunk : 1);
+    hipLaunchKernelGGL((k_conv_gemm<MODE, 64, 64>), grid, dim3(256), 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+static ConvArgs conv_args(const CnnPlan& P, int l) {
+  ConvArgs a{};
+  a.g.B = P.B;
+  a.g.Hi = P.hs[l]; a.g.Wi = P.ws[l]; a.g.Ci = kLayers[l].Ci;
+  a.g.Ho = P.hs[l + 1]; a.g.Wo = P.ws[l + 1]; a.g.Co = kLayers[l].Co;
+  a.g.stride = kLayers[l].stride;
+  return a;
+}
+
+// Forward through the convolutions, pool and head.  targets != null: also loss and
+// every gradient (into b.grads).
+static hipError_t cnn_run(const CnnPlan& P, const CnnBufs& b, const float* images, const float* params,
+                          const float* targets, hipStream_t s) {
+  const CnnOffsets O = cnn_offsets();
+  const int64_t nin = (int64_t)P.B * P.H * P.W;
+  hipLaunchKernelGGL(k_cnn_input, dim3(blocks(nin)), dim3(256), 0, s, images, nin, b.act + P.x_off[0]);
+  for (int l = 0; l < 6; ++l) {
+    const int64_t nw = 9LL * kLayers[l].Ci * kLayers[l].Co;
+    hipLaunchKernelGGL(k_cnn_to_bf16, dim3(blocks(nw)), dim3(256), 0, s, params + O.w[l], nw, b.wbf + P.wbf_off[l]);
+  }
+  for (int l = 0; l < 6; ++l) {
+    ConvArgs a = conv_args(P, l);
+    a.x = b.act + P.x_off[l];
+    a.w = b.wbf + P.wbf_off[l];
+    a.bias = params + O.b[l];
+    a.out_bf16 = b.act + P.x_off[l + 1];
+    a.M = P.B * P.hs[l + 1] * P.ws[l + 1];
+    a.N = kLayers[l].Co;
+    a.K = 9 * kLayers[l].Ci;
+    hipError_t e = launch_conv<CONV_FWD>(a, s);
+    if (e != hipSuccess) return e;
+  }
+  const int hw6 = P.hs[6] * P.ws[6];
+  hipLaunchKernelGGL(k_cnn_pool, dim3(P.B), dim3(256), 0, s, b.act + P.x_off[6], hw6, 128, b.pool);
+  hipLaunchKernelGGL(k_cnn_head, dim3(1), dim3(256), 0, s, b.pool, P.B, params + O.w7, params + O.b7,
+                     params + O.w8, params + O.b8, b.pred, targets, b.grads + O.w7, b.grads + O.b7,
+                     b.grads + O.w8, b.grads + O.b8, b.gpool, b.loss);
+  if (!targets) return hipGetLastError();
+  // backward through the convolutions
+  uint16_t* gy = b.ga0;
+  uint16_t* gx = b.ga1;
+  const int64_t n6 = (int64_t)P.B * hw6 * 128;
+  hipLaunchKernelGGL(k_cnn_unpool, dim3(blocks(n6)), dim3(256), 0, s, b.gpool, P.B, hw6, 128, gy);
+  for (int l = 5; l >= 0; --l) {
+    ConvArgs a = conv_args(P, l);
+    a.x = b.act + P.x_off[l];
+    a.y = b.act + P.x_off[l + 1];
+    a.gy = gy;
+    a.w = b.wbf + P.wbf_off[l];
+    const int64_t npix = (int64_t)P.B * P.hs[l + 1] * P.ws[l + 1];
+    // weight gradient: split over pixels, reduced in order
+    a.out_f32 = b.part;
+    a.M = 9 * kLayers[l].Ci;
+    a.N = kLayers[l].Co;
+    a.K = (int)npix;
+    a.k_chunk = (int)((wgrad_chunk(P, l) + 15) / 16 * 16);
+    const int nsplit = (a.K + a.k_chunk - 1) / a.k_chunk;
+    hipError_t e = launch_conv<CONV_WGRAD>(a, s);
+    if (e != hipSuccess) return e;
+    const int64_t nw = (int64_t)a.M * a.N;
+    hipLaunchKernelGGL(k_cnn_reduce, dim3(blocks(nw)), dim3(256), 0, s, b.part, nsplit, nw, b.grads + O.w[l]);
+    // bias gradient
+    const int64_t chunk = (npix + 255) / 256;
+    hipLaunchKernelGGL(k_cnn_bias_partials, dim3((unsigned)((npix + chunk - 1) / chunk)), dim3(256), 0, s,
+                       a.y, gy, npix, kLayers[l].Co, chunk, b.part);
+    hipLaunchKernelGGL(k_cnn_reduce, dim3(blocks(kLayers[l].Co)), dim3(256), 0, s, b.part,
+                       (int)((npix + chunk - 1) / chunk), (int64_t)kLayers[l].Co, b.grads + O.b[l]);
+    if (l > 0) {  // input gradient
+      ConvArgs d = a;
+      d.out_bf16 = gx;
+      d.M = P.B * P.hs[l] * P.ws[l];
+      d.N = kLayers[l].Ci;
+      d.K = 9 * kLayers[l].Co;
+      d.k_chunk = 0;
+      if ((e = launch_conv<CONV_DGRAD>(d, s)) != hipSuccess) return e;
+      std::swap(gy, gx);
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t cnn_forward(int B, int H, int W, const float* images, const float* params, float* pred, void* ws,
+                       hipStream_t s) {
+  const CnnPlan P = cnn_plan(B, H, W);
+  const CnnBufs b = cnn_carve(ws, P);
+  hipError_t e = cnn_run(P, b, images, params, nullptr, s);
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(pred, b.pred, sizeof(float) * B * 4, hipMemcpyDeviceToDevice, s);
+}
+
+hipError_t cnn_train_step(int B, int H, int W, const float* images, const float* targets, float* params,
+                          float* m, float* v, int step, float lr, float* loss, float* grads_out, void* ws,
+                          hipStream_t s) {
+  const CnnPlan P = cnn_plan(B, H, W);
+  const CnnBufs b = cnn_carve(ws, P);
+  hipError_t e = cnn_run(P, b, images, params, targets, s);
+  if (e != hipSuccess) return e;
+  const int64_t n = cnn_param_count();
+  if (grads_out && (e = hipMemcpyAsync(grads_out, b.grads, sizeof(float) * n, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+    return e;
+  if (loss && (e = hipMemcpyAsync(loss, b.loss, sizeof(float), hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+  if (step > 0) {
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_cnn_adam, dim3(blocks(n)), dim3(256), 0, s, params, m, v, b.grads, n, lr, b1, b2, 1e-8f,
+                       c1, c2);
+  }
+  return hipGetLastError();
+}
+
+// Single convolution, for checking the MFMA kernels against a reference.
+hipError_t conv3x3(int mode, int B, int Hi, int Wi, int Ci, int Co, int stride, const uint16_t* x,
+                   const uint16_t* y, const uint16_t* gy, const uint16_t* w, const float* bias, uint16_t* out_bf16,
+                   float* out_f32, void* ws, hipStream_t s) {
+  ConvArgs a{};
+  a.g.B = B; a.g.Hi = Hi; a.g.Wi = Wi; a.g.Ci = Ci; a.g.Co = Co; a.g.stride = stride;
+  a.g.Ho = stride == 2 ? Hi / 2 : Hi;
+  a.g.Wo = stride == 2 ? Wi / 2 : Wi;
+  a.x = x; a.y = y; a.gy = gy; a.w = w; a.bias = bias;
+  if (mode == CONV_FWD) {
+    a.out_bf16 = out_bf16; a.M = B * a.g.Ho * a.g.Wo; a.N = Co; a.K = 9 * Ci;
+    return launch_conv<CONV_FWD>(a, s);
+  }
+  if (mode == CONV_DGRAD) {
+    a.out_bf16 = out_bf16; a.M = B * Hi * Wi; a.N = Ci; a.K = 9 * Co;
+    return launch_conv<CONV_DGRAD>(a, s);
+  }
+  a.M = 9 * Ci; a.N = Co; a.K = B * a.g.Ho * a.g.Wo;
+  const int nsplit = std::max(1, std::min(64, a.K / 4096));
+  a.k_chunk = ((a.K + nsplit - 1) / nsplit + 15) / 16 * 16;
+  const int ns = (a.K + a.k_chunk - 1) / a.k_chunk;
+  a.out_f32 = static_cast<float*>(ws);
+  hipError_t e = launch_conv<CONV_WGRAD>(a, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cnn_reduce, dim3(blocks((int64_t)a.M * a.N)), dim3(256), 0, s, a.out_f32, ns,
+                     (int64_t)a.M * a.N, out_f32);
+  return hipGetLastError();
+}
+
+size_t conv3x3_workspace_bytes(int mode, int B, int Hi, int Wi, int Ci, int Co, int stride) {
+  if (mode != CONV_WGRAD) return 256;
+  const int Ho = stride == 2 ? Hi / 2 : Hi, Wo = stride == 2 ? Wi / 2 : Wi;
+  const int K = B * Ho * Wo;
+  const int nsplit = std::max(1, std::min(64, K / 4096));
+  const int chunk = ((K + nsplit - 1) / nsplit + 15) / 16 * 16;
+  const int ns = (K + chunk - 1) / chunk;
+  return (size_t)ns * 9 * Ci * Co * 4 + 256;
+}
+
+}  // namespace osog

@@ -17,134 +17,35 @@
 
 #include "fft_common.h"
 #include "osog_internal.h"
+#include "stages.h"
 
 namespace osog {
 
-// ---------------------------------------------------------------- pass 1 -----
 template <int LOGW>
-__global__ void __launch_bounds__(kThreads) k_pass1(const float* __restrict__ opd, int kx_lo,
-                                                    int kx_n, float phase_k,
-                                                    const float2* __restrict__ tw,
-                                                    float2* __restrict__ band) {
-  constexpr int W = 1 << LOGW, RB = rows_per_block(W);
-  __shared__ float2 buf[RB * W];
-  const int t = threadIdx.x, rb = blockIdx.x;
-  const float* src = opd + (size_t)rb * RB * W;
-  for (int idx = t; idx < RB * W; idx += kThreads) {
-    float s, c;
-    sincosf(phase_k * src[idx], &s, &c);
-    buf[idx] = make_float2(c, s);
-  }
-  __syncthreads();
-  Stages<W, RB, -1, 1, LOGW>::run(buf, tw);
-  float2* dst = band + (size_t)rb * kx_n * RB;
-  for (int idx = t; idx < kx_n * RB; idx += kThreads) {
-    const int b = idx / RB, r = idx - b * RB;
-    dst[idx] = buf[r * W + ((kx_lo + b) & (W - 1))];
-  }
+__global__ void __launch_bounds__(kThreads) k_pass1(FrameDev F, const float2* __restrict__ tw) {
+  __shared__ __align__(16) char lds[rows_per_block(1 << LOGW) * (1 << LOGW) * sizeof(float2)];
+  pass1_body<LOGW>(F, blockIdx.x, tw, lds);
 }
 
-// ---------------------------------------------------------------- pass 2 -----
 template <int LOGH>
-__global__ void __launch_bounds__(kThreads) k_pass2(float2* __restrict__ band, OpticsArgs o,
-                                                    const float* __restrict__ globals,
-                                                    const float2* __restrict__ tw,
-                                                    double* __restrict__ colsum) {
-  constexpr int H = 1 << LOGH;
-  __shared__ float2 buf[H];
-  __shared__ int chord[2];
-  __shared__ double red[kThreads];
-  const int t = threadIdx.x, b = blockIdx.x, kx = o.kx_lo + b;
-  const int RB = o.rb;
-  for (int i = t; i < H; i += kThreads) buf[i] = band[((size_t)(i / RB) * o.kx_n + b) * RB + (i % RB)];
-  if (t == 0) band_chord(o, kx, &chord[0], &chord[1]);
-  __syncthreads();
-  Stages<H, 1, -1, 1, LOGH>::run(buf, tw);
-  const float dz = globals[0], shear = globals[1], bias = globals[2];
-  const int lo = chord[0], hi = chord[1];
-  double part = 0.0;
-  for (int m = t; m < H; m += kThreads) {
-    const int ky = m < H / 2 ? m : m - H;
-    float2 g = make_float2(0.0f, 0.0f);
-    if (ky >= lo && ky <= hi) {
-      g = cmul(buf[m], transfer(o, kx, ky, dz, shear, bias));
-      part += (double)g.x * g.x + (double)g.y * g.y;
-    }
-    buf[m] = g;
-  }
-  red[t] = part;
-  __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] += red[t + s];
-    __syncthreads();
-  }
-  if (t == 0) colsum[b] = red[0];
-  Stages<H, 1, 1, 1, LOGH>::run(buf, tw);
-  for (int i = t; i < H; i += kThreads) band[((size_t)(i / RB) * o.kx_n + b) * RB + (i % RB)] = buf[i];
+__global__ void __launch_bounds__(kThreads) k_pass2(FrameDev F, const float2* __restrict__ tw) {
+  __shared__ __align__(16) char lds[(1 << LOGH) * sizeof(float2) + kThreads * sizeof(double) + 16];
+  pass2_body<LOGH>(F, blockIdx.x, tw, lds);
 }
 
-// ---------------------------------------------------------------- pass 3 -----
 template <int LOGW>
-__global__ void __launch_bounds__(kThreads) k_pass3(const float2* __restrict__ band, OpticsArgs o,
-                                                    const double* __restrict__ colsum,
-                                                    const float2* __restrict__ tw,
-                                                    float* __restrict__ out,
-                                                    float* __restrict__ noise_scale) {
-  constexpr int W = 1 << LOGW, RB = rows_per_block(W);
-  __shared__ float2 buf[RB * W];
-  __shared__ double red[kThreads];
-  const int t = threadIdx.x, rb = blockIdx.x;
-  for (int idx = t; idx < RB * W; idx += kThreads) buf[idx] = make_float2(0.0f, 0.0f);
-  __syncthreads();
-  const float2* src = band + (size_t)rb * o.kx_n * RB;
-  for (int idx = t; idx < o.kx_n * RB; idx += kThreads) {
-    const int b = idx / RB, r = idx - b * RB;
-    buf[r * W + ((o.kx_lo + b) & (W - 1))] = src[idx];
-  }
-  // block 0: photon scale s = photons / mean(I), the mean from the per-column
-  // Parseval sums in a fixed summation order (read by the noise kernel)
-  if (o.photons > 0.0f && rb == 0) {
-    double s = 0.0;
-    for (int b = t; b < o.kx_n; b += kThreads) s += colsum[b];
-    red[t] = s;
-  }
-  __syncthreads();
-  if (o.photons > 0.0f && rb == 0) {
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-      if (t < s) red[t] += red[t + s];
-      __syncthreads();
-    }
-    if (t == 0) {
-      const double hw = (double)o.H * (double)W;
-      const double mean = red[0] / (hw * hw);
-      *noise_scale = mean > 0.0 ? (float)((double)o.photons / mean) : 0.0f;
-    }
-  }
-  Stages<W, RB, 1, 1, LOGW>::run(buf, tw);
-  const float inv = o.inv_hw;
-  float* dst = out + (size_t)rb * RB * W;
-  for (int idx = t; idx < RB * W; idx += kThreads) {
-    const float2 e = buf[idx];
-    const float er = e.x * inv, ei = e.y * inv;
-    dst[idx] = er * er + ei * ei;
-  }
+__global__ void __launch_bounds__(kThreads) k_pass3(FrameDev F, const float2* __restrict__ tw) {
+  __shared__ __align__(16) char lds[rows_per_block(1 << LOGW) * (1 << LOGW) * sizeof(float2) +
+                                    kThreads * sizeof(double)];
+  pass3_body<LOGW>(F, blockIdx.x, tw, lds);
 }
 
-// Shot noise in place: I <- Poisson(s I) / s, one pixel pair per thread (its
-// own kernel so the sampler runs at full occupancy, not under pass 3's LDS
-// budget).  The pair's shared Philox block feeds both first attempts.
-__global__ void __launch_bounds__(kThreads) k_noise(float* __restrict__ img, int64_t npix,
-                                                    const float* __restrict__ noise_scale,
-                                                    uint32_t frame, uint32_t k0, uint32_t k1) {
+// Shot noise in place, one pixel pair per thread (its own kernel so the sampler
+// runs at full occupancy, not under pass 3's LDS budget).
+__global__ void __launch_bounds__(kThreads) k_noise(FrameDev F) {
   const int64_t m = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const float scale = *noise_scale;
-  if (2 * m >= npix || !(scale > 0.0f)) return;
-  const float2 I = reinterpret_cast<const float2*>(img)[m];
-  const uint4 r = philox4x32_10(make_uint4((uint32_t)m, frame, 0u, 0u), k0, k1);
-  float2 out;
-  out.x = (float)poisson(scale * I.x, r.x, r.y, (uint32_t)(2 * m), frame, k0, k1) / scale;
-  out.y = (float)poisson(scale * I.y, r.z, r.w, (uint32_t)(2 * m + 1), frame, k0, k1) / scale;
-  reinterpret_cast<float2*>(img)[m] = out;
+  if (2 * m >= (int64_t)F.H * F.W) return;
+  noise_pairs(F, m);
 }
 
 // ------------------------------------------------------------ dispatch -------
@@ -163,9 +64,10 @@ __global__ void __launch_bounds__(kThreads) k_noise(float* __restrict__ img, int
 
 hipError_t launch_pass1(const FramePlan& p, const float* opd, FrameBufs& b, const float2* tw,
                         hipStream_t s) {
+  FrameDev F = make_dev(p, b);
+  F.opd = const_cast<float*>(opd);
   const int rbn = p.H / p.rb;
-#define L1(LG) hipLaunchKernelGGL(k_pass1<LG>, dim3(rbn), dim3(kThreads), 0, s, opd, p.kx_lo, \
-                                  p.kx_n, p.phase_k, tw, b.band)
+#define L1(LG) hipLaunchKernelGGL(k_pass1<LG>, dim3(rbn), dim3(kThreads), 0, s, F, tw)
   OSOG_SIZE_SWITCH(p.logW, L1)
 #undef L1
   return hipGetLastError();
@@ -173,9 +75,9 @@ hipError_t launch_pass1(const FramePlan& p, const float* opd, FrameBufs& b, cons
 
 hipError_t launch_pass2(const FramePlan& p, const float* globals, FrameBufs& b, const float2* tw,
                         hipStream_t s) {
-  OpticsArgs o = optics_args(p);
-#define L2(LG) hipLaunchKernelGGL(k_pass2<LG>, dim3(p.kx_n), dim3(kThreads), 0, s, b.band, o, \
-                                  globals, tw, b.colsum)
+  FrameDev F = make_dev(p, b);
+  F.globals = globals;
+#define L2(LG) hipLaunchKernelGGL(k_pass2<LG>, dim3(p.kx_n), dim3(kThreads), 0, s, F, tw)
   OSOG_SIZE_SWITCH(p.logH, L2)
 #undef L2
   return hipGetLastError();
@@ -183,16 +85,15 @@ hipError_t launch_pass2(const FramePlan& p, const float* globals, FrameBufs& b, 
 
 hipError_t launch_pass3(const FramePlan& p, FrameBufs& b, const float2* tw, float* intensity,
                         hipStream_t s) {
-  OpticsArgs o = optics_args(p);
+  FrameDev F = make_dev(p, b);
+  F.intensity = intensity;
   const int rbn = p.H / p.rb;
-#define L3(LG) hipLaunchKernelGGL(k_pass3<LG>, dim3(rbn), dim3(kThreads), 0, s, b.band, o, \
-                                  b.colsum, tw, intensity, (float*)(b.scal + 2))
+#define L3(LG) hipLaunchKernelGGL(k_pass3<LG>, dim3(rbn), dim3(kThreads), 0, s, F, tw)
   OSOG_SIZE_SWITCH(p.logW, L3)
 #undef L3
   if (p.photons > 0.0f && p.kx_n > 0) {
-    const int64_t npix = (int64_t)p.H * p.W;
-    hipLaunchKernelGGL(k_noise, dim3((unsigned)((npix / 2 + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
-                       intensity, npix, (const float*)(b.scal + 2), p.frame, p.seed_lo, p.seed_hi);
+    const int64_t npairs = (int64_t)p.H * p.W / 2;
+    hipLaunchKernelGGL(k_noise, dim3((unsigned)((npairs + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, F);
   }
   return hipGetLastError();
 }

@@ -43,6 +43,7 @@ __device__ __forceinline__ float2 mul_i(float2 z) {  // z * (DIR i)
 
 template <int DIR>
 __device__ __forceinline__ void dft4(float2& v0, float2& v1, float2& v2, float2& v3) {
+#pragma clang fp contract(off)
   float2 t0 = cadd(v0, v2), t1 = csub(v0, v2), t2 = cadd(v1, v3), t3 = mul_i<DIR>(csub(v1, v3));
   v0 = cadd(t0, t2);
   v2 = csub(t0, t2);
@@ -52,6 +53,7 @@ __device__ __forceinline__ void dft4(float2& v0, float2& v1, float2& v2, float2&
 
 template <int R, int DIR>
 __device__ __forceinline__ void dft(float2* v) {
+#pragma clang fp contract(off)
   if constexpr (R == 2) {
     float2 a = v[0];
     v[0] = cadd(a, v[1]);
@@ -81,6 +83,7 @@ __device__ __forceinline__ void dft(float2* v) {
 template <int N, int ROWS, int DIR, int NS, int REM>
 struct Stages {
   static __device__ __forceinline__ void run(float2* buf, const float2* __restrict__ tw) {
+#pragma clang fp contract(off)
     constexpr int R = REM >= 3 ? 8 : (REM == 2 ? 4 : 2);
     constexpr int LR = REM >= 3 ? 3 : REM;
     constexpr int NB = N / R, TOT = ROWS * NB, BPT = (TOT + kThreads - 1) / kThreads;
@@ -136,6 +139,7 @@ struct Stages<N, ROWS, DIR, NS, 0> {
 // DIC: P (e^{i th} e^{+2 pi i f.ds} - e^{-i th} e^{-2 pi i f.ds}) = 2 i sin(2 pi f.ds + th) P.
 __device__ __forceinline__ float2 transfer(const OpticsArgs& o, int kx, int ky, float dz,
                                            float shear, float bias) {
+#pragma clang fp contract(off)
   const float two_pi = 6.283185307179586f;
   const float fx = (float)kx * o.inv_wdx, fy = (float)ky * o.inv_hdx;
   const float gx = fx + o.tfx, gy = fy + o.tfy;

@@ -11,6 +11,7 @@ namespace osog {
 // Written as (fraction of [lo,hi] inside [0,1]) * (mean inside) + (fraction
 // above 1) so that short or flat segments stay well conditioned.
 __device__ __forceinline__ float clamp_avg(float y1, float y2) {
+#pragma clang fp contract(off)
   float lo = fminf(y1, y2), hi = fmaxf(y1, y2);
   float clo = fminf(fmaxf(lo, 0.0f), 1.0f), chi = fminf(fmaxf(hi, 0.0f), 1.0f);
   float d = hi - lo;
@@ -26,6 +27,7 @@ __device__ __forceinline__ float clamp_avg(float y1, float y2) {
 // -integral over x in [0,1] of clamp(y(x), 0, 1) dx along the edge (Green's
 // theorem, area = -closed integral y dx, with y clamped to the square).
 __device__ __forceinline__ float edge_area(float px, float py, float qx, float qy, float sl) {
+#pragma clang fp contract(off)
   float xl = fminf(px, qx), xr = fmaxf(px, qx);
   float a = fmaxf(xl, 0.0f), b = fminf(xr, 1.0f);
   if (!(b > a)) return 0.0f;
@@ -45,6 +47,7 @@ __device__ __forceinline__ float4 prism_bounds(const PRec& r) {
 // is inside (coverage exactly 1), -1 when it is certainly outside, 0 otherwise.
 // The pixel lies in the disc of radius sqrt(2)/2 about its centre.
 __device__ __forceinline__ int prism_classify(const PRec& r, float px, float py, float margin) {
+#pragma clang fp contract(off)
   const float c = r.f[4], s = r.f[5], a = r.f[6], b = r.f[7];
   const float dx = px - r.f[0], dy = py - r.f[1];
   const float u = c * dx + s * dy, v = -s * dx + c * dy;
@@ -60,6 +63,7 @@ __device__ __forceinline__ int prism_classify(const PRec& r, float px, float py,
 // p = max(|nx|,|ny|), q = min: 0 for t <= -(p+q)/2, 1 for t >= (p+q)/2, linear
 // 1/2 + t/p for |t| <= (p-q)/2 and quadratic in between.
 __device__ __forceinline__ float halfplane_cover(float t, float nx, float ny) {
+#pragma clang fp contract(off)
   const float p = fmaxf(fabsf(nx), fabsf(ny)), q = fminf(fabsf(nx), fabsf(ny));
   const float h = 0.5f * (p + q), l = 0.5f * (p - q);
   if (t >= h) return 1.0f;
@@ -77,6 +81,7 @@ __device__ __forceinline__ float halfplane_cover(float t, float nx, float ny) {
 // Pixel-corner offsets j - cx and i - cy are exact in FP32 for on-canvas
 // particles, so the clip runs in small local coordinates.
 __device__ __forceinline__ float prism_cover(const PRec& r, const float4& bb, int i, int j) {
+#pragma clang fp contract(off)
   const float fj = (float)j, fi = (float)i;
   if (bb.y <= fj || bb.x >= fj + 1.0f || bb.w <= fi || bb.z >= fi + 1.0f) return 0.0f;
   const float c = r.f[4], s = r.f[5], a = r.f[6], b = r.f[7];
@@ -103,6 +108,7 @@ __device__ __forceinline__ float prism_cover(const PRec& r, const float4& bb, in
 // Ellipsoid thickness times dn at the centre of pixel (i, j).  Within 2e-3 of
 // the rim, where sqrt(1 - q) amplifies rounding, q is recomputed in FP64.
 __device__ __forceinline__ float ellipsoid_opd(const PRec& r, int i, int j) {
+#pragma clang fp contract(off)
   float cx = r.f[0], cy = r.f[1], c = r.f[4], s = r.f[5];
   float dx = ((float)j + 0.5f) - cx, dy = ((float)i + 0.5f) - cy;
   float u = (c * dx + s * dy) * r.f[8], v = (-s * dx + c * dy) * r.f[9];

@@ -98,6 +98,19 @@ hipError_t launch_global_grads(const FramePlan& p, FrameBufs& b, float* grad_glo
 
 void set_error(const std::string& msg);
 
+// learned initializer (cnn.hip)
+int64_t cnn_param_count();
+size_t cnn_workspace_bytes(int B, int H, int W);
+hipError_t cnn_forward(int B, int H, int W, const float* images, const float* params, float* pred, void* ws,
+                       hipStream_t s);
+hipError_t cnn_train_step(int B, int H, int W, const float* images, const float* targets, float* params,
+                          float* m, float* v, int step, float lr, float* loss, float* grads_out, void* ws,
+                          hipStream_t s);
+hipError_t conv3x3(int mode, int B, int Hi, int Wi, int Ci, int Co, int stride, const uint16_t* x,
+                   const uint16_t* y, const uint16_t* gy, const uint16_t* w, const float* bias, uint16_t* out_bf16,
+                   float* out_f32, void* ws, hipStream_t s);
+size_t conv3x3_workspace_bytes(int mode, int B, int Hi, int Wi, int Ci, int Co, int stride);
+
 struct Profiler;
 // host helpers shared by the entry points (api.cpp)
 FramePlan make_plan(const osog_context* ctx, int H, int W, int64_t n, int64_t ld, const osog_optics& o,
@@ -124,6 +137,7 @@ hipError_t profiler_read(Profiler* p, double* ms, int64_t* launches);
 namespace osog {
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+#pragma clang fp contract(off)
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }

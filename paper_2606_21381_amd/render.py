@@ -197,3 +197,64 @@ def philox(ctr: torch.Tensor, key0: int, key1: int) -> torch.Tensor:
     _lib.check(_lib.load().osog_philox4x32_10(_stream(c.device), _ptr(c), c.shape[0], key0 & 0xFFFFFFFF,
                                                key1 & 0xFFFFFFFF, _ptr(out)), "osog_philox4x32_10")
     return out
+
+
+class Batch:
+    """A batch of frames rendered by one persistent kernel launch (HIP graph).
+
+    ``frames``: list of (soa [8, n] CUDA float32, H, W, optics, globals [4] CUDA float32).
+    Outputs are allocated once; ``run()`` re-renders into them (replaying the
+    captured graph after the first call) and returns the outputs.
+    """
+
+    def __init__(self, frames, want_opd: bool = False, pairs_per_particle: int = 0, device=None, out=None):
+        self.device = frames[0][0].device if device is None else torch.device(device)
+        self.lib = _lib.load()
+        self.ctx = context(self.device)
+        self.inputs = frames
+        self.out = out if out is not None else [torch.empty((H, W), dtype=torch.float32, device=self.device)
+                                                for (_, H, W, _, _) in frames]
+        self.opd = [torch.empty((H, W), dtype=torch.float32, device=self.device) if want_opd else None
+                    for (_, H, W, _, _) in frames]
+        n = len(frames)
+        self.c_frames = (_lib.Frame * n)()
+        for f, (soa, H, W, optics, g) in enumerate(frames):
+            nn, ld = _check_soa(soa)
+            _check_globals(g, self.device)
+            fr = self.c_frames[f]
+            fr.height, fr.width = H, W
+            fr.soa = soa.data_ptr() if nn else None
+            fr.n, fr.ld = nn, ld
+            fr.optics = _lib.make_optics(optics)
+            fr.globals = g.data_ptr()
+            fr.opd_out = self.opd[f].data_ptr() if want_opd else None
+            fr.intensity_out = self.out[f].data_ptr()
+        b = ctypes.c_size_t()
+        _lib.check(self.lib.osog_batch_workspace_size(self.ctx, self.c_frames, n, pairs_per_particle,
+                                                      ctypes.byref(b)), "osog_batch_workspace_size")
+        self.ws = torch.empty(b.value, dtype=torch.uint8, device=self.device)
+        self.done_ns = torch.zeros(n + 1, dtype=torch.int64, device=self.device)
+
+    def run(self):
+        _lib.check(self.lib.osog_batch_render(self.ctx, _stream(self.device), self.c_frames, len(self.inputs),
+                                              _ptr(self.ws), self.ws.numel(), _ptr(self.done_ns)),
+                   "osog_batch_render")
+        return self.out
+
+    def error_flag(self) -> int:
+        f = ctypes.c_int32()
+        _lib.check(self.lib.osog_batch_error(self.ctx, _ptr(self.ws), ctypes.byref(f)), "osog_batch_error")
+        return f.value
+
+    def latencies_ms(self):
+        """Per-frame completion time after the launch started, ms (after a sync)."""
+        t = self.done_ns.cpu().numpy().astype("float64")
+        return (t[:-1] - t[-1]) / 1e6
+
+
+def set_batch_group(group: int, device=None):
+    _lib.check(_lib.load().osog_set_batch_group(context(device), group), "osog_set_batch_group")
+
+
+def set_size_tiling(H: int, W: int, tile_h: int, tile_w: int, device=None):
+    _lib.check(_lib.load().osog_set_size_tiling(context(device), H, W, tile_h, tile_w), "osog_set_size_tiling")

@@ -1,0 +1,131 @@
+"""The learned initializer's MFMA convolutions against float64 PyTorch on the CPU,
+full-network gradients against float64 autograd, and a short training run on
+crops the renderer produces."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+import torch
+import torch.nn.functional as Fn
+
+from tests.gpu_util import need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+
+def bf16_bits(t):
+    return t.to(torch.bfloat16).view(torch.int16)
+
+
+def bits_to_f64(b):
+    return b.view(torch.bfloat16).double()
+
+
+def conv_call(mode, B, H, W, Ci, Co, s, x=None, y=None, gy=None, w=None, bias=None):
+    from paper_2606_21381_amd import _lib, render
+    lib = _lib.load()
+    ctx = render.context()
+    Ho, Wo = (H // 2, W // 2) if s == 2 else (H, W)
+    nb = ctypes.c_size_t()
+    _lib.check(lib.osog_conv3x3_workspace_size(mode, B, H, W, Ci, Co, s, ctypes.byref(nb)), "ws")
+    ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    p = lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None
+    if mode == 0:
+        out = torch.empty((B, Ho, Wo, Co), dtype=torch.int16, device="cuda")
+        _lib.check(lib.osog_conv3x3(ctx, None, 0, B, H, W, Ci, Co, s, p(x), None, None, p(w), p(bias), p(out), None,
+                                    p(ws), ws.numel()), "conv fwd")
+    elif mode == 1:
+        out = torch.empty((B, H, W, Ci), dtype=torch.int16, device="cuda")
+        _lib.check(lib.osog_conv3x3(ctx, None, 1, B, H, W, Ci, Co, s, None, p(y), p(gy), p(w), None, p(out), None,
+                                    p(ws), ws.numel()), "conv dgrad")
+    else:
+        out = torch.empty((3, 3, Ci, Co), dtype=torch.float32, device="cuda")
+        _lib.check(lib.osog_conv3x3(ctx, None, 2, B, H, W, Ci, Co, s, p(x), p(y), p(gy), None, None, None, p(out),
+                                    p(ws), ws.numel()), "conv wgrad")
+    torch.cuda.synchronize()
+    return out
+
+
+def rel(a, b):
+    return float((a - b).norm() / b.norm())
+
+
+@pytest.mark.parametrize("B,H,W,Ci,Co,s", [(2, 16, 16, 1, 32, 2), (3, 20, 12, 32, 32, 1), (2, 16, 16, 32, 64, 2),
+                                           (1, 8, 8, 128, 128, 2), (2, 12, 16, 64, 64, 1)])
+def test_conv_modes_vs_float64(B, H, W, Ci, Co, s):
+    need_gpu()
+    g = torch.Generator().manual_seed(B * 100 + Ci)
+    x = torch.randn(B, H, W, Ci, generator=g)
+    w = torch.randn(3, 3, Ci, Co, generator=g) / math.sqrt(9 * Ci)
+    bias = torch.randn(Co, generator=g) * 0.1
+    xb, wb = bf16_bits(x), bf16_bits(w)
+    X = bits_to_f64(xb).permute(0, 3, 1, 2)
+    Wt = bits_to_f64(wb).permute(3, 2, 0, 1).contiguous()
+    ref = torch.relu(Fn.conv2d(X, Wt, bias.double(), stride=s, padding=1))
+    y = conv_call(0, B, H, W, Ci, Co, s, x=xb.cuda(), w=wb.cuda(), bias=bias.cuda())
+    Y = bits_to_f64(y.cpu()).permute(0, 3, 1, 2)
+    e_f = rel(Y, ref)
+    # gradients through the ReLU of this layer's output
+    gy = torch.randn(Y.shape[0], Y.shape[2], Y.shape[3], Co, generator=g)
+    gyb = bf16_bits(gy)
+    gz = bits_to_f64(gyb).permute(0, 3, 1, 2) * (Y > 0)
+    ref_dx = torch.nn.grad.conv2d_input(X.shape, Wt, gz, stride=s, padding=1)
+    ref_dw = torch.nn.grad.conv2d_weight(X, Wt.shape, gz, stride=s, padding=1)
+    dx = conv_call(1, B, H, W, Ci, Co, s, y=y, gy=gyb.cuda(), w=wb.cuda())
+    dw = conv_call(2, B, H, W, Ci, Co, s, x=xb.cuda(), y=y, gy=gyb.cuda())
+    e_dx = rel(bits_to_f64(dx.cpu()).permute(0, 3, 1, 2), ref_dx)
+    e_dw = rel(dw.cpu().double().permute(3, 2, 0, 1), ref_dw)
+    say("conv B%d %dx%d %d->%d s%d: fwd %.2e dgrad %.2e wgrad %.2e" % (B, H, W, Ci, Co, s, e_f, e_dx, e_dw))
+    assert e_f < 1e-2 and e_dx < 1e-2 and e_dw < 1e-2
+
+
+def reference_net(params, images):
+    """The same network in float64 PyTorch (CPU), returning predictions."""
+    from paper_2606_21381_amd import cnn
+    p = params.double()
+    off = 0
+    x = (images.double() * 0.25 - 1.0)[:, None]
+    for l, (ci, co) in enumerate(cnn.LAYERS):
+        w = p[off:off + 9 * ci * co].view(3, 3, ci, co).permute(3, 2, 0, 1)
+        off += 9 * ci * co
+        b = p[off:off + co]
+        off += co
+        x = torch.relu(Fn.conv2d(x, w, b, stride=2 if l in (0, 2, 4, 5) else 1, padding=1))
+    pool = x.mean(dim=(2, 3))
+    W7 = p[off:off + 128 * 64].view(128, 64); off += 128 * 64
+    b7 = p[off:off + 64]; off += 64
+    W8 = p[off:off + 64 * 4].view(64, 4); off += 64 * 4
+    b8 = p[off:off + 4]
+    return torch.relu(pool @ W7 + b7) @ W8 + b8
+
+
+def test_network_gradients_vs_float64_autograd():
+    need_gpu()
+    from paper_2606_21381_amd import cnn
+    net = cnn.LearnedInit(batch=4, crop=64)
+    g = torch.Generator().manual_seed(3)
+    images = (4.0 + torch.randn(4, 64, 64, generator=g)).float()
+    targets = torch.randn(4, 4, generator=g).float()
+    grads = torch.empty_like(net.params)
+    loss = net.train_step(images.cuda(), targets.cuda(), 0.0, grads_out=grads, update=False)
+    pred = net.forward(images.cuda())
+    torch.cuda.synchronize()
+    P = net.params.cpu().double().requires_grad_(True)
+    ref_pred = reference_net(P, images)
+    ref_loss = ((ref_pred - targets.double()) ** 2).mean()
+    ref_loss.backward()
+    e_pred = rel(pred.cpu().double(), ref_pred.detach())
+    gg = grads.cpu().double()
+    cos = float(torch.dot(gg, P.grad) / (gg.norm() * P.grad.norm()))
+    say("cnn: pred rel %.2e, loss %.6f vs %.6f, grad cosine %.6f" % (e_pred, float(loss.item()), float(ref_loss), cos))
+    assert e_pred < 3e-2 and abs(float(loss.item()) - float(ref_loss)) < 3e-2 * float(ref_loss) and cos > 0.995
+
+
+def test_training_on_engine_crops_reduces_loss():
+    need_gpu()
+    from paper_2606_21381_amd import cnn
+    net = cnn.LearnedInit(batch=32, crop=128, n_max=16)
+    losses, secs = net.train(samples=32 * 60, lr=2e-3)
+    say("cnn training smoke: loss %.4f -> %.4f in %.2f s" % (losses[:5].mean(), losses[-5:].mean(), secs))
+    assert np.isfinite(losses).all() and losses[-10:].mean() < 0.8 * losses[:10].mean()
