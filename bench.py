@@ -81,6 +81,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=50)
+    ap.add_argument("--no-extras", action="store_true", help="skip the backward, batch and inverse-solve legs")
+    ap.add_argument("--learned", action="store_true",
+                    help="also train the learned initializer (200,000 rendered crops) and compare inverse solves")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X with no sharding "
@@ -163,9 +166,89 @@ def main():
         "roofline": roof,
         "paper_context": "paper: 40,000 particles in under 50 ms on one NVIDIA A100 (1024^2 canvas)",
     }
+    if not args.no_extras:
+        res["backward"] = bench_backward(render, soa, g, fr, dev)
+        res["batch"] = bench_batch(render, dev)
+        res["inverse"] = bench_inverse(dev, learned=args.learned)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(fr)
     print(json.dumps(res), flush=True)
+
+
+def bench_backward(render, soa, g, fr, dev, reps=20):
+    """ms per adjoint call (forward recompute + adjoint) at the headline frame."""
+    import torch
+    gi = torch.randn(fr.H, fr.W, device=dev)
+    for _ in range(3):
+        render.render_backward(soa, fr.H, fr.W, fr.optics, g, gi)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        render.render_backward(soa, fr.H, fr.W, fr.optics, g, gi)
+    e1.record()
+    torch.cuda.synchronize()
+    return {"ms_per_backward": round(e0.elapsed_time(e1) / reps, 4), "workload": "dic2048_n40000"}
+
+
+def bench_batch(render, dev, reps=10):
+    """64 frames of 512/1024/2048^2, 100..40000 particles, DIC + oblique, one persistent launch."""
+    import torch
+    from paper_2606_21381_amd import autotune, workloads
+    frs = workloads.config2()
+    fr = [(torch.from_numpy(x.soa).to(dev), x.H, x.W, x.optics, torch.from_numpy(x.globals4).to(dev)) for x in frs]
+    # autotune one representative frame per canvas size (largest particle count of that size)
+    reps_by_size = {}
+    for x, f in zip(frs, fr):
+        k = (x.H, x.W)
+        if k not in reps_by_size or f[0].shape[1] > reps_by_size[k][0].shape[1]:
+            reps_by_size[k] = (f[0], x.optics, f[4])
+    choices = autotune.tune_sizes(reps_by_size, reps=3, device=dev)
+    b = render.Batch(fr)
+    b.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    lats = []
+    e0.record()
+    for _ in range(reps):
+        b.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    for _ in range(3):
+        b.run()
+        torch.cuda.synchronize()
+        lats.append(b.latencies_ms())
+    lat = np.concatenate(lats)
+    px = sum(x.H * x.W for x in frs)
+    parts = sum(x.soa.shape[1] for x in frs)
+    return {"workload": "batch64_mixed", "frames": len(frs), "ms_per_batch": round(ms, 4),
+            "frames_per_s": round(len(frs) * 1000.0 / ms, 1), "px_per_s": round(px * 1000.0 / ms, 1),
+            "particles_per_s": round(parts * 1000.0 / ms, 1),
+            "latency_p50_ms": round(float(np.percentile(lat, 50)), 4),
+            "latency_p99_ms": round(float(np.percentile(lat, 99)), 4),
+            "error_flag": b.error_flag(), "autotune": choices}
+
+
+def bench_inverse(dev, learned=False):
+    """1024^2 DIC, 500 prisms: Adam through the adjoint from the perturbed start (500 steps)."""
+    import torch
+    from paper_2606_21381_amd import inverse, workloads
+    prob = workloads.config3()
+    target, start, truth = inverse.problem_tensors(prob, dev)
+    inverse.solve(target, inverse.problem_tensors(prob, dev)[1], truth, prob.target.H, prob.target.W,
+                  prob.target.optics, inverse.SolverConfig(steps=3))  # warm-up
+    res = inverse.solve(target, start, truth, prob.target.H, prob.target.W, prob.target.optics,
+                        inverse.SolverConfig())
+    out = {"workload": "dic1024_n500_adam500", "time_to_1e-3_s": res.time_to_target_s,
+           "steps_to_1e-3": res.steps_to_target, "final_error": float(res.error[-1]),
+           "final_loss": float(res.loss[-1]), "steps_per_s": round(len(res.loss) / float(res.time_s[-1]), 1)}
+    if learned:
+        from paper_2606_21381_amd import cnn
+        rep = cnn.compare(dev)
+        rep.pop("targets")
+        out["learned"] = rep
+    return out
 
 
 if __name__ == "__main__":

@@ -177,6 +177,22 @@ osog_status osog_set_batch_group(osog_context* ctx, int32_t group);
 osog_status osog_set_size_tiling(osog_context* ctx, int32_t height, int32_t width, int32_t tile_h,
                                  int32_t tile_w);
 
+/* FFT plan for frames of one canvas size: the largest Stockham radix, 8
+ * (default) or 4.  Renders of that size in osog_render, osog_render_backward
+ * and osog_batch_render use it. */
+osog_status osog_set_size_radix(osog_context* ctx, int32_t height, int32_t width, int32_t fft_radix);
+
+/* Autotuner: renders this frame `reps` times for every candidate plan -- tile
+ * shape 16x16, 8x32 or 32x8 and FFT radix 8 or 4 -- timed with HIP events on
+ * the stream (waits for the device), and records the fastest for frames of
+ * this canvas size (as osog_set_size_tiling / osog_set_size_radix would).
+ * Writes the choice and its mean milliseconds per render.  workspace: as for
+ * osog_render. */
+osog_status osog_autotune(osog_context* ctx, void* stream, int32_t height, int32_t width, const float* soa,
+                          int64_t n, int64_t ld, const osog_optics* optics, const float* globals,
+                          float* intensity_out, void* workspace, size_t workspace_bytes, int32_t reps,
+                          int32_t* tile_h, int32_t* tile_w, int32_t* fft_radix, float* best_ms);
+
 /* Binning only (steps F1-F4 of the renderer), for inspection and testing:
  * writes the pairs sorted by (tile key, particle id):
  *   keys_out, pids_out  device int32[capacity]; pair_count_out device int32[1]

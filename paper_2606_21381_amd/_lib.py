@@ -20,7 +20,7 @@ STAGES = ["binning", "raster", "pass1", "pass2", "pass3", "adj_pass3", "adj_pass
 EXPORTS = [
     "osog_context_create", "osog_context_destroy", "osog_set_tiling", "osog_get_tiling",
     "osog_workspace_size", "osog_render", "osog_render_backward", "osog_batch_workspace_size",
-    "osog_batch_render", "osog_batch_error", "osog_set_batch_group", "osog_set_size_tiling", "osog_bin", "osog_band_info", "osog_philox4x32_10", "osog_profile_enable",
+    "osog_batch_render", "osog_batch_error", "osog_set_batch_group", "osog_set_size_tiling", "osog_set_size_radix", "osog_autotune", "osog_bin", "osog_band_info", "osog_philox4x32_10", "osog_profile_enable",
     "osog_profile_read", "osog_cnn_param_count", "osog_cnn_workspace_size", "osog_cnn_forward",
     "osog_cnn_train_step", "osog_conv3x3_workspace_size", "osog_conv3x3", "osog_status_string",
     "osog_last_error",
@@ -90,6 +90,9 @@ def load(path: str = LIB_PATH):
         "osog_batch_error": [vp, vp, ctypes.POINTER(i32)],
         "osog_set_batch_group": [vp, i32],
         "osog_set_size_tiling": [vp, i32, i32, i32, i32],
+        "osog_set_size_radix": [vp, i32, i32, i32],
+        "osog_autotune": [vp, vp, i32, i32, vp, i64, i64, ctypes.POINTER(Optics), vp, vp, vp, sz, i32,
+                          ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)],
         "osog_bin": [vp, vp, i32, i32, vp, i64, i64, vp, vp, i64, vp, vp, vp, vp, sz],
         "osog_philox4x32_10": [vp, vp, i64, u32, u32, vp],
         "osog_band_info": [vp, i32, i32, ctypes.POINTER(Optics), ctypes.POINTER(i32), ctypes.POINTER(i32)],

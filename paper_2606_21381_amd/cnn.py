@@ -171,3 +171,75 @@ class LearnedInit:
             pred = self.forward(self.images)
             errs.append(np.abs(denormalize(pred.double().cpu().numpy()) - denormalize(tgt.double().cpu().numpy())))
         return np.concatenate(errs).mean(axis=0)
+
+
+def _seed_globals(start, g):
+    """Overwrite the four global parameters of an inverse-solve start in place."""
+    with torch.no_grad():
+        start.dn.fill_(float(g[0]))
+        start.dz.fill_(float(g[1]))
+        start.shear.fill_(float(g[2]))
+        start.bias.fill_(float(g[3]))
+
+
+def compare(device="cuda", samples: int = 200_000, n_targets: int = 10, target_seed0: int = 300,
+            net: Optional["LearnedInit"] = None, cfg=None, log=None) -> dict:
+    """Learned-init against default-init inverse solves on 1024^2 DIC targets of 500 prisms.
+
+    Both runs start every prism from the same perturbed position, angle and
+    width; they differ only in the four globals: the default start perturbs
+    them by x(1 + U[-0.2, 0.2]), the learned start takes the network's
+    prediction on the full target frame.  Fallback: when the image loss at the
+    learned start exceeds the loss at the default start, the learned run uses
+    the default start instead (counted).  Returns training cost, held-out
+    per-global error, and the median time and steps to e <= 1e-3 of each arm.
+    """
+    from . import inverse
+    from .render import render
+    device = torch.device(device)
+    cfg = cfg or inverse.SolverConfig()
+    if net is None:
+        net = LearnedInit(device)
+        losses, t_train = net.train(samples, log=log)
+    else:
+        losses, t_train = np.array([]), 0.0
+    mae = net.evaluate()
+    rows = []
+    fallbacks = 0
+    for k in range(n_targets):
+        prob = workloads.config3(seed=target_seed0 + k)
+        H, W, opt = prob.target.H, prob.target.W, prob.target.optics
+        target, start_def, truth = inverse.problem_tensors(prob, device)
+        _, start_cnn, _ = inverse.problem_tensors(prob, device)
+        g_pred = net.predict(target)
+        _seed_globals(start_cnn, g_pred)
+        with torch.no_grad():
+            l_def = float(torch.mean((render(start_def.soa(), H, W, opt, start_def.globals4()) - target) ** 2))
+            l_cnn = float(torch.mean((render(start_cnn.soa(), H, W, opt, start_cnn.globals4()) - target) ** 2))
+        used_fallback = l_cnn > l_def
+        if used_fallback:
+            fallbacks += 1
+            _, start_cnn, _ = inverse.problem_tensors(prob, device)
+        r_def = inverse.solve(target, start_def, truth, H, W, opt, cfg)
+        r_cnn = inverse.solve(target, start_cnn, truth, H, W, opt, cfg)
+        g_true = truth.globals4.double().cpu().numpy()
+        rows.append({"seed": target_seed0 + k, "loss_start_default": l_def, "loss_start_learned": l_cnn,
+                     "fallback": used_fallback,
+                     "pred_abs_err": np.abs(g_pred - g_true).tolist(),
+                     "default": (r_def.steps_to_target, r_def.time_to_target_s, float(r_def.error[-1])),
+                     "learned": (r_cnn.steps_to_target, r_cnn.time_to_target_s, float(r_cnn.error[-1]))})
+        if log:
+            log(k, rows[-1])
+
+    def med(arm, i):
+        v = [r[arm][i] if r[arm][i] is not None else math.inf for r in rows]
+        return float(np.median(v))
+
+    return {"workload": "dic1024_n500 x %d targets" % n_targets, "train_samples": samples,
+            "train_s": round(t_train, 2), "train_final_loss": float(losses[-20:].mean()) if len(losses) else None,
+            "heldout_mae": dict(zip(("dn", "dz_um", "shear_px", "bias_rad"), map(float, mae))),
+            "fallbacks": fallbacks,
+            "median_time_to_1e-3_s": {"default": med("default", 1), "learned": med("learned", 1)},
+            "median_steps_to_1e-3": {"default": med("default", 0), "learned": med("learned", 0)},
+            "median_final_error": {"default": med("default", 2), "learned": med("learned", 2)},
+            "targets": rows}

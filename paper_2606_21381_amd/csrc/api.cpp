@@ -7,6 +7,7 @@
 #include <climits>
 #include <algorithm>
 #include <map>
+#include <optional>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -23,6 +24,8 @@ struct osog_context {
   float2* twiddle = nullptr;  // kTwN entries: (cos, sin)(2 pi m / kTwN)
   int tile_h = 16, tile_w = 16;
   std::map<std::pair<int, int>, std::pair<int, int>> size_tiling;  // per canvas size (autotuner)
+  std::map<std::pair<int, int>, int> size_radix;                   // per canvas size (autotuner)
+  int fft_radix = 8;
   int batch_group = 16;
   osog::BatchCache* batch = nullptr;
   osog::Profiler* prof = nullptr;
@@ -161,6 +164,9 @@ static osog_status check_optics(const osog_optics* o) {
   return OSOG_OK;
 }
 
+void context_tiling(const osog_context* ctx, int H, int W, int* th, int* tw);
+int context_radix(const osog_context* ctx, int H, int W);
+
 static osog_status check_frame(const osog_context* ctx, int H, int W, const float* soa, int64_t n,
                                int64_t ld, const osog_optics* optics, const float* globals) {
   if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
@@ -172,20 +178,35 @@ static osog_status check_frame(const osog_context* ctx, int H, int W, const floa
   if (st != OSOG_OK) return st;
   if (!pow2_in(H, 32, 4096) || !pow2_in(W, 32, 4096))
     return fail(OSOG_ERR_UNSUPPORTED, "height and width must be powers of two in [32, 4096]");
-  if (H % ctx->tile_h || W % ctx->tile_w)
-    return fail(OSOG_ERR_UNSUPPORTED, "canvas sides must be multiples of the tile sides");
+  int th, tw;
+  context_tiling(ctx, H, W, &th, &tw);
+  if (H % th || W % tw) return fail(OSOG_ERR_UNSUPPORTED, "canvas sides must be multiples of the tile sides");
   return OSOG_OK;
 }
+
+void context_tiling(const osog_context* ctx, int H, int W, int* th, int* tw) {
+  auto it = ctx->size_tiling.find({H, W});
+  if (it != ctx->size_tiling.end()) { *th = it->second.first; *tw = it->second.second; }
+  else { *th = ctx->tile_h; *tw = ctx->tile_w; }
+}
+int context_radix(const osog_context* ctx, int H, int W) {
+  auto it = ctx->size_radix.find({H, W});
+  return it != ctx->size_radix.end() ? it->second : ctx->fft_radix;
+}
+const float2* context_twiddle(const osog_context* ctx) { return ctx->twiddle; }
+int context_device(const osog_context* ctx) { return ctx->device; }
+BatchCache* context_batch(osog_context* ctx) { return ctx->batch; }
 
 FramePlan make_plan(const osog_context* ctx, int H, int W, int64_t n, int64_t ld,
                     const osog_optics& o, int64_t cap) {
   FramePlan p{};
   p.H = H; p.W = W; p.logH = ilog2(H); p.logW = ilog2(W);
-  p.tile_h = ctx->tile_h; p.tile_w = ctx->tile_w;
+  context_tiling(ctx, H, W, &p.tile_h, &p.tile_w);
   p.ntx = W / p.tile_w; p.nty = H / p.tile_h; p.n_tiles = p.ntx * p.nty;
   p.key_bits = ilog2(p.n_tiles);
   band_range(H, W, o, &p.kx_lo, &p.kx_n);
   p.rb = rows_per_block(W);
+  p.fft_radix = context_radix(ctx, H, W);
   p.n = n; p.ld = ld; p.cap = cap;
   p.mode = o.mode;
   p.phase_k = (float)(2.0 * M_PI / o.wavelength_um);
@@ -207,14 +228,11 @@ FramePlan make_plan(const osog_context* ctx, int H, int W, int64_t n, int64_t ld
   return p;
 }
 
-void context_tiling(const osog_context* ctx, int H, int W, int* th, int* tw) {
-  auto it = ctx->size_tiling.find({H, W});
-  if (it != ctx->size_tiling.end()) { *th = it->second.first; *tw = it->second.second; }
-  else { *th = ctx->tile_h; *tw = ctx->tile_w; }
+static int tile_of(const osog_context* ctx, int H, int W, int which) {
+  int th, tw;
+  context_tiling(ctx, H, W, &th, &tw);
+  return which == 0 ? th : tw;
 }
-const float2* context_twiddle(const osog_context* ctx) { return ctx->twiddle; }
-int context_device(const osog_context* ctx) { return ctx->device; }
-BatchCache* context_batch(osog_context* ctx) { return ctx->batch; }
 
 static int effective_ppp(int ppp) { return ppp > 0 ? ppp : kDefaultPairsPerParticle; }
 
@@ -317,9 +335,9 @@ osog_status osog_workspace_size(const osog_context* ctx, int32_t height, int32_t
   if (pairs_per_particle < 0) return fail(OSOG_ERR_INVALID_ARGUMENT, "pairs_per_particle must be >= 0");
   if (!pow2_in(height, 32, 4096) || !pow2_in(width, 32, 4096))
     return fail(OSOG_ERR_UNSUPPORTED, "height and width must be powers of two in [32, 4096]");
-  if (height % ctx->tile_h || width % ctx->tile_w)
+  if (height % tile_of(ctx, height, width, 0) || width % tile_of(ctx, height, width, 1))
     return fail(OSOG_ERR_UNSUPPORTED, "canvas sides must be multiples of the tile sides");
-  *bytes = frame_workspace_bytes(height, width, n, ctx->tile_h, ctx->tile_w,
+  *bytes = frame_workspace_bytes(height, width, n, tile_of(ctx, height, width, 0), tile_of(ctx, height, width, 1),
                                  effective_ppp(pairs_per_particle), with_backward != 0);
   return OSOG_OK;
 }
@@ -335,7 +353,7 @@ osog_status osog_render(osog_context* ctx, void* stream, int32_t height, int32_t
   // the largest pair capacity this workspace holds
   int ppp = 0;
   for (int cand = 1 << 20; cand >= 1; cand >>= 1)
-    if (frame_workspace_bytes(height, width, n, ctx->tile_h, ctx->tile_w, cand, false) <= workspace_bytes) {
+    if (frame_workspace_bytes(height, width, n, tile_of(ctx, height, width, 0), tile_of(ctx, height, width, 1), cand, false) <= workspace_bytes) {
       ppp = cand;
       break;
     }
@@ -343,7 +361,7 @@ osog_status osog_render(osog_context* ctx, void* stream, int32_t height, int32_t
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   int64_t cap = 0;
-  FrameBufs b = carve(workspace, height, width, n, ctx->tile_h, ctx->tile_w, ppp, false, &cap);
+  FrameBufs b = carve(workspace, height, width, n, tile_of(ctx, height, width, 0), tile_of(ctx, height, width, 1), ppp, false, &cap);
   FramePlan p = make_plan(ctx, height, width, n, ld, *optics, cap);
   e = forward_frame(ctx, p, soa, globals, b, opd_out, intensity_out, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "osog_render launch");
@@ -361,7 +379,7 @@ osog_status osog_render_backward(osog_context* ctx, void* stream, int32_t height
   if (!workspace) return fail(OSOG_ERR_WORKSPACE, "workspace is NULL");
   int ppp = 0;
   for (int cand = 1 << 20; cand >= 1; cand >>= 1)
-    if (frame_workspace_bytes(height, width, n, ctx->tile_h, ctx->tile_w, cand, true) <= workspace_bytes) {
+    if (frame_workspace_bytes(height, width, n, tile_of(ctx, height, width, 0), tile_of(ctx, height, width, 1), cand, true) <= workspace_bytes) {
       ppp = cand;
       break;
     }
@@ -369,7 +387,7 @@ osog_status osog_render_backward(osog_context* ctx, void* stream, int32_t height
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   int64_t cap = 0;
-  FrameBufs b = carve(workspace, height, width, n, ctx->tile_h, ctx->tile_w, ppp, true, &cap);
+  FrameBufs b = carve(workspace, height, width, n, tile_of(ctx, height, width, 0), tile_of(ctx, height, width, 1), ppp, true, &cap);
   FramePlan p = make_plan(ctx, height, width, n, ld, *optics, cap);
   hipStream_t s = (hipStream_t)stream;
   Profiler* pr = ctx->prof;
@@ -420,20 +438,20 @@ osog_status osog_bin(osog_context* ctx, void* stream, int32_t height, int32_t wi
   if (capacity < 0 || capacity > INT_MAX - 1) return fail(OSOG_ERR_INVALID_ARGUMENT, "bad capacity");
   if (!pow2_in(height, 32, 4096) || !pow2_in(width, 32, 4096))
     return fail(OSOG_ERR_UNSUPPORTED, "height and width must be powers of two in [32, 4096]");
-  if (height % ctx->tile_h || width % ctx->tile_w)
+  if (height % tile_of(ctx, height, width, 0) || width % tile_of(ctx, height, width, 1))
     return fail(OSOG_ERR_UNSUPPORTED, "canvas sides must be multiples of the tile sides");
-  size_t need = frame_workspace_bytes(height, width, n, ctx->tile_h, ctx->tile_w, 1, false);
+  size_t need = frame_workspace_bytes(height, width, n, tile_of(ctx, height, width, 0), tile_of(ctx, height, width, 1), 1, false);
   if (!workspace || workspace_bytes < need) return fail(OSOG_ERR_WORKSPACE, "workspace too small");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   int ppp = 1;
   for (int cand = 1 << 20; cand >= 1; cand >>= 1)
-    if (frame_workspace_bytes(height, width, n, ctx->tile_h, ctx->tile_w, cand, false) <= workspace_bytes) {
+    if (frame_workspace_bytes(height, width, n, tile_of(ctx, height, width, 0), tile_of(ctx, height, width, 1), cand, false) <= workspace_bytes) {
       ppp = cand;
       break;
     }
   int64_t cap = 0;
-  FrameBufs b = carve(workspace, height, width, n, ctx->tile_h, ctx->tile_w, ppp, false, &cap);
+  FrameBufs b = carve(workspace, height, width, n, tile_of(ctx, height, width, 0), tile_of(ctx, height, width, 1), ppp, false, &cap);
   if (cap > capacity) cap = capacity;
   osog_optics o{};
   o.mode = OSOG_BRIGHTFIELD; o.wavelength_um = 0.55; o.na = 0.5; o.n_medium = 1.33; o.pixel_um = 0.1;
@@ -636,6 +654,75 @@ osog_status osog_conv3x3(osog_context* ctx, void* stream, int32_t mode, int32_t 
     e = conv3x3(mode, batch, height, width, c_in, c_out, stride, x, y, grad_y, w, bias, out_bf16, out_f32, workspace,
                 (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "osog_conv3x3");
+  return OSOG_OK;
+}
+
+osog_status osog_set_size_radix(osog_context* ctx, int32_t height, int32_t width, int32_t fft_radix) {
+  if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
+  if (fft_radix != 4 && fft_radix != 8) return fail(OSOG_ERR_UNSUPPORTED, "fft_radix must be 4 or 8");
+  if (!pow2_in(height, 32, 4096) || !pow2_in(width, 32, 4096))
+    return fail(OSOG_ERR_UNSUPPORTED, "height and width must be powers of two in [32, 4096]");
+  ctx->size_radix[{height, width}] = fft_radix;
+  return OSOG_OK;
+}
+
+osog_status osog_autotune(osog_context* ctx, void* stream, int32_t height, int32_t width, const float* soa,
+                          int64_t n, int64_t ld, const osog_optics* optics, const float* globals,
+                          float* intensity_out, void* workspace, size_t workspace_bytes, int32_t reps,
+                          int32_t* tile_h, int32_t* tile_w, int32_t* fft_radix, float* best_ms) {
+  osog_status st = check_frame(ctx, height, width, soa, n, ld, optics, globals);
+  if (st != OSOG_OK) return st;
+  if (!intensity_out || !tile_h || !tile_w || !fft_radix || reps < 1)
+    return fail(OSOG_ERR_INVALID_ARGUMENT, "NULL output or reps < 1");
+  hipStream_t s = (hipStream_t)stream;
+  const std::pair<int, int> key{height, width};
+  const auto saved_t = ctx->size_tiling.find(key) != ctx->size_tiling.end()
+                           ? std::optional<std::pair<int, int>>(ctx->size_tiling[key]) : std::nullopt;
+  const auto saved_r = ctx->size_radix.find(key) != ctx->size_radix.end()
+                           ? std::optional<int>(ctx->size_radix[key]) : std::nullopt;
+  const int cand_t[3][2] = {{16, 16}, {8, 32}, {32, 8}};
+  const int cand_r[2] = {8, 4};
+  float best = 1e30f;
+  int bt = -1, br = -1;
+  hipEvent_t e0, e1;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+  if ((e = hipEventCreate(&e1)) != hipSuccess) { (void)hipEventDestroy(e0); return hip_fail(e, "hipEventCreate"); }
+  osog_status out = OSOG_OK;
+  for (int ti = 0; ti < 3 && out == OSOG_OK; ++ti) {
+    if (height % cand_t[ti][0] || width % cand_t[ti][1]) continue;
+    for (int ri = 0; ri < 2 && out == OSOG_OK; ++ri) {
+      ctx->size_tiling[key] = {cand_t[ti][0], cand_t[ti][1]};
+      ctx->size_radix[key] = cand_r[ri];
+      out = osog_render(ctx, stream, height, width, soa, n, ld, optics, globals, nullptr, intensity_out,
+                        workspace, workspace_bytes);
+      if (out != OSOG_OK) break;
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < reps && out == OSOG_OK; ++r)
+        out = osog_render(ctx, stream, height, width, soa, n, ld, optics, globals, nullptr, intensity_out,
+                          workspace, workspace_bytes);
+      (void)hipEventRecord(e1, s);
+      if ((e = hipEventSynchronize(e1)) != hipSuccess) { out = hip_fail(e, "autotune timing"); break; }
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      ms /= (float)reps;
+      if (ms < best) { best = ms; bt = ti; br = ri; }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (out != OSOG_OK || bt < 0) {
+    if (saved_t) ctx->size_tiling[key] = *saved_t; else ctx->size_tiling.erase(key);
+    if (saved_r) ctx->size_radix[key] = *saved_r; else ctx->size_radix.erase(key);
+    return out != OSOG_OK ? out : fail(OSOG_ERR_UNSUPPORTED, "no candidate tiling divides the canvas");
+  }
+  ctx->size_tiling[key] = {cand_t[bt][0], cand_t[bt][1]};
+  ctx->size_radix[key] = cand_r[br];
+  *tile_h = cand_t[bt][0];
+  *tile_w = cand_t[bt][1];
+  *fft_radix = cand_r[br];
+  if (best_ms) *best_ms = best;
   return OSOG_OK;
 }
 

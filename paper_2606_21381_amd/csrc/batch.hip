@@ -62,11 +62,17 @@ __device__ __forceinline__ int find_segment(const int* __restrict__ seg_start, i
   return lo;
 }
 
+template <int LOG, int MAXR>
+__device__ __forceinline__ void run_fft_plan(const FrameDev& F, int stage, int k, const float2* tw, char* lds) {
+  if (stage == ST_PASS1) pass1_body<LOG, MAXR>(F, k, tw, lds);
+  else if (stage == ST_PASS2) pass2_body<LOG, MAXR>(F, k, tw, lds);
+  else pass3_body<LOG, MAXR>(F, k, tw, lds);
+}
+
 template <int LOG>
 __device__ __forceinline__ void run_fft_stage(const FrameDev& F, int stage, int k, const float2* tw, char* lds) {
-  if (stage == ST_PASS1) pass1_body<LOG>(F, k, tw, lds);
-  else if (stage == ST_PASS2) pass2_body<LOG>(F, k, tw, lds);
-  else pass3_body<LOG>(F, k, tw, lds);
+  if (F.fft_radix == 4) run_fft_plan<LOG, 4>(F, stage, k, tw, lds);
+  else run_fft_plan<LOG, 8>(F, stage, k, tw, lds);
 }
 
 __device__ __forceinline__ void fft_stage(const FrameDev& F, int stage, int k, const float2* tw, char* lds) {
@@ -253,6 +259,7 @@ static void stage_counts(const FrameDev& F, int counts[ST_COUNT]) {
 FramePlan make_plan(const osog_context* ctx, int H, int W, int64_t n, int64_t ld, const osog_optics& o,
                     int64_t cap);
 void context_tiling(const osog_context* ctx, int H, int W, int* th, int* tw);
+int context_radix(const osog_context* ctx, int H, int W);
 const float2* context_twiddle(const osog_context* ctx);
 int context_device(const osog_context* ctx);
 BatchCache* context_batch(osog_context* ctx);
@@ -265,6 +272,7 @@ static std::vector<FramePlan> batch_plans(const osog_context* ctx, const osog_fr
     context_tiling(ctx, fr.height, fr.width, &th, &tw);
     FramePlan p = make_plan(ctx, fr.height, fr.width, fr.n, fr.ld, fr.optics, 0);
     p.tile_h = th; p.tile_w = tw;
+    p.fft_radix = context_radix(ctx, fr.height, fr.width);
     p.ntx = fr.width / tw; p.nty = fr.height / th; p.n_tiles = p.ntx * p.nty;
     int kb = 0;
     while ((1 << kb) < p.n_tiles) ++kb;
@@ -310,7 +318,7 @@ hipError_t batch_render(osog_context* ctx, hipStream_t stream, const osog_frame*
     fd[f] = F;
     stage_counts(F, counts[f].data());
     sig += "|" + std::to_string(p.H) + "," + std::to_string(p.W) + "," + std::to_string(p.n) + "," +
-           std::to_string(p.tile_h) + "," + std::to_string(p.kx_lo) + "," + std::to_string(p.kx_n) + "," +
+           std::to_string(p.tile_h) + "," + std::to_string(p.fft_radix) + "," + std::to_string(p.kx_lo) + "," + std::to_string(p.kx_n) + "," +
            std::to_string(counts[f][ST_NOISE] > 0);
   }
   int nseg = 0, total = 0;

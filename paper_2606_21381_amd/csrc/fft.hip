@@ -21,23 +21,23 @@
 
 namespace osog {
 
-template <int LOGW>
+template <int LOGW, int MAXR>
 __global__ void __launch_bounds__(kThreads) k_pass1(FrameDev F, const float2* __restrict__ tw) {
   __shared__ __align__(16) char lds[rows_per_block(1 << LOGW) * (1 << LOGW) * sizeof(float2)];
-  pass1_body<LOGW>(F, blockIdx.x, tw, lds);
+  pass1_body<LOGW, MAXR>(F, blockIdx.x, tw, lds);
 }
 
-template <int LOGH>
+template <int LOGH, int MAXR>
 __global__ void __launch_bounds__(kThreads) k_pass2(FrameDev F, const float2* __restrict__ tw) {
   __shared__ __align__(16) char lds[(1 << LOGH) * sizeof(float2) + kThreads * sizeof(double) + 16];
-  pass2_body<LOGH>(F, blockIdx.x, tw, lds);
+  pass2_body<LOGH, MAXR>(F, blockIdx.x, tw, lds);
 }
 
-template <int LOGW>
+template <int LOGW, int MAXR>
 __global__ void __launch_bounds__(kThreads) k_pass3(FrameDev F, const float2* __restrict__ tw) {
   __shared__ __align__(16) char lds[rows_per_block(1 << LOGW) * (1 << LOGW) * sizeof(float2) +
                                     kThreads * sizeof(double)];
-  pass3_body<LOGW>(F, blockIdx.x, tw, lds);
+  pass3_body<LOGW, MAXR>(F, blockIdx.x, tw, lds);
 }
 
 // Shot noise in place, one pixel pair per thread (its own kernel so the sampler
@@ -67,7 +67,9 @@ hipError_t launch_pass1(const FramePlan& p, const float* opd, FrameBufs& b, cons
   FrameDev F = make_dev(p, b);
   F.opd = const_cast<float*>(opd);
   const int rbn = p.H / p.rb;
-#define L1(LG) hipLaunchKernelGGL(k_pass1<LG>, dim3(rbn), dim3(kThreads), 0, s, F, tw)
+#define L1(LG)                                                                              \
+  if (p.fft_radix == 4) hipLaunchKernelGGL((k_pass1<LG, 4>), dim3(rbn), dim3(kThreads), 0, s, F, tw); \
+  else hipLaunchKernelGGL((k_pass1<LG, 8>), dim3(rbn), dim3(kThreads), 0, s, F, tw)
   OSOG_SIZE_SWITCH(p.logW, L1)
 #undef L1
   return hipGetLastError();
@@ -77,7 +79,9 @@ hipError_t launch_pass2(const FramePlan& p, const float* globals, FrameBufs& b, 
                         hipStream_t s) {
   FrameDev F = make_dev(p, b);
   F.globals = globals;
-#define L2(LG) hipLaunchKernelGGL(k_pass2<LG>, dim3(p.kx_n), dim3(kThreads), 0, s, F, tw)
+#define L2(LG)                                                                                  \
+  if (p.fft_radix == 4) hipLaunchKernelGGL((k_pass2<LG, 4>), dim3(p.kx_n), dim3(kThreads), 0, s, F, tw); \
+  else hipLaunchKernelGGL((k_pass2<LG, 8>), dim3(p.kx_n), dim3(kThreads), 0, s, F, tw)
   OSOG_SIZE_SWITCH(p.logH, L2)
 #undef L2
   return hipGetLastError();
@@ -88,7 +92,9 @@ hipError_t launch_pass3(const FramePlan& p, FrameBufs& b, const float2* tw, floa
   FrameDev F = make_dev(p, b);
   F.intensity = intensity;
   const int rbn = p.H / p.rb;
-#define L3(LG) hipLaunchKernelGGL(k_pass3<LG>, dim3(rbn), dim3(kThreads), 0, s, F, tw)
+#define L3(LG)                                                                              \
+  if (p.fft_radix == 4) hipLaunchKernelGGL((k_pass3<LG, 4>), dim3(rbn), dim3(kThreads), 0, s, F, tw); \
+  else hipLaunchKernelGGL((k_pass3<LG, 8>), dim3(rbn), dim3(kThreads), 0, s, F, tw)
   OSOG_SIZE_SWITCH(p.logW, L3)
 #undef L3
   if (p.photons > 0.0f && p.kx_n > 0) {

@@ -78,14 +78,15 @@ __device__ __forceinline__ void dft(float2* v) {
 
 // One Stockham autosort stage over ROWS rows of N points held in LDS, then the
 // remaining stages.  NS = product of the radices done so far, REM = log2 of the
-// part still to transform.  Butterfly j of radix R reads x[j + r N/R],
+// part still to transform, MAXR = the plan's largest radix (8: radix-8 stages
+// then one radix-4 or -2 stage; 4: radix-4 stages then one radix-2 stage).  Butterfly j of radix R reads x[j + r N/R],
 // twiddles by W^(r (j mod NS) N/(NS R)), and writes to (j/NS) NS R + (j mod NS) + r NS.
-template <int N, int ROWS, int DIR, int NS, int REM>
+template <int N, int ROWS, int DIR, int NS, int REM, int MAXR = 8>
 struct Stages {
   static __device__ __forceinline__ void run(float2* buf, const float2* __restrict__ tw) {
 #pragma clang fp contract(off)
-    constexpr int R = REM >= 3 ? 8 : (REM == 2 ? 4 : 2);
-    constexpr int LR = REM >= 3 ? 3 : REM;
+    constexpr int R = (REM >= 3 && MAXR == 8) ? 8 : (REM >= 2 ? 4 : 2);
+    constexpr int LR = R == 8 ? 3 : (R == 4 ? 2 : 1);
     constexpr int NB = N / R, TOT = ROWS * NB, BPT = (TOT + kThreads - 1) / kThreads;
     constexpr int TSTRIDE = kTwN / N;
     float2 v[BPT][R];
@@ -123,12 +124,12 @@ struct Stages {
       }
     }
     __syncthreads();
-    Stages<N, ROWS, DIR, NS * R, REM - LR>::run(buf, tw);
+    Stages<N, ROWS, DIR, NS * R, REM - LR, MAXR>::run(buf, tw);
   }
 };
 
-template <int N, int ROWS, int DIR, int NS>
-struct Stages<N, ROWS, DIR, NS, 0> {
+template <int N, int ROWS, int DIR, int NS, int MAXR>
+struct Stages<N, ROWS, DIR, NS, 0, MAXR> {
   static __device__ __forceinline__ void run(float2*, const float2* __restrict__) {}
 };
 

@@ -36,6 +36,7 @@ struct FramePlan {
   int key_bits;          // bits of the tile key (0 when one tile)
   int kx_lo, kx_n;       // in-band signed kx range [kx_lo, kx_lo + kx_n)
   int rb;                // rows per band block of the blocked spectrum layout
+  int fft_radix;         // FFT plan: largest Stockham radix (8 or 4)
   int64_t n, ld, cap;    // particles, leading dimension, pair capacity
   // optics in the precision the kernels use
   int mode;

@@ -23,6 +23,7 @@ constexpr int kStageLds = 8192 * 8 + kThreads * 8;
 struct FrameDev {
   int H, W, logH, logW, tile_h, tile_w, ntx, n_tiles;
   int d1, d2, nsl, nblk;          // radix digit widths, slice capacity, particle blocks
+  int fft_radix;                   // FFT plan: largest Stockham radix (8 or 4)
   int64_t n, ld, cap;
   OpticsArgs o;
   float phase_k;
@@ -359,7 +360,7 @@ __device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int lan
 }
 
 // ---- F6: pass 1, rows --------------------------------------------------------
-template <int LOGW>
+template <int LOGW, int MAXR>
 __device__ __forceinline__ void pass1_body(const FrameDev& F, int rb, const float2* __restrict__ tw, char* lds) {
 #pragma clang fp contract(off)
   constexpr int W = 1 << LOGW, RB = rows_per_block(W);
@@ -373,7 +374,7 @@ __device__ __forceinline__ void pass1_body(const FrameDev& F, int rb, const floa
     buf[idx] = make_float2(c, s);
   }
   __syncthreads();
-  Stages<W, RB, -1, 1, LOGW>::run(buf, tw);
+  Stages<W, RB, -1, 1, LOGW, MAXR>::run(buf, tw);
   const int kx_lo = F.o.kx_lo, kx_n = F.o.kx_n;
   float2* dst = F.band + (size_t)rb * kx_n * RB;
   for (int idx = t; idx < kx_n * RB; idx += kThreads) {
@@ -384,7 +385,7 @@ __device__ __forceinline__ void pass1_body(const FrameDev& F, int rb, const floa
 }
 
 // ---- F7: pass 2, one in-band column ------------------------------------------
-template <int LOGH>
+template <int LOGH, int MAXR>
 __device__ __forceinline__ void pass2_body(const FrameDev& F, int b, const float2* __restrict__ tw, char* lds) {
 #pragma clang fp contract(off)
   constexpr int H = 1 << LOGH;
@@ -398,7 +399,7 @@ __device__ __forceinline__ void pass2_body(const FrameDev& F, int b, const float
   for (int i = t; i < H; i += kThreads) buf[i] = band[((size_t)(i / RB) * o.kx_n + b) * RB + (i % RB)];
   if (t == 0) band_chord(o, kx, &chord[0], &chord[1]);
   __syncthreads();
-  Stages<H, 1, -1, 1, LOGH>::run(buf, tw);
+  Stages<H, 1, -1, 1, LOGH, MAXR>::run(buf, tw);
   const float dz = F.globals[0], shear = F.globals[1], bias = F.globals[2];
   const int lo = chord[0], hi = chord[1];
   double part = 0.0;
@@ -418,7 +419,7 @@ __device__ __forceinline__ void pass2_body(const FrameDev& F, int b, const float
     __syncthreads();
   }
   if (t == 0) F.colsum[b] = red[0];
-  Stages<H, 1, 1, 1, LOGH>::run(buf, tw);
+  Stages<H, 1, 1, 1, LOGH, MAXR>::run(buf, tw);
   for (int i = t; i < H; i += kThreads) band[((size_t)(i / RB) * o.kx_n + b) * RB + (i % RB)] = buf[i];
   __syncthreads();
 }
@@ -426,7 +427,7 @@ __device__ __forceinline__ void pass2_body(const FrameDev& F, int b, const float
 // ---- F8: pass 3, rows: inverse FFT from the band, |E|^2 ------------------------
 // Block 0 also forms the photon scale s = photons / mean(I) from the per-column
 // Parseval sums (fixed summation order) for the noise stage.
-template <int LOGW>
+template <int LOGW, int MAXR>
 __device__ __forceinline__ void pass3_body(const FrameDev& F, int rb, const float2* __restrict__ tw, char* lds) {
 #pragma clang fp contract(off)
   constexpr int W = 1 << LOGW, RB = rows_per_block(W);
@@ -459,7 +460,7 @@ __device__ __forceinline__ void pass3_body(const FrameDev& F, int rb, const floa
       reinterpret_cast<float*>(F.scal)[2] = mean > 0.0 ? (float)((double)o.photons / mean) : 0.0f;
     }
   }
-  Stages<W, RB, 1, 1, LOGW>::run(buf, tw);
+  Stages<W, RB, 1, 1, LOGW, MAXR>::run(buf, tw);
   const float inv = o.inv_hw;
   float* dst = F.intensity + (size_t)rb * RB * W;
   for (int idx = t; idx < RB * W; idx += kThreads) {
@@ -512,6 +513,7 @@ inline FrameDev make_dev(const FramePlan& p, const FrameBufs& b) {
   // two passes end in a (a -> b -> a), one pass in b, none (one tile) in a
   F.sorted_vals = (F.d1 > 0 && F.d2 == 0) ? b.vals_b : b.vals_a;
   F.band = b.band; F.colsum = b.colsum;
+  F.fft_radix = p.fft_radix;
   F.opd = b.opd;
   return F;
 }

@@ -228,3 +228,26 @@ def test_noise_statistics_and_oracle_counts():
     same = np.mean(np.round(Ig * s) == np.round(ref * s))
     say("noise: counts identical to the oracle's on %.4f of pixels" % same)
     assert same > 0.98
+
+
+def test_radix4_plan_and_autotuner():
+    r = R()
+    from paper_2606_21381_amd import autotune, render
+    fr = mid_frame(12, 512, 2000, workloads.DIC)
+    soa, g = dev_soa(fr.soa), dev_globals(fr.globals4)
+    ropd, rI = oracle_frame(fr)
+    lib = render._lib.load()
+    render._lib.check(lib.osog_set_size_radix(render.context(), 512, 512, 4), "radix")
+    I4 = render.render(soa, 512, 512, fr.optics, g)
+    torch.cuda.synchronize()
+    e4 = rel_l2(I4.cpu().numpy(), rI)
+    choice = autotune.tune_frame(soa, 512, 512, fr.optics, g, reps=2)
+    I = render.render(soa, 512, 512, fr.optics, g)
+    torch.cuda.synchronize()
+    e = rel_l2(I.cpu().numpy(), rI)
+    say("radix-4 plan rel L2 %.2e; autotuner chose %s, rel L2 %.2e" % (e4, choice, e))
+    assert e4 <= I_TOL and e <= I_TOL
+    assert (choice["tile_h"], choice["tile_w"]) in [(16, 16), (8, 32), (32, 8)] and choice["fft_radix"] in (4, 8)
+    # back to the defaults for the other tests
+    render._lib.check(lib.osog_set_size_tiling(render.context(), 512, 512, 16, 16), "tiling")
+    render._lib.check(lib.osog_set_size_radix(render.context(), 512, 512, 8), "radix")
