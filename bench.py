@@ -82,6 +82,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-extras", action="store_true", help="skip the backward, batch and inverse-solve legs")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the timed run, one plain device-to-device copy of this many MiB "
+                         "(reference dispatch for hardware byte counters)")
     ap.add_argument("--learned", action="store_true",
                     help="also train the learned initializer (200,000 rendered crops) and compare inverse solves")
     args = ap.parse_args()
@@ -170,6 +173,14 @@ def main():
         res["backward"] = bench_backward(render, soa, g, fr, dev)
         res["batch"] = bench_batch(render, dev)
         res["inverse"] = bench_inverse(dev, learned=args.learned)
+    if args.calib_copy_mib > 0:
+        nb = args.calib_copy_mib << 20
+        src = torch.ones(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        res["calib_copy_bytes"] = nb
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(fr)
     print(json.dumps(res), flush=True)

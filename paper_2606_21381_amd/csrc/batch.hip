@@ -8,8 +8,10 @@
 // one atomic.  Before running item (f, s, k), a workgroup waits until every
 // item of the frame's previous non-empty stage has finished; an item only ever
 // waits for items earlier in the queue, which running workgroups already hold,
-// so the queue always drains.  The wait is bounded: past its spin limit a
-// workgroup records an error flag and proceeds, so no wave can wait forever.
+// so the queue always drains.  Waits are bounded in time on the device's
+// constant-rate clock, and so is a workgroup's working life: past either limit
+// the workgroup raises an error flag, after which every workgroup only drains
+// the queue (pops items without waiting or working), so the launch always ends.
 // Producers publish with a release fence before bumping a stage's completion
 // counter; consumers acquire after observing it.
 //
@@ -32,11 +34,11 @@ namespace osog {
 
 enum Stage {
   ST_PREPARE = 0, ST_EMIT, ST_OFF0, ST_SCAT0, ST_OFF1, ST_SCAT1, ST_RASTER, ST_PASS1, ST_PASS2,
-  ST_PASS3, ST_NOISE, ST_COUNT
+  ST_PASS3, ST_COUNT
 };
 constexpr int kScatterItems = 64;     // workgroup items per scatter stage (each loops over slices)
-constexpr int kNoisePairsPerItem = kThreads * 16;
-constexpr int kSpinLimit = 1 << 21;   // ~0.1-0.2 s of polling before the error path
+constexpr double kWaitSeconds = 1.0;  // one dependency wait, then the error path
+constexpr double kLifeSeconds = 4.0;  // a workgroup's working life, then the error path
 
 struct Segment {
   int frame, stage, count;
@@ -48,6 +50,8 @@ struct Segment {
 struct BatchHeader {
   unsigned long long* frame_done;  // caller's timestamps (or null)
   double ns_per_tick;
+  unsigned long long wait_ticks;   // longest wait for one dependency (device clock ticks)
+  unsigned long long life_ticks;   // longest a workgroup keeps doing work after it starts
   int n_frames, nseg, total;
   int pad;
 };
@@ -101,34 +105,45 @@ __global__ void __launch_bounds__(kThreads) k_batch(const BatchHeader* __restric
                                                     int* __restrict__ done,
                                                     const float2* __restrict__ tw) {
   __shared__ __align__(16) char lds[kStageLds];
-  __shared__ int s_item, s_seg;
+  __shared__ int s_item, s_seg, s_skip;
   const int t = threadIdx.x;
   const int total = hdr->total, nseg = hdr->nseg;
+  const unsigned long long born = wall_clock64();
   for (;;) {
     if (t == 0) {
       const int item = atomicAdd(&ctl[0], 1);
       s_item = item;
+      s_skip = 0;
       if (item < total) {
         const int sg = find_segment(seg_start, nseg, item);
         s_seg = sg;
         if (item == 0 && hdr->frame_done)
           hdr->frame_done[hdr->n_frames] = (unsigned long long)((double)wall_clock64() * hdr->ns_per_tick);
-        // wait for every item of the frame's previous non-empty stage (bounded)
+        // After any error (here or in another workgroup) or past this workgroup's
+        // working life, items are only drained: no wait, no work.
+        bool bad = __hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                   wall_clock64() - born > hdr->life_ticks;
+        // Wait for every item of the frame's previous non-empty stage.  The poll is
+        // relaxed (no cache invalidation per iteration, which would stall the L2 of
+        // this die for the producers); one acquire fence follows.  Bounded in time.
         const int dep = segs[sg].dep;
-        if (dep >= 0) {
+        if (!bad && dep >= 0) {
           const int need = segs[sg].dep_need;
-          int spins = 0;
-          while (__hip_atomic_load(&done[dep], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
-            __builtin_amdgcn_s_sleep(2);
-            // give up past the limit, or at once after any other workgroup gave up
-            if (++spins > kSpinLimit ||
-                __hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-              atomicOr(&ctl[1], 1);
+          const unsigned long long w0 = wall_clock64();
+          while (__hip_atomic_load(&done[dep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+            __builtin_amdgcn_s_sleep(8);
+            if (__hip_atomic_load(&ctl[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                wall_clock64() - w0 > hdr->wait_ticks) {
+              bad = true;
               break;
             }
           }
-          __threadfence();
         }
+        if (bad) {
+          atomicOr(&ctl[1], 1);
+          s_skip = 1;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
     }
     __syncthreads();
@@ -137,7 +152,7 @@ __global__ void __launch_bounds__(kThreads) k_batch(const BatchHeader* __restric
     const Segment sg = segs[s_seg];
     const int k = item - seg_start[s_seg];
     const FrameDev& F = frames[sg.frame];
-    switch (sg.stage) {
+    switch (s_skip ? -1 : sg.stage) {
       case ST_PREPARE: prepare_body(F, k, max(1, F.nblk), lds); break;
       case ST_EMIT: emit_body(F, k, lds); break;
       case ST_OFF0: digit_offsets_body(F, 0, k, lds); break;
@@ -157,12 +172,6 @@ __global__ void __launch_bounds__(kThreads) k_batch(const BatchHeader* __restric
       case ST_PASS1:
       case ST_PASS2:
       case ST_PASS3: fft_stage(F, sg.stage, k, tw, lds); break;
-      case ST_NOISE: {
-        const int64_t npairs = (int64_t)F.H * F.W / 2;
-        const int64_t m0 = (int64_t)k * kNoisePairsPerItem;
-        for (int64_t m = m0 + t; m < min(npairs, m0 + kNoisePairsPerItem); m += kThreads) noise_pairs(F, m);
-        break;
-      }
       default: break;
     }
     __syncthreads();
@@ -251,9 +260,6 @@ static void stage_counts(const FrameDev& F, int counts[ST_COUNT]) {
   counts[ST_PASS1] = F.H / F.o.rb;
   counts[ST_PASS2] = F.o.kx_n;
   counts[ST_PASS3] = F.H / F.o.rb;
-  const int64_t npairs = (int64_t)F.H * F.W / 2;
-  counts[ST_NOISE] = (F.o.photons > 0.0f && F.o.kx_n > 0)
-                         ? (int)((npairs + kNoisePairsPerItem - 1) / kNoisePairsPerItem) : 0;
 }
 
 FramePlan make_plan(const osog_context* ctx, int H, int W, int64_t n, int64_t ld, const osog_optics& o,
@@ -318,8 +324,7 @@ hipError_t batch_render(osog_context* ctx, hipStream_t stream, const osog_frame*
     fd[f] = F;
     stage_counts(F, counts[f].data());
     sig += "|" + std::to_string(p.H) + "," + std::to_string(p.W) + "," + std::to_string(p.n) + "," +
-           std::to_string(p.tile_h) + "," + std::to_string(p.fft_radix) + "," + std::to_string(p.kx_lo) + "," + std::to_string(p.kx_n) + "," +
-           std::to_string(counts[f][ST_NOISE] > 0);
+           std::to_string(p.tile_h) + "," + std::to_string(p.fft_radix) + "," + std::to_string(p.kx_lo) + "," + std::to_string(p.kx_n);
   }
   int nseg = 0, total = 0;
   std::vector<int> last_stage(nf, -1);
@@ -347,6 +352,9 @@ hipError_t batch_render(osog_context* ctx, hipStream_t stream, const osog_frame*
   (void)hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, context_device(ctx));
   hdr->frame_done = reinterpret_cast<unsigned long long*>(frame_done_ns);
   hdr->ns_per_tick = rate_khz > 0 ? 1.0e6 / (double)rate_khz : 10.0;
+  const double ticks_per_s = rate_khz > 0 ? 1.0e3 * (double)rate_khz : 1.0e8;
+  hdr->wait_ticks = (unsigned long long)(kWaitSeconds * ticks_per_s);
+  hdr->life_ticks = (unsigned long long)(kLifeSeconds * ticks_per_s);
   hdr->n_frames = nf;
   hdr->nseg = nseg;
   hdr->total = total;

@@ -8,7 +8,8 @@
 //                    oblique shift P(f + f_t)), sum |U~ H|^2 per column (Parseval:
 //                    gives the image mean for the noise scale), inverse FFT along y
 //   pass 3 (rows)    inverse FFT along x from the in-band columns, I = |E|^2,
-//                    optional Poisson shot noise (Sec. III.C, last paragraph)
+//                    optional Poisson shot noise (Sec. III.C, last paragraph),
+//                    sampled in place on the rows the workgroup holds
 //
 // Transforms are radix-8 Stockham stages (radix 4 or 2 last) on data held in
 // LDS, one butterfly group per thread and a barrier between stages; twiddles
@@ -35,17 +36,8 @@ __global__ void __launch_bounds__(kThreads) k_pass2(FrameDev F, const float2* __
 
 template <int LOGW, int MAXR>
 __global__ void __launch_bounds__(kThreads) k_pass3(FrameDev F, const float2* __restrict__ tw) {
-  __shared__ __align__(16) char lds[rows_per_block(1 << LOGW) * (1 << LOGW) * sizeof(float2) +
-                                    kThreads * sizeof(double)];
+  __shared__ __align__(16) char lds[pass3_buf_bytes(1 << LOGW) + kThreads * sizeof(double)];
   pass3_body<LOGW, MAXR>(F, blockIdx.x, tw, lds);
-}
-
-// Shot noise in place, one pixel pair per thread (its own kernel so the sampler
-// runs at full occupancy, not under pass 3's LDS budget).
-__global__ void __launch_bounds__(kThreads) k_noise(FrameDev F) {
-  const int64_t m = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (2 * m >= (int64_t)F.H * F.W) return;
-  noise_pairs(F, m);
 }
 
 // ------------------------------------------------------------ dispatch -------
@@ -97,10 +89,6 @@ hipError_t launch_pass3(const FramePlan& p, FrameBufs& b, const float2* tw, floa
   else hipLaunchKernelGGL((k_pass3<LG, 8>), dim3(rbn), dim3(kThreads), 0, s, F, tw)
   OSOG_SIZE_SWITCH(p.logW, L3)
 #undef L3
-  if (p.photons > 0.0f && p.kx_n > 0) {
-    const int64_t npairs = (int64_t)p.H * p.W / 2;
-    hipLaunchKernelGGL(k_noise, dim3((unsigned)((npairs + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, F);
-  }
   return hipGetLastError();
 }
 

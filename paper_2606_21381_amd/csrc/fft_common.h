@@ -245,53 +245,85 @@ __device__ __forceinline__ float log_factorial(float k) {
   return (x - 0.5f) * logf(x) - x + 0.918938533f + 1.0f / (12.0f * x) - 1.0f / (360.0f * x * x * x);
 }
 
-// One PTRS attempt from two words; returns k >= 0 when accepted, -1 when rejected.
-__device__ __forceinline__ int ptrs_attempt(uint32_t wu, uint32_t wv, float mu, float log_mu, float a,
-                                            float b, float inv_alpha, float vr) {
+// PTRS constants for one mean (mu >= 10).
+struct PtrsConst {
+  float log_mu, a, b, inv_alpha, vr;
+};
+
+__device__ __forceinline__ PtrsConst ptrs_const(float mu) {
+#pragma clang fp contract(off)
+  PtrsConst c;
+  const float smu = sqrtf(mu);
+  c.log_mu = logf(mu);
+  c.b = 0.931f + 2.53f * smu;
+  c.a = -0.059f + 0.02483f * c.b;
+  c.inv_alpha = 1.1239f + 1.1328f / (c.b - 3.4f);
+  c.vr = 0.9277f - 3.6224f / (c.b - 2.0f);
+  return c;
+}
+
+// The cheap part of a PTRS attempt: the candidate k and whether the squeeze
+// accepts it without the log test.
+__device__ __forceinline__ bool ptrs_quick(uint32_t wu, uint32_t wv, float mu, float a, float b, float vr,
+                                           float* U_out, float* V_out, float* us_out, float* kf_out) {
 #pragma clang fp contract(off)
   const float U = u01(wu) - 0.5f;
   const float V = u01(wv);
   const float us = 0.5f - fabsf(U);
   const float kf = floorf((((2.0f * a) / us) + b) * U + (mu + 0.43f));
-  if (us >= 0.07f && V <= vr) return (int)kf;
+  *U_out = U; *V_out = V; *us_out = us; *kf_out = kf;
+  return us >= 0.07f && V <= vr;
+}
+
+// One PTRS attempt from two words; returns k >= 0 when accepted, -1 when rejected.
+__device__ __forceinline__ int ptrs_attempt(uint32_t wu, uint32_t wv, float mu, const PtrsConst& c) {
+#pragma clang fp contract(off)
+  float U, V, us, kf;
+  if (ptrs_quick(wu, wv, mu, c.a, c.b, c.vr, &U, &V, &us, &kf)) return (int)kf;
   if (kf < 0.0f || (us < 0.013f && V > us)) return -1;
-  const float lhs = logf(V * inv_alpha / (a / (us * us) + b));
-  const float rhs = (-mu + kf * log_mu) - log_factorial(kf);
+  const float lhs = logf(V * c.inv_alpha / (c.a / (us * us) + c.b));
+  const float rhs = (-mu + kf * c.log_mu) - log_factorial(kf);
   return lhs <= rhs ? (int)kf : -1;
+}
+
+// Inversion by sequential search for mu < 10 (at most 40 steps) on one word.
+__device__ __forceinline__ int poisson_small(float mu, uint32_t w0) {
+#pragma clang fp contract(off)
+  const float u = u01(w0);
+  float p = expf(-mu);
+  float F = p;
+  int k = 0;
+  while (u > F && k < 40) {
+    ++k;
+    p = p * (mu / (float)k);
+    F = F + p;
+  }
+  return k;
+}
+
+// PTRS for mu >= 10 from the pixel's two shared words, then up to 15 own blocks.
+__device__ __forceinline__ int poisson_large(float mu, uint32_t w0, uint32_t w1, uint32_t pixel, uint32_t frame,
+                                             uint32_t k0, uint32_t k1) {
+#pragma clang fp contract(off)
+  const PtrsConst c = ptrs_const(mu);
+  int k = ptrs_attempt(w0, w1, mu, c);
+  if (k >= 0) return k;
+  for (uint32_t rnd = 1; rnd < 16; ++rnd) {
+    const uint4 r = philox4x32_10(make_uint4(pixel, frame, rnd, 1u), k0, k1);
+    k = ptrs_attempt(r.x, r.y, mu, c);
+    if (k >= 0) return k;
+    k = ptrs_attempt(r.z, r.w, mu, c);
+    if (k >= 0) return k;
+  }
+  return (int)floorf(mu);
 }
 
 // Poisson(mu) for one pixel; (w0, w1) are its two words of the shared block.
 __device__ __forceinline__ int poisson(float mu, uint32_t w0, uint32_t w1, uint32_t pixel,
                                        uint32_t frame, uint32_t k0, uint32_t k1) {
-#pragma clang fp contract(off)
   if (!(mu > 0.0f)) return 0;
-  if (mu < 10.0f) {
-    const float u = u01(w0);
-    float p = expf(-mu);
-    float F = p;
-    int k = 0;
-    while (u > F && k < 40) {
-      ++k;
-      p = p * (mu / (float)k);
-      F = F + p;
-    }
-    return k;
-  }
-  const float smu = sqrtf(mu), log_mu = logf(mu);
-  const float b = 0.931f + 2.53f * smu;
-  const float a = -0.059f + 0.02483f * b;
-  const float inv_alpha = 1.1239f + 1.1328f / (b - 3.4f);
-  const float vr = 0.9277f - 3.6224f / (b - 2.0f);
-  int k = ptrs_attempt(w0, w1, mu, log_mu, a, b, inv_alpha, vr);
-  if (k >= 0) return k;
-  for (uint32_t rnd = 1; rnd < 16; ++rnd) {
-    const uint4 r = philox4x32_10(make_uint4(pixel, frame, rnd, 1u), k0, k1);
-    k = ptrs_attempt(r.x, r.y, mu, log_mu, a, b, inv_alpha, vr);
-    if (k >= 0) return k;
-    k = ptrs_attempt(r.z, r.w, mu, log_mu, a, b, inv_alpha, vr);
-    if (k >= 0) return k;
-  }
-  return (int)floorf(mu);
+  if (mu < 10.0f) return poisson_small(mu, w0);
+  return poisson_large(mu, w0, w1, pixel, frame, k0, k1);
 }
 
 }  // namespace osog

@@ -17,7 +17,7 @@ namespace osog {
 
 // LDS one stage body may use: the largest is pass 3 at RB * W = 8192 points
 // plus a 256-entry double reduction array.
-constexpr int kStageLds = 8192 * 8 + kThreads * 8;
+constexpr int kStageLds = 8192 * 8 + kThreads * 8;  // >= pass3_buf_bytes(W) + kThreads * 8 for every W
 
 // Everything a stage needs to know about one frame, in device-readable form.
 struct FrameDev {
@@ -424,15 +424,113 @@ __device__ __forceinline__ void pass2_body(const FrameDev& F, int b, const float
   __syncthreads();
 }
 
-// ---- F8: pass 3, rows: inverse FFT from the band, |E|^2 ------------------------
-// Block 0 also forms the photon scale s = photons / mean(I) from the per-column
-// Parseval sums (fixed summation order) for the noise stage.
+// ---- F8: pass 3, rows: inverse FFT from the band, |E|^2, shot noise ------------
+// With noise, every workgroup forms the photon scale s = photons / mean(I) from
+// the per-column Parseval sums of pass 2 (the same fixed summation order in every
+// workgroup, so all agree bit for bit) and samples its rows' counts in place:
+// I <- Poisson(s I) / s.  Pixels 2m, 2m+1 share the Philox block (m, frame, 0, 0).
+//
+// Sampling is split so that the costly branch runs on compacted work: every lane
+// first draws its pixels' shared blocks and applies the PTRS squeeze (or the
+// inversion for means below 10); pixels the squeeze does not settle go, with
+// their two words, to a per-wave queue in LDS, which the wave then drains with
+// all lanes busy (full PTRS attempt, then own blocks).  Each pixel's arithmetic
+// is exactly that of poisson().
+constexpr int kNoiseChunk = 4;                                   // pairs per lane per round
+constexpr int kNoiseQueueBytes = kThreads * 2 * kNoiseChunk * 16;  // uint4 entries, 32 KB
+
+__host__ __device__ constexpr int pass3_buf_bytes(int W) {
+  return rows_per_block(W) * W * 8 > kNoiseQueueBytes ? rows_per_block(W) * W * 8 : kNoiseQueueBytes;
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int u = __shfl_up(v, d, 64);
+    if (lane >= d) v += u;
+  }
+  return v;
+}
+
+template <int NP>
+__device__ __forceinline__ void noise_rows(const FrameDev& F, float scale, int64_t pix0, const float* Ipix,
+                                           float* dst, char* lds) {
+#pragma clang fp contract(off)
+  constexpr int PP = (NP + kThreads - 1) / kThreads;  // pairs per thread
+  constexpr int CH = PP < kNoiseChunk ? PP : kNoiseChunk;
+  const OpticsArgs& o = F.o;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  uint4* queue = reinterpret_cast<uint4*>(lds) + wave * (64 * 2 * CH);
+  float2* out = reinterpret_cast<float2*>(dst);
+  for (int k0 = 0; k0 < PP; k0 += CH) {
+    float res[2 * CH];
+    uint4 ent[2 * CH];
+    unsigned pend = 0u;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int ml = t + kThreads * (k0 + c);
+      res[2 * c] = 0.0f;
+      res[2 * c + 1] = 0.0f;
+      if (ml >= NP) continue;
+      const int64_t p = pix0 + 2 * ml;
+      const uint32_t m = (uint32_t)(p >> 1);
+      const uint4 r = philox4x32_10(make_uint4(m, o.frame, 0u, 0u), o.seed_lo, o.seed_hi);
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const float mu = scale * Ipix[2 * (k0 + c) + x];
+        const uint32_t w0 = x ? r.z : r.x, w1 = x ? r.w : r.y;
+        if (!(mu > 0.0f)) {
+          res[2 * c + x] = 0.0f;
+        } else if (mu < 10.0f) {
+          res[2 * c + x] = (float)poisson_small(mu, w0);
+        } else {
+          const PtrsConst pc = ptrs_const(mu);
+          float U, V, us, kf;
+          if (ptrs_quick(w0, w1, mu, pc.a, pc.b, pc.vr, &U, &V, &us, &kf)) {
+            res[2 * c + x] = (float)(int)kf;
+          } else {
+            pend |= 1u << (2 * c + x);
+            ent[2 * c + x] = make_uint4((uint32_t)(p + x), __float_as_uint(mu), w0, w1);
+          }
+        }
+      }
+    }
+    // compact the unsettled pixels into the wave's queue
+    const int cnt = __popc(pend);
+    const int incl = wave_incl_scan(cnt, lane);
+    const int total = __shfl(incl, 63, 64);
+    int pos = incl - cnt;
+#pragma unroll
+    for (int e = 0; e < 2 * CH; ++e)
+      if (pend & (1u << e)) queue[pos++] = ent[e];
+    __syncthreads();
+    for (int q = lane; q < total; q += 64) {
+      const uint4 en = queue[q];
+      const int k = poisson_large(__uint_as_float(en.y), en.z, en.w, en.x, o.frame, o.seed_lo, o.seed_hi);
+      queue[q].y = (uint32_t)k;
+    }
+    __syncthreads();
+    pos = incl - cnt;
+#pragma unroll
+    for (int e = 0; e < 2 * CH; ++e)
+      if (pend & (1u << e)) res[e] = (float)(int)queue[pos++].y;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const int ml = t + kThreads * (k0 + c);
+      if (ml < NP) out[ml] = make_float2(res[2 * c] / scale, res[2 * c + 1] / scale);
+    }
+    __syncthreads();  // the queue is reused by the next round
+  }
+}
+
 template <int LOGW, int MAXR>
 __device__ __forceinline__ void pass3_body(const FrameDev& F, int rb, const float2* __restrict__ tw, char* lds) {
 #pragma clang fp contract(off)
-  constexpr int W = 1 << LOGW, RB = rows_per_block(W);
+  constexpr int W = 1 << LOGW, RB = rows_per_block(W), NP = RB * W / 2;
+  constexpr int PP = (NP + kThreads - 1) / kThreads;
   float2* buf = reinterpret_cast<float2*>(lds);
-  double* red = reinterpret_cast<double*>(lds + RB * W * sizeof(float2));
+  double* red = reinterpret_cast<double*>(lds + pass3_buf_bytes(W));
   const OpticsArgs& o = F.o;
   const int t = threadIdx.x;
   for (int idx = t; idx < RB * W; idx += kThreads) buf[idx] = make_float2(0.0f, 0.0f);
@@ -442,50 +540,53 @@ __device__ __forceinline__ void pass3_body(const FrameDev& F, int rb, const floa
     const int b = idx / RB, r = idx - b * RB;
     buf[r * W + ((o.kx_lo + b) & (W - 1))] = src[idx];
   }
-  const bool scale_block = o.photons > 0.0f && rb == 0;
-  if (scale_block) {
+  const bool noise = o.photons > 0.0f;
+  if (noise) {
     double s = 0.0;
     for (int b = t; b < o.kx_n; b += kThreads) s += F.colsum[b];
     red[t] = s;
   }
   __syncthreads();
-  if (scale_block) {
+  float scale = 0.0f;
+  if (noise) {
     for (int s = kThreads / 2; s > 0; s >>= 1) {
       if (t < s) red[t] += red[t + s];
       __syncthreads();
     }
-    if (t == 0) {
-      const double hw = (double)o.H * (double)W;
-      const double mean = red[0] / (hw * hw);
-      reinterpret_cast<float*>(F.scal)[2] = mean > 0.0 ? (float)((double)o.photons / mean) : 0.0f;
-    }
+    const double hw = (double)o.H * (double)W;
+    const double mean = red[0] / (hw * hw);
+    scale = mean > 0.0 ? (float)((double)o.photons / mean) : 0.0f;
   }
   Stages<W, RB, 1, 1, LOGW, MAXR>::run(buf, tw);
   const float inv = o.inv_hw;
   float* dst = F.intensity + (size_t)rb * RB * W;
-  for (int idx = t; idx < RB * W; idx += kThreads) {
-    const float2 e = buf[idx];
-    const float er = e.x * inv, ei = e.y * inv;
-    dst[idx] = er * er + ei * ei;
+  if (!(scale > 0.0f)) {
+    for (int idx = t; idx < RB * W; idx += kThreads) {
+      const float2 e = buf[idx];
+      const float er = e.x * inv, ei = e.y * inv;
+      dst[idx] = er * er + ei * ei;
+    }
+    __syncthreads();
+    return;
+  }
+  // intensities of this thread's pixel pairs (ml = t + 256 k), then the LDS is free
+  float Ipix[2 * PP];
+#pragma unroll
+  for (int k = 0; k < PP; ++k) {
+    const int ml = t + kThreads * k;
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+      float v = 0.0f;
+      if (ml < NP) {
+        const float2 e = buf[2 * ml + x];
+        const float er = e.x * inv, ei = e.y * inv;
+        v = er * er + ei * ei;
+      }
+      Ipix[2 * k + x] = v;
+    }
   }
   __syncthreads();
-}
-
-// ---- shot noise: pixel pairs [first, first + count) ---------------------------
-// I <- Poisson(s I) / s; pixels 2m, 2m+1 share the Philox block (m, frame, 0, 0)
-// for their first attempt.
-__device__ __forceinline__ void noise_pairs(const FrameDev& F, int64_t m) {
-#pragma clang fp contract(off)
-  const float scale = reinterpret_cast<const float*>(F.scal)[2];
-  if (!(scale > 0.0f)) return;
-  const OpticsArgs& o = F.o;
-  float2* img = reinterpret_cast<float2*>(F.intensity);
-  const float2 I = img[m];
-  const uint4 r = philox4x32_10(make_uint4((uint32_t)m, o.frame, 0u, 0u), o.seed_lo, o.seed_hi);
-  float2 out;
-  out.x = (float)poisson(scale * I.x, r.x, r.y, (uint32_t)(2 * m), o.frame, o.seed_lo, o.seed_hi) / scale;
-  out.y = (float)poisson(scale * I.y, r.z, r.w, (uint32_t)(2 * m + 1), o.frame, o.seed_lo, o.seed_hi) / scale;
-  img[m] = out;
+  noise_rows<NP>(F, scale, (int64_t)rb * RB * W, Ipix, dst, lds);
 }
 
 }  // namespace osog

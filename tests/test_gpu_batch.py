@@ -37,6 +37,7 @@ def test_batch_equals_single_frames_bitwise():
         render.set_batch_group(group)
         b = render.Batch(fr, want_opd=True)
         for rep in range(2):  # second call replays the captured graph
+            say("batch of %d small frames, group %d, call %d" % (len(fr), group, rep))
             b.run()
             torch.cuda.synchronize()
             assert b.error_flag() == 0
@@ -57,6 +58,7 @@ def test_batch_headline_mix_runs_and_matches_spot_frames():
     frs = workloads.config2()
     fr = [(dev_soa(x.soa), x.H, x.W, x.optics, dev_globals(x.globals4)) for x in frs]
     b = render.Batch(fr)
+    say("batch of %d headline-mix frames" % len(fr))
     b.run()
     torch.cuda.synchronize()
     assert b.error_flag() == 0
