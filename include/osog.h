@@ -151,25 +151,28 @@ osog_status osog_batch_workspace_size(osog_context* ctx, const osog_frame* frame
                                       int32_t n_frames, int32_t pairs_per_particle,
                                       size_t* bytes);
 
-/* Render many frames of uneven size and particle count in one persistent
- * kernel launch (a device work queue over (frame, stage, item) in dependency
- * order), captured once per batch signature in a HIP graph owned by the context
- * and replayed on later calls with the same signature.  Each frame's output is
- * bitwise identical to osog_render of that frame with the same tiling.
- *   frame_done_ns  device uint64[n_frames] or NULL: GPU timestamp (ns, the
+/* Render many frames of uneven size and particle count in one launch of a HIP
+ * graph, captured once per batch signature (frame descriptors, workspace,
+ * timestamp buffer, per-size tiling and FFT radix, branch count) and replayed
+ * on later calls with the same signature.  The graph holds one kernel chain per
+ * frame (the launches osog_render makes) on `group` concurrent branches (see
+ * osog_set_batch_group); every dependency is a graph edge.  Each frame's output
+ * is bitwise identical to osog_render of that frame with the same tiling.
+ * Asynchronous on `stream`.
+ *   frame_done_ns  device uint64[n_frames + 1] or NULL: GPU timestamp (ns, the
  *                  device's constant-rate clock) at which each frame finished,
- *                  and [n_frames] = launch start, for latency percentiles. */
+ *                  and [n_frames] = the batch start, for latency percentiles. */
 osog_status osog_batch_render(osog_context* ctx, void* stream, const osog_frame* frames,
                               int32_t n_frames, void* workspace, size_t workspace_bytes,
                               uint64_t* frame_done_ns);
 
-/* Nonzero *flag (host) if a workgroup of the last batch launch on this
- * workspace gave up waiting for a dependency (its outputs are then invalid).
- * Waits for the device. */
+/* Number of frames of the last batch on this workspace whose pair list
+ * overflowed its capacity (they were rendered by the slower per-particle
+ * fallback, with the same result), into *flag (host).  Waits for the device. */
 osog_status osog_batch_error(osog_context* ctx, void* workspace, int32_t* flag);
 
-/* Batch scheduling: frames are queued in groups of `group` consecutive frames,
- * stage-major inside a group (0: one group).  Default 16. */
+/* Batch scheduling: the number of concurrent branches of the batch graph,
+ * frame f on branch f mod group (0: the maximum, 8).  Default 4. */
 osog_status osog_set_batch_group(osog_context* ctx, int32_t group);
 
 /* Tiling used for frames of one canvas size in batches (the autotuner's
@@ -272,7 +275,7 @@ enum {
   OSOG_STAGE_ADJ_PASS2 = 6,
   OSOG_STAGE_ADJ_PASS1 = 7,
   OSOG_STAGE_ADJ_RASTER = 8,
-  OSOG_STAGE_BATCH = 9,     /* the persistent batch kernel                        */
+  OSOG_STAGE_BATCH = 9,     /* a whole batch graph launch                          */
   OSOG_NSTAGES = 10
 };
 osog_status osog_profile_enable(osog_context* ctx, int32_t enable);

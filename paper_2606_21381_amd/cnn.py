@@ -2,7 +2,7 @@
 
 The network regresses the global optical parameters (dn, defocus, DIC shear,
 DIC bias) of a DIC frame.  It is trained on crops the renderer itself produces
-(one persistent batch launch per training batch) with the library's own
+(one batch graph launch per training batch) with the library's own
 forward, backward and Adam kernels; PyTorch only holds the buffers.
 
 Target normalisation (zero-centred, about unit range over the training draw):
@@ -116,7 +116,7 @@ class LearnedInit:
 
     # -- training data rendered by the engine -------------------------------------
     def _crop_source(self):
-        """Fixed-shape batch of crops (padded particle tables) rendered by one persistent launch."""
+        """Fixed-shape batch of crops (padded particle tables) rendered by one batch graph launch."""
         B, S, N = self.batch, self.crop, self.n_max
         self.soa_dev = torch.zeros((B, 8, N), dtype=torch.float32, device=self.device)
         self.g_dev = torch.zeros((B, 4), dtype=torch.float32, device=self.device)

@@ -26,7 +26,7 @@ struct osog_context {
   std::map<std::pair<int, int>, std::pair<int, int>> size_tiling;  // per canvas size (autotuner)
   std::map<std::pair<int, int>, int> size_radix;                   // per canvas size (autotuner)
   int fft_radix = 8;
-  int batch_group = 16;
+  int batch_group = 4;
   osog::BatchCache* batch = nullptr;
   osog::Profiler* prof = nullptr;
 };
@@ -239,9 +239,9 @@ static int effective_ppp(int ppp) { return ppp > 0 ? ppp : kDefaultPairsPerParti
 // Forward chain of one frame on a carved workspace.
 hipError_t forward_frame(const osog_context* ctx, const FramePlan& p, const float* soa,
                          const float* globals, FrameBufs& b, float* opd_out, float* intensity,
-                         hipStream_t s) {
+                         hipStream_t s, bool profile) {
   float* opd = opd_out ? opd_out : b.opd;
-  Profiler* pr = ctx->prof;
+  Profiler* pr = profile ? ctx->prof : nullptr;
   hipError_t e;
   profile_begin(pr, OSOG_STAGE_BINNING, s);
   if ((e = launch_binning(p, soa, b, s)) != hipSuccess) return e;
@@ -363,7 +363,7 @@ osog_status osog_render(osog_context* ctx, void* stream, int32_t height, int32_t
   int64_t cap = 0;
   FrameBufs b = carve(workspace, height, width, n, tile_of(ctx, height, width, 0), tile_of(ctx, height, width, 1), ppp, false, &cap);
   FramePlan p = make_plan(ctx, height, width, n, ld, *optics, cap);
-  e = forward_frame(ctx, p, soa, globals, b, opd_out, intensity_out, (hipStream_t)stream);
+  e = forward_frame(ctx, p, soa, globals, b, opd_out, intensity_out, (hipStream_t)stream, true);
   if (e != hipSuccess) return hip_fail(e, "osog_render launch");
   return OSOG_OK;
 }
@@ -546,7 +546,7 @@ osog_status osog_batch_error(osog_context* ctx, void* workspace, int32_t* flag) 
 
 osog_status osog_set_batch_group(osog_context* ctx, int32_t group) {
   if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
-  if (group < 0) return fail(OSOG_ERR_INVALID_ARGUMENT, "group must be >= 0 (0: all frames in one group)");
+  if (group < 0) return fail(OSOG_ERR_INVALID_ARGUMENT, "group must be >= 0 (0: the maximum, 8)");
   ctx->batch_group = group;
   return OSOG_OK;
 }

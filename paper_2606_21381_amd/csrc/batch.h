@@ -1,4 +1,4 @@
-// Batched persistent rendering: cache of captured HIP graphs per batch signature.
+// Batched rendering: cache of captured HIP graphs per batch signature.
 #pragma once
 
 #include <hip/hip_runtime.h>

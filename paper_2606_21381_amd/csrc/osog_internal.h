@@ -118,7 +118,7 @@ FramePlan make_plan(const osog_context* ctx, int H, int W, int64_t n, int64_t ld
                     int64_t cap);
 hipError_t forward_frame(const osog_context* ctx, const FramePlan& p, const float* soa,
                          const float* globals, FrameBufs& b, float* opd_out, float* intensity,
-                         hipStream_t s);
+                         hipStream_t s, bool profile);
 
 // Stage profiler owned by the context (HIP events around stage launches).
 struct Profiler;

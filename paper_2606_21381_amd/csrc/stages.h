@@ -1,6 +1,6 @@
 // The forward renderer's stages as workgroup-level device bodies over a device
 // frame descriptor.  The single-frame kernels (bin.hip, raster.hip, fft.hip)
-// and the batched persistent kernel (batch.hip) both call these, so a frame
+// call these; the batch graph (batch.hip) replays those kernels, so a frame
 // rendered alone or inside a batch goes through identical arithmetic.
 //
 // Every body is executed by one 256-thread workgroup (the raster body by one

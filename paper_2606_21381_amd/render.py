@@ -200,7 +200,7 @@ def philox(ctr: torch.Tensor, key0: int, key1: int) -> torch.Tensor:
 
 
 class Batch:
-    """A batch of frames rendered by one persistent kernel launch (HIP graph).
+    """A batch of frames rendered by one HIP graph launch (one kernel chain per frame).
 
     ``frames``: list of (soa [8, n] CUDA float32, H, W, optics, globals [4] CUDA float32).
     Outputs are allocated once; ``run()`` re-renders into them (replaying the
