@@ -43,6 +43,43 @@ def algorithmic_bytes(H, W, n, P, kx_n):
     }
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "counters_dic2048_n40000.txt")
+
+
+def source_hash():
+    """sha1 over the library's kernel sources (names and bytes, sorted by name)."""
+    import glob
+    import hashlib
+    h = hashlib.sha1()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2606_21381_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_counters(kernel):
+    """HBM bytes (scaled FETCH_SIZE + WRITE_SIZE) and VALU busy share of `kernel`
+    from the committed rocprofv3 counter summary, or None when that summary was
+    taken on other kernel sources than the ones built now."""
+    try:
+        lines = open(COUNTERS).read().splitlines()
+    except OSError:
+        return None
+    stamp = [l for l in lines if l.startswith("# kernel sources: sha1 ")]
+    if not stamp or stamp[0].split()[4] != source_hash():
+        return None
+    for l in lines:
+        f = l.split()
+        if f and not l.startswith("#") and f[0].startswith(kernel):
+            # kernel name may contain spaces ("k_pass1<11, 8>"): numbers are the last 6 fields
+            fetch, write, total, winst, avg_us, valu = map(float, f[-6:])
+            return {"traffic": total * 1e6, "fetch": fetch * 1e6, "write": write * 1e6,
+                    "valu_winst": winst, "valu_busy": valu / 100.0}
+    return None
+
+
 def cpu_baseline(fr, budget_s=20.0):
     """The FP64 oracle on a bounded sample of the same workload, scaled to frames/s.
 
@@ -142,9 +179,14 @@ def main():
     alg = algorithmic_bytes(H, W, n, P, kx_n)
     dom = max((k for k in stage_us if k in alg), key=lambda k: stage_us[k])
     achieved = alg[dom] / (stage_us[dom] * 1e-6) / 1e9
+    kname = {"binning": "k_scatter", "raster": "k_raster", "pass1": "k_pass1", "pass2": "k_pass2",
+             "pass3": "k_pass3"}[dom]
+    cnt = measured_counters(kname)
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "algorithmic_bytes": alg[dom], "avg_us": round(stage_us[dom], 2)}
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": round(cnt["traffic"]) if cnt else None,
+            "algorithmic_bytes": alg[dom], "avg_us": round(stage_us[dom], 2),
+            "valu_busy": round(cnt["valu_busy"], 3) if cnt else None}
     total_alg = sum(alg.values())
     res = {
         "metric": METRIC,
@@ -166,6 +208,7 @@ def main():
         "stage_us": {k: round(v, 2) for k, v in stage_us.items()},
         "frame_alg_bytes": total_alg,
         "frame_alg_gbs": round(total_alg / (ms * 1e-3) / 1e9, 1),
+        "frame_hbm_frac": round(total_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roof,
         "paper_context": "paper: 40,000 particles in under 50 ms on one NVIDIA A100 (1024^2 canvas)",
     }
