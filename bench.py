@@ -296,6 +296,8 @@ def bench_inverse(dev, learned=False):
                         inverse.SolverConfig())
     out = {"workload": "dic1024_n500_adam500", "time_to_1e-3_s": res.time_to_target_s,
            "steps_to_1e-3": res.steps_to_target, "final_error": float(res.error[-1]),
+           "final_error_glob": float(res.error_glob[-1]), "final_error_part": float(res.error_part[-1]),
+           "glob_steps_to_1e-3": res.steps_to_glob_target, "glob_time_to_1e-3_s": res.time_to_glob_target_s,
            "final_loss": float(res.loss[-1]), "steps_per_s": round(len(res.loss) / float(res.time_s[-1]), 1)}
     if learned:
         from paper_2606_21381_amd import cnn

@@ -226,20 +226,30 @@ def compare(device="cuda", samples: int = 200_000, n_targets: int = 10, target_s
         rows.append({"seed": target_seed0 + k, "loss_start_default": l_def, "loss_start_learned": l_cnn,
                      "fallback": used_fallback,
                      "pred_abs_err": np.abs(g_pred - g_true).tolist(),
-                     "default": (r_def.steps_to_target, r_def.time_to_target_s, float(r_def.error[-1])),
-                     "learned": (r_cnn.steps_to_target, r_cnn.time_to_target_s, float(r_cnn.error[-1]))})
+                     "default": _arm(r_def), "learned": _arm(r_cnn)})
         if log:
             log(k, rows[-1])
 
-    def med(arm, i):
-        v = [r[arm][i] if r[arm][i] is not None else math.inf for r in rows]
-        return float(np.median(v))
+    def med(key):
+        out = {}
+        for arm in ("default", "learned"):
+            v = [r[arm][key] if r[arm][key] is not None else math.inf for r in rows]
+            out[arm] = float(np.median(v))
+        return out
 
-    return {"workload": "dic1024_n500 x %d targets" % n_targets, "train_samples": samples,
-            "train_s": round(t_train, 2), "train_final_loss": float(losses[-20:].mean()) if len(losses) else None,
-            "heldout_mae": dict(zip(("dn", "dz_um", "shear_px", "bias_rad"), map(float, mae))),
-            "fallbacks": fallbacks,
-            "median_time_to_1e-3_s": {"default": med("default", 1), "learned": med("learned", 1)},
-            "median_steps_to_1e-3": {"default": med("default", 0), "learned": med("learned", 0)},
-            "median_final_error": {"default": med("default", 2), "learned": med("learned", 2)},
-            "targets": rows}
+    rep = {"workload": "dic1024_n500 x %d targets" % n_targets, "train_samples": samples,
+           "train_s": round(t_train, 2), "train_final_loss": float(losses[-20:].mean()) if len(losses) else None,
+           "heldout_mae": dict(zip(("dn", "dz_um", "shear_px", "bias_rad"), map(float, mae))),
+           "fallbacks": fallbacks, "targets": rows}
+    for key in ("time_to_1e-3_s", "steps_to_1e-3", "glob_time_to_1e-3_s", "glob_steps_to_1e-3", "final_e",
+                "final_e_glob", "final_e_part", "glob_error_at_60"):
+        rep["median_" + key] = med(key)
+    return rep
+
+
+def _arm(r) -> dict:
+    """Summary of one inverse solve: time/steps to e <= 1e-3 and to e_glob <= 1e-3, final errors."""
+    return {"time_to_1e-3_s": r.time_to_target_s, "steps_to_1e-3": r.steps_to_target,
+            "glob_time_to_1e-3_s": r.time_to_glob_target_s, "glob_steps_to_1e-3": r.steps_to_glob_target,
+            "final_e": float(r.error[-1]), "final_e_glob": float(r.error_glob[-1]),
+            "final_e_part": float(r.error_part[-1]), "glob_error_at_60": float(r.error_glob[min(60, r.steps)])}

@@ -28,10 +28,14 @@ __global__ void __launch_bounds__(kThreads) k_pass1(FrameDev F, const float2* __
   pass1_body<LOGW, MAXR>(F, blockIdx.x, tw, lds);
 }
 
+// Column b of the band lives in 32-byte pieces (RB rows) next to columns b +- 1,
+// so neighbouring columns share cache lines: each XCD (workgroup i runs on XCD
+// i mod 8) takes one contiguous run of columns, and a line is fetched once.
 template <int LOGH, int MAXR>
-__global__ void __launch_bounds__(kThreads) k_pass2(FrameDev F, const float2* __restrict__ tw) {
+__global__ void __launch_bounds__(kThreads) k_pass2(FrameDev F, const float2* __restrict__ tw, int per_xcd) {
   __shared__ __align__(16) char lds[(1 << LOGH) * sizeof(float2) + kThreads * sizeof(double) + 16];
-  pass2_body<LOGH, MAXR>(F, blockIdx.x, tw, lds);
+  const int b = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+  if (b < F.o.kx_n) pass2_body<LOGH, MAXR>(F, b, tw, lds);
 }
 
 template <int LOGW, int MAXR>
@@ -71,9 +75,10 @@ hipError_t launch_pass2(const FramePlan& p, const float* globals, FrameBufs& b, 
                         hipStream_t s) {
   FrameDev F = make_dev(p, b);
   F.globals = globals;
+  const int per = (p.kx_n + kXcds - 1) / kXcds;
 #define L2(LG)                                                                                  \
-  if (p.fft_radix == 4) hipLaunchKernelGGL((k_pass2<LG, 4>), dim3(p.kx_n), dim3(kThreads), 0, s, F, tw); \
-  else hipLaunchKernelGGL((k_pass2<LG, 8>), dim3(p.kx_n), dim3(kThreads), 0, s, F, tw)
+  if (p.fft_radix == 4) hipLaunchKernelGGL((k_pass2<LG, 4>), dim3(per * kXcds), dim3(kThreads), 0, s, F, tw, per); \
+  else hipLaunchKernelGGL((k_pass2<LG, 8>), dim3(per * kXcds), dim3(kThreads), 0, s, F, tw, per)
   OSOG_SIZE_SWITCH(p.logH, L2)
 #undef L2
   return hipGetLastError();

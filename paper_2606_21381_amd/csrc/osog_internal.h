@@ -14,6 +14,7 @@ namespace osog {
 constexpr int kThreads = 256;     // every kernel runs 256-thread workgroups (4 wave64)
 constexpr int kTwN = 4096;        // twiddle table length (largest FFT)
 constexpr int kDefaultPairsPerParticle = 32;
+constexpr int kXcds = 8;          // MI355X: 8 accelerator dies, each with its own L2
 
 // Per-particle raster record, 128 bytes, written once by the prepare kernel and
 // read by the raster through the scalar cache.

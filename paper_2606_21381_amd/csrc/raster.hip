@@ -14,12 +14,19 @@
 
 namespace osog {
 
-__global__ void __launch_bounds__(64) k_raster(FrameDev F) { raster_tile(F, blockIdx.x, threadIdx.x); }
+// Workgroups are dealt to the 8 XCDs in turn (workgroup i to XCD i mod 8), so
+// the tile of workgroup i is chosen to give each XCD one contiguous band of
+// tiles: a particle spanning neighbouring tiles is then fetched into one L2.
+__global__ void __launch_bounds__(64) k_raster(FrameDev F, int per_xcd) {
+  const int tile = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+  if (tile < F.n_tiles) raster_tile(F, tile, threadIdx.x);
+}
 
 hipError_t launch_raster(const FramePlan& p, FrameBufs& b, float* opd, hipStream_t s) {
   FrameDev F = make_dev(p, b);
   F.opd = opd;
-  hipLaunchKernelGGL(k_raster, dim3(p.n_tiles), dim3(64), 0, s, F);
+  const int per = (p.n_tiles + kXcds - 1) / kXcds;
+  hipLaunchKernelGGL(k_raster, dim3(per * kXcds), dim3(64), 0, s, F, per);
   return hipGetLastError();
 }
 

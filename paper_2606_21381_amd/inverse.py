@@ -6,6 +6,11 @@ frame rendered from known prisms, and Adam recovers the shared dn, the defocus,
 the DIC shear and bias, and every prism's centre, angle and half-width from a
 perturbed start, minimising the mean squared image error.
 
+Schedule: for the first ``globals_first`` steps only the four globals move (the
+per-particle parameters would otherwise drift to compensate for 20 % errors in
+dn, defocus, shear and bias, and some settle in other basins); then everything
+moves, with a cosine decay of every rate over the last part of the run.
+
 Parameter error (how "1e-3 relative parameter error" is measured):
   e = max(e_glob, e_part)
   e_glob = max over dn, dz, shear, bias of |p - p*| / max(|p*|, floor)
@@ -46,6 +51,7 @@ class SolverConfig:
     decay_to: float = 0.1      # final rate multiplier (cosine)
     target_error: float = 1e-3
     width_floor: float = 1.0   # half-width kept >= 1 px
+    globals_first: int = 60    # steps during which only dn, dz, shear, bias move
 
 
 @dataclass
@@ -60,12 +66,16 @@ class Truth:
 @dataclass
 class SolveResult:
     steps: int
-    error: np.ndarray          # per step (after the update), len = steps + 1 (index 0 = start)
+    error: np.ndarray          # e per step (after the update), len = steps + 1 (index 0 = start)
     loss: np.ndarray           # per step (before the update)
     time_s: np.ndarray         # GPU time since the start of step 0, per step end
     steps_to_target: Optional[int]
     time_to_target_s: Optional[float]
     final: dict = field(default_factory=dict)
+    error_glob: Optional[np.ndarray] = None   # e_glob per step, len = steps + 1
+    error_part: Optional[np.ndarray] = None   # e_part per step, len = steps + 1
+    steps_to_glob_target: Optional[int] = None
+    time_to_glob_target_s: Optional[float] = None
 
 
 class Params(torch.nn.Module):
@@ -95,14 +105,20 @@ class Params(torch.nn.Module):
         return torch.cat([self.dn, self.dz, self.shear, self.bias])
 
 
-def parameter_error(p: Params, truth: Truth) -> torch.Tensor:
-    """e = max(e_glob, e_part) on the device (see the module docstring)."""
+def parameter_errors(p: Params, truth: Truth):
+    """(e_glob, e_part) on the device (see the module docstring)."""
     g = p.glob()
     floor = torch.tensor([0.0, 0.5, 0.0, 0.0], device=g.device, dtype=g.dtype)
     e_glob = ((g - truth.globals4).abs() / torch.maximum(truth.globals4.abs(), floor)).max()
     da = torch.remainder(p.angle - truth.angle + math.pi / 4, math.pi / 2) - math.pi / 4
     e_part = torch.stack([((p.x - truth.x).abs() / 3.0).max(), ((p.y - truth.y).abs() / 3.0).max(),
                           (da.abs() / 0.2).max(), ((p.width - truth.width).abs() / 3.0).max()]).max()
+    return e_glob, e_part
+
+
+def parameter_error(p: Params, truth: Truth) -> torch.Tensor:
+    """e = max(e_glob, e_part) on the device (see the module docstring)."""
+    e_glob, e_part = parameter_errors(p, truth)
     return torch.maximum(e_glob, e_part)
 
 
@@ -137,13 +153,13 @@ def solve(target: torch.Tensor, start: Params, truth: Optional[Truth], H: int, W
     base = [g["lr"] for g in opt.param_groups]
     dev = target.device
     losses = torch.zeros(cfg.steps, device=dev)
-    errors = torch.zeros(cfg.steps + 1, device=dev)
+    errors = torch.zeros((cfg.steps + 1, 2), device=dev)
     timing = target.is_cuda
     events = [torch.cuda.Event(enable_timing=True) for _ in range(cfg.steps + 1)] if timing else None
     t_host = []
     with torch.no_grad():
         if truth is not None:
-            errors[0] = parameter_error(start, truth)
+            errors[0] = torch.stack(parameter_errors(start, truth))
     if timing:
         events[0].record()
     t0 = time.perf_counter()
@@ -158,12 +174,15 @@ def solve(target: torch.Tensor, start: Params, truth: Optional[Truth], H: int, W
         I = render_fn(start.soa(), start.globals4())
         loss = torch.mean((I - target) ** 2)
         loss.backward()
+        if k < cfg.globals_first:  # per-particle parameters wait until the globals have settled
+            for q in (start.x, start.y, start.angle, start.width):
+                q.grad = None
         opt.step()
         with torch.no_grad():
             start.width.clamp_(min=cfg.width_floor)
             losses[k] = loss.detach()
             if truth is not None:
-                errors[k + 1] = parameter_error(start, truth)
+                errors[k + 1] = torch.stack(parameter_errors(start, truth))
         if timing:
             events[k + 1].record()
         else:
@@ -173,12 +192,15 @@ def solve(target: torch.Tensor, start: Params, truth: Optional[Truth], H: int, W
         times = np.array([events[0].elapsed_time(e) / 1000.0 for e in events[1:]])
     else:
         times = np.array(t_host)
-    err = errors.cpu().numpy()
+    eg = errors.cpu().numpy()
+    err = eg.max(axis=1)
     hit = np.nonzero(err[1:] <= cfg.target_error)[0] if truth is not None else np.array([])
-    steps_to = int(hit[0]) + 1 if hit.size else None
-    return SolveResult(cfg.steps, err, losses.cpu().numpy(), times, steps_to,
-                       float(times[hit[0]]) if hit.size else None,
-                       {k: float(v) for k, v in zip(GLOBAL_NAMES, start.glob().detach().cpu().numpy())})
+    hitg = np.nonzero(eg[1:, 0] <= cfg.target_error)[0] if truth is not None else np.array([])
+    return SolveResult(cfg.steps, err, losses.cpu().numpy(), times,
+                       int(hit[0]) + 1 if hit.size else None, float(times[hit[0]]) if hit.size else None,
+                       {k: float(v) for k, v in zip(GLOBAL_NAMES, start.glob().detach().cpu().numpy())},
+                       eg[:, 0], eg[:, 1], int(hitg[0]) + 1 if hitg.size else None,
+                       float(times[hitg[0]]) if hitg.size else None)
 
 
 def problem_tensors(prob, device):
