@@ -32,9 +32,9 @@ def algorithmic_bytes(H, W, n, P, kx_n):
     hw4 = 4.0 * H * W
     band = 8.0 * H * kx_n
     return {
-        # SoA table, per-particle counts and offsets, pairs emitted, sorted (2 passes
-        # of read + write of 8-byte pairs), tile offsets
-        "binning": 32.0 * n + 16.0 * n + 8.0 * P * (1 + 2 * 2) + 4.0 * (H * W / 256 + 1),
+        # SoA table read, per-particle pair counts, the pair list (one 4-byte id per
+        # pair, written once), per-tile count / first / end
+        "binning": 32.0 * n + 4.0 * n + 4.0 * P + 12.0 * (H * W / 256),
         # pair list + the 8 attributes of each listed particle, OPD written once
         "raster": 4.0 * P + 32.0 * P + hw4,
         "pass1": hw4 + band,
@@ -179,7 +179,7 @@ def main():
     alg = algorithmic_bytes(H, W, n, P, kx_n)
     dom = max((k for k in stage_us if k in alg), key=lambda k: stage_us[k])
     achieved = alg[dom] / (stage_us[dom] * 1e-6) / 1e9
-    kname = {"binning": "k_scatter", "raster": "k_raster", "pass1": "k_pass1", "pass2": "k_pass2",
+    kname = {"binning": "k_fill", "raster": "k_raster", "pass1": "k_pass1", "pass2": "k_pass2",
              "pass3": "k_pass3"}[dom]
     cnt = measured_counters(kname)
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

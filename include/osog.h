@@ -100,10 +100,10 @@ osog_status osog_get_tiling(const osog_context* ctx, int32_t* tile_h, int32_t* t
 
 /* Bytes of device workspace needed by osog_render (with_backward = 0) or by
  * osog_render_backward (with_backward = 1) for an H x W canvas and n particles.
- * pairs_per_particle bounds the mean number of (tile, particle) pairs the
- * workspace holds (0 selects 32).  If a frame needs more pairs than that, the
- * render stays correct and bitwise identical but rasterises by a slow
- * brute-force scan of all particles per tile. */
+ * pairs_per_particle sizes the per-tile pair buckets: (pairs_per_particle * n +
+ * tiles) / tiles ids per tile, rounded up to a multiple of 8, in [8, 1024]
+ * (0 selects 32).  A tile with more pairs than its bucket holds stays correct
+ * and bitwise identical but is rasterised by a slow scan of all particles. */
 osog_status osog_workspace_size(const osog_context* ctx, int32_t height, int32_t width, int64_t n,
                                 int32_t pairs_per_particle, int32_t with_backward, size_t* bytes);
 
@@ -166,9 +166,9 @@ osog_status osog_batch_render(osog_context* ctx, void* stream, const osog_frame*
                               int32_t n_frames, void* workspace, size_t workspace_bytes,
                               uint64_t* frame_done_ns);
 
-/* Number of frames of the last batch on this workspace whose pair list
- * overflowed its capacity (they were rendered by the slower per-particle
- * fallback, with the same result), into *flag (host).  Waits for the device. */
+/* Number of frames of the last batch on this workspace in which some tile's
+ * pair bucket overflowed (those tiles were rendered by the slower all-particle
+ * scan, with the same result), into *flag (host).  Waits for the device. */
 osog_status osog_batch_error(osog_context* ctx, void* workspace, int32_t* flag);
 
 /* Batch scheduling: the number of concurrent branches of the batch graph,
@@ -200,9 +200,10 @@ osog_status osog_autotune(osog_context* ctx, void* stream, int32_t height, int32
  * writes the pairs sorted by (tile key, particle id):
  *   keys_out, pids_out  device int32[capacity]; pair_count_out device int32[1]
  *   tile_start_out      device int32[n_tiles + 1]; counts_out device int32[n] or NULL
- * n_tiles = (height / tile_h) * (width / tile_w).  If more than `capacity`
- * pairs exist, *pair_count_out is set to the full count and the lists hold
- * nothing meaningful. */
+ * n_tiles = (height / tile_h) * (width / tile_w).  *pair_count_out is the full
+ * pair count; if it exceeds `capacity`, keys_out and pids_out are not written.
+ * workspace: as for osog_render (its buckets are filled as a render fills them;
+ * an overflowing tile's ids are produced by the same id-ordered scan). */
 osog_status osog_bin(osog_context* ctx, void* stream, int32_t height, int32_t width,
                      const float* soa, int64_t n, int64_t ld, int32_t* keys_out,
                      int32_t* pids_out, int64_t capacity, int32_t* pair_count_out,

@@ -68,34 +68,27 @@ struct Carver {
   }
 };
 
-static int64_t pair_capacity(int64_t n, int n_tiles, int ppp) {
-  int64_t cap = n * (int64_t)ppp + n_tiles;
-  return cap > INT_MAX - 1 ? INT_MAX - 1 : cap;
+// Ids per tile bucket: the pair capacity ppp * n + n_tiles spread evenly over the
+// tiles, rounded up to a multiple of 8, in [8, kMaxBucket].
+static int64_t bucket_capacity(int64_t n, int n_tiles, int ppp) {
+  int64_t per = (n * (int64_t)ppp + n_tiles + n_tiles - 1) / n_tiles;
+  per = (per + 7) / 8 * 8;
+  return per < 8 ? 8 : (per > kMaxBucket ? kMaxBucket : per);
 }
 
 static FrameBufs carve_impl(Carver& c, int H, int W, int64_t n, int tile_h, int tile_w, int ppp,
                             bool backward, int64_t* cap_out) {
   const int n_tiles = (H / tile_h) * (W / tile_w);
-  const int64_t cap = pair_capacity(n, n_tiles, ppp);
+  const int64_t cap = bucket_capacity(n, n_tiles, ppp);
   const size_t hw = (size_t)H * W;
   FrameBufs b{};
   b.recs = c.take<PRec>(n > 0 ? n : 1);
   b.boxes = c.take<int4>(n > 0 ? n : 1);
   b.counts = c.take<int>(n > 0 ? n : 1);
-  const int64_t nblk = (n + kThreads - 1) / kThreads;
-  b.blocksum = c.take<long long>(nblk > 0 ? nblk : 1);
-  b.emit_start = c.take<long long>(n + 1);
   b.scal = c.take<int>(64);
-  b.keys_a = c.take<int>(cap);
-  b.vals_a = c.take<int>(cap);
-  b.keys_b = c.take<int>(cap);
-  b.vals_b = c.take<int>(cap);
-  const size_t nsl = (size_t)((cap + kThreads - 1) / kThreads);
-  b.hist1 = c.take<int>(256 * (nsl > 0 ? nsl : 1));
-  b.hist2 = c.take<int>(256 * (nsl > 0 ? nsl : 1));
-  b.dtot = c.take<int>(512);
+  b.tile_count = c.take<int>(n_tiles);
   b.tile_first = c.take<int>(n_tiles);
-  b.tile_end = c.take<int>(n_tiles);
+  b.pids = c.take<int>((size_t)n_tiles * cap);
   b.opd = c.take<float>(hw);
   b.band = c.take<float2>(hw);
   b.colsum = c.take<double>(W);
@@ -203,7 +196,6 @@ FramePlan make_plan(const osog_context* ctx, int H, int W, int64_t n, int64_t ld
   p.H = H; p.W = W; p.logH = ilog2(H); p.logW = ilog2(W);
   context_tiling(ctx, H, W, &p.tile_h, &p.tile_w);
   p.ntx = W / p.tile_w; p.nty = H / p.tile_h; p.n_tiles = p.ntx * p.nty;
-  p.key_bits = ilog2(p.n_tiles);
   band_range(H, W, o, &p.kx_lo, &p.kx_n);
   p.rb = rows_per_block(W);
   p.fft_radix = context_radix(ctx, H, W);
@@ -452,21 +444,15 @@ osog_status osog_bin(osog_context* ctx, void* stream, int32_t height, int32_t wi
     }
   int64_t cap = 0;
   FrameBufs b = carve(workspace, height, width, n, tile_of(ctx, height, width, 0), tile_of(ctx, height, width, 1), ppp, false, &cap);
-  if (cap > capacity) cap = capacity;
   osog_optics o{};
   o.mode = OSOG_BRIGHTFIELD; o.wavelength_um = 0.55; o.na = 0.5; o.n_medium = 1.33; o.pixel_um = 0.1;
   FramePlan p = make_plan(ctx, height, width, n, ld, o, cap);
   hipStream_t s = (hipStream_t)stream;
   if ((e = launch_binning(p, soa, b, s)) != hipSuccess) return hip_fail(e, "osog_bin launch");
-  if ((e = hipMemcpyAsync(pair_count_out, b.emit_start + n, sizeof(int32_t), hipMemcpyDeviceToDevice, s)) != hipSuccess)
+  if ((e = launch_bin_outputs(p, b, keys_out, pids_out, capacity, tile_start_out, s)) != hipSuccess)
+    return hip_fail(e, "osog_bin sort");
+  if ((e = hipMemcpyAsync(pair_count_out, b.scal + 3, sizeof(int32_t), hipMemcpyDeviceToDevice, s)) != hipSuccess)
     return hip_fail(e, "copy pair count");
-  if (cap > 0) {
-    if ((e = hipMemcpyAsync(keys_out, b.sorted_keys, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s)) != hipSuccess)
-      return hip_fail(e, "copy keys");
-    if ((e = hipMemcpyAsync(pids_out, b.sorted_vals, sizeof(int32_t) * cap, hipMemcpyDeviceToDevice, s)) != hipSuccess)
-      return hip_fail(e, "copy pids");
-  }
-  if ((e = launch_tile_start(p, b, tile_start_out, s)) != hipSuccess) return hip_fail(e, "tile offsets");
   if (counts_out && n > 0 &&
       (e = hipMemcpyAsync(counts_out, b.counts, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s)) != hipSuccess)
     return hip_fail(e, "copy counts");

@@ -1,22 +1,17 @@
-// Integer tile binning of the particle table (steps F1-F4): per-particle pixel
-// box -> pair counts -> particle-major emission of (tile key, particle id)
-// pairs -> stable two-pass LSD radix sort on the tile key -> per-tile first and
-// one-past-last sorted index.  The paper composes particle patches with an
-// atomic scatter-add (Sec. III.C, Eq. 7); sorting the pairs instead lets every
-// tile sum its particles in ascending id with no float atomics, so the canvas
-// is bitwise reproducible.
+// Integer tile binning of the particle table (steps F1-F4): a one-digit
+// counting sort of (tile key, particle id) pairs on the tile key, whose radix
+// is the number of tiles, into fixed-size per-tile buckets.  The paper composes
+// particle patches with an atomic scatter-add (Sec. III.C, Eq. 7); grouping the
+// pairs by tile instead lets every tile sum its particles in ascending id with no
+// float atomics, so the canvas is bitwise reproducible.
 //
-// Six small kernels, none of them a single-workgroup scan (bodies in stages.h):
-//   k_prepare   records, boxes, counts, per-block count sums; clears the
-//               counters the later kernels accumulate into
-//   k_emit      each block sums the preceding blocks' totals (its emission
-//               offset), scans its own counts, emits its pairs and counts their
-//               low key digit per 256-pair slice
-//   k_digit_offsets + k_scatter (pass 0): stable scatter on the low digit;
-//               counts the high digit per output slice
-//   k_digit_offsets + k_scatter (pass 1): stable scatter on the high digit;
-//               marks each tile's first and one-past-last sorted index
-// Integer atomics only ever form order-independent results (sums, min, max).
+//   k_bin_clear  tile counters and flags = 0
+//   k_bin        records, boxes, pairs per particle; every pair takes the next
+//                slot of its tile's bucket through an atomic cursor
+// Integer atomics only form order-independent results (counts) or slots inside
+// a tile's bucket; the order of ids inside a bucket is restored by the reader,
+// which sorts it (raster_tile; k_sort_segments for the inspection API).  A tile
+// whose bucket overflows is read by an id-ordered scan of all particles.
 #include <hip/hip_runtime.h>
 
 #include "osog_internal.h"
@@ -24,63 +19,85 @@
 
 namespace osog {
 
-__global__ void __launch_bounds__(kThreads) k_prepare(FrameDev F) {
-  __shared__ __align__(16) char lds[2 * kThreads * sizeof(long long)];
-  prepare_body(F, blockIdx.x, gridDim.x, lds);
+__global__ void __launch_bounds__(kThreads) k_bin_clear(FrameDev F) {
+  const int t = blockIdx.x * kThreads + threadIdx.x;
+  if (t < F.n_tiles) F.tile_count[t] = 0;
+  if (t < 4) F.scal[t] = 0;
 }
 
-__global__ void __launch_bounds__(kThreads) k_emit(FrameDev F) {
-  __shared__ __align__(16) char lds[2 * kThreads * sizeof(long long)];
-  emit_body(F, blockIdx.x, lds);
+__global__ void __launch_bounds__(kThreads) k_bin(FrameDev F) {
+  bin_body(F, (int64_t)blockIdx.x * kThreads + threadIdx.x);
 }
 
-__global__ void __launch_bounds__(kThreads) k_digit_offsets(FrameDev F, int pass) {
-  __shared__ __align__(16) char lds[kThreads * sizeof(int)];
-  digit_offsets_body(F, pass, blockIdx.x, lds);
+__global__ void __launch_bounds__(kScanThreads) k_tile_scan(FrameDev F) {
+  __shared__ long long buf[kScanChunk];
+  __shared__ long long part[kScanThreads];
+  tile_scan_body(F, buf, part);
 }
 
-__global__ void __launch_bounds__(kThreads) k_scatter(FrameDev F, int pass) {
-  __shared__ __align__(16) char lds[5 * 256 * sizeof(int)];
-  scatter_body(F, pass, blockIdx.x, lds);
-}
-
-// tile_start[k] = first sorted pair with key >= k (only for the inspection API)
-__global__ void __launch_bounds__(kThreads) k_tile_start(const int* __restrict__ keys,
-                                                         const int* __restrict__ scal, int n_tiles,
-                                                         int* __restrict__ tile_start) {
-  int k = blockIdx.x * kThreads + threadIdx.x;
-  if (k > n_tiles) return;
-  int P = scal[1] ? 0 : scal[0];
-  int lo = 0, hi = P;
-  while (lo < hi) {
-    int mid = (lo + hi) >> 1;
-    if (keys[mid] < k) lo = mid + 1; else hi = mid;
+// Inspection only: writes every tile's ids in ascending order at
+// out_pids[tile_first .. + count) with their keys (when all pairs fit in
+// `capacity`), and tile_start[0..n_tiles].  One wave per tile, the raster's sort;
+// a tile whose bucket overflowed is rebuilt by scanning all particles in id
+// order (ballot-compacted), as the raster visits them.
+__global__ void __launch_bounds__(64) k_sort_segments(FrameDev F, int* __restrict__ out_keys,
+                                                      int* __restrict__ out_pids, int64_t capacity,
+                                                      int* __restrict__ tile_start) {
+  __shared__ int seg[kSegSort];
+  const int tile = blockIdx.x, lane = threadIdx.x;
+  const int start = F.tile_first[tile];
+  if (tile == 0 && lane == 0) tile_start[F.n_tiles] = F.scal[3];
+  if (lane == 0) tile_start[tile] = start;
+  if ((int64_t)F.scal[3] > capacity) return;  // the lists would not fit: left untouched
+  const int cnt = F.tile_count[tile];
+  const int cap = (int)F.cap;
+  const int* __restrict__ bucket = F.pids + (int64_t)tile * cap;
+  if (cnt <= cap && cnt <= 64) {
+    const int v = wave_sort64(lane < cnt ? bucket[lane] : INT_MAX, lane);
+    if (lane < cnt) out_pids[start + lane] = v;
+  } else if (cnt <= cap) {
+    int n2 = 128;
+    while (n2 < cnt) n2 <<= 1;
+    for (int i = lane; i < n2; i += 64) seg[i] = i < cnt ? bucket[i] : INT_MAX;
+    __syncthreads();
+    lds_sort(seg, n2, lane);
+    for (int i = lane; i < cnt; i += 64) out_pids[start + i] = seg[i];
+  } else {
+    const int ty = tile / F.ntx, tx = tile - ty * F.ntx;
+    const int x0 = tx * F.tile_w, x1 = x0 + F.tile_w - 1, y0 = ty * F.tile_h, y1 = y0 + F.tile_h - 1;
+    const unsigned long long lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+    int base = start;
+    for (int64_t p0 = 0; p0 < F.n; p0 += 64) {
+      const int64_t p = p0 + lane;
+      bool hit = false;
+      if (p < F.n) {
+        const int4 b = F.boxes[p];
+        hit = !(b.x > b.y || b.x > x1 || b.y < x0 || b.z > y1 || b.w < y0);
+      }
+      const unsigned long long m = __ballot(hit);
+      if (hit) out_pids[base + __popcll(m & lt)] = (int)p;
+      base += __popcll(m);
+    }
   }
-  tile_start[k] = lo;
+  for (int i = lane; i < cnt; i += 64) out_keys[start + i] = tile;
 }
 
 hipError_t launch_binning(const FramePlan& p, const float* soa, FrameBufs& b, hipStream_t s) {
   FrameDev F = make_dev(p, b);
   F.soa = soa;
-  const int gridp = F.nblk > 0 ? F.nblk : 1;
-  hipLaunchKernelGGL(k_prepare, dim3(gridp), dim3(kThreads), 0, s, F);
-  hipLaunchKernelGGL(k_emit, dim3(gridp), dim3(kThreads), 0, s, F);
-  if (F.d1 > 0 && F.nblk > 0) {
-    hipLaunchKernelGGL(k_digit_offsets, dim3(1 << F.d1), dim3(kThreads), 0, s, F, 0);
-    hipLaunchKernelGGL(k_scatter, dim3(F.nsl), dim3(kThreads), 0, s, F, 0);
-    if (F.d2 > 0) {
-      hipLaunchKernelGGL(k_digit_offsets, dim3(1 << F.d2), dim3(kThreads), 0, s, F, 1);
-      hipLaunchKernelGGL(k_scatter, dim3(F.nsl), dim3(kThreads), 0, s, F, 1);
-    }
-  }
-  b.sorted_vals = F.sorted_vals;
-  b.sorted_keys = (F.d1 > 0 && F.d2 == 0) ? b.keys_b : b.keys_a;
+  const unsigned gt = (unsigned)((p.n_tiles + kThreads - 1) / kThreads);
+  const unsigned gp = (unsigned)(p.n > 0 ? (p.n + kThreads - 1) / kThreads : 1);
+  hipLaunchKernelGGL(k_bin_clear, dim3(gt), dim3(kThreads), 0, s, F);
+  hipLaunchKernelGGL(k_bin, dim3(gp), dim3(kThreads), 0, s, F);
   return hipGetLastError();
 }
 
-hipError_t launch_tile_start(const FramePlan& p, FrameBufs& b, int* tile_start, hipStream_t s) {
-  hipLaunchKernelGGL(k_tile_start, dim3((p.n_tiles + 1 + kThreads - 1) / kThreads), dim3(kThreads), 0,
-                     s, b.sorted_keys, b.scal, p.n_tiles, tile_start);
+hipError_t launch_bin_outputs(const FramePlan& p, FrameBufs& b, int* keys_out, int* pids_out, int64_t capacity,
+                              int* tile_start, hipStream_t s) {
+  FrameDev F = make_dev(p, b);
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(kScanThreads), 0, s, F);
+  hipLaunchKernelGGL(k_sort_segments, dim3(p.n_tiles), dim3(64), 0, s, F, keys_out, pids_out, capacity,
+                     tile_start);
   return hipGetLastError();
 }
 

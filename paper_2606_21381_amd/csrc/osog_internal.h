@@ -14,7 +14,8 @@ namespace osog {
 constexpr int kThreads = 256;     // every kernel runs 256-thread workgroups (4 wave64)
 constexpr int kTwN = 4096;        // twiddle table length (largest FFT)
 constexpr int kDefaultPairsPerParticle = 32;
-constexpr int kXcds = 8;          // MI355X: 8 accelerator dies, each with its own L2
+constexpr int kXcds = 8;
+constexpr int kMaxBucket = 1024;  // ids per tile bucket at most (the raster sorts up to this many)          // MI355X: 8 accelerator dies, each with its own L2
 
 // Per-particle raster record, 128 bytes, written once by the prepare kernel and
 // read by the raster through the scalar cache.
@@ -34,11 +35,10 @@ struct __align__(16) PRec {
 struct FramePlan {
   int H, W, logH, logW;
   int tile_h, tile_w, ntx, nty, n_tiles;
-  int key_bits;          // bits of the tile key (0 when one tile)
   int kx_lo, kx_n;       // in-band signed kx range [kx_lo, kx_lo + kx_n)
   int rb;                // rows per band block of the blocked spectrum layout
   int fft_radix;         // FFT plan: largest Stockham radix (8 or 4)
-  int64_t n, ld, cap;    // particles, leading dimension, pair capacity
+  int64_t n, ld, cap;    // particles, leading dimension, ids per tile bucket
   // optics in the precision the kernels use
   int mode;
   float phase_k;         // 2 pi / lambda  [rad/um]
@@ -57,18 +57,11 @@ struct FramePlan {
 struct FrameBufs {
   PRec* recs;
   int4* boxes;
-  int* counts;
-  long long* blocksum;    // one per 256-particle block
-  long long* emit_start;  // n + 1
-  int* scal;              // [0] pair count (0 on overflow), [1] overflow flag
-  int* keys_a; int* vals_a; int* keys_b; int* vals_b;
-  int* hist1;             // low-digit counts: 2^d1 digits x (capacity / 256) slices
-  int* hist2;             // high-digit counts: 2^d2 digits x (capacity / 256) slices
-  int* dtot;              // 2 x 256 digit totals
-  int* tile_first;        // n_tiles: first sorted pair of the tile (INT_MAX if none)
-  int* tile_end;          // n_tiles: one past its last sorted pair (0 if none)
-  int* sorted_keys;       // set by launch_binning: where the sorted pairs ended
-  int* sorted_vals;
+  int* counts;            // pairs per particle
+  int* scal;              // [1] tiles whose bucket overflowed, [3] total pairs (inspection)
+  int* tile_count;        // n_tiles: pairs per tile
+  int* tile_first;        // n_tiles: inspection only, prefix of the tile counts
+  int* pids;              // n_tiles x bucket: particle ids per tile
   float* opd;             // H*W (used when the caller passes no opd_out)
   float2* band;           // H * W complex (blocked layout, kx_n used)
   double* colsum;         // W
@@ -83,7 +76,8 @@ FrameBufs carve(void* ws, int H, int W, int64_t n, int tile_h, int tile_w, int p
 
 // launchers (return hipError_t of the last launch)
 hipError_t launch_binning(const FramePlan& p, const float* soa, FrameBufs& b, hipStream_t s);
-hipError_t launch_tile_start(const FramePlan& p, FrameBufs& b, int* tile_start, hipStream_t s);
+hipError_t launch_bin_outputs(const FramePlan& p, FrameBufs& b, int* keys_out, int* pids_out, int64_t capacity,
+                              int* tile_start, hipStream_t s);
 hipError_t launch_raster(const FramePlan& p, FrameBufs& b, float* opd, hipStream_t s);
 hipError_t launch_pass1(const FramePlan& p, const float* opd, FrameBufs& b, const float2* tw, hipStream_t s);
 hipError_t launch_pass2(const FramePlan& p, const float* globals, FrameBufs& b, const float2* tw, hipStream_t s);

@@ -1,7 +1,7 @@
 // OPD rasterisation (step F5): one 64-lane wave per tile, four pixels per lane.
 // Every pixel adds dn * thickness of each of its tile's particles in ascending
-// particle id, so the sum order -- and the canvas, bit for bit -- does not
-// depend on the tiling, the launch order or the GPU.  This replaces the
+// particle id (the wave sorts its tile's ids first), so the sum order -- and the
+// canvas, bit for bit -- does not depend on the tiling, the launch order or the GPU.  This replaces the
 // paper's atomic scatter-add (Sec. III.C, Eq. 7) by a gather over the sorted
 // pair list.  The particle id and its 128-byte record are wave-uniform and are
 // read through the scalar cache; each 64-pixel slot first tests the particle
@@ -18,8 +18,9 @@ namespace osog {
 // the tile of workgroup i is chosen to give each XCD one contiguous band of
 // tiles: a particle spanning neighbouring tiles is then fetched into one L2.
 __global__ void __launch_bounds__(64) k_raster(FrameDev F, int per_xcd) {
+  __shared__ int seg[kSegSort];
   const int tile = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
-  if (tile < F.n_tiles) raster_tile(F, tile, threadIdx.x);
+  if (tile < F.n_tiles) raster_tile(F, tile, threadIdx.x, seg);
 }
 
 hipError_t launch_raster(const FramePlan& p, FrameBufs& b, float* opd, hipStream_t s) {

@@ -22,9 +22,8 @@ constexpr int kStageLds = 8192 * 8 + kThreads * 8;  // >= pass3_buf_bytes(W) + k
 // Everything a stage needs to know about one frame, in device-readable form.
 struct FrameDev {
   int H, W, logH, logW, tile_h, tile_w, ntx, n_tiles;
-  int d1, d2, nsl, nblk;          // radix digit widths, slice capacity, particle blocks
   int fft_radix;                   // FFT plan: largest Stockham radix (8 or 4)
-  int64_t n, ld, cap;
+  int64_t n, ld, cap;              // cap: ids per tile bucket
   OpticsArgs o;
   float phase_k;
   const float* soa;
@@ -33,237 +32,146 @@ struct FrameDev {
   float* intensity;
   PRec* recs;
   int4* boxes;
-  int* counts;
-  long long* blocksum;
-  long long* emit_start;
-  int* scal;                       // [0] pairs, [1] overflow, [2] noise scale (float bits)
-  int* keys_a; int* vals_a; int* keys_b; int* vals_b;
-  int* hist1; int* hist2; int* dtot;
-  int* tile_first; int* tile_end;
-  int* sorted_vals;                // where the final radix pass leaves the particle ids
+  int* counts;                     // pairs per particle
+  int* scal;                       // [1] tiles whose bucket overflowed, [3] total pairs (inspection)
+  int* tile_count;                 // pairs per tile (the fill cursor; may exceed the bucket)
+  int* tile_first;                 // inspection only: exclusive prefix of the tile counts
+  int* pids;                       // n_tiles buckets of `cap` particle ids
   float2* band;
   double* colsum;
 };
 
-// ---- F1: records, pixel boxes, pair counts; clears later accumulators ---------
-__device__ __forceinline__ void prepare_body(const FrameDev& F, int blk, int nblocks, char* lds) {
-  long long* red = reinterpret_cast<long long*>(lds);
-  const int t = threadIdx.x;
-  const int64_t p = (int64_t)blk * kThreads + t;
-  const int64_t gsz = (int64_t)nblocks * kThreads;
-  const int64_t n1 = F.d1 > 0 ? ((int64_t)1 << F.d1) * F.nsl : 0;
-  const int64_t n2 = F.d2 > 0 ? ((int64_t)1 << F.d2) * F.nsl : 0;
-  for (int64_t q = p; q < n1; q += gsz) F.hist1[q] = 0;
-  for (int64_t q = p; q < n2; q += gsz) F.hist2[q] = 0;
-  for (int64_t q = p; q < F.n_tiles; q += gsz) {
-    F.tile_end[q] = 0;
-    F.tile_first[q] = INT_MAX;
-  }
+// ---- F1-F3: records, pixel boxes, pairs per particle; tile buckets -----------
+// A one-digit counting sort on the tile key with fixed-size buckets: every pair
+// (tile, particle) takes the next slot of its tile's bucket through an atomic
+// cursor.  The counters must be zero on entry (k_bin_clear); they end as the
+// tiles' true pair counts, which may exceed the bucket (the reader then falls
+// back to an id-ordered scan for that tile, and scal[1] counts such tiles).  The
+// order of ids inside a bucket is restored by the reader, which sorts it.
+// Up to kFillBatch cursor increments are issued before their results are used.
+constexpr int kFillBatch = 8;
+
+__device__ __forceinline__ void bin_body(const FrameDev& F, int64_t p) {
+  if (p >= F.n) return;
+  const float* soa = F.soa;
+  const int64_t ld = F.ld;
+  const float cx = soa[0 * ld + p], cy = soa[1 * ld + p], ang = soa[2 * ld + p];
+  const float a = soa[3 * ld + p], b = soa[4 * ld + p], h = soa[5 * ld + p];
+  const float dn = soa[6 * ld + p], shape = soa[7 * ld + p];
+  int4 box;
+  const bool ok = pixel_box(cx, cy, a, b, shape, F.H, F.W, &box);
+  PRec r;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) r.f[k] = 0.0f;
   int cnt = 0;
-  if (p < F.n) {
-    const float* soa = F.soa;
-    const int64_t ld = F.ld;
-    const float cx = soa[0 * ld + p], cy = soa[1 * ld + p], ang = soa[2 * ld + p];
-    const float a = soa[3 * ld + p], b = soa[4 * ld + p], h = soa[5 * ld + p];
-    const float dn = soa[6 * ld + p], shape = soa[7 * ld + p];
-    int4 box;
-    const bool ok = pixel_box(cx, cy, a, b, shape, F.H, F.W, &box);
-    PRec r;
-#pragma unroll
-    for (int k = 0; k < 32; ++k) r.f[k] = 0.0f;
-    if (ok) {
-      const int tx0 = box.x / F.tile_w, tx1 = box.y / F.tile_w, ty0 = box.z / F.tile_h, ty1 = box.w / F.tile_h;
-      cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-      make_record(cx, cy, ang, a, b, h, dn, shape, &r);
-    } else {
-      r.f[3] = -1.0f;
-      box = make_int4(1, 0, 1, 0);
-    }
-    F.recs[p] = r;
-    F.boxes[p] = box;
-    F.counts[p] = cnt;
+  if (ok) {
+    make_record(cx, cy, ang, a, b, h, dn, shape, &r);
+  } else {
+    r.f[3] = -1.0f;
+    box = make_int4(1, 0, 1, 0);
   }
-  red[t] = cnt;
-  __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] += red[t + s];
-    __syncthreads();
-  }
-  if (t == 0) F.blocksum[blk] = red[0];
-  __syncthreads();
-}
-
-// ---- F2/F3: offsets, emission, the first radix histogram ----------------------
-// hist1[d * nsl + s] = number of emitted keys with low digit d in 256-key slice s.
-__device__ __forceinline__ void emit_body(const FrameDev& F, int blk, char* lds) {
-  long long* red = reinterpret_cast<long long*>(lds);
-  long long* scan = red + kThreads;
-  const int t = threadIdx.x;
-  long long pre = 0, tot = 0;
-  for (int b = t; b < F.nblk; b += kThreads) {
-    const long long v = F.blocksum[b];
-    tot += v;
-    if (b < blk) pre += v;
-  }
-  red[t] = pre;
-  scan[t] = tot;
-  __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (t < s) { red[t] += red[t + s]; scan[t] += scan[t + s]; }
-    __syncthreads();
-  }
-  const long long base = red[0], total = scan[0];
-  const bool overflow = total > F.cap;
-  if (blk == 0 && t == 0) {
-    F.scal[0] = overflow ? 0 : (int)total;
-    F.scal[1] = overflow ? 1 : 0;
-    F.emit_start[F.n] = total;
-  }
-  __syncthreads();
-  const int64_t p = (int64_t)blk * kThreads + t;
-  const int c = p < F.n ? F.counts[p] : 0;
-  scan[t] = c;
-  __syncthreads();
-  for (int off = 1; off < kThreads; off <<= 1) {
-    long long v = t >= off ? scan[t - off] : 0;
-    __syncthreads();
-    scan[t] += v;
-    __syncthreads();
-  }
-  long long e = base + scan[t] - c;
-  if (p < F.n) F.emit_start[p] = e;
-  if (!overflow && c > 0) {
-    const int4 box = F.boxes[p];
+  F.recs[p] = r;
+  F.boxes[p] = box;
+  if (ok) {
     const int tx0 = box.x / F.tile_w, tx1 = box.y / F.tile_w, ty0 = box.z / F.tile_h, ty1 = box.w / F.tile_h;
-    const int mask = (1 << F.d1) - 1;
-    for (int ty = ty0; ty <= ty1; ++ty)
-      for (int tx = tx0; tx <= tx1; ++tx) {
-        const int key = ty * F.ntx + tx;
-        F.keys_a[e] = key;
-        F.vals_a[e] = (int)p;
-        if (F.d1 > 0) {
-          atomicAdd(&F.hist1[(size_t)(key & mask) * F.nsl + (e >> 8)], 1);
-        } else {  // a single tile: the emission order is already sorted
-          atomicMin(&F.tile_first[key], (int)e);
-          atomicMax(&F.tile_end[key], (int)e + 1);
-        }
-        ++e;
-      }
-  }
-  __syncthreads();
-}
-
-// ---- per-digit exclusive prefix over slices (in place), digit totals ---------
-__device__ __forceinline__ void digit_offsets_body(const FrameDev& F, int pass, int d, char* lds) {
-  int* part = reinterpret_cast<int*>(lds);
-  const int t = threadIdx.x;
-  if (F.scal[1]) return;
-  int* hist = pass == 0 ? F.hist1 : F.hist2;
-  int* dtot = F.dtot + (pass == 0 ? 0 : 256);
-  const int nslice = (F.scal[0] + kThreads - 1) / kThreads;
-  int* row = hist + (size_t)d * F.nsl;
-  const int per = (nslice + kThreads - 1) / kThreads;
-  const int b0 = min(nslice, t * per), b1 = min(nslice, b0 + per);
-  int s = 0;
-  for (int b = b0; b < b1; ++b) s += row[b];
-  part[t] = s;
-  __syncthreads();
-  for (int off = 1; off < kThreads; off <<= 1) {
-    int v = t >= off ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  int run = part[t] - s;
-  for (int b = b0; b < b1; ++b) {
-    const int v = row[b];
-    row[b] = run;
-    run += v;
-  }
-  if (t == kThreads - 1) dtot[d] = part[t];
-  __syncthreads();
-}
-
-// ---- F4: one stable scatter pass on 256-key slice `blk` -----------------------
-// Per-digit output base = (exclusive scan over digits of the digit totals) +
-// (exclusive prefix of the digit over earlier slices).  Keys are ranked in input
-// order inside the slice (ballot-matched peers within a wave, per-wave counts
-// across waves), so the sort is stable.  Pass 0 of two counts the next digit per
-// output slice; the final pass marks each tile's first and one-past-last index
-// (run boundaries only).  Returns without touching LDS when the slice is empty.
-__device__ __forceinline__ void scatter_body(const FrameDev& F, int pass, int blk, char* lds) {
-  int* base = reinterpret_cast<int*>(lds);
-  int* wcnt = base + 256;  // [4][256]
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  if (F.scal[1]) return;
-  const int P = F.scal[0];
-  const int lo = blk * kThreads;
-  if (lo >= P) return;
-  const bool final_pass = (pass == 1) || F.d2 == 0;
-  const int shift = pass == 0 ? 0 : F.d1, bits = pass == 0 ? F.d1 : F.d2;
-  const int* kin = pass == 0 ? F.keys_a : F.keys_b;
-  const int* vin = pass == 0 ? F.vals_a : F.vals_b;
-  int* kout = pass == 0 ? F.keys_b : F.keys_a;
-  int* vout = pass == 0 ? F.vals_b : F.vals_a;
-  const int* hist = pass == 0 ? F.hist1 : F.hist2;
-  const int* dtot = F.dtot + (pass == 0 ? 0 : 256);
-  const int hi = min(P, lo + kThreads);
-  const int nd = 1 << bits, mask = nd - 1;
-  const int tot = t < nd ? dtot[t] : 0;
-  base[t] = tot;
+    const int nx = tx1 - tx0 + 1;
+    cnt = nx * (ty1 - ty0 + 1);
+    const int cap = (int)F.cap;
+    for (int e0 = 0; e0 < cnt; e0 += kFillBatch) {
+      int key[kFillBatch], pos[kFillBatch];
 #pragma unroll
-  for (int w = 0; w < kThreads / 64; ++w) wcnt[w * 256 + t] = 0;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    int v = t >= off ? base[t - off] : 0;
-    __syncthreads();
-    base[t] += v;
-    __syncthreads();
-  }
-  const int excl = (t < nd) ? base[t] - tot + hist[(size_t)t * F.nsl + blk] : 0;
-  __syncthreads();
-  base[t] = excl;
-  __syncthreads();
-  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int q = lo + t;
-  const bool valid = q < hi;
-  int key = 0, val = 0;
-  unsigned d = 0;
-  if (valid) {
-    key = kin[q];
-    val = vin[q];
-    d = (key >> shift) & mask;
-  }
-  unsigned long long peers = __ballot(valid);
-  for (int bit = 0; bit < bits; ++bit) {
-    const bool on = (d >> bit) & 1u;
-    const unsigned long long m = __ballot(on);
-    peers &= on ? m : ~m;
-  }
-  if (!valid) peers = 0;
-  const int rank = __popcll(peers & lt);
-  if (valid && rank == 0) wcnt[wave * 256 + d] = __popcll(peers);
-  __syncthreads();
-  if (valid) {
-    int off = base[d] + rank;
-    for (int w = 0; w < wave; ++w) off += wcnt[w * 256 + d];
-    kout[off] = key;
-    vout[off] = val;
-    if (final_pass) {
-      // peers with one digit keep input (low-digit) order, so equal keys are
-      // adjacent among them: a tile run starts/ends where the neighbouring peer differs
-      const unsigned long long before = peers & lt, after = peers & ~lt & ~(1ull << lane);
-      const int prev_lane = before ? 63 - __clzll(before) : -1;
-      const int next_lane = after ? __ffsll(after) - 1 : -1;
-      const int prev_key = __shfl(key, prev_lane < 0 ? lane : prev_lane);
-      const int next_key = __shfl(key, next_lane < 0 ? lane : next_lane);
-      if (prev_lane < 0 || prev_key != key) atomicMin(&F.tile_first[key], off);
-      if (next_lane < 0 || next_key != key) atomicMax(&F.tile_end[key], off + 1);
-    } else {
-      atomicAdd(&F.hist2[(size_t)((key >> F.d1) & ((1 << F.d2) - 1)) * F.nsl + (off >> 8)], 1);
+      for (int u = 0; u < kFillBatch; ++u) {
+        const int e = e0 + u;
+        key[u] = e < cnt ? (ty0 + e / nx) * F.ntx + tx0 + e % nx : -1;
+        pos[u] = key[u] >= 0 ? atomicAdd(&F.tile_count[key[u]], 1) : 0;
+      }
+#pragma unroll
+      for (int u = 0; u < kFillBatch; ++u) {
+        if (key[u] < 0) continue;
+        if (pos[u] < cap) F.pids[(int64_t)key[u] * cap + pos[u]] = (int)p;
+        else if (pos[u] == cap) atomicAdd(&F.scal[1], 1);
+      }
     }
   }
-  __syncthreads();
+  F.counts[p] = cnt;
+}
+
+// ---- inspection: exclusive prefix of the tile counts (one workgroup) -----------
+// tile_first = prefix of the true counts; total pairs -> scal[3].  The counts
+// pass through LDS in chunks of kScanChunk, read and written coalesced.
+constexpr int kScanThreads = 1024;
+constexpr int kScanChunk = 8192;
+
+__device__ __forceinline__ void tile_scan_body(const FrameDev& F, long long* buf, long long* part) {
+  const int t = threadIdx.x;
+  const int nt = F.n_tiles;
+  long long carry = 0;
+  for (int c0 = 0; c0 < nt; c0 += kScanChunk) {
+    const int cn = min(kScanChunk, nt - c0);
+    for (int i = t; i < cn; i += kScanThreads) buf[i] = F.tile_count[c0 + i];
+    __syncthreads();
+    const int per = (cn + kScanThreads - 1) / kScanThreads;
+    const int b0 = min(cn, t * per), b1 = min(cn, b0 + per);
+    long long s = 0;
+    for (int k = b0; k < b1; ++k) s += buf[k];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < kScanThreads; off <<= 1) {
+      const long long v = t >= off ? part[t - off] : 0;
+      __syncthreads();
+      part[t] += v;
+      __syncthreads();
+    }
+    long long run = carry + part[t] - s;
+    for (int k = b0; k < b1; ++k) {
+      const long long c = buf[k];
+      buf[k] = run;
+      run += c;
+    }
+    const long long chunk_total = part[kScanThreads - 1];
+    __syncthreads();
+    for (int i = t; i < cn; i += kScanThreads) F.tile_first[c0 + i] = (int)(buf[i] < INT_MAX ? buf[i] : INT_MAX);
+    carry += chunk_total;
+    __syncthreads();
+  }
+  if (t == 0) F.scal[3] = carry < INT_MAX ? (int)carry : INT_MAX;
+}
+
+// ---- F4: a tile's particle ids in ascending order, for one 64-lane wave -------
+// The fill leaves each tile's ids in arbitrary order.  Up to 64 ids are sorted
+// in registers (bitonic network over the lanes); up to kSegSort in LDS; a
+// longer list is not materialised: the caller visits all particles in id order
+// and keeps those whose box meets the tile (the same ids, the same order).
+constexpr int kSegSort = kMaxBucket;
+
+__device__ __forceinline__ int wave_sort64(int v, int lane) {
+#pragma unroll
+  for (int k = 2; k <= 64; k <<= 1)
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int o = __shfl_xor(v, j, 64);
+      const bool keep_min = ((lane & j) == 0) == ((lane & k) == 0);
+      v = keep_min ? min(v, o) : max(v, o);
+    }
+  return v;
+}
+
+// In-place ascending bitonic sort of seg[0, n2), n2 a power of two <= kSegSort,
+// by the 64 lanes of a single-wave workgroup.
+__device__ __forceinline__ void lds_sort(int* seg, int n2, int lane) {
+  for (int k = 2; k <= n2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int q = lane; q < n2 / 2; q += 64) {
+        const int i = ((q & ~(j - 1)) << 1) | (q & (j - 1));  // q with a 0 inserted at bit log2(j)
+        const int a = seg[i], b = seg[i + j];
+        const bool asc = (i & k) == 0;
+        if ((a > b) == asc) {
+          seg[i] = b;
+          seg[i + j] = a;
+        }
+      }
+      __syncthreads();
+    }
 }
 
 // ---- F5: rasterise one tile with one 64-lane wave ------------------------------
@@ -313,50 +221,73 @@ __device__ __forceinline__ float contribution(const PRec& r, const SubRect& R, i
 // Lane `lane` of the wave owns pixels lane, lane+64, lane+128, lane+192 of the
 // tile.  The particle loop, the record load (scalar cache) and the kind dispatch
 // run once per (tile, particle); ids are fetched 64 at a time and broadcast.
-__device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int lane) {
+// Particles are visited in ascending id: the tile's bucket is sorted on the fly
+// (wave_sort64 / lds_sort); a tile whose bucket overflowed is served by a scan of
+// all particles in id order that keeps those whose box meets the tile.  All three visit the same
+// particles in the same order, so the sums are identical.  `seg`: kSegSort ints
+// of LDS; the workgroup is this single wave.
+struct TileAcc {
+  int pi[4], pj[4];
+  SubRect R[4];
+  float acc[4];
+};
+
+__device__ __forceinline__ void raster_ids(const FrameDev& F, TileAcc& T, int mine, int m) {
+#pragma clang fp contract(off)
+  const PRec* __restrict__ recs = F.recs;
+  PRec nxt = recs[__builtin_amdgcn_readlane(mine, 0)];
+  for (int k = 0; k < m; ++k) {
+    const PRec cur = nxt;
+    if (k + 1 < m) nxt = recs[__builtin_amdgcn_readlane(mine, k + 1)];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) T.acc[q] += contribution(cur, T.R[q], T.pi[q], T.pj[q]);
+  }
+}
+
+__device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int lane, int* seg) {
 #pragma clang fp contract(off)
   const int tile_w = F.tile_w, tile_h = F.tile_h;
   const int ty = tile / F.ntx, tx = tile - ty * F.ntx;
-  int pi[4], pj[4];
-  SubRect R[4];
+  TileAcc T;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int q = lane + 64 * k, li = q / tile_w, lj = q - li * tile_w;
-    pi[k] = ty * tile_h + li;
-    pj[k] = tx * tile_w + lj;
-    R[k] = slot_rect(64 * k, tile_w, tx, ty, tile_h);
+    T.pi[k] = ty * tile_h + li;
+    T.pj[k] = tx * tile_w + lj;
+    T.R[k] = slot_rect(64 * k, tile_w, tx, ty, tile_h);
+    T.acc[k] = 0.0f;
   }
-  float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-  const PRec* __restrict__ recs = F.recs;
-  if (!F.scal[1]) {
-    const int start = F.tile_first[tile];
-    const int cnt = max(0, F.tile_end[tile] - start);
-    const int* __restrict__ pids = F.sorted_vals;
+  const int cnt = F.tile_count[tile];
+  const bool overflow = cnt > (int)F.cap;     // the bucket could not hold the tile's ids
+  const int* __restrict__ pids = F.pids + (int64_t)tile * F.cap;
+  const int start = 0;
+  if (!overflow && cnt <= 64) {
+    if (cnt > 0) {
+      const int mine = wave_sort64(lane < cnt ? pids[start + lane] : INT_MAX, lane);
+      raster_ids(F, T, mine, cnt);
+    }
+  } else if (!overflow && cnt <= kSegSort) {
+    int n2 = 128;
+    while (n2 < cnt) n2 <<= 1;
+    for (int i = lane; i < n2; i += 64) seg[i] = i < cnt ? pids[start + i] : INT_MAX;
+    __syncthreads();
+    lds_sort(seg, n2, lane);
     for (int c0 = 0; c0 < cnt; c0 += 64) {
       const int m = min(64, cnt - c0);
-      const int mine = lane < m ? pids[start + c0 + lane] : 0;
-      PRec nxt = recs[__builtin_amdgcn_readlane(mine, 0)];
-      for (int k = 0; k < m; ++k) {
-        const PRec cur = nxt;
-        if (k + 1 < m) nxt = recs[__builtin_amdgcn_readlane(mine, k + 1)];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] += contribution(cur, R[q], pi[q], pj[q]);
-      }
+      raster_ids(F, T, lane < m ? seg[c0 + lane] : 0, m);
     }
   } else {
-    // The pair list overflowed its capacity: visit every particle in id order and
-    // keep those whose pixel box meets this tile (same records, same order, same sums).
     const int x0 = tx * tile_w, x1 = x0 + tile_w - 1, y0 = ty * tile_h, y1 = y0 + tile_h - 1;
     for (int64_t p = 0; p < F.n; ++p) {
       const int4 b = F.boxes[p];
       if (b.x > b.y || b.x > x1 || b.y < x0 || b.z > y1 || b.w < y0) continue;
-      const PRec r = recs[p];
+      const PRec r = F.recs[p];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] += contribution(r, R[q], pi[q], pj[q]);
+      for (int q = 0; q < 4; ++q) T.acc[q] += contribution(r, T.R[q], T.pi[q], T.pj[q]);
     }
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) F.opd[(int64_t)pi[q] * F.W + pj[q]] = acc[q];
+  for (int q = 0; q < 4; ++q) F.opd[(int64_t)T.pi[q] * F.W + T.pj[q]] = T.acc[q];
 }
 
 // ---- F6: pass 1, rows --------------------------------------------------------
@@ -599,20 +530,12 @@ inline FrameDev make_dev(const FramePlan& p, const FrameBufs& b) {
   FrameDev F{};
   F.H = p.H; F.W = p.W; F.logH = p.logH; F.logW = p.logW;
   F.tile_h = p.tile_h; F.tile_w = p.tile_w; F.ntx = p.ntx; F.n_tiles = p.n_tiles;
-  F.d1 = (p.key_bits + 1) / 2;
-  F.d2 = p.key_bits - F.d1;
-  F.nsl = (int)((p.cap + kThreads - 1) / kThreads);
-  F.nblk = (int)((p.n + kThreads - 1) / kThreads);
   F.n = p.n; F.ld = p.ld; F.cap = p.cap;
   F.o = optics_args(p);
   F.phase_k = p.phase_k;
-  F.recs = b.recs; F.boxes = b.boxes; F.counts = b.counts; F.blocksum = b.blocksum;
-  F.emit_start = b.emit_start; F.scal = b.scal;
-  F.keys_a = b.keys_a; F.vals_a = b.vals_a; F.keys_b = b.keys_b; F.vals_b = b.vals_b;
-  F.hist1 = b.hist1; F.hist2 = b.hist2; F.dtot = b.dtot;
-  F.tile_first = b.tile_first; F.tile_end = b.tile_end;
-  // two passes end in a (a -> b -> a), one pass in b, none (one tile) in a
-  F.sorted_vals = (F.d1 > 0 && F.d2 == 0) ? b.vals_b : b.vals_a;
+  F.recs = b.recs; F.boxes = b.boxes; F.counts = b.counts; F.scal = b.scal;
+  F.tile_count = b.tile_count; F.tile_first = b.tile_first;
+  F.pids = b.pids;
   F.band = b.band; F.colsum = b.colsum;
   F.fft_radix = p.fft_radix;
   F.opd = b.opd;
