@@ -24,7 +24,7 @@ namespace osog {
 
 template <int LOGW, int MAXR>
 __global__ void __launch_bounds__(kThreads) k_pass1(FrameDev F, const float2* __restrict__ tw) {
-  __shared__ __align__(16) char lds[rows_per_block(1 << LOGW) * (1 << LOGW) * sizeof(float2)];
+  __shared__ __align__(16) char lds[rows_per_fft_block(1 << LOGW) * (1 << LOGW) * sizeof(float2)];
   pass1_body<LOGW, MAXR>(F, blockIdx.x, tw, lds);
 }
 
@@ -62,7 +62,7 @@ hipError_t launch_pass1(const FramePlan& p, const float* opd, FrameBufs& b, cons
                         hipStream_t s) {
   FrameDev F = make_dev(p, b);
   F.opd = const_cast<float*>(opd);
-  const int rbn = p.H / p.rb;
+  const int rbn = p.H / rows_per_fft_block(p.W);
 #define L1(LG)                                                                              \
   if (p.fft_radix == 4) hipLaunchKernelGGL((k_pass1<LG, 4>), dim3(rbn), dim3(kThreads), 0, s, F, tw); \
   else hipLaunchKernelGGL((k_pass1<LG, 8>), dim3(rbn), dim3(kThreads), 0, s, F, tw)
@@ -88,7 +88,7 @@ hipError_t launch_pass3(const FramePlan& p, FrameBufs& b, const float2* tw, floa
                         hipStream_t s) {
   FrameDev F = make_dev(p, b);
   F.intensity = intensity;
-  const int rbn = p.H / p.rb;
+  const int rbn = p.H / rows_per_fft_block(p.W);
 #define L3(LG)                                                                              \
   if (p.fft_radix == 4) hipLaunchKernelGGL((k_pass3<LG, 4>), dim3(rbn), dim3(kThreads), 0, s, F, tw); \
   else hipLaunchKernelGGL((k_pass3<LG, 8>), dim3(rbn), dim3(kThreads), 0, s, F, tw)

@@ -74,12 +74,27 @@ __device__ __forceinline__ float halfplane_cover(float t, float nx, float ny) {
   return t > 0.0f ? 1.0f - tri : tri;
 }
 
+// Area of pixel (i, j) inside the prism footprint by the clipped-polygon
+// integral over its four edges (any pixel; used where two edges reach it).
+// Pixel-corner offsets j - cx and i - cy are exact in FP32 for on-canvas
+// particles, so the clip runs in small local coordinates.
+__device__ __forceinline__ float prism_clip_area(const PRec& r, int i, int j) {
+#pragma clang fp contract(off)
+  const float fj = (float)j, fi = (float)i;
+  const float X0 = fj - r.f[0], Y0 = fi - r.f[1];
+  const float x0 = r.f[8] - X0, y0 = r.f[9] - Y0, x1 = r.f[10] - X0, y1 = r.f[11] - Y0;
+  const float x2 = r.f[12] - X0, y2 = r.f[13] - Y0, x3 = r.f[14] - X0, y3 = r.f[15] - Y0;
+  float area = edge_area(x0, y0, x1, y1, r.f[16]);
+  area += edge_area(x1, y1, x2, y2, r.f[17]);
+  area += edge_area(x2, y2, x3, y3, r.f[18]);
+  area += edge_area(x3, y3, x0, y0, r.f[19]);
+  return area;
+}
+
 // Exact area of pixel (i, j) covered by the prism footprint of record r (bounds
 // bb from prism_bounds).  Exactly 0 for a pixel outside the bounds and exactly 1
 // for a pixel whose disc is inside both slabs; a single half-plane's box filter
 // where only one edge reaches the pixel; otherwise the clipped polygon area.
-// Pixel-corner offsets j - cx and i - cy are exact in FP32 for on-canvas
-// particles, so the clip runs in small local coordinates.
 __device__ __forceinline__ float prism_cover(const PRec& r, const float4& bb, int i, int j) {
 #pragma clang fp contract(off)
   const float fj = (float)j, fi = (float)i;
@@ -95,14 +110,21 @@ __device__ __forceinline__ float prism_cover(const PRec& r, const float4& bb, in
   // one is >= 2a - hd away): the pixel meets a single half-plane
   if (dv < -hd && a >= hd) return halfplane_cover(-du, c, s);
   if (du < -hd && b >= hd) return halfplane_cover(-dv, s, c);
-  const float X0 = fj - r.f[0], Y0 = fi - r.f[1];
-  const float x0 = r.f[8] - X0, y0 = r.f[9] - Y0, x1 = r.f[10] - X0, y1 = r.f[11] - Y0;
-  const float x2 = r.f[12] - X0, y2 = r.f[13] - Y0, x3 = r.f[14] - X0, y3 = r.f[15] - Y0;
-  float area = edge_area(x0, y0, x1, y1, r.f[16]);
-  area += edge_area(x1, y1, x2, y2, r.f[17]);
-  area += edge_area(x2, y2, x3, y3, r.f[18]);
-  area += edge_area(x3, y3, x0, y0, r.f[19]);
-  return area;
+  return prism_clip_area(r, i, j);
+}
+
+// Ellipsoid thickness times dn at the centre of pixel (i, j) with q recomputed
+// in FP64 (used within 2e-3 of the rim, where sqrt(1 - q) amplifies rounding).
+__device__ __forceinline__ float ellipsoid_rim(const PRec& r, int i, int j) {
+#pragma clang fp contract(off)
+  const float cx = r.f[0], cy = r.f[1];
+  double cd = __hiloint2double(__float_as_int(r.f[11]), __float_as_int(r.f[10]));
+  double sd = __hiloint2double(__float_as_int(r.f[13]), __float_as_int(r.f[12]));
+  double ddx = ((double)j + 0.5) - (double)cx, ddy = ((double)i + 0.5) - (double)cy;
+  double uu = (cd * ddx + sd * ddy) / (double)r.f[6];
+  double vv = (-sd * ddx + cd * ddy) / (double)r.f[7];
+  double qq = uu * uu + vv * vv;
+  return qq < 1.0 ? (float)((double)r.f[14] * (double)r.f[15] * sqrt(1.0 - qq)) : 0.0f;
 }
 
 // Ellipsoid thickness times dn at the centre of pixel (i, j).  Within 2e-3 of
@@ -114,15 +136,7 @@ __device__ __forceinline__ float ellipsoid_opd(const PRec& r, int i, int j) {
   float u = (c * dx + s * dy) * r.f[8], v = (-s * dx + c * dy) * r.f[9];
   float q = u * u + v * v;
   if (q >= 1.002f) return 0.0f;
-  if (q > 0.998f) {
-    double cd = __hiloint2double(__float_as_int(r.f[11]), __float_as_int(r.f[10]));
-    double sd = __hiloint2double(__float_as_int(r.f[13]), __float_as_int(r.f[12]));
-    double ddx = ((double)j + 0.5) - (double)cx, ddy = ((double)i + 0.5) - (double)cy;
-    double uu = (cd * ddx + sd * ddy) / (double)r.f[6];
-    double vv = (-sd * ddx + cd * ddy) / (double)r.f[7];
-    double qq = uu * uu + vv * vv;
-    return qq < 1.0 ? (float)((double)r.f[14] * (double)r.f[15] * sqrt(1.0 - qq)) : 0.0f;
-  }
+  if (q > 0.998f) return ellipsoid_rim(r, i, j);
   return r.f[2] * sqrtf(1.0f - q);
 }
 

@@ -191,31 +191,112 @@ __device__ __forceinline__ SubRect slot_rect(int first, int tile_w, int tx, int 
   return R;
 }
 
-// Contribution of one particle to one pixel of a 64-pixel slot, with the
-// slot-level shortcuts (both give exactly what the per-pixel code would).
-__device__ __forceinline__ float contribution(const PRec& r, const SubRect& R, int i, int j) {
+struct TileAcc {
+  int pi[4], pj[4];
+  SubRect R[4];
+  float acc[4];
+};
+
+// Adds one particle to the four pixel slots a lane owns.  Per 64-pixel slot, a
+// slot the particle misses is skipped and a slot inside its footprint takes the
+// full amplitude (both wave-uniform); otherwise every lane evaluates its pixel
+// without branching for the common cases -- outside, inside, one edge (the
+// half-plane box filter) for a prism; the centre sample for an ellipsoid -- and
+// only marks the rare costly pixels: a prism pixel two edges reach (the
+// clipped-polygon area) and an ellipsoid pixel within 2e-3 of the rim (FP64).
+// Those are evaluated after the four slots, each lane serving its own marks,
+// so the costly code runs once per particle rather than once per slot.  Every
+// pixel still receives exactly one term per particle, the same value the
+// per-pixel functions (prism_cover, ellipsoid_opd) return, in particle order.
+__device__ __forceinline__ void add_particle(const PRec& r, TileAcc& T) {
 #pragma clang fp contract(off)
   const float kind = r.f[3];
+  const float amp = r.f[2];
+  unsigned marks = 0u;
   if (kind == 0.0f) {
-    if (r.f[21] <= R.x0 || r.f[20] >= R.x1 || r.f[23] <= R.y0 || r.f[22] >= R.y1) return 0.0f;
-    // every pixel centre of the slot deep inside both slabs: coverage 1 everywhere
-    // (max |u| over the rectangle of centres = |u at its middle| + |c| hx + |s| hy)
+    const float c = r.f[4], s = r.f[5], a = r.f[6], b = r.f[7];
+    const float hd = 0.70712f;  // > sqrt(2)/2: a pixel lies in this disc around its centre
+    // half-plane box filter constants (as in halfplane_cover; (c, s) and (s, c) share them)
+    const float hp_p = fmaxf(fabsf(c), fabsf(s)), hp_q = fminf(fabsf(c), fabsf(s));
+    const float hp_h = 0.5f * (hp_p + hp_q), hp_l = 0.5f * (hp_p - hp_q);
+    const float hp_rp = __builtin_amdgcn_rcpf(hp_p), hp_r2 = __builtin_amdgcn_rcpf(2.0f * hp_p * hp_q);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const SubRect& R = T.R[q];
+      if (r.f[21] <= R.x0 || r.f[20] >= R.x1 || r.f[23] <= R.y0 || r.f[22] >= R.y1) continue;
+      {  // every pixel centre of the slot deep inside both slabs: coverage 1 everywhere
+        const float hx = 0.5f * (R.x1 - R.x0 - 1.0f), hy = 0.5f * (R.y1 - R.y0 - 1.0f);
+        const float dx = 0.5f * (R.x0 + R.x1) - r.f[0], dy = 0.5f * (R.y0 + R.y1) - r.f[1];
+        const float ux = fabsf(c * dx + s * dy) + fabsf(c) * hx + fabsf(s) * hy;
+        const float vy = fabsf(-s * dx + c * dy) + fabsf(s) * hx + fabsf(c) * hy;
+        const float lim = 0.70712f + 1e-4f;
+        if (ux < a - lim && vy < b - lim) {
+          T.acc[q] += amp;
+          continue;
+        }
+      }
+      const float fj = (float)T.pj[q], fi = (float)T.pi[q];
+      const bool off_box = r.f[21] <= fj || r.f[20] >= fj + 1.0f || r.f[23] <= fi || r.f[22] >= fi + 1.0f;
+      const float dx = (fj + 0.5f) - r.f[0], dy = (fi + 0.5f) - r.f[1];
+      const float u = c * dx + s * dy, v = -s * dx + c * dy;
+      const float du = fabsf(u) - a, dv = fabsf(v) - b;
+      const bool outside = off_box || du > hd || dv > hd;
+      const bool inside = du < -hd && dv < -hd;
+      const bool edge_u = dv < -hd && a >= hd;
+      const bool edge_v = !edge_u && du < -hd && b >= hd;
+      // halfplane_cover(t, .) with t = -du (edge_u) or -dv (edge_v), branch-free
+      const float t = edge_u ? -du : -dv;
+      const float at = fabsf(t);
+      const float lin = 0.5f + t * hp_rp;
+      const float e = hp_h - at;
+      const float tri = e * e * hp_r2;
+      const float quad = t > 0.0f ? 1.0f - tri : tri;
+      const float hpv = t >= hp_h ? 1.0f : (t <= -hp_h ? 0.0f : (at <= hp_l ? lin : quad));
+      float cover = 0.0f;
+      if (!outside) cover = inside ? 1.0f : ((edge_u || edge_v) ? hpv : 0.0f);
+      if (!outside && !inside && !edge_u && !edge_v) marks |= 1u << q;
+      else T.acc[q] += amp * cover;
+    }
+    while (marks) {
+      const int q = __builtin_ctz(marks);
+      marks &= marks - 1u;
+      // one call site; selects keep the slot arrays in registers
+      const int ii = q == 0 ? T.pi[0] : (q == 1 ? T.pi[1] : (q == 2 ? T.pi[2] : T.pi[3]));
+      const int jj = q == 0 ? T.pj[0] : (q == 1 ? T.pj[1] : (q == 2 ? T.pj[2] : T.pj[3]));
+      const float add = amp * prism_clip_area(r, ii, jj);
+      if (q == 0) T.acc[0] += add;
+      else if (q == 1) T.acc[1] += add;
+      else if (q == 2) T.acc[2] += add;
+      else T.acc[3] += add;
+    }
+  } else if (kind == 1.0f) {
     const float c = r.f[4], s = r.f[5];
-    const float hx = 0.5f * (R.x1 - R.x0 - 1.0f), hy = 0.5f * (R.y1 - R.y0 - 1.0f);
-    const float dx = 0.5f * (R.x0 + R.x1) - r.f[0], dy = 0.5f * (R.y0 + R.y1) - r.f[1];
-    const float ux = fabsf(c * dx + s * dy) + fabsf(c) * hx + fabsf(s) * hy;
-    const float vy = fabsf(-s * dx + c * dy) + fabsf(s) * hx + fabsf(c) * hy;
-    const float lim = 0.70712f + 1e-4f;
-    if (ux < r.f[6] - lim && vy < r.f[7] - lim) return r.f[2];
-    return r.f[2] * prism_cover(r, make_float4(r.f[20], r.f[21], r.f[22], r.f[23]), i, j);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const SubRect& R = T.R[q];
+      if (R.x1 - 0.5f - r.f[0] < -r.f[16] || R.x0 + 0.5f - r.f[0] > r.f[16] || R.y1 - 0.5f - r.f[1] < -r.f[17] ||
+          R.y0 + 0.5f - r.f[1] > r.f[17])
+        continue;
+      const float dx = ((float)T.pj[q] + 0.5f) - r.f[0], dy = ((float)T.pi[q] + 0.5f) - r.f[1];
+      const float u = (c * dx + s * dy) * r.f[8], v = (-s * dx + c * dy) * r.f[9];
+      const float qv = u * u + v * v;
+      const bool rim = qv > 0.998f && qv < 1.002f;
+      const float val = qv <= 0.998f ? amp * sqrtf(fmaxf(1.0f - qv, 0.0f)) : 0.0f;
+      if (rim) marks |= 1u << q;
+      else T.acc[q] += val;
+    }
+    while (marks) {
+      const int q = __builtin_ctz(marks);
+      marks &= marks - 1u;
+      const int ii = q == 0 ? T.pi[0] : (q == 1 ? T.pi[1] : (q == 2 ? T.pi[2] : T.pi[3]));
+      const int jj = q == 0 ? T.pj[0] : (q == 1 ? T.pj[1] : (q == 2 ? T.pj[2] : T.pj[3]));
+      const float add = ellipsoid_rim(r, ii, jj);
+      if (q == 0) T.acc[0] += add;
+      else if (q == 1) T.acc[1] += add;
+      else if (q == 2) T.acc[2] += add;
+      else T.acc[3] += add;
+    }
   }
-  if (kind == 1.0f) {
-    if (R.x1 - 0.5f - r.f[0] < -r.f[16] || R.x0 + 0.5f - r.f[0] > r.f[16] || R.y1 - 0.5f - r.f[1] < -r.f[17] ||
-        R.y0 + 0.5f - r.f[1] > r.f[17])
-      return 0.0f;
-    return ellipsoid_opd(r, i, j);
-  }
-  return 0.0f;
 }
 
 // Lane `lane` of the wave owns pixels lane, lane+64, lane+128, lane+192 of the
@@ -226,12 +307,6 @@ __device__ __forceinline__ float contribution(const PRec& r, const SubRect& R, i
 // all particles in id order that keeps those whose box meets the tile.  All three visit the same
 // particles in the same order, so the sums are identical.  `seg`: kSegSort ints
 // of LDS; the workgroup is this single wave.
-struct TileAcc {
-  int pi[4], pj[4];
-  SubRect R[4];
-  float acc[4];
-};
-
 __device__ __forceinline__ void raster_ids(const FrameDev& F, TileAcc& T, int mine, int m) {
 #pragma clang fp contract(off)
   const PRec* __restrict__ recs = F.recs;
@@ -239,8 +314,7 @@ __device__ __forceinline__ void raster_ids(const FrameDev& F, TileAcc& T, int mi
   for (int k = 0; k < m; ++k) {
     const PRec cur = nxt;
     if (k + 1 < m) nxt = recs[__builtin_amdgcn_readlane(mine, k + 1)];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) T.acc[q] += contribution(cur, T.R[q], T.pi[q], T.pj[q]);
+    add_particle(cur, T);
   }
 }
 
@@ -281,9 +355,7 @@ __device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int lan
     for (int64_t p = 0; p < F.n; ++p) {
       const int4 b = F.boxes[p];
       if (b.x > b.y || b.x > x1 || b.y < x0 || b.z > y1 || b.w < y0) continue;
-      const PRec r = F.recs[p];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) T.acc[q] += contribution(r, T.R[q], T.pi[q], T.pj[q]);
+      add_particle(F.recs[p], T);
     }
   }
 #pragma unroll
@@ -291,26 +363,29 @@ __device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int lan
 }
 
 // ---- F6: pass 1, rows --------------------------------------------------------
+// Workgroup g transforms rows [g RPB, (g + 1) RPB); the band keeps its row blocks
+// of RB >= RPB rows, so a workgroup fills RPB of the RB entries of each column.
 template <int LOGW, int MAXR>
-__device__ __forceinline__ void pass1_body(const FrameDev& F, int rb, const float2* __restrict__ tw, char* lds) {
+__device__ __forceinline__ void pass1_body(const FrameDev& F, int g, const float2* __restrict__ tw, char* lds) {
 #pragma clang fp contract(off)
-  constexpr int W = 1 << LOGW, RB = rows_per_block(W);
+  constexpr int W = 1 << LOGW, RB = rows_per_block(W), RPB = rows_per_fft_block(W);
   float2* buf = reinterpret_cast<float2*>(lds);
   const int t = threadIdx.x;
-  const float* src = F.opd + (size_t)rb * RB * W;
+  const float* src = F.opd + (size_t)g * RPB * W;
   const float pk = F.phase_k;
-  for (int idx = t; idx < RB * W; idx += kThreads) {
+  for (int idx = t; idx < RPB * W; idx += kThreads) {
     float s, c;
     sincosf(pk * src[idx], &s, &c);
     buf[idx] = make_float2(c, s);
   }
   __syncthreads();
-  Stages<W, RB, -1, 1, LOGW, MAXR>::run(buf, tw);
+  Stages<W, RPB, -1, 1, LOGW, MAXR>::run(buf, tw);
   const int kx_lo = F.o.kx_lo, kx_n = F.o.kx_n;
-  float2* dst = F.band + (size_t)rb * kx_n * RB;
-  for (int idx = t; idx < kx_n * RB; idx += kThreads) {
-    const int b = idx / RB, r = idx - b * RB;
-    dst[idx] = buf[r * W + ((kx_lo + b) & (W - 1))];
+  const int row0 = g * RPB, blk = row0 / RB, r0 = row0 % RB;
+  float2* dst = F.band + (size_t)blk * kx_n * RB + r0;
+  for (int idx = t; idx < kx_n * RPB; idx += kThreads) {
+    const int b = idx / RPB, r = idx - b * RPB;
+    dst[(size_t)b * RB + r] = buf[r * W + ((kx_lo + b) & (W - 1))];
   }
   __syncthreads();
 }
@@ -371,7 +446,7 @@ constexpr int kNoiseChunk = 4;                                   // pairs per la
 constexpr int kNoiseQueueBytes = kThreads * 2 * kNoiseChunk * 16;  // uint4 entries, 32 KB
 
 __host__ __device__ constexpr int pass3_buf_bytes(int W) {
-  return rows_per_block(W) * W * 8 > kNoiseQueueBytes ? rows_per_block(W) * W * 8 : kNoiseQueueBytes;
+  return rows_per_fft_block(W) * W * 8 > kNoiseQueueBytes ? rows_per_fft_block(W) * W * 8 : kNoiseQueueBytes;
 }
 
 // Inclusive prefix sum over the 64 lanes of a wave.
@@ -456,20 +531,21 @@ __device__ __forceinline__ void noise_rows(const FrameDev& F, float scale, int64
 }
 
 template <int LOGW, int MAXR>
-__device__ __forceinline__ void pass3_body(const FrameDev& F, int rb, const float2* __restrict__ tw, char* lds) {
+__device__ __forceinline__ void pass3_body(const FrameDev& F, int g, const float2* __restrict__ tw, char* lds) {
 #pragma clang fp contract(off)
-  constexpr int W = 1 << LOGW, RB = rows_per_block(W), NP = RB * W / 2;
+  constexpr int W = 1 << LOGW, RB = rows_per_block(W), RPB = rows_per_fft_block(W), NP = RPB * W / 2;
   constexpr int PP = (NP + kThreads - 1) / kThreads;
   float2* buf = reinterpret_cast<float2*>(lds);
   double* red = reinterpret_cast<double*>(lds + pass3_buf_bytes(W));
   const OpticsArgs& o = F.o;
   const int t = threadIdx.x;
-  for (int idx = t; idx < RB * W; idx += kThreads) buf[idx] = make_float2(0.0f, 0.0f);
+  for (int idx = t; idx < RPB * W; idx += kThreads) buf[idx] = make_float2(0.0f, 0.0f);
   __syncthreads();
-  const float2* src = F.band + (size_t)rb * o.kx_n * RB;
-  for (int idx = t; idx < o.kx_n * RB; idx += kThreads) {
-    const int b = idx / RB, r = idx - b * RB;
-    buf[r * W + ((o.kx_lo + b) & (W - 1))] = src[idx];
+  const int row0 = g * RPB, blk = row0 / RB, r0 = row0 % RB;
+  const float2* src = F.band + (size_t)blk * o.kx_n * RB + r0;
+  for (int idx = t; idx < o.kx_n * RPB; idx += kThreads) {
+    const int b = idx / RPB, r = idx - b * RPB;
+    buf[r * W + ((o.kx_lo + b) & (W - 1))] = src[(size_t)b * RB + r];
   }
   const bool noise = o.photons > 0.0f;
   if (noise) {
@@ -488,11 +564,11 @@ __device__ __forceinline__ void pass3_body(const FrameDev& F, int rb, const floa
     const double mean = red[0] / (hw * hw);
     scale = mean > 0.0 ? (float)((double)o.photons / mean) : 0.0f;
   }
-  Stages<W, RB, 1, 1, LOGW, MAXR>::run(buf, tw);
+  Stages<W, RPB, 1, 1, LOGW, MAXR>::run(buf, tw);
   const float inv = o.inv_hw;
-  float* dst = F.intensity + (size_t)rb * RB * W;
+  float* dst = F.intensity + (size_t)row0 * W;
   if (!(scale > 0.0f)) {
-    for (int idx = t; idx < RB * W; idx += kThreads) {
+    for (int idx = t; idx < RPB * W; idx += kThreads) {
       const float2 e = buf[idx];
       const float er = e.x * inv, ei = e.y * inv;
       dst[idx] = er * er + ei * ei;
@@ -517,7 +593,7 @@ __device__ __forceinline__ void pass3_body(const FrameDev& F, int rb, const floa
     }
   }
   __syncthreads();
-  noise_rows<NP>(F, scale, (int64_t)rb * RB * W, Ipix, dst, lds);
+  noise_rows<NP>(F, scale, (int64_t)row0 * W, Ipix, dst, lds);
 }
 
 }  // namespace osog
