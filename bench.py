@@ -70,13 +70,17 @@ def measured_counters(kernel):
     stamp = [l for l in lines if l.startswith("# kernel sources: sha1 ")]
     if not stamp or stamp[0].split()[4] != source_hash():
         return None
+    head = [l.split() for l in lines if l.startswith("kernel ")]
+    if not head:
+        return None
+    cols = head[0][1:]
     for l in lines:
         f = l.split()
         if f and not l.startswith("#") and f[0].startswith(kernel):
-            # kernel name may contain spaces ("k_pass1<11, 8>"): numbers are the last 6 fields
-            fetch, write, total, winst, avg_us, valu = map(float, f[-6:])
-            return {"traffic": total * 1e6, "fetch": fetch * 1e6, "write": write * 1e6,
-                    "valu_winst": winst, "valu_busy": valu / 100.0}
+            # the kernel name may contain spaces ("k_pass1<11, 8>"): the numbers are the last fields
+            v = dict(zip(cols, map(float, f[-len(cols):])))
+            return {"traffic": v["total_MB"] * 1e6, "fetch": v["fetch_MB"] * 1e6, "write": v["write_MB"] * 1e6,
+                    "valu_winst": v["valu_winst"], "valu_busy": v["valu%"] / 100.0}
     return None
 
 

@@ -22,10 +22,14 @@
 
 namespace osog {
 
+// Workgroups of consecutive row groups fill the two halves of the same band
+// pieces, so each XCD (workgroup i runs on XCD i mod 8) takes one contiguous run
+// of row groups and the halves meet in one L2.  per_xcd * 8 >= groups.
 template <int LOGW, int MAXR>
-__global__ void __launch_bounds__(kThreads) k_pass1(FrameDev F, const float2* __restrict__ tw) {
+__global__ void __launch_bounds__(kThreads) k_pass1(FrameDev F, const float2* __restrict__ tw, int per_xcd) {
   __shared__ __align__(16) char lds[rows_per_fft_block(1 << LOGW) * (1 << LOGW) * sizeof(float2)];
-  pass1_body<LOGW, MAXR>(F, blockIdx.x, tw, lds);
+  const int g = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+  if (g * rows_per_fft_block(1 << LOGW) < F.H) pass1_body<LOGW, MAXR>(F, g, tw, lds);
 }
 
 // Column b of the band lives in 32-byte pieces (RB rows) next to columns b +- 1,
@@ -39,9 +43,10 @@ __global__ void __launch_bounds__(kThreads) k_pass2(FrameDev F, const float2* __
 }
 
 template <int LOGW, int MAXR>
-__global__ void __launch_bounds__(kThreads) k_pass3(FrameDev F, const float2* __restrict__ tw) {
+__global__ void __launch_bounds__(kThreads) k_pass3(FrameDev F, const float2* __restrict__ tw, int per_xcd) {
   __shared__ __align__(16) char lds[pass3_buf_bytes(1 << LOGW) + kThreads * sizeof(double)];
-  pass3_body<LOGW, MAXR>(F, blockIdx.x, tw, lds);
+  const int g = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
+  if (g * rows_per_fft_block(1 << LOGW) < F.H) pass3_body<LOGW, MAXR>(F, g, tw, lds);
 }
 
 // ------------------------------------------------------------ dispatch -------
@@ -62,10 +67,10 @@ hipError_t launch_pass1(const FramePlan& p, const float* opd, FrameBufs& b, cons
                         hipStream_t s) {
   FrameDev F = make_dev(p, b);
   F.opd = const_cast<float*>(opd);
-  const int rbn = p.H / rows_per_fft_block(p.W);
+  const int rbn = p.H / rows_per_fft_block(p.W), per = (rbn + kXcds - 1) / kXcds;
 #define L1(LG)                                                                              \
-  if (p.fft_radix == 4) hipLaunchKernelGGL((k_pass1<LG, 4>), dim3(rbn), dim3(kThreads), 0, s, F, tw); \
-  else hipLaunchKernelGGL((k_pass1<LG, 8>), dim3(rbn), dim3(kThreads), 0, s, F, tw)
+  if (p.fft_radix == 4) hipLaunchKernelGGL((k_pass1<LG, 4>), dim3(per * kXcds), dim3(kThreads), 0, s, F, tw, per); \
+  else hipLaunchKernelGGL((k_pass1<LG, 8>), dim3(per * kXcds), dim3(kThreads), 0, s, F, tw, per)
   OSOG_SIZE_SWITCH(p.logW, L1)
 #undef L1
   return hipGetLastError();
@@ -88,10 +93,10 @@ hipError_t launch_pass3(const FramePlan& p, FrameBufs& b, const float2* tw, floa
                         hipStream_t s) {
   FrameDev F = make_dev(p, b);
   F.intensity = intensity;
-  const int rbn = p.H / rows_per_fft_block(p.W);
+  const int rbn = p.H / rows_per_fft_block(p.W), per = (rbn + kXcds - 1) / kXcds;
 #define L3(LG)                                                                              \
-  if (p.fft_radix == 4) hipLaunchKernelGGL((k_pass3<LG, 4>), dim3(rbn), dim3(kThreads), 0, s, F, tw); \
-  else hipLaunchKernelGGL((k_pass3<LG, 8>), dim3(rbn), dim3(kThreads), 0, s, F, tw)
+  if (p.fft_radix == 4) hipLaunchKernelGGL((k_pass3<LG, 4>), dim3(per * kXcds), dim3(kThreads), 0, s, F, tw, per); \
+  else hipLaunchKernelGGL((k_pass3<LG, 8>), dim3(per * kXcds), dim3(kThreads), 0, s, F, tw, per)
   OSOG_SIZE_SWITCH(p.logW, L3)
 #undef L3
   return hipGetLastError();
