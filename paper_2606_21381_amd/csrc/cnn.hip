@@ -111,12 +111,123 @@ __device__ __forceinline__ uint16_t gather_b(const ConvArgs& a, int k, int n) {
   }
 }
 
+// ---- vectorised tile loads -------------------------------------------------------
+// When the channel dimension that runs along a 16-wide k step (FWD: Ci, DGRAD: Co)
+// or along a group of 8 rows / columns (WGRAD: Ci and Co) is a multiple of 16 / 8,
+// a step's elements are contiguous channels of one pixel and one tap: they are
+// fetched 8 at a time (16 bytes) with the pixel's coordinates computed once.
+__device__ __forceinline__ uint4 ld16(const uint16_t* p) { return *reinterpret_cast<const uint4*>(p); }
+
+__device__ __forceinline__ uint4 relu_mask8(uint4 g, uint4 y) {
+  // bf16 gradient kept where the bf16 activation is > 0 (the ReLU was open)
+  uint32_t gv[4] = {g.x, g.y, g.z, g.w}, yv[4] = {y.x, y.y, y.z, y.w}, o[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t ylo = yv[q] & 0xFFFFu, yhi = yv[q] >> 16;
+    const uint32_t mlo = (ylo != 0u && !(ylo & 0x8000u)) ? 0xFFFFu : 0u;
+    const uint32_t mhi = (yhi != 0u && !(yhi & 0x8000u)) ? 0xFFFF0000u : 0u;
+    o[q] = gv[q] & (mlo | mhi);
+  }
+  return make_uint4(o[0], o[1], o[2], o[3]);
+}
+
+__device__ __forceinline__ void put8_col(uint16_t (*S)[16], int row0, int kk, uint4 v) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    S[row0 + 2 * q][kk] = (uint16_t)(w[q] & 0xFFFFu);
+    S[row0 + 2 * q + 1][kk] = (uint16_t)(w[q] >> 16);
+  }
+}
+
+template <int MODE, int BM>
+__device__ __forceinline__ void load_a_vec(const ConvArgs& a, uint16_t (*As)[16], int m0, int k0, int kend, int t) {
+  const ConvGeom& g = a.g;
+  const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+  if (MODE == CONV_FWD) {
+    const int tap = k0 / g.Ci, ci0 = k0 - tap * g.Ci, ky = tap / 3, kx = tap - 3 * (tap / 3);
+    for (int e = t; e < BM * 2; e += 256) {
+      const int r = e >> 1, h = e & 1, m = m0 + r;
+      uint4 v = z;
+      if (m < a.M) {
+        const int hw = g.Ho * g.Wo, b = m / hw, rr = m - b * hw, oy = rr / g.Wo, ox = rr - oy * g.Wo;
+        const int iy = oy * g.stride - 1 + ky, ix = ox * g.stride - 1 + kx;
+        if (iy >= 0 && iy < g.Hi && ix >= 0 && ix < g.Wi)
+          v = ld16(a.x + (((int64_t)b * g.Hi + iy) * g.Wi + ix) * g.Ci + ci0 + 8 * h);
+      }
+      *reinterpret_cast<uint4*>(&As[r][8 * h]) = v;
+    }
+  } else if (MODE == CONV_DGRAD) {
+    const int tap = k0 / g.Co, co0 = k0 - tap * g.Co, ky = tap / 3, kx = tap - 3 * (tap / 3);
+    for (int e = t; e < BM * 2; e += 256) {
+      const int r = e >> 1, h = e & 1, m = m0 + r;
+      uint4 v = z;
+      if (m < a.M) {
+        const int hw = g.Hi * g.Wi, b = m / hw, rr = m - b * hw, y = rr / g.Wi, x = rr - y * g.Wi;
+        const int ny = y + 1 - ky, nx = x + 1 - kx;
+        if (ny >= 0 && nx >= 0 && ny % g.stride == 0 && nx % g.stride == 0) {
+          const int oy = ny / g.stride, ox = nx / g.stride;
+          if (oy < g.Ho && ox < g.Wo) {
+            const int64_t at = (((int64_t)b * g.Ho + oy) * g.Wo + ox) * g.Co + co0 + 8 * h;
+            v = relu_mask8(ld16(a.gy + at), ld16(a.y + at));
+          }
+        }
+      }
+      *reinterpret_cast<uint4*>(&As[r][8 * h]) = v;
+    }
+  } else {
+    const int hw = g.Ho * g.Wo;
+    for (int e = t; e < (BM / 8) * 16; e += 256) {
+      const int kk = e & 15, gi = e >> 4, m = m0 + 8 * gi, k = k0 + kk;
+      uint4 v = z;
+      if (m < a.M && k < kend) {
+        const int tap = m / g.Ci, ci0 = m - tap * g.Ci, ky = tap / 3, kx = tap - 3 * (tap / 3);
+        const int b = k / hw, rr = k - b * hw, oy = rr / g.Wo, ox = rr - oy * g.Wo;
+        const int iy = oy * g.stride - 1 + ky, ix = ox * g.stride - 1 + kx;
+        if (iy >= 0 && iy < g.Hi && ix >= 0 && ix < g.Wi)
+          v = ld16(a.x + (((int64_t)b * g.Hi + iy) * g.Wi + ix) * g.Ci + ci0);
+      }
+      put8_col(As, 8 * gi, kk, v);
+    }
+  }
+}
+
+template <int MODE, int BN>
+__device__ __forceinline__ void load_b_vec(const ConvArgs& a, uint16_t (*Bs)[16], int n0, int k0, int kend, int t) {
+  const ConvGeom& g = a.g;
+  const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+  if (MODE == CONV_FWD) {
+    for (int e = t; e < (BN / 8) * 16; e += 256) {
+      const int kk = e / (BN / 8), c = e - kk * (BN / 8), n = n0 + 8 * c;
+      const uint4 v = (n < a.N && k0 + kk < kend) ? ld16(a.w + (int64_t)(k0 + kk) * g.Co + n) : z;
+      put8_col(Bs, 8 * c, kk, v);
+    }
+  } else if (MODE == CONV_DGRAD) {
+    const int tap = k0 / g.Co, co0 = k0 - tap * g.Co;
+    for (int e = t; e < BN * 2; e += 256) {
+      const int c = e >> 1, h = e & 1, n = n0 + c;
+      const uint4 v = n < a.N ? ld16(a.w + ((int64_t)tap * g.Ci + n) * g.Co + co0 + 8 * h) : z;
+      *reinterpret_cast<uint4*>(&Bs[c][8 * h]) = v;
+    }
+  } else {
+    for (int e = t; e < (BN / 8) * 16; e += 256) {
+      const int kk = e & 15, c = e >> 4, n = n0 + 8 * c, k = k0 + kk;
+      uint4 v = z;
+      if (n < a.N && k < kend) {
+        const int64_t at = (int64_t)k * g.Co + n;
+        v = relu_mask8(ld16(a.gy + at), ld16(a.y + at));
+      }
+      put8_col(Bs, 8 * c, kk, v);
+    }
+  }
+}
+
 // One workgroup computes a BM x BN tile of C with 4 waves (2 x 2), each wave a
 // (BM/2) x (BN/2) block of 16 x 16 MFMA tiles.  K advances 16 at a time through
 // LDS tiles stored [row][16] so every MFMA operand is one 8-byte LDS read:
 // A lane l reads row l%16, k 4(l/16)..+3; B lane l reads column l%16 likewise;
 // C lane l holds rows 4(l/16)..+3 of column l%16 (v_mfma_f32_16x16x16_bf16).
-template <int MODE, int BM, int BN>
+template <int MODE, int BM, int BN, bool VA, bool VB>
 __global__ void __launch_bounds__(256) k_conv_gemm(ConvArgs a) {
   constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
   __shared__ __align__(16) uint16_t As[BM][16];
@@ -135,13 +246,21 @@ __global__ void __launch_bounds__(256) k_conv_gemm(ConvArgs a) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int k0 = kbeg; k0 < kend; k0 += 16) {
-    for (int e = t; e < BM * 16; e += 256) {
-      const int r = e >> 4, kk = e & 15, m = m0 + r, k = k0 + kk;
-      As[r][kk] = (m < a.M && k < kend) ? gather_a<MODE>(a, m, k) : (uint16_t)0;
+    if constexpr (VA) {
+      load_a_vec<MODE, BM>(a, As, m0, k0, kend, t);
+    } else {
+      for (int e = t; e < BM * 16; e += 256) {
+        const int r = e >> 4, kk = e & 15, m = m0 + r, k = k0 + kk;
+        As[r][kk] = (m < a.M && k < kend) ? gather_a<MODE>(a, m, k) : (uint16_t)0;
+      }
     }
-    for (int e = t; e < BN * 16; e += 256) {
-      const int c = e >> 4, kk = e & 15, n = n0 + c, k = k0 + kk;
-      Bs[c][kk] = (n < a.N && k < kend) ? gather_b<MODE>(a, k, n) : (uint16_t)0;
+    if constexpr (VB) {
+      load_b_vec<MODE, BN>(a, Bs, n0, k0, kend, t);
+    } else {
+      for (int e = t; e < BN * 16; e += 256) {
+        const int c = e >> 4, kk = e & 15, n = n0 + c, k = k0 + kk;
+        Bs[c][kk] = (n < a.N && k < kend) ? gather_b<MODE>(a, k, n) : (uint16_t)0;
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -200,73 +319,91 @@ __global__ void __launch_bounds__(256) k_cnn_pool(const uint16_t* __restrict__ a
   p[b * C + c] = s / (float)hw;
 }
 
-// Dense head, one workgroup over the whole batch (fixed order):
+// Dense head, one 128-thread workgroup per sample:
 //   h = relu(W7^T p + b7) [64], out = W8^T h + b8 [4];
-//   with targets: loss = mean (out - t)^2 and the gradients of the head's
-//   parameters (written into grads) and of p (gp [B][128]).
-__global__ void __launch_bounds__(256) k_cnn_head(const float* __restrict__ p, int B,
-                                                  const float* __restrict__ W7, const float* __restrict__ b7,
-                                                  const float* __restrict__ W8, const float* __restrict__ b8,
-                                                  float* __restrict__ pred, const float* __restrict__ targets,
-                                                  float* __restrict__ gW7, float* __restrict__ gb7,
-                                                  float* __restrict__ gW8, float* __restrict__ gb8,
-                                                  float* __restrict__ gp, float* __restrict__ loss) {
+//   with targets: the sample's loss term (out - t)^2 summed / (4 B), the output
+//   and hidden gradients go, gh (kept per sample) and the pooled gradient gp.
+__global__ void __launch_bounds__(128) k_cnn_head_fwd(const float* __restrict__ p, int B,
+                                                      const float* __restrict__ W7, const float* __restrict__ b7,
+                                                      const float* __restrict__ W8, const float* __restrict__ b8,
+                                                      float* __restrict__ pred, const float* __restrict__ targets,
+                                                      float* __restrict__ hs, float* __restrict__ gos,
+                                                      float* __restrict__ ghs, float* __restrict__ gp,
+                                                      float* __restrict__ loss_b) {
   __shared__ float h[64], go[4], gh[64], pp[128];
-  __shared__ float acc_loss;
-  const int t = threadIdx.x;
-  // zero the head gradients (each thread owns a strided subset)
-  if (targets) {
-    for (int i = t; i < 128 * 64; i += 256) gW7[i] = 0.0f;
-    for (int i = t; i < 64; i += 256) gb7[i] = 0.0f;
-    for (int i = t; i < 64 * 4; i += 256) gW8[i] = 0.0f;
-    if (t < 4) gb8[t] = 0.0f;
-    if (t == 0) acc_loss = 0.0f;
+  const int t = threadIdx.x, b = blockIdx.x;
+  pp[t] = p[b * 128 + t];
+  __syncthreads();
+  if (t < 64) {
+    float s = b7[t];
+    for (int i = 0; i < 128; ++i) s += W7[i * 64 + t] * pp[i];
+    h[t] = fmaxf(s, 0.0f);
+    hs[b * 64 + t] = h[t];
   }
   __syncthreads();
-  for (int b = 0; b < B; ++b) {
-    if (t < 128) pp[t] = p[b * 128 + t];
-    __syncthreads();
-    if (t < 64) {
-      float s = b7[t];
-      for (int i = 0; i < 128; ++i) s += W7[i * 64 + t] * pp[i];
-      h[t] = fmaxf(s, 0.0f);
+  if (t < 4) {
+    float s = b8[t];
+    for (int i = 0; i < 64; ++i) s += W8[i * 4 + t] * h[i];
+    pred[b * 4 + t] = s;
+    if (targets) {
+      go[t] = 2.0f * (s - targets[b * 4 + t]) / (float)(4 * B);
+      gos[b * 4 + t] = go[t];
     }
-    __syncthreads();
-    if (t < 4) {
-      float s = b8[t];
-      for (int i = 0; i < 64; ++i) s += W8[i * 4 + t] * h[i];
-      pred[b * 4 + t] = s;
-      if (targets) go[t] = 2.0f * (s - targets[b * 4 + t]) / (float)(4 * B);
-    }
-    __syncthreads();
-    if (!targets) continue;
-    if (t == 0) {
-      float l = 0.0f;
-      for (int k = 0; k < 4; ++k) {
-        const float d = pred[b * 4 + k] - targets[b * 4 + k];
-        l += d * d;
-      }
-      acc_loss += l / (float)(4 * B);
-    }
-    if (t < 4) gb8[t] += go[t];
-    for (int i = t; i < 64 * 4; i += 256) gW8[i] += h[i / 4] * go[i % 4];
-    if (t < 64) {
-      float s = 0.0f;
-      for (int k = 0; k < 4; ++k) s += W8[t * 4 + k] * go[k];
-      gh[t] = h[t] > 0.0f ? s : 0.0f;
-    }
-    __syncthreads();
-    if (t < 64) gb7[t] += gh[t];
-    for (int i = t; i < 128 * 64; i += 256) gW7[i] += pp[i / 64] * gh[i % 64];
-    if (t < 128) {
-      float s = 0.0f;
-      for (int k = 0; k < 64; ++k) s += W7[t * 64 + k] * gh[k];
-      gp[b * 128 + t] = s;
-    }
-    __syncthreads();
   }
-  if (targets && t == 0) *loss = acc_loss;
+  __syncthreads();
+  if (!targets) return;
+  if (t == 0) {
+    float l = 0.0f;
+    for (int k = 0; k < 4; ++k) {
+      const float d = pred[b * 4 + k] - targets[b * 4 + k];
+      l += d * d;
+    }
+    loss_b[b] = l / (float)(4 * B);
+  }
+  if (t < 64) {
+    float s = 0.0f;
+    for (int k = 0; k < 4; ++k) s += W8[t * 4 + k] * go[k];
+    gh[t] = h[t] > 0.0f ? s : 0.0f;
+    ghs[b * 64 + t] = gh[t];
+  }
+  __syncthreads();
+  float s = 0.0f;
+  for (int k = 0; k < 64; ++k) s += W7[t * 64 + k] * gh[k];
+  gp[b * 128 + t] = s;
 }
+
+// Head parameter gradients and the loss: one thread per output, each a sum over
+// the batch in sample order.
+__global__ void __launch_bounds__(256) k_cnn_head_grad(const float* __restrict__ p, const float* __restrict__ hs,
+                                                       const float* __restrict__ gos, const float* __restrict__ ghs,
+                                                       const float* __restrict__ loss_b, int B,
+                                                       float* __restrict__ gW7, float* __restrict__ gb7,
+                                                       float* __restrict__ gW8, float* __restrict__ gb8,
+                                                       float* __restrict__ loss) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  float s = 0.0f;
+  if (q < 128 * 64) {
+    const int i = q / 64, j = q % 64;
+    for (int b = 0; b < B; ++b) s += p[b * 128 + i] * ghs[b * 64 + j];
+    gW7[q] = s;
+  } else if (q < 128 * 64 + 64) {
+    const int j = q - 128 * 64;
+    for (int b = 0; b < B; ++b) s += ghs[b * 64 + j];
+    gb7[j] = s;
+  } else if (q < 128 * 64 + 64 + 256) {
+    const int e = q - 128 * 64 - 64, j = e / 4, k = e % 4;
+    for (int b = 0; b < B; ++b) s += hs[b * 64 + j] * gos[b * 4 + k];
+    gW8[e] = s;
+  } else if (q < 128 * 64 + 64 + 256 + 4) {
+    const int k = q - 128 * 64 - 64 - 256;
+    for (int b = 0; b < B; ++b) s += gos[b * 4 + k];
+    gb8[k] = s;
+  } else if (q == 128 * 64 + 64 + 256 + 4) {
+    for (int b = 0; b < B; ++b) s += loss_b[b];
+    *loss = s;
+  }
+}
+constexpr int kHeadGradOutputs = 128 * 64 + 64 + 256 + 4 + 1;
 
 // dL/d(last activations) from the pooled gradient: gy[b][i][c] = gp[b][c] / hw.
 __global__ void __launch_bounds__(256) k_cnn_unpool(const float* __restrict__ gp, int B, int hw, int C,
@@ -278,20 +415,27 @@ __global__ void __launch_bounds__(256) k_cnn_unpool(const float* __restrict__ gp
   gy[e] = f2bf(gp[b * C + c] / (float)hw);
 }
 
-// Bias-gradient partials: part[chunk][c] = sum over the chunk's pixels of the
-// ReLU-masked output gradient.
+// Bias-gradient partials: part[blk][c] = sum over the block's pixels of the
+// ReLU-masked output gradient of channel c.  C divides 256: the 256 / C threads
+// of one channel take every (256 / C)-th pixel and are then summed in order.
 __global__ void __launch_bounds__(256) k_cnn_bias_partials(const uint16_t* __restrict__ y,
                                                            const uint16_t* __restrict__ gy, int64_t npix,
                                                            int C, int64_t chunk, float* __restrict__ part) {
-  const int c = threadIdx.x;
-  if (c >= C) return;
+  __shared__ float red[256];
+  const int t = threadIdx.x, c = t % C, r = t / C, R = 256 / C;
   const int64_t p0 = (int64_t)blockIdx.x * chunk, p1 = min(npix, p0 + chunk);
   float s = 0.0f;
-  for (int64_t p = p0; p < p1; ++p) {
+  for (int64_t p = p0 + r; p < p1; p += R) {
     const uint16_t yv = y[p * C + c];
     if (yv != 0 && !(yv & 0x8000u)) s += bf2f(gy[p * C + c]);
   }
-  part[(int64_t)blockIdx.x * C + c] = s;
+  red[t] = s;
+  __syncthreads();
+  if (t < C) {
+    float tot = 0.0f;
+    for (int k = 0; k < R; ++k) tot += red[k * C + t];
+    part[(int64_t)blockIdx.x * C + t] = tot;
+  }
 }
 
 // out[i] = sum over s of part[s][i], in order of s.
@@ -363,6 +507,8 @@ struct CnnPlan {
   int split[6];
 };
 
+constexpr int kBiasBlocks = 1024;  // bias-gradient partial sums per layer (at most)
+
 static int64_t wgrad_chunk(const CnnPlan& P, int l) {
   const int64_t K = (int64_t)P.B * P.hs[l + 1] * P.ws[l + 1];
   return (K + P.split[l] - 1) / P.split[l];
@@ -394,12 +540,18 @@ static CnnPlan cnn_plan(int B, int H, int W) {
   size_t part = 0;
   for (int l = 0; l < 6; ++l) {
     const int64_t K = (int64_t)B * P.hs[l + 1] * P.ws[l + 1];
-    // split the pixel reduction so each split holds ~16K pixels (at most 512 splits)
-    int s = (int)std::min<int64_t>(512, std::max<int64_t>(1, K / 16384));
+    // split the pixel reduction so that the weight-gradient GEMM has about 2048
+    // workgroups (at most 512 splits, at least 256 pixels each)
+    const int M = 9 * kLayers[l].Ci, N = kLayers[l].Co;
+    const int bm = N <= 32 ? 128 : 64, bn = N <= 32 ? 32 : 64;
+    const int64_t tiles = (int64_t)((M + bm - 1) / bm) * ((N + bn - 1) / bn);
+    int64_t sp = (2048 + tiles - 1) / tiles;
+    sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / 256));
+    int s = (int)std::min<int64_t>(512, std::max<int64_t>(1, sp));
     P.split[l] = s;
-    part = std::max(part, (size_t)s * 9 * kLayers[l].Ci * kLayers[l].Co);
-    part = std::max(part, (size_t)s * kLayers[l].Co);
+    part = std::max(part, (size_t)s * M * N);
   }
+  part = std::max(part, (size_t)kBiasBlocks * 128);
   P.part_elems = part;
   return P;
 }
@@ -415,6 +567,10 @@ struct CnnBufs {
   float* gpool;       // [B][128]
   float* pred;        // [B][4]
   float* loss;        // [1]
+  float* hs;          // [B][64] hidden activations of the head
+  float* gos;         // [B][4] output gradients
+  float* ghs;         // [B][64] hidden gradients
+  float* loss_b;      // [B] per-sample loss terms
   size_t total;
 };
 
@@ -433,6 +589,10 @@ static CnnBufs cnn_carve(void* ws, const CnnPlan& P) {
   b.gpool = (float*)take((size_t)P.B * 128 * 4);
   b.pred = (float*)take((size_t)P.B * 4 * 4);
   b.loss = (float*)take(256);
+  b.hs = (float*)take((size_t)P.B * 64 * 4);
+  b.gos = (float*)take((size_t)P.B * 4 * 4);
+  b.ghs = (float*)take((size_t)P.B * 64 * 4);
+  b.loss_b = (float*)take((size_t)P.B * 4);
   b.total = off;
   return b;
 }
@@ -441,15 +601,35 @@ size_t cnn_workspace_bytes(int B, int H, int W) { return cnn_carve(nullptr, cnn_
 
 static unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// Vectorised loads need the channel runs described above (16-byte aligned); the
+// A and B operands are decided separately.
+template <int MODE>
+static bool conv_vec_a(const ConvArgs& a) {
+  if (MODE == CONV_FWD) return a.g.Ci % 16 == 0;
+  if (MODE == CONV_DGRAD) return a.g.Co % 16 == 0;
+  return a.g.Ci % 8 == 0;
+}
+template <int MODE>
+static bool conv_vec_b(const ConvArgs& a) {
+  if (MODE == CONV_FWD) return a.g.Co % 8 == 0;
+  if (MODE == CONV_DGRAD) return a.g.Co % 16 == 0;
+  return a.g.Co % 8 == 0;
+}
+
+template <int MODE, int BM, int BN>
+static void launch_tile(const ConvArgs& a, dim3 grid, hipStream_t s) {
+  const bool va = conv_vec_a<MODE>(a), vb = conv_vec_b<MODE>(a);
+  if (va && vb) hipLaunchKernelGGL((k_conv_gemm<MODE, BM, BN, true, true>), grid, dim3(256), 0, s, a);
+  else if (vb) hipLaunchKernelGGL((k_conv_gemm<MODE, BM, BN, false, true>), grid, dim3(256), 0, s, a);
+  else if (va) hipLaunchKernelGGL((k_conv_gemm<MODE, BM, BN, true, false>), grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_conv_gemm<MODE, BM, BN, false, false>), grid, dim3(256), 0, s, a);
+}
+
 template <int MODE>
 static hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
-  if (a.N <= 32) {
-    dim3 grid((a.M + 127) / 128, (a.N + 31) / 32, MODE == CONV_WGRAD ? (a.K + a.k_chunk - 1) / a.k_chunk : 1);
-    hipLaunchKernelGGL((k_conv_gemm<MODE, 128, 32>), grid, dim3(256), 0, s, a);
-  } else {
-    dim3 grid((a.M + 63) / 64, (a.N + 63) / 64, MODE == CONV_WGRAD ? (a.K + a.k_chunk - 1) / a.k_chunk : 1);
-    hipLaunchKernelGGL((k_conv_gemm<MODE, 64, 64>), grid, dim3(256), 0, s, a);
-  }
+  const int kz = MODE == CONV_WGRAD ? (a.K + a.k_chunk - 1) / a.k_chunk : 1;
+  if (a.N <= 32) launch_tile<MODE, 128, 32>(a, dim3((a.M + 127) / 128, (a.N + 31) / 32, kz), s);
+  else launch_tile<MODE, 64, 64>(a, dim3((a.M + 63) / 64, (a.N + 63) / 64, kz), s);
   return hipGetLastError();
 }
 
@@ -487,9 +667,11 @@ static hipError_t cnn_run(const CnnPlan& P, const CnnBufs& b, const float* image
   }
   const int hw6 = P.hs[6] * P.ws[6];
   hipLaunchKernelGGL(k_cnn_pool, dim3(P.B), dim3(256), 0, s, b.act + P.x_off[6], hw6, 128, b.pool);
-  hipLaunchKernelGGL(k_cnn_head, dim3(1), dim3(256), 0, s, b.pool, P.B, params + O.w7, params + O.b7,
-                     params + O.w8, params + O.b8, b.pred, targets, b.grads + O.w7, b.grads + O.b7,
-                     b.grads + O.w8, b.grads + O.b8, b.gpool, b.loss);
+  hipLaunchKernelGGL(k_cnn_head_fwd, dim3(P.B), dim3(128), 0, s, b.pool, P.B, params + O.w7, params + O.b7,
+                     params + O.w8, params + O.b8, b.pred, targets, b.hs, b.gos, b.ghs, b.gpool, b.loss_b);
+  if (targets)
+    hipLaunchKernelGGL(k_cnn_head_grad, dim3((kHeadGradOutputs + 255) / 256), dim3(256), 0, s, b.pool, b.hs, b.gos,
+                       b.ghs, b.loss_b, P.B, b.grads + O.w7, b.grads + O.b7, b.grads + O.w8, b.grads + O.b8, b.loss);
   if (!targets) return hipGetLastError();
   // backward through the convolutions
   uint16_t* gy = b.ga0;
@@ -515,11 +697,12 @@ static hipError_t cnn_run(const CnnPlan& P, const CnnBufs& b, const float* image
     const int64_t nw = (int64_t)a.M * a.N;
     hipLaunchKernelGGL(k_cnn_reduce, dim3(blocks(nw)), dim3(256), 0, s, b.part, nsplit, nw, b.grads + O.w[l]);
     // bias gradient
-    const int64_t chunk = (npix + 255) / 256;
-    hipLaunchKernelGGL(k_cnn_bias_partials, dim3((unsigned)((npix + chunk - 1) / chunk)), dim3(256), 0, s,
-                       a.y, gy, npix, kLayers[l].Co, chunk, b.part);
-    hipLaunchKernelGGL(k_cnn_reduce, dim3(blocks(kLayers[l].Co)), dim3(256), 0, s, b.part,
-                       (int)((npix + chunk - 1) / chunk), (int64_t)kLayers[l].Co, b.grads + O.b[l]);
+    const int64_t chunk = std::max<int64_t>(256, (npix + kBiasBlocks - 1) / kBiasBlocks);
+    const int nbb = (int)((npix + chunk - 1) / chunk);
+    hipLaunchKernelGGL(k_cnn_bias_partials, dim3((unsigned)nbb), dim3(256), 0, s, a.y, gy, npix, kLayers[l].Co,
+                       chunk, b.part);
+    hipLaunchKernelGGL(k_cnn_reduce, dim3(blocks(kLayers[l].Co)), dim3(256), 0, s, b.part, nbb,
+                       (int64_t)kLayers[l].Co, b.grads + O.b[l]);
     if (l > 0) {  // input gradient
       ConvArgs d = a;
       d.out_bf16 = gx;
