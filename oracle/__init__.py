@@ -10,6 +10,7 @@ may import it; the product path never does.
   optics.py   exit wave, DFT, pupil/defocus, BF / DIC / oblique, |E|^2, direct DFT
   noise.py    Philox4x32-10 and Poisson shot noise
   grad.py     central finite-difference gradients, solver loss
+  cnn.py      the learned initializer's network in float64 PyTorch (autograd gradients)
 """
 from __future__ import annotations
 
