@@ -146,6 +146,59 @@ def test_pair_overflow_fallback_is_bitwise_identical():
     assert torch.equal(o1, o2) and torch.equal(I1, I2)
 
 
+def crowded_frame(seed=11):
+    """256^2 brightfield frame whose particles crowd into a few tiles: 700 small
+    prisms and ellipsoids in a 48x48 px patch (tiles of 100-400 particles: the
+    LDS sort) and 500 more centred in one 16x16 tile (more than its bucket of
+    ceil((32 * 1200 + 256) / 256) = 152 ids: the id-ordered scan)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a = workloads.mixed(rng, 700, 256, 256)
+    a[0] = rng.uniform(100, 148, 700)
+    a[1] = rng.uniform(60, 108, 700)
+    a[3] = rng.uniform(1.5, 4, 700)
+    a[4] = np.where(a[7] > 0.5, rng.uniform(1.5, 4, 700), a[3])
+    b = workloads.mixed(rng, 500, 256, 256)
+    b[0] = rng.uniform(200, 208, 500)
+    b[1] = rng.uniform(200, 208, 500)
+    b[3] = rng.uniform(1, 3, 500)
+    b[4] = np.where(b[7] > 0.5, rng.uniform(1, 3, 500), b[3])
+    soa = workloads.f32(np.concatenate([a, b], axis=1))
+    opt = workloads.OpticsSpec(mode=workloads.BRIGHTFIELD, na=0.4)
+    return workloads.Frame(256, 256, soa, opt, np.array([1.0, 0, 0, 0], np.float32), "crowded")
+
+
+def test_crowded_tiles_sorted_and_scanned_paths():
+    r = R()
+    fr = crowded_frame()
+    soa, g = dev_soa(fr.soa), dev_globals(fr.globals4)
+    keys, pids, ts, counts, P = r.bin_pairs(soa, fr.H, fr.W)
+    ref = oracle.binning.bin_pairs(fr.soa, fr.H, fr.W, 16, 16)
+    per_tile = np.diff(ref["tile_start"])
+    say("crowded: pairs %d, max per tile %d, tiles over 64: %d, over 152: %d" % (
+        P, per_tile.max(), (per_tile > 64).sum(), (per_tile > 152).sum()))
+    assert (per_tile > 64).sum() > 0 and (per_tile > 152).sum() > 0
+    assert P == len(ref["keys"])
+    assert np.array_equal(keys.cpu().numpy(), ref["keys"])
+    assert np.array_equal(pids.cpu().numpy(), ref["pids"])
+    assert np.array_equal(ts.cpu().numpy(), ref["tile_start"])
+    I, opd = r.render(soa, fr.H, fr.W, fr.optics, g, want_opd=True)
+    torch.cuda.synchronize()
+    ref_opd = oracle.raster.opd(fr.soa, fr.H, fr.W)
+    e = float(np.abs(opd.cpu().numpy() - ref_opd).max())
+    ref_I = oracle.optics.intensity(ref_opd, oracle_optics(fr.optics), 1.0, 0.0, 0.0)
+    e_i = rel_l2(I.cpu().numpy(), ref_I)
+    say("crowded: OPD max abs %.3e um, I rel L2 %.3e" % (e, e_i))
+    assert e <= 1e-5 and e_i <= 1e-4
+    # a tiling whose tiles hold everything differently must give the same canvas
+    r.set_tiling(8, 32)
+    try:
+        I2, opd2 = r.render(soa, fr.H, fr.W, fr.optics, g, want_opd=True)
+        torch.cuda.synchronize()
+    finally:
+        r.set_tiling(16, 16)
+    assert torch.equal(opd, opd2) and torch.equal(I, I2)
+
+
 @pytest.mark.parametrize("mode", [0, 1, 2])
 def test_empty_canvas(mode):
     r = R()
