@@ -127,3 +127,36 @@ def test_backward_deterministic_and_autograd():
     torch.cuda.synchronize()
     assert np.array_equal(s.grad.cpu().double().numpy(), a[0])
     assert np.array_equal(gl.grad.cpu().double().numpy(), a[1])
+
+
+@pytest.mark.parametrize("kinds,mode", [("mixed", workloads.DIC), ("mixed", workloads.OBLIQUE)])
+def test_dot_product_random_direction(kinds, mode):
+    """<J v, w> = <v, J^T w> along one random direction v over every particle
+    attribute and the three optical globals at once: J v by FP64 central
+    differences of the oracle image, J^T w by the GPU adjoint."""
+    need_gpu()
+    soa, opt, g, w = case(21 + mode, 10, 64, kinds, mode)
+    rng = np.random.Generator(np.random.PCG64(99))
+    scale = np.array([1.0, 1.0, 0.1, 1.0, 1.0, 0.3, 0.005])[:, None]  # px, px, rad, px, px, um, 1
+    v_soa = rng.uniform(-1, 1, (7, soa.shape[1])) * scale
+    v_g = rng.uniform(-1, 1, 3) * np.array([0.3, 0.1, 0.1]) if mode == workloads.DIC else \
+        np.array([rng.uniform(-0.3, 0.3), 0.0, 0.0])
+    gs, gg = gpu_grads(soa, opt, g, w, 64)
+    adj = float(np.sum(gs[:7] * v_soa) + np.dot(gg[:3], v_g))
+    o = oracle_optics(opt)
+    s64 = soa.astype(np.float64)
+    g64 = g.astype(np.float64)
+    vals = []
+    for eps in (1e-5, 5e-6):
+        sp, sm = s64.copy(), s64.copy()
+        sp[:7] += eps * v_soa
+        sm[:7] -= eps * v_soa
+        gp, gm = g64.copy(), g64.copy()
+        gp[:3] += eps * v_g
+        gm[:3] -= eps * v_g
+        vals.append((oracle.grad.loss(sp, 64, 64, o, gp, w) - oracle.grad.loss(sm, 64, 64, o, gm, w)) / (2 * eps))
+    fd = vals[0]
+    say("dot product (%s, mode %d): <Jv,w> %.9e (eps/2: %.9e), <v,J^T w> %.9e, rel %.2e" % (
+        kinds, mode, vals[0], vals[1], adj, abs(adj - fd) / abs(fd)))
+    assert abs(vals[0] - vals[1]) <= 1e-4 * abs(fd)      # the difference quotient has converged
+    assert abs(adj - fd) <= 1e-3 * abs(fd)
