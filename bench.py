@@ -217,6 +217,7 @@ def main():
         "paper_context": "paper: 40,000 particles in under 50 ms on one NVIDIA A100 (1024^2 canvas)",
     }
     if not args.no_extras:
+        res["multimodal"] = bench_multimodal(render, soa, fr, dev)
         res["backward"] = bench_backward(render, soa, g, fr, dev)
         res["batch"] = bench_batch(render, dev)
         res["inverse"] = bench_inverse(dev, learned=args.learned)
@@ -231,6 +232,41 @@ def main():
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(fr)
     print(json.dumps(res), flush=True)
+
+
+def bench_multimodal(render, soa, fr, dev, reps=20):
+    """Brightfield, DIC (with the frame's noise) and oblique images of the headline
+    particle table: one osog_render_multi call against three osog_render calls."""
+    import torch
+    from paper_2606_21381_amd import workloads
+    opts = [workloads.OpticsSpec(mode=workloads.BRIGHTFIELD, na=0.5), fr.optics,
+            workloads.OpticsSpec(mode=workloads.OBLIQUE, na=0.5, tilt_fx=0.3 * 0.5 / 0.55)]
+    g = torch.tensor([[float(fr.globals4[0]), 0, 0, 0], list(map(float, fr.globals4)),
+                      [float(fr.globals4[0]), 0, 0, 0]], dtype=torch.float32, device=dev)
+    outs = [torch.empty((fr.H, fr.W), dtype=torch.float32, device=dev) for _ in opts]
+
+    def multi():
+        render.render_multi(soa, fr.H, fr.W, opts, g, out=outs)
+
+    def singles():
+        for k, o in enumerate(opts):
+            render.render(soa, fr.H, fr.W, o, g[k], out=outs[k])
+
+    res = {}
+    for name, fn in (("multi", multi), ("three_singles", singles)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name + "_ms"] = round(e0.elapsed_time(e1) / reps, 4)
+    res["workload"] = "dic2048_n40000 as brightfield + DIC + oblique"
+    res["images_per_s"] = round(3000.0 / res["multi_ms"], 1)
+    return res
 
 
 def bench_backward(render, soa, g, fr, dev, reps=20):

@@ -120,6 +120,28 @@ osog_status osog_render(osog_context* ctx, void* stream, int32_t height, int32_t
                         const float* globals, float* opd_out, float* intensity_out,
                         void* workspace, size_t workspace_bytes);
 
+/* Several imaging modalities of one particle table, pixel-aligned (paper Sec.
+ * III, the multi-modal output of one geometry buffer): binning, rasterisation
+ * and the row FFT run once over the union of the modes' in-band spectrum
+ * columns; the column pass and the row IFFT (with each mode's noise) run per
+ * mode.  Each intensity_out[m] is bitwise identical to osog_render with
+ * optics[m], globals[m] and the same tiling.
+ *   n_modes        1..64
+ *   optics         host osog_optics[n_modes]; all share wavelength_um, pixel_um
+ *                  and n_medium (one OPD, one phase); mode, NA, shear angle,
+ *                  tilt, photons and seed may differ
+ *   globals        device float[n_modes][4]
+ *   intensity_out  host array of n_modes device pointers, each float[H][W]
+ *   opd_out        device float[H][W] or NULL
+ *   workspace      as for osog_render_backward (osog_workspace_size with
+ *                  with_backward = 1)
+ * Errors: OSOG_ERR_INVALID_ARGUMENT for a bad count, NULL pointer or optics that
+ * differ in wavelength, pixel size or medium index; otherwise as osog_render. */
+osog_status osog_render_multi(osog_context* ctx, void* stream, int32_t height, int32_t width,
+                              const float* soa, int64_t n, int64_t ld, int32_t n_modes,
+                              const osog_optics* optics, const float* globals, float* const* intensity_out,
+                              float* opd_out, void* workspace, size_t workspace_bytes);
+
 /* Adjoint of the noiseless render (the gradient the paper keeps after Eq. 7):
  * given dL/dI (and optionally dL/dOPD) of a real loss L, writes
  *   grad_soa      device float[OSOG_D][ld] or NULL: dL/d(cx, cy, angle, a, b,

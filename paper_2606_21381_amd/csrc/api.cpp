@@ -360,6 +360,65 @@ osog_status osog_render(osog_context* ctx, void* stream, int32_t height, int32_t
   return OSOG_OK;
 }
 
+osog_status osog_render_multi(osog_context* ctx, void* stream, int32_t height, int32_t width,
+                              const float* soa, int64_t n, int64_t ld, int32_t n_modes,
+                              const osog_optics* optics, const float* globals, float* const* intensity_out,
+                              float* opd_out, void* workspace, size_t workspace_bytes) {
+  if (n_modes < 1 || n_modes > 64 || !optics || !intensity_out)
+    return fail(OSOG_ERR_INVALID_ARGUMENT, "need 1 <= n_modes <= 64, optics[n_modes] and intensity_out[n_modes]");
+  if (!globals) return fail(OSOG_ERR_INVALID_ARGUMENT, "globals is NULL");
+  for (int m = 0; m < n_modes; ++m) {
+    osog_status st = check_frame(ctx, height, width, soa, n, ld, &optics[m], globals + 4 * m);
+    if (st != OSOG_OK) return fail(st, "mode " + std::to_string(m) + ": " + g_last_error);
+    if (!intensity_out[m]) return fail(OSOG_ERR_INVALID_ARGUMENT, "intensity_out[" + std::to_string(m) + "] is NULL");
+    if (optics[m].wavelength_um != optics[0].wavelength_um || optics[m].pixel_um != optics[0].pixel_um ||
+        optics[m].n_medium != optics[0].n_medium)
+      return fail(OSOG_ERR_INVALID_ARGUMENT, "all modes must share wavelength_um, pixel_um and n_medium");
+  }
+  if (!workspace) return fail(OSOG_ERR_WORKSPACE, "workspace is NULL");
+  const int th = tile_of(ctx, height, width, 0), tw = tile_of(ctx, height, width, 1);
+  int ppp = 0;
+  for (int cand = 1 << 20; cand >= 1; cand >>= 1)
+    if (frame_workspace_bytes(height, width, n, th, tw, cand, true) <= workspace_bytes) {
+      ppp = cand;
+      break;
+    }
+  if (ppp == 0) return fail(OSOG_ERR_WORKSPACE, "workspace smaller than osog_workspace_size(with_backward=1)");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  int64_t cap = 0;
+  FrameBufs b = carve(workspace, height, width, n, th, tw, ppp, true, &cap);
+  std::vector<FramePlan> plans;
+  int lo = INT_MAX, hi = INT_MIN;
+  for (int m = 0; m < n_modes; ++m) {
+    plans.push_back(make_plan(ctx, height, width, n, ld, optics[m], cap));
+    if (plans.back().kx_n > 0) {
+      lo = std::min(lo, plans.back().kx_lo);
+      hi = std::max(hi, plans.back().kx_lo + plans.back().kx_n - 1);
+    }
+  }
+  // pass 1 once, over the union of the modes' in-band columns
+  FramePlan u = plans[0];
+  u.kx_lo = lo <= hi ? lo : 0;
+  u.kx_n = lo <= hi ? hi - lo + 1 : 0;
+  hipStream_t s = (hipStream_t)stream;
+  float* opd = opd_out ? opd_out : b.opd;
+  if ((e = launch_binning(u, soa, b, s)) != hipSuccess) return hip_fail(e, "osog_render_multi: binning");
+  if ((e = launch_raster(u, b, opd, s)) != hipSuccess) return hip_fail(e, "osog_render_multi: raster");
+  if ((e = launch_pass1(u, opd, b, ctx->twiddle, s)) != hipSuccess) return hip_fail(e, "osog_render_multi: pass 1");
+  // passes 2 and 3 per mode, one after the other in the second band buffer
+  for (int m = 0; m < n_modes; ++m) {
+    FrameBufs bm = b;
+    bm.band = b.band2;
+    if (plans[m].kx_n > 0 &&
+        (e = launch_pass2(plans[m], globals + 4 * m, bm, ctx->twiddle, s, b.band, u.kx_lo, u.kx_n)) != hipSuccess)
+      return hip_fail(e, "osog_render_multi: pass 2");
+    if ((e = launch_pass3(plans[m], bm, ctx->twiddle, intensity_out[m], s)) != hipSuccess)
+      return hip_fail(e, "osog_render_multi: pass 3");
+  }
+  return OSOG_OK;
+}
+
 osog_status osog_render_backward(osog_context* ctx, void* stream, int32_t height, int32_t width,
                                  const float* soa, int64_t n, int64_t ld, const osog_optics* optics,
                                  const float* globals, const float* grad_intensity,

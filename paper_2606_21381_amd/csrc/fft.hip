@@ -77,9 +77,14 @@ hipError_t launch_pass1(const FramePlan& p, const float* opd, FrameBufs& b, cons
 }
 
 hipError_t launch_pass2(const FramePlan& p, const float* globals, FrameBufs& b, const float2* tw,
-                        hipStream_t s) {
+                        hipStream_t s, const float2* band_in, int in_kx_lo, int in_kx_n) {
   FrameDev F = make_dev(p, b);
   F.globals = globals;
+  if (band_in) {
+    F.band_in = band_in;
+    F.in_kx_lo = in_kx_lo;
+    F.in_kx_n = in_kx_n;
+  }
   const int per = (p.kx_n + kXcds - 1) / kXcds;
 #define L2(LG)                                                                                  \
   if (p.fft_radix == 4) hipLaunchKernelGGL((k_pass2<LG, 4>), dim3(per * kXcds), dim3(kThreads), 0, s, F, tw, per); \

@@ -80,7 +80,10 @@ hipError_t launch_bin_outputs(const FramePlan& p, FrameBufs& b, int* keys_out, i
                               int* tile_start, hipStream_t s);
 hipError_t launch_raster(const FramePlan& p, FrameBufs& b, float* opd, hipStream_t s);
 hipError_t launch_pass1(const FramePlan& p, const float* opd, FrameBufs& b, const float2* tw, hipStream_t s);
-hipError_t launch_pass2(const FramePlan& p, const float* globals, FrameBufs& b, const float2* tw, hipStream_t s);
+// pass 2 of a frame; band_in (if not null) is another band holding this frame's
+// columns inside its range [in_kx_lo, in_kx_lo + in_kx_n) (a shared pass 1)
+hipError_t launch_pass2(const FramePlan& p, const float* globals, FrameBufs& b, const float2* tw, hipStream_t s,
+                        const float2* band_in = nullptr, int in_kx_lo = 0, int in_kx_n = 0);
 hipError_t launch_pass3(const FramePlan& p, FrameBufs& b, const float2* tw, float* intensity, hipStream_t s);
 hipError_t launch_philox(const uint32_t* ctr, int64_t count, uint32_t k0, uint32_t k1, uint32_t* out, hipStream_t s);
 

@@ -39,6 +39,10 @@ struct FrameDev {
   int* pids;                       // n_tiles buckets of `cap` particle ids
   float2* band;
   double* colsum;
+  // pass 2 reads its columns from band_in, whose in-band range is [in_kx_lo, in_kx_lo + in_kx_n)
+  // (the frame's own band unless several modalities share one pass 1)
+  const float2* band_in;
+  int in_kx_lo, in_kx_n;
 };
 
 // ---- F1-F3: records, pixel boxes, pairs per particle; tile buckets -----------
@@ -402,7 +406,9 @@ __device__ __forceinline__ void pass2_body(const FrameDev& F, int b, const float
   const int t = threadIdx.x, kx = o.kx_lo + b;
   const int RB = o.rb;
   float2* band = F.band;
-  for (int i = t; i < H; i += kThreads) buf[i] = band[((size_t)(i / RB) * o.kx_n + b) * RB + (i % RB)];
+  const float2* src = F.band_in;
+  const int bi = kx - F.in_kx_lo, in_n = F.in_kx_n;
+  for (int i = t; i < H; i += kThreads) buf[i] = src[((size_t)(i / RB) * in_n + bi) * RB + (i % RB)];
   if (t == 0) band_chord(o, kx, &chord[0], &chord[1]);
   __syncthreads();
   Stages<H, 1, -1, 1, LOGH, MAXR>::run(buf, tw);
@@ -613,6 +619,7 @@ inline FrameDev make_dev(const FramePlan& p, const FrameBufs& b) {
   F.tile_count = b.tile_count; F.tile_first = b.tile_first;
   F.pids = b.pids;
   F.band = b.band; F.colsum = b.colsum;
+  F.band_in = b.band; F.in_kx_lo = p.kx_lo; F.in_kx_n = p.kx_n;
   F.fft_radix = p.fft_radix;
   F.opd = b.opd;
   return F;

@@ -108,6 +108,29 @@ def render(soa: torch.Tensor, H: int, W: int, optics, globals4: torch.Tensor, wa
     return (out, opd_out) if want_opd else out
 
 
+def render_multi(soa: torch.Tensor, H: int, W: int, optics_list, globals_modes: torch.Tensor,
+                 want_opd: bool = False, out=None, workspace: Optional[torch.Tensor] = None):
+    """Several modalities of one particle table, pixel-aligned (one binning, raster
+    and row FFT): list of intensities [H, W] (and the OPD if want_opd).
+    ``globals_modes``: CUDA float32 [n_modes, 4]."""
+    device = soa.device
+    n, ld = _check_soa(soa)
+    m = len(optics_list)
+    g = globals_modes.contiguous()
+    if g.shape != (m, 4) or g.dtype != torch.float32 or g.device != device:
+        raise ValueError("globals_modes must be a float32 [n_modes, 4] tensor on the particle table's device")
+    outs = out if out is not None else [torch.empty((H, W), dtype=torch.float32, device=device) for _ in range(m)]
+    opd = torch.empty((H, W), dtype=torch.float32, device=device) if want_opd else None
+    nb = workspace_size(H, W, n, True, 0, device)
+    ws = workspace if workspace is not None else _workspace(nb, device)
+    opts = (_lib.Optics * m)(*[_lib.make_optics(o) for o in optics_list])
+    ptrs = (ctypes.c_void_p * m)(*[o.data_ptr() for o in outs])
+    _lib.check(_lib.load().osog_render_multi(context(device), _stream(device), H, W, _ptr(soa) if n else None,
+                                              n, ld, m, opts, _ptr(g), ptrs, _ptr(opd), _ptr(ws), ws.numel()),
+               "osog_render_multi")
+    return (outs, opd) if want_opd else outs
+
+
 def render_backward(soa: torch.Tensor, H: int, W: int, optics, globals4: torch.Tensor,
                     grad_intensity: torch.Tensor, grad_opd: Optional[torch.Tensor] = None,
                     need_soa: bool = True, need_globals: bool = True,
