@@ -43,15 +43,20 @@ __device__ __forceinline__ float4 prism_bounds(const PRec& r) {
   return make_float4(r.f[20], r.f[21], r.f[22], r.f[23]);
 }
 
+// Half-extent of the unit pixel along either prism axis, (|cos| + |sin|) / 2,
+// plus a margin for the FP32 rounding of the rotated centre offsets (< 1e-5 px).
+__device__ __forceinline__ float pixel_half_extent(float c, float s) {
+  return 0.5f * (fabsf(c) + fabsf(s)) + 1e-4f;
+}
+
 // Centre-sample test of a pixel against the prism slabs: +1 when the whole pixel
 // is inside (coverage exactly 1), -1 when it is certainly outside, 0 otherwise.
-// The pixel lies in the disc of radius sqrt(2)/2 about its centre.
 __device__ __forceinline__ int prism_classify(const PRec& r, float px, float py, float margin) {
 #pragma clang fp contract(off)
   const float c = r.f[4], s = r.f[5], a = r.f[6], b = r.f[7];
   const float dx = px - r.f[0], dy = py - r.f[1];
   const float u = c * dx + s * dy, v = -s * dx + c * dy;
-  const float hd = 0.70712f;
+  const float hd = pixel_half_extent(c, s);
   if (fabsf(u) > a + hd || fabsf(v) > b + hd) return -1;
   if (fabsf(u) < a - hd - margin && fabsf(v) < b - hd - margin) return 1;
   return 0;
@@ -93,7 +98,7 @@ __device__ __forceinline__ float prism_clip_area(const PRec& r, int i, int j) {
 
 // Exact area of pixel (i, j) covered by the prism footprint of record r (bounds
 // bb from prism_bounds).  Exactly 0 for a pixel outside the bounds and exactly 1
-// for a pixel whose disc is inside both slabs; a single half-plane's box filter
+// for a pixel inside both slabs; a single half-plane's box filter
 // where only one edge reaches the pixel; otherwise the clipped polygon area.
 __device__ __forceinline__ float prism_cover(const PRec& r, const float4& bb, int i, int j) {
 #pragma clang fp contract(off)
@@ -102,7 +107,7 @@ __device__ __forceinline__ float prism_cover(const PRec& r, const float4& bb, in
   const float c = r.f[4], s = r.f[5], a = r.f[6], b = r.f[7];
   const float dx = (fj + 0.5f) - r.f[0], dy = (fi + 0.5f) - r.f[1];
   const float u = c * dx + s * dy, v = -s * dx + c * dy;
-  const float hd = 0.70712f;  // > sqrt(2)/2: the pixel lies in this disc around its centre
+  const float hd = pixel_half_extent(c, s);
   const float du = fabsf(u) - a, dv = fabsf(v) - b;  // signed distances to the nearer edges
   if (du > hd || dv > hd) return 0.0f;
   if (du < -hd && dv < -hd) return 1.0f;

@@ -196,53 +196,67 @@ __device__ __forceinline__ SubRect slot_rect(int first, int tile_w, int tx, int 
 }
 
 struct TileAcc {
-  int pi[4], pj[4];
-  SubRect R[4];
+  int pi[4], pj[4];          // canvas row and column of the lane's pixel in each slot
+  float px[4], py[4];        // that pixel's centre, j + 1/2 and i + 1/2
+  // every lane also holds the bounds of slot (lane & 3), so that the four
+  // wave-uniform slot tests of a particle run as one vector instruction each
+  float sx0, sx1, sy0, sy1;  // pixel-edge bounds of that slot (canvas pixels)
+  float scx, scy, shx, shy;  // centre of its pixel centres, half extents
   float acc[4];
 };
 
-// Adds one particle to the four pixel slots a lane owns.  Per 64-pixel slot, a
-// slot the particle misses is skipped and a slot inside its footprint takes the
-// full amplitude (both wave-uniform); otherwise every lane evaluates its pixel
-// without branching for the common cases -- outside, inside, one edge (the
-// half-plane box filter) for a prism; the centre sample for an ellipsoid -- and
-// only marks the rare costly pixels: a prism pixel two edges reach (the
-// clipped-polygon area) and an ellipsoid pixel within 2e-3 of the rim (FP64).
-// Those are evaluated after the four slots, each lane serving its own marks,
-// so the costly code runs once per particle rather than once per slot.  Every
-// pixel still receives exactly one term per particle, the same value the
-// per-pixel functions (prism_cover, ellipsoid_opd) return, in particle order.
+// Adds one particle to the four pixel slots a lane owns.  The slot tests (does
+// the particle reach the slot; is every pixel centre of the slot deep inside a
+// prism) are evaluated for the four slots at once, one slot per lane, and read
+// back as wave-uniform bit masks: a slot the particle misses is skipped and a
+// slot inside its footprint takes the full amplitude.  In any other slot every
+// lane evaluates its pixel without branching for the common cases -- outside,
+// inside, one edge (the half-plane box filter) for a prism; the centre sample for
+// an ellipsoid -- and only marks the rare costly pixels: a prism pixel two edges
+// reach (the clipped-polygon area) and an ellipsoid pixel within 2e-3 of the rim
+// (FP64).  Those are evaluated after the four slots, each lane serving its own
+// marks, so the costly code runs once per particle rather than once per slot.
+// The offset of a pixel centre from the particle centre is exact in FP32 (both
+// are multiples of the centre's ulp and the difference is small), so the rotated
+// offsets u, v carry ~1e-6 px of rounding and depend on the pixel and the
+// particle alone: the canvas is bitwise the same under every tiling.  Every
+// pixel receives exactly one term per particle, in particle order.
 __device__ __forceinline__ void add_particle(const PRec& r, TileAcc& T) {
 #pragma clang fp contract(off)
   const float kind = r.f[3];
   const float amp = r.f[2];
   unsigned marks = 0u;
+  const float c = r.f[4], s = r.f[5];
   if (kind == 0.0f) {
-    const float c = r.f[4], s = r.f[5], a = r.f[6], b = r.f[7];
-    const float hd = 0.70712f;  // > sqrt(2)/2: a pixel lies in this disc around its centre
+    const float a = r.f[6], b = r.f[7];
     // half-plane box filter constants (as in halfplane_cover; (c, s) and (s, c) share them)
     const float hp_p = fmaxf(fabsf(c), fabsf(s)), hp_q = fminf(fabsf(c), fabsf(s));
     const float hp_h = 0.5f * (hp_p + hp_q), hp_l = 0.5f * (hp_p - hp_q);
+    const float hd = pixel_half_extent(c, s);  // equals hp_h + margin
     const float hp_rp = __builtin_amdgcn_rcpf(hp_p), hp_r2 = __builtin_amdgcn_rcpf(2.0f * hp_p * hp_q);
+    const float bx0 = r.f[20] - 0.5f, bx1 = r.f[21] + 0.5f, by0 = r.f[22] - 0.5f, by1 = r.f[23] + 0.5f;
+    unsigned hit_m, in_m;
+    {  // slot (lane & 3): reached at all; every pixel centre deep inside both slabs
+      const bool hit = !(r.f[21] <= T.sx0 || r.f[20] >= T.sx1 || r.f[23] <= T.sy0 || r.f[22] >= T.sy1);
+      const float sdx = T.scx - r.f[0], sdy = T.scy - r.f[1];
+      const float uc = __builtin_fmaf(c, sdx, s * sdy), vc = __builtin_fmaf(c, sdy, -(s * sdx));
+      const float ux = fabsf(uc) + fabsf(c) * T.shx + fabsf(s) * T.shy;
+      const float vy = fabsf(vc) + fabsf(s) * T.shx + fabsf(c) * T.shy;
+      const bool deep = ux < a - hd && vy < b - hd;
+      hit_m = (unsigned)__ballot(hit) & 15u;
+      in_m = (unsigned)__ballot(hit && deep) & 15u;
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const SubRect& R = T.R[q];
-      if (r.f[21] <= R.x0 || r.f[20] >= R.x1 || r.f[23] <= R.y0 || r.f[22] >= R.y1) continue;
-      {  // every pixel centre of the slot deep inside both slabs: coverage 1 everywhere
-        const float hx = 0.5f * (R.x1 - R.x0 - 1.0f), hy = 0.5f * (R.y1 - R.y0 - 1.0f);
-        const float dx = 0.5f * (R.x0 + R.x1) - r.f[0], dy = 0.5f * (R.y0 + R.y1) - r.f[1];
-        const float ux = fabsf(c * dx + s * dy) + fabsf(c) * hx + fabsf(s) * hy;
-        const float vy = fabsf(-s * dx + c * dy) + fabsf(s) * hx + fabsf(c) * hy;
-        const float lim = 0.70712f + 1e-4f;
-        if (ux < a - lim && vy < b - lim) {
-          T.acc[q] += amp;
-          continue;
-        }
+      if (!((hit_m >> q) & 1u)) continue;
+      if ((in_m >> q) & 1u) {
+        T.acc[q] += amp;
+        continue;
       }
-      const float fj = (float)T.pj[q], fi = (float)T.pi[q];
-      const bool off_box = r.f[21] <= fj || r.f[20] >= fj + 1.0f || r.f[23] <= fi || r.f[22] >= fi + 1.0f;
-      const float dx = (fj + 0.5f) - r.f[0], dy = (fi + 0.5f) - r.f[1];
-      const float u = c * dx + s * dy, v = -s * dx + c * dy;
+      // the pixel [j, j+1) x [i, i+1) misses the footprint bounds (exact shifts by 1/2)
+      const bool off_box = T.px[q] >= bx1 || T.px[q] <= bx0 || T.py[q] >= by1 || T.py[q] <= by0;
+      const float dx = T.px[q] - r.f[0], dy = T.py[q] - r.f[1];
+      const float u = __builtin_fmaf(c, dx, s * dy), v = __builtin_fmaf(c, dy, -(s * dx));
       const float du = fabsf(u) - a, dv = fabsf(v) - b;
       const bool outside = off_box || du > hd || dv > hd;
       const bool inside = du < -hd && dv < -hd;
@@ -274,15 +288,15 @@ __device__ __forceinline__ void add_particle(const PRec& r, TileAcc& T) {
       else T.acc[3] += add;
     }
   } else if (kind == 1.0f) {
-    const float c = r.f[4], s = r.f[5];
+    // slot (lane & 3) meets the bounding box of the pixel centres the ellipse reaches
+    const bool hit = !(T.sx1 - 0.5f - r.f[0] < -r.f[16] || T.sx0 + 0.5f - r.f[0] > r.f[16] ||
+                       T.sy1 - 0.5f - r.f[1] < -r.f[17] || T.sy0 + 0.5f - r.f[1] > r.f[17]);
+    const unsigned hit_m = (unsigned)__ballot(hit) & 15u;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const SubRect& R = T.R[q];
-      if (R.x1 - 0.5f - r.f[0] < -r.f[16] || R.x0 + 0.5f - r.f[0] > r.f[16] || R.y1 - 0.5f - r.f[1] < -r.f[17] ||
-          R.y0 + 0.5f - r.f[1] > r.f[17])
-        continue;
-      const float dx = ((float)T.pj[q] + 0.5f) - r.f[0], dy = ((float)T.pi[q] + 0.5f) - r.f[1];
-      const float u = (c * dx + s * dy) * r.f[8], v = (-s * dx + c * dy) * r.f[9];
+      if (!((hit_m >> q) & 1u)) continue;
+      const float dx = T.px[q] - r.f[0], dy = T.py[q] - r.f[1];
+      const float u = __builtin_fmaf(c, dx, s * dy) * r.f[8], v = __builtin_fmaf(c, dy, -(s * dx)) * r.f[9];
       const float qv = u * u + v * v;
       const bool rim = qv > 0.998f && qv < 1.002f;
       const float val = qv <= 0.998f ? amp * sqrtf(fmaxf(1.0f - qv, 0.0f)) : 0.0f;
@@ -332,8 +346,20 @@ __device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int lan
     const int q = lane + 64 * k, li = q / tile_w, lj = q - li * tile_w;
     T.pi[k] = ty * tile_h + li;
     T.pj[k] = tx * tile_w + lj;
-    T.R[k] = slot_rect(64 * k, tile_w, tx, ty, tile_h);
+    T.px[k] = (float)T.pj[k] + 0.5f;
+    T.py[k] = (float)T.pi[k] + 0.5f;
     T.acc[k] = 0.0f;
+  }
+  {
+    const SubRect R = slot_rect(64 * (lane & 3), tile_w, tx, ty, tile_h);
+    T.sx0 = R.x0;
+    T.sx1 = R.x1;
+    T.sy0 = R.y0;
+    T.sy1 = R.y1;
+    T.scx = 0.5f * (R.x0 + R.x1);
+    T.scy = 0.5f * (R.y0 + R.y1);
+    T.shx = 0.5f * (R.x1 - R.x0 - 1.0f);
+    T.shy = 0.5f * (R.y1 - R.y0 - 1.0f);
   }
   const int cnt = F.tile_count[tile];
   const bool overflow = cnt > (int)F.cap;     // the bucket could not hold the tile's ids
