@@ -60,6 +60,15 @@ __device__ __forceinline__ void make_record(float cx, float cy, float ang, float
       ylo = fminf(ylo, r.f[9 + 2 * k]); yhi = fmaxf(yhi, r.f[9 + 2 * k]);
     }
     r.f[20] = cx + xlo; r.f[21] = cx + xhi; r.f[22] = cy + ylo; r.f[23] = cy + yhi;
+    // per-particle constants of the raster's pixel tests: the half-plane box
+    // filter of an edge whose normal is (c, s) or (s, c) (p = max, q = min of
+    // |c|, |s|), and the footprint bounds widened by half a pixel (exact shifts)
+    const float p = fmaxf(fabsf(c), fabsf(s)), q = fminf(fabsf(c), fabsf(s));
+    r.f[24] = 0.5f * (p + q);
+    r.f[25] = 0.5f * (p - q);
+    r.f[26] = __builtin_amdgcn_rcpf(p);
+    r.f[27] = __builtin_amdgcn_rcpf(fmaxf(2.0f * p * q, 1e-30f));
+    r.f[28] = r.f[20] - 0.5f; r.f[29] = r.f[21] + 0.5f; r.f[30] = r.f[22] - 0.5f; r.f[31] = r.f[23] + 0.5f;
   } else {
     r.f[3] = 1.0f;
     r.f[8] = 1.0f / a;

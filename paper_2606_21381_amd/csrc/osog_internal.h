@@ -14,8 +14,8 @@ namespace osog {
 constexpr int kThreads = 256;     // every kernel runs 256-thread workgroups (4 wave64)
 constexpr int kTwN = 4096;        // twiddle table length (largest FFT)
 constexpr int kDefaultPairsPerParticle = 32;
-constexpr int kXcds = 8;
-constexpr int kMaxBucket = 1024;  // ids per tile bucket at most (the raster sorts up to this many)          // MI355X: 8 accelerator dies, each with its own L2
+constexpr int kXcds = 8;          // MI355X: 8 accelerator dies, each with its own L2
+constexpr int kMaxBucket = 1024;  // ids per tile bucket at most (the raster sorts up to this many)
 
 // Per-particle raster record, 128 bytes, written once by the prepare kernel and
 // read by the raster through the scalar cache.
@@ -24,6 +24,9 @@ constexpr int kMaxBucket = 1024;  // ids per tile bucket at most (the raster sor
 //   prism     f[8..15]  footprint corner offsets from the centre (x0,y0,...,x3,y3), CCW
 //             f[16..19] edge slopes dy/dx of edges 0-1, 1-2, 2-3, 3-0
 //             f[20..23] footprint bounds xmin, xmax, ymin, ymax in canvas pixels
+//             f[24..27] half-plane filter constants (p+q)/2, (p-q)/2, 1/p, 1/(2pq)
+//                       with p = max(|cos|,|sin|), q = min (1/(2pq) kept finite)
+//             f[28..31] the bounds widened by half a pixel (xmin-1/2, xmax+1/2, ...)
 //   ellipsoid f[8] 1/a f[9] 1/b f[10..11] cos as double f[12..13] sin as double
 //             f[14] dn f[15] h     (the FP64 rim refinement uses these)
 //             f[16], f[17] half extents of the bounding box, enlarged (see ellipse_extent)

@@ -195,6 +195,12 @@ __device__ __forceinline__ SubRect slot_rect(int first, int tile_w, int tx, int 
   return R;
 }
 
+// A select the compiler keeps as v_cndmask (both operands already computed)
+// rather than turning into a divergent branch.
+__device__ __forceinline__ float sel(bool c, float x, float y) {
+  return __builtin_unpredictable(c) ? x : y;
+}
+
 struct TileAcc {
   int pi[4], pj[4];          // canvas row and column of the lane's pixel in each slot
   float px[4], py[4];        // that pixel's centre, j + 1/2 and i + 1/2
@@ -230,21 +236,19 @@ __device__ __forceinline__ void add_particle(const PRec& r, TileAcc& T) {
   if (kind == 0.0f) {
     const float a = r.f[6], b = r.f[7];
     // half-plane box filter constants (as in halfplane_cover; (c, s) and (s, c) share them)
-    const float hp_p = fmaxf(fabsf(c), fabsf(s)), hp_q = fminf(fabsf(c), fabsf(s));
-    const float hp_h = 0.5f * (hp_p + hp_q), hp_l = 0.5f * (hp_p - hp_q);
-    const float hd = pixel_half_extent(c, s);  // equals hp_h + margin
-    const float hp_rp = __builtin_amdgcn_rcpf(hp_p), hp_r2 = __builtin_amdgcn_rcpf(2.0f * hp_p * hp_q);
-    const float bx0 = r.f[20] - 0.5f, bx1 = r.f[21] + 0.5f, by0 = r.f[22] - 0.5f, by1 = r.f[23] + 0.5f;
+    const float hp_h = r.f[24], hp_l = r.f[25], hp_rp = r.f[26], hp_r2 = r.f[27];
+    const float hd = hp_h + 1e-4f;  // pixel_half_extent(c, s)
+    const bool a_ok = a >= hd, b_ok = b >= hd;  // the pixel cannot reach both edges of a pair
     unsigned hit_m, in_m;
     {  // slot (lane & 3): reached at all; every pixel centre deep inside both slabs
-      const bool hit = !(r.f[21] <= T.sx0 || r.f[20] >= T.sx1 || r.f[23] <= T.sy0 || r.f[22] >= T.sy1);
+      const bool hit = !((r.f[21] <= T.sx0) | (r.f[20] >= T.sx1) | (r.f[23] <= T.sy0) | (r.f[22] >= T.sy1));
       const float sdx = T.scx - r.f[0], sdy = T.scy - r.f[1];
       const float uc = __builtin_fmaf(c, sdx, s * sdy), vc = __builtin_fmaf(c, sdy, -(s * sdx));
       const float ux = fabsf(uc) + fabsf(c) * T.shx + fabsf(s) * T.shy;
       const float vy = fabsf(vc) + fabsf(s) * T.shx + fabsf(c) * T.shy;
-      const bool deep = ux < a - hd && vy < b - hd;
+      const bool deep = (ux < a - hd) & (vy < b - hd);
       hit_m = (unsigned)__ballot(hit) & 15u;
-      in_m = (unsigned)__ballot(hit && deep) & 15u;
+      in_m = (unsigned)__ballot(hit & deep) & 15u;
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -253,27 +257,31 @@ __device__ __forceinline__ void add_particle(const PRec& r, TileAcc& T) {
         T.acc[q] += amp;
         continue;
       }
-      // the pixel [j, j+1) x [i, i+1) misses the footprint bounds (exact shifts by 1/2)
-      const bool off_box = T.px[q] >= bx1 || T.px[q] <= bx0 || T.py[q] >= by1 || T.py[q] <= by0;
+      // straight-line code: every case is a select.  A pixel two edges reach
+      // takes 0 here and its clipped-polygon area below.
+      const bool off_box = (T.px[q] >= r.f[29]) | (T.px[q] <= r.f[28]) | (T.py[q] >= r.f[31]) | (T.py[q] <= r.f[30]);
       const float dx = T.px[q] - r.f[0], dy = T.py[q] - r.f[1];
       const float u = __builtin_fmaf(c, dx, s * dy), v = __builtin_fmaf(c, dy, -(s * dx));
-      const float du = fabsf(u) - a, dv = fabsf(v) - b;
-      const bool outside = off_box || du > hd || dv > hd;
-      const bool inside = du < -hd && dv < -hd;
-      const bool edge_u = dv < -hd && a >= hd;
-      const bool edge_v = !edge_u && du < -hd && b >= hd;
-      // halfplane_cover(t, .) with t = -du (edge_u) or -dv (edge_v), branch-free
+      const float du = fabsf(u) - a, dv = fabsf(v) - b;  // signed distances to the nearer edges
+      const bool in_u = du < -hd, in_v = dv < -hd;
+      const bool inside = in_u & in_v;
+      const bool outside = off_box | (du > hd) | (dv > hd);
+      const bool edge_u = in_v & a_ok;
+      const bool edge = edge_u | (in_u & b_ok);
+      // halfplane_cover(t, .) with t = -du (edge_u) or -dv; beyond the pixel's
+      // half-extent e = 0, so the triangle term gives exactly 0 or 1
       const float t = edge_u ? -du : -dv;
       const float at = fabsf(t);
-      const float lin = 0.5f + t * hp_rp;
-      const float e = hp_h - at;
+      const float e = fmaxf(hp_h - at, 0.0f);
       const float tri = e * e * hp_r2;
-      const float quad = t > 0.0f ? 1.0f - tri : tri;
-      const float hpv = t >= hp_h ? 1.0f : (t <= -hp_h ? 0.0f : (at <= hp_l ? lin : quad));
-      float cover = 0.0f;
-      if (!outside) cover = inside ? 1.0f : ((edge_u || edge_v) ? hpv : 0.0f);
-      if (!outside && !inside && !edge_u && !edge_v) marks |= 1u << q;
-      else T.acc[q] += amp * cover;
+      const float lin = 0.5f + t * hp_rp;
+      float cover = sel(t > 0.0f, 1.0f - tri, tri);
+      cover = sel(at <= hp_l, lin, cover);
+      cover = sel(edge, cover, 0.0f);
+      cover = sel(inside, 1.0f, cover);
+      cover = sel(outside, 0.0f, cover);
+      T.acc[q] += amp * cover;
+      marks |= (unsigned)(!(outside | inside | edge)) << q;
     }
     while (marks) {
       const int q = __builtin_ctz(marks);
@@ -289,8 +297,8 @@ __device__ __forceinline__ void add_particle(const PRec& r, TileAcc& T) {
     }
   } else if (kind == 1.0f) {
     // slot (lane & 3) meets the bounding box of the pixel centres the ellipse reaches
-    const bool hit = !(T.sx1 - 0.5f - r.f[0] < -r.f[16] || T.sx0 + 0.5f - r.f[0] > r.f[16] ||
-                       T.sy1 - 0.5f - r.f[1] < -r.f[17] || T.sy0 + 0.5f - r.f[1] > r.f[17]);
+    const bool hit = !((T.sx1 - 0.5f - r.f[0] < -r.f[16]) | (T.sx0 + 0.5f - r.f[0] > r.f[16]) |
+                       (T.sy1 - 0.5f - r.f[1] < -r.f[17]) | (T.sy0 + 0.5f - r.f[1] > r.f[17]));
     const unsigned hit_m = (unsigned)__ballot(hit) & 15u;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -298,10 +306,13 @@ __device__ __forceinline__ void add_particle(const PRec& r, TileAcc& T) {
       const float dx = T.px[q] - r.f[0], dy = T.py[q] - r.f[1];
       const float u = __builtin_fmaf(c, dx, s * dy) * r.f[8], v = __builtin_fmaf(c, dy, -(s * dx)) * r.f[9];
       const float qv = u * u + v * v;
-      const bool rim = qv > 0.998f && qv < 1.002f;
-      const float val = qv <= 0.998f ? amp * sqrtf(fmaxf(1.0f - qv, 0.0f)) : 0.0f;
-      if (rim) marks |= 1u << q;
-      else T.acc[q] += val;
+      // outside: 0; within 2e-3 of the rim: 0 here and the FP64 value below
+      const bool rim = (qv > 0.998f) & (qv < 1.002f);
+      // 1 - q >= 0.002 where the value is kept, so the hardware square root
+      // (within 1 ulp, no denormal scaling needed) serves
+      const float val = sel(qv <= 0.998f, amp * __builtin_amdgcn_sqrtf(fmaxf(1.0f - qv, 0.0f)), 0.0f);
+      T.acc[q] += val;
+      marks |= (unsigned)rim << q;
     }
     while (marks) {
       const int q = __builtin_ctz(marks);
