@@ -20,8 +20,11 @@ from . import raster as _raster
 
 
 def image64(soa64: np.ndarray, H: int, W: int, optics, g64) -> np.ndarray:
-    opd = _raster.opd(np.asarray(soa64, dtype=np.float64), H, W)
-    return _optics.intensity(opd, optics, float(g64[0]), float(g64[1]), float(g64[2]))
+    """Noiseless image of an FP64 table; a [9][n] table is an absorbing one."""
+    soa64 = np.asarray(soa64, dtype=np.float64)
+    opd = _raster.opd(soa64, H, W)
+    tau = _raster.absorbance(soa64, H, W) if soa64.shape[0] == 9 else None
+    return _optics.intensity(opd, optics, float(g64[0]), float(g64[1]), float(g64[2]), tau=tau)
 
 
 def loss(soa64, H, W, optics, g64, weights) -> float:
@@ -37,16 +40,16 @@ def fd_gradients(soa, H, W, optics, globals4, weights, rows=(0, 1, 2, 3, 4, 5, 6
                  delta: float = 1e-5):
     """FD gradients of sum(weights * I) w.r.t. SoA rows ``rows`` and globals 0..2.
 
-    Returns (grad_soa [8][n] FP64 with untouched rows zero, grad_globals [3],
-    flags_soa [8][n] bool, flags_globals [3] bool).
+    Returns (grad_soa [rows of the table][n] FP64 with untouched rows zero,
+    grad_globals [3], flags_soa bool like grad_soa, flags_globals [3] bool).
     """
     soa64 = np.array(soa, dtype=np.float64)
     g64 = np.array(globals4, dtype=np.float64)
-    n = soa64.shape[1]
+    D, n = soa64.shape
     # rounding noise of a central difference is ~ eps |L| / d; never flag below it
     floor = 1e-9 * max(abs(loss(soa64, H, W, optics, g64, weights)), 1.0)
-    gs = np.zeros((8, n))
-    fs = np.zeros((8, n), dtype=bool)
+    gs = np.zeros((D, n))
+    fs = np.zeros((D, n), dtype=bool)
     for r in rows:
         for p in range(n):
             def f(v, r=r, p=p):

@@ -2,7 +2,10 @@
 
 Plain FP64 statement of what the renderer computes from an OPD canvas:
 
-  exit wave      U = A exp(i 2 pi / lambda * OPD), A = 1          (Sec. III.B, Eq. 2)
+  exit wave      U = A exp(i 2 pi / lambda * OPD)                 (Sec. III.B, Eq. 2)
+                 A = 1 for a phase object; with absorption A = exp(-tau), tau the
+                 absorbance canvas (Eq. 4's Beer-Lambert factor, with its Fresnel
+                 transmittance taken as 1 and no caustic term: see the readings)
   spectrum       Ut[ky,kx] = sum_ij U[i,j] exp(-2 pi i (ky i/H + kx j/W))
   pupil          P(f) = circ(|f| <= NA/lambda) exp(i dz sqrt(k0^2 - (2 pi |f|)^2)),
                  k0 = 2 pi n_m / lambda                              (Eq. 3)
@@ -96,25 +99,29 @@ def transfer(H: int, W: int, optics: Optics, defocus_um: float, shear_px: float,
     raise ValueError("unknown mode %r" % optics.mode)
 
 
-def exit_wave(opd: np.ndarray, optics: Optics) -> np.ndarray:
-    """U = exp(i 2 pi / lambda * OPD) (Eq. 2 with A = 1, OPD in micrometres)."""
-    return np.exp(1j * (2.0 * np.pi / optics.wavelength_um) * np.asarray(opd, dtype=np.float64))
+def exit_wave(opd: np.ndarray, optics: Optics, tau=None) -> np.ndarray:
+    """U = A exp(i 2 pi / lambda * OPD) (Eq. 2, OPD in micrometres), A = 1 or,
+    given the absorbance canvas tau, A = exp(-tau) (Eq. 4)."""
+    U = np.exp(1j * (2.0 * np.pi / optics.wavelength_um) * np.asarray(opd, dtype=np.float64))
+    if tau is not None:
+        U = U * np.exp(-np.asarray(tau, dtype=np.float64))
+    return U
 
 
 def field(opd: np.ndarray, optics: Optics, defocus_um: float, shear_px: float = 0.0,
-          bias_rad: float = 0.0, dft=None, idft=None) -> np.ndarray:
+          bias_rad: float = 0.0, dft=None, idft=None, tau=None) -> np.ndarray:
     """Image-plane field E = IDFT(DFT(U) * H); ``dft``/``idft`` default to numpy's FFT."""
     dft = dft or np.fft.fft2
     idft = idft or np.fft.ifft2
     H, W = opd.shape
-    U = exit_wave(opd, optics)
+    U = exit_wave(opd, optics, tau)
     return idft(dft(U) * transfer(H, W, optics, defocus_um, shear_px, bias_rad))
 
 
 def intensity(opd: np.ndarray, optics: Optics, defocus_um: float, shear_px: float = 0.0,
-              bias_rad: float = 0.0, dft=None, idft=None) -> np.ndarray:
+              bias_rad: float = 0.0, dft=None, idft=None, tau=None) -> np.ndarray:
     """Noiseless image I = |E|^2."""
-    E = field(opd, optics, defocus_um, shear_px, bias_rad, dft, idft)
+    E = field(opd, optics, defocus_um, shear_px, bias_rad, dft, idft, tau)
     return E.real * E.real + E.imag * E.imag
 
 

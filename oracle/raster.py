@@ -53,11 +53,12 @@ def opd(soa: np.ndarray, H: int, W: int) -> np.ndarray:
     """OPD canvas [H][W] in micrometres, FP64.
 
     ``soa`` is the [8][ld] particle table (rows: cx, cy, angle, a, b, height, dn,
-    shape).  An FP32 table is widened value by value to FP64; an FP64 table is
-    used as is (finite differences step below FP32 resolution).
+    shape; a ninth row, if present, is ignored).  An FP32 table is widened value
+    by value to FP64; an FP64 table is used as is (finite differences step below
+    FP32 resolution).
     """
     lib = _load()
-    soa = np.ascontiguousarray(soa)
+    soa = np.ascontiguousarray(soa[:8])
     assert soa.ndim == 2 and soa.shape[0] == 8
     n = soa.shape[1]
     out = np.zeros((H, W), dtype=np.float64)
@@ -68,6 +69,22 @@ def opd(soa: np.ndarray, H: int, W: int) -> np.ndarray:
     else:
         raise TypeError("soa must be float32 or float64")
     return out
+
+
+def absorbance(soa: np.ndarray, H: int, W: int) -> np.ndarray:
+    """Absorbance canvas tau [H][W], FP64, of a [9][n] table whose row 8 is the
+    attenuation contrast dmu = mu_particle - mu_solvent [1/um].
+
+    Eq. 4's Beer-Lambert factor is exp(-h (mu_p - mu_s)) for a particle of
+    thickness h; over overlapping particles the exponents add, so
+    tau(x) = sum_p dmu_p t_p(x) with the same thickness t_p of Eq. 1 that the OPD
+    weights by dn_p.  It is that same integral with dmu in the place of dn.
+    """
+    soa = np.asarray(soa)
+    assert soa.ndim == 2 and soa.shape[0] == 9
+    t = np.array(soa[:8], copy=True)
+    t[6] = soa[8]
+    return opd(t, H, W)
 
 
 def opd_at(soa: np.ndarray, H: int, W: int, rows, cols) -> np.ndarray:
