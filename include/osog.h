@@ -59,7 +59,10 @@ enum {
   OSOG_HEIGHT = 5, /* prism height / ellipsoid full central thickness [um]      */
   OSOG_DN = 6,     /* n_particle - n_medium                                     */
   OSOG_SHAPE = 7,  /* < 0.5: prism (box-filtered exact area); else ellipsoid    */
-  OSOG_D = 8
+  OSOG_D = 8,
+  /* absorbing tables (osog_optics.absorption = 1) carry one more row:           */
+  OSOG_DMU = 8,    /* mu_particle - mu_solvent, attenuation contrast [1/um]    */
+  OSOG_D_ABS = 9
 };
 
 /* Static optics of a frame (host memory).  Lengths in micrometres. */
@@ -75,6 +78,11 @@ typedef struct {
   double photons_mean;     /* > 0: Poisson shot noise at this mean photon count/px    */
   uint64_t seed;           /* Philox4x32-10 key of the noise                           */
   uint32_t noise_frame;    /* second Philox counter word (frame index)                 */
+  /* 0: phase object, exit-wave amplitude A = 1, table of OSOG_D rows.
+   * 1: Beer-Lambert absorption (Eq. 4's exponential factor): the table has
+   *    OSOG_D_ABS rows and A = exp(-tau) with the absorbance canvas
+   *    tau = sum over particles of dmu * thickness, built like the OPD. */
+  int32_t absorption;
 } osog_optics;
 
 /* Differentiable per-frame globals live in DEVICE memory, float[4]:
@@ -108,10 +116,13 @@ osog_status osog_workspace_size(const osog_context* ctx, int32_t height, int32_t
                                 int32_t pairs_per_particle, int32_t with_backward, size_t* bytes);
 
 /* Forward render (paper Sec. III, f(Theta) = I):
- *   soa           device float[OSOG_D][ld], ld >= n, n >= 0 (n = 0: empty canvas)
+ *   soa           device float[OSOG_D][ld] (absorbing: float[OSOG_D_ABS][ld]),
+ *                 ld >= n, n >= 0 (n = 0: empty canvas)
  *   optics        host, static optics
  *   globals       device float[4] (see above)
- *   opd_out       device float[height][width] or NULL: OPD canvas [um] (Eq. 2's integral)
+ *   opd_out       device float[height][width] or NULL: OPD canvas [um] (Eq. 2's
+ *                 integral); absorbing: float[2][height][width], the OPD then
+ *                 the absorbance tau
  *   intensity_out device float[height][width]: |E|^2, with shot noise if photons_mean > 0
  *   workspace     device, >= osog_workspace_size(..., with_backward = 0) bytes
  * height, width: powers of two in [32, 4096], multiples of the tile sides. */
@@ -127,12 +138,12 @@ osog_status osog_render(osog_context* ctx, void* stream, int32_t height, int32_t
  * mode.  Each intensity_out[m] is bitwise identical to osog_render with
  * optics[m], globals[m] and the same tiling.
  *   n_modes        1..64
- *   optics         host osog_optics[n_modes]; all share wavelength_um, pixel_um
- *                  and n_medium (one OPD, one phase); mode, NA, shear angle,
- *                  tilt, photons and seed may differ
+ *   optics         host osog_optics[n_modes]; all share wavelength_um, pixel_um,
+ *                  n_medium and absorption (one OPD, one exit wave); mode, NA,
+ *                  shear angle, tilt, photons and seed may differ
  *   globals        device float[n_modes][4]
  *   intensity_out  host array of n_modes device pointers, each float[H][W]
- *   opd_out        device float[H][W] or NULL
+ *   opd_out        device float[H][W] (absorbing: [2][H][W]) or NULL
  *   workspace      as for osog_render_backward (osog_workspace_size with
  *                  with_backward = 1)
  * Errors: OSOG_ERR_INVALID_ARGUMENT for a bad count, NULL pointer or optics that
@@ -144,8 +155,12 @@ osog_status osog_render_multi(osog_context* ctx, void* stream, int32_t height, i
 
 /* Adjoint of the noiseless render (the gradient the paper keeps after Eq. 7):
  * given dL/dI (and optionally dL/dOPD) of a real loss L, writes
- *   grad_soa      device float[OSOG_D][ld] or NULL: dL/d(cx, cy, angle, a, b,
- *                 height, dn); row OSOG_SHAPE is written as 0
+ *   grad_opd      device float[height][width] or NULL: dL/dOPD added to the
+ *                 chain's own; absorbing: float[2][height][width], dL/dOPD then
+ *                 dL/dtau
+ *   grad_soa      device float[OSOG_D][ld] (absorbing: [OSOG_D_ABS][ld]) or NULL:
+ *                 dL/d(cx, cy, angle, a, b, height, dn[, dmu]); row OSOG_SHAPE
+ *                 is written as 0
  *   grad_globals  device float[4] or NULL: dL/d(defocus, shear, bias), [3] = 0
  * Forward intermediates are recomputed inside the call, not stored.  Shot
  * noise is treated as a constant.  workspace: >= osog_workspace_size(...,

@@ -40,6 +40,7 @@ class Optics(ctypes.Structure):
         ("photons_mean", ctypes.c_double),
         ("seed", ctypes.c_uint64),
         ("noise_frame", ctypes.c_uint32),
+        ("absorption", ctypes.c_int32),
     ]
 
 
@@ -143,4 +144,5 @@ def make_optics(spec) -> Optics:
     o.photons_mean = float(spec.photons_mean)
     o.seed = int(spec.seed) & 0xFFFFFFFFFFFFFFFF
     o.noise_frame = int(getattr(spec, "noise_frame", 0)) & 0xFFFFFFFF
+    o.absorption = 1 if getattr(spec, "absorption", 0) else 0
     return o

@@ -15,14 +15,14 @@ from typing import Dict, Optional
 import torch
 
 from . import _lib
-from .render import _check_globals, _check_soa, _ptr, _stream, context, workspace_size
+from .render import _check_globals, _check_soa, _ptr, _stream, context, soa_rows, workspace_size
 
 
 def tune_frame(soa: torch.Tensor, H: int, W: int, optics, globals4: torch.Tensor, reps: int = 5,
                device=None) -> dict:
     """Time every plan on this frame; the context adopts the fastest for H x W."""
     device = soa.device if device is None else torch.device(device)
-    n, ld = _check_soa(soa)
+    n, ld = _check_soa(soa, soa_rows(optics))
     _check_globals(globals4, device)
     out = torch.empty((H, W), dtype=torch.float32, device=device)
     ws = torch.empty(workspace_size(H, W, n, device=device), dtype=torch.uint8, device=device)

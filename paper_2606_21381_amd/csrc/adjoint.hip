@@ -7,9 +7,11 @@
 //   pass 2   U~ = DFT_y(A), G = U~ H, B = IDFT_y(G) g_G = DFT_y(g_B);  g_U~ = conj(H) g_G;
 //                                                   dL/dpsi = Re sum conj(g_G) U~ dH/dpsi;
 //                                                   g_A = IDFT_y(g_U~)
-//   pass 1   A = band of DFT_x(U), U = e^{i phi}   g_U = IDFT_x(g_A zero-filled);
-//                                                   g_OPD = (2 pi/lambda) Im(conj(U) g_U)
-//   raster   OPD = sum_p dn_p t_p                  dL/dtheta_p = sum over p's pixels of g_OPD dOPD/dtheta_p
+//   pass 1   A = band of DFT_x(U),                 g_U = IDFT_x(g_A zero-filled);
+//            U = e^{-tau} e^{i phi}                  g_OPD = (2 pi/lambda) Im(conj(U) g_U)
+//            (tau = 0 without absorption)            g_tau = -Re(conj(U) g_U)
+//   raster   OPD = sum_p dn_p t_p,                 dL/dtheta_p = sum over p's pixels of
+//            tau = sum_p dmu_p t_p                   (g_OPD dn_p + g_tau dmu_p) dt_p/dtheta_p
 //
 // (IDFT here is unnormalised.)  Forward intermediates are recomputed by the
 // caller before these kernels run; nothing of frame size is kept between calls.
@@ -140,12 +142,16 @@ __global__ void __launch_bounds__(kThreads) k_adj_pass2(const float2* __restrict
 }
 
 // ---- adjoint of pass 1 (rows): g_OPD ------------------------------------------
+// (absorbing frames: tau and gtau not null; grad_opd, if given, holds dL/dOPD
+// then dL/dtau, one plane each)
 template <int LOGW>
 __global__ void __launch_bounds__(kThreads) k_adj_pass1(const float2* __restrict__ band2, OpticsArgs o,
                                                         const float* __restrict__ opd,
+                                                        const float* __restrict__ tau,
                                                         const float* __restrict__ grad_opd,
                                                         float phase_k, const float2* __restrict__ tw,
-                                                        float* __restrict__ gopd) {
+                                                        float* __restrict__ gopd, float* __restrict__ gtau,
+                                                        int64_t plane) {
   constexpr int W = 1 << LOGW, RB = rows_per_block(W);
   __shared__ float2 buf[RB * W];
   const int t = threadIdx.x, rb = blockIdx.x;
@@ -162,11 +168,21 @@ __global__ void __launch_bounds__(kThreads) k_adj_pass1(const float2* __restrict
   for (int idx = t; idx < RB * W; idx += kThreads) {
     float s, c;
     sincosf(phase_k * opd[off + idx], &s, &c);
+    if (tau) {  // U = e^{-tau} (c + i s), as pass 1 forms it
+      const float am = expf(-tau[off + idx]);
+      c = am * c;
+      s = am * s;
+    }
     const float2 g = buf[idx];
     // Im(conj(U) g_U) with U = c + i s
     float go = phase_k * (c * g.y - s * g.x);
     if (grad_opd) go += grad_opd[off + idx];
     gopd[off + idx] = go;
+    if (tau) {  // -Re(conj(U) g_U)
+      float gt = -(c * g.x + s * g.y);
+      if (grad_opd) gt += grad_opd[plane + off + idx];
+      gtau[off + idx] = gt;
+    }
   }
 }
 
@@ -199,19 +215,24 @@ __device__ __forceinline__ EdgeClip clip_edge(float px, float py, float qx, floa
   return {(t1 - t0) * sqrtf(dx * dx + dy * dy), 0.5f * (t0 + t1)};
 }
 
+// ABS: the thickness also enters tau with weight dmu; acc[7] = dL/d dmu.
+template <bool ABS>
 __global__ void __launch_bounds__(kThreads) k_adj_raster(const float* __restrict__ soa, int64_t n,
                                                          int64_t ld, const PRec* __restrict__ recs,
                                                          const int4* __restrict__ boxes, int W,
                                                          int tile_h, int tile_w,
                                                          const float* __restrict__ gopd,
+                                                         const float* __restrict__ gtau,
                                                          float* __restrict__ grad_soa) {
-  __shared__ float red[7][kThreads];
+  constexpr int NA = ABS ? 8 : 7;
+  __shared__ float red[NA][kThreads];
   const int t = threadIdx.x;
   const int64_t p = blockIdx.x;
   const PRec r = recs[p];
   const int4 box = boxes[p];
   const float h = soa[5 * ld + p], dn = soa[6 * ld + p];
-  float acc[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  const float dmu = ABS ? soa[8 * ld + p] : 0.0f;
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (r.f[3] >= 0.0f && box.x <= box.y) {
     const int tx0 = box.x / tile_w, tx1 = box.y / tile_w, ty0 = box.z / tile_h, ty1 = box.w / tile_h;
     const int li = t / tile_w, lj = t - li * tile_w;
@@ -223,20 +244,25 @@ __global__ void __launch_bounds__(kThreads) k_adj_raster(const float* __restrict
         const int i = ty * tile_h + li, j = tx * tile_w + lj;
         if (j < box.x || j > box.y || i < box.z || i > box.w) continue;
         const float g = gopd[(int64_t)i * W + j];
-        if (g == 0.0f) continue;
+        const float gt = ABS ? gtau[(int64_t)i * W + j] : 0.0f;
+        if (g == 0.0f && gt == 0.0f) continue;
+        // dL/d(thickness) per unit thickness of this particle at this pixel
+        const float gw = ABS ? g * dn + gt * dmu : g * dn;
         if (prism) {
           const float fj = (float)j, fi = (float)i;
           if (bb.y <= fj || bb.x >= fj + 1.0f || bb.w <= fi || bb.z >= fi + 1.0f) continue;
           const int cls = prism_classify(r, fj + 0.5f, fi + 0.5f, 0.0f);
           if (cls < 0) continue;
-          if (cls > 0) {  // fully covered: only height and dn act
-            acc[5] += g * dn;
+          if (cls > 0) {  // fully covered: only height, dn (and dmu) act
+            acc[5] += gw;
             acc[6] += g * h;
+            if (ABS) acc[7] += gt * h;
             continue;
           }
           const float cov = prism_cover(r, bb, i, j);
-          acc[5] += g * dn * cov;
+          acc[5] += gw * cov;
           acc[6] += g * h * cov;
+          if (ABS) acc[7] += gt * h * cov;
           // corners relative to the pixel corner, CCW: (-a,-b) (a,-b) (a,b) (-a,b)
           const float X0 = fj - r.f[0], Y0 = fi - r.f[1];
           float vx[4], vy[4];
@@ -260,7 +286,7 @@ __global__ void __launch_bounds__(kThreads) k_adj_raster(const float* __restrict
             else if (k == 2) { fang += e.len * (a - 2.0f * a * e.mid); fb += e.len; }
             else { fang += e.len * (b - 2.0f * b * e.mid); fa += e.len; }
           }
-          const float amp = g * r.f[2];
+          const float amp = ABS ? gw * h : g * r.f[2];
           acc[0] += amp * fx;
           acc[1] += amp * fy;
           acc[2] += amp * fang;
@@ -273,9 +299,10 @@ __global__ void __launch_bounds__(kThreads) k_adj_raster(const float* __restrict
           const float q = u * u * ia * ia + v * v * ib * ib;
           if (!(q < 1.0f)) continue;
           const float sq = sqrtf(1.0f - q);
-          acc[5] += g * dn * sq;
+          acc[5] += gw * sq;
           acc[6] += g * h * sq;
-          const float dcq = -g * r.f[2] * 0.5f / fmaxf(sq, 1e-20f);  // d c / d q
+          if (ABS) acc[7] += gt * h * sq;
+          const float dcq = -(ABS ? gw * h : g * r.f[2]) * 0.5f / fmaxf(sq, 1e-20f);  // d c / d q
           const float qu = 2.0f * u * ia * ia, qv = 2.0f * v * ib * ib;
           acc[0] += dcq * (qu * -c + qv * s);
           acc[1] += dcq * (qu * -s + qv * -c);
@@ -286,16 +313,17 @@ __global__ void __launch_bounds__(kThreads) k_adj_raster(const float* __restrict
       }
   }
 #pragma unroll
-  for (int k = 0; k < 7; ++k) red[k][t] = acc[k];
+  for (int k = 0; k < NA; ++k) red[k][t] = acc[k];
   __syncthreads();
   for (int st = kThreads / 2; st > 0; st >>= 1) {
     if (t < st) {
 #pragma unroll
-      for (int k = 0; k < 7; ++k) red[k][t] += red[k][t + st];
+      for (int k = 0; k < NA; ++k) red[k][t] += red[k][t + st];
     }
     __syncthreads();
   }
-  if (t < 8) grad_soa[(int64_t)t * ld + p] = t < 7 ? red[t][0] : 0.0f;
+  // rows 0-6 from acc[0..6], row 7 (shape) = 0, row 8 (dmu) = acc[7]
+  if (t < NA + 1) grad_soa[(int64_t)t * ld + p] = t < 7 ? red[t][0] : (t == 7 ? 0.0f : red[NA - 1][0]);
 }
 
 // grad_globals[k] = sum over columns of colgrad[k][col], fixed order; [3] = 0
@@ -368,11 +396,13 @@ hipError_t launch_adj_pass2(const FramePlan& p, const float* globals, FrameBufs&
   return hipGetLastError();
 }
 
-hipError_t launch_adj_pass1(const FramePlan& p, const float* opd, const float* grad_opd, FrameBufs& b,
-                            const float2* tw, hipStream_t s) {
+hipError_t launch_adj_pass1(const FramePlan& p, const float* opd, const float* tau, const float* grad_opd,
+                            FrameBufs& b, const float2* tw, hipStream_t s) {
   OpticsArgs o = optics_args(p);
-#define K(LG) hipLaunchKernelGGL(k_adj_pass1<LG>, dim3(p.H / p.rb), dim3(kThreads), 0, s, b.band2, o, opd, \
-                                 grad_opd, p.phase_k, tw, b.gopd)
+  const float* ta = p.absorb ? tau : nullptr;
+  const int64_t plane = (int64_t)p.H * p.W;
+#define K(LG) hipLaunchKernelGGL(k_adj_pass1<LG>, dim3(p.H / p.rb), dim3(kThreads), 0, s, b.band2, o, opd, ta, \
+                                 grad_opd, p.phase_k, tw, b.gopd, b.gtau, plane)
   OSOG_SIZE_SWITCH(p.logW, K)
 #undef K
   return hipGetLastError();
@@ -380,9 +410,12 @@ hipError_t launch_adj_pass1(const FramePlan& p, const float* opd, const float* g
 
 hipError_t launch_raster_adjoint(const FramePlan& p, const float* soa, FrameBufs& b, float* grad_soa,
                                  hipStream_t s) {
-  if (p.n > 0)
-    hipLaunchKernelGGL(k_adj_raster, dim3((unsigned)p.n), dim3(kThreads), 0, s, soa, p.n, p.ld, b.recs,
-                       b.boxes, p.W, p.tile_h, p.tile_w, b.gopd, grad_soa);
+  if (p.n > 0 && p.absorb)
+    hipLaunchKernelGGL(k_adj_raster<true>, dim3((unsigned)p.n), dim3(kThreads), 0, s, soa, p.n, p.ld, b.recs,
+                       b.boxes, p.W, p.tile_h, p.tile_w, b.gopd, b.gtau, grad_soa);
+  else if (p.n > 0)
+    hipLaunchKernelGGL(k_adj_raster<false>, dim3((unsigned)p.n), dim3(kThreads), 0, s, soa, p.n, p.ld, b.recs,
+                       b.boxes, p.W, p.tile_h, p.tile_w, b.gopd, b.gtau, grad_soa);
   return hipGetLastError();
 }
 

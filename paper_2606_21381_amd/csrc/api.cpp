@@ -90,11 +90,14 @@ static FrameBufs carve_impl(Carver& c, int H, int W, int64_t n, int tile_h, int 
   b.tile_first = c.take<int>(n_tiles);
   b.pids = c.take<int>((size_t)n_tiles * cap);
   b.opd = c.take<float>(hw);
+  b.tau = c.take<float>(hw);
+  b.absr = c.take<float2>(n > 0 ? n : 1);
   b.band = c.take<float2>(hw);
   b.colsum = c.take<double>(W);
   if (backward) {
     b.band2 = c.take<float2>(hw);
     b.gopd = c.take<float>(hw);
+    b.gtau = c.take<float>(hw);
     b.colgrad = c.take<double>(3 * (size_t)W);
   }
   if (cap_out) *cap_out = cap;
@@ -154,6 +157,8 @@ static osog_status check_optics(const osog_optics* o) {
     return fail(OSOG_ERR_INVALID_ARGUMENT, "optics shear angle and tilt must be finite");
   if (!(o->photons_mean >= 0.0) || !std::isfinite(o->photons_mean))
     return fail(OSOG_ERR_INVALID_ARGUMENT, "optics.photons_mean must be finite and >= 0");
+  if (o->absorption != 0 && o->absorption != 1)
+    return fail(OSOG_ERR_INVALID_ARGUMENT, "optics.absorption must be 0 or 1");
   return OSOG_OK;
 }
 
@@ -217,6 +222,7 @@ FramePlan make_plan(const osog_context* ctx, int H, int W, int64_t n, int64_t ld
   p.seed_lo = (uint32_t)(o.seed & 0xffffffffu);
   p.seed_hi = (uint32_t)(o.seed >> 32);
   p.frame = o.noise_frame;
+  p.absorb = o.absorption ? 1 : 0;
   return p;
 }
 
@@ -233,16 +239,17 @@ hipError_t forward_frame(const osog_context* ctx, const FramePlan& p, const floa
                          const float* globals, FrameBufs& b, float* opd_out, float* intensity,
                          hipStream_t s, bool profile) {
   float* opd = opd_out ? opd_out : b.opd;
+  float* tau = opd_out ? opd_out + (size_t)p.H * p.W : b.tau;  // absorbing frames: second plane
   Profiler* pr = profile ? ctx->prof : nullptr;
   hipError_t e;
   profile_begin(pr, OSOG_STAGE_BINNING, s);
   if ((e = launch_binning(p, soa, b, s)) != hipSuccess) return e;
   profile_end(pr, OSOG_STAGE_BINNING, s);
   profile_begin(pr, OSOG_STAGE_RASTER, s);
-  if ((e = launch_raster(p, b, opd, s)) != hipSuccess) return e;
+  if ((e = launch_raster(p, b, opd, tau, s)) != hipSuccess) return e;
   profile_end(pr, OSOG_STAGE_RASTER, s);
   profile_begin(pr, OSOG_STAGE_PASS1, s);
-  if ((e = launch_pass1(p, opd, b, ctx->twiddle, s)) != hipSuccess) return e;
+  if ((e = launch_pass1(p, opd, tau, b, ctx->twiddle, s)) != hipSuccess) return e;
   profile_end(pr, OSOG_STAGE_PASS1, s);
   if (p.kx_n > 0) {
     profile_begin(pr, OSOG_STAGE_PASS2, s);
@@ -372,8 +379,9 @@ osog_status osog_render_multi(osog_context* ctx, void* stream, int32_t height, i
     if (st != OSOG_OK) return fail(st, "mode " + std::to_string(m) + ": " + g_last_error);
     if (!intensity_out[m]) return fail(OSOG_ERR_INVALID_ARGUMENT, "intensity_out[" + std::to_string(m) + "] is NULL");
     if (optics[m].wavelength_um != optics[0].wavelength_um || optics[m].pixel_um != optics[0].pixel_um ||
-        optics[m].n_medium != optics[0].n_medium)
-      return fail(OSOG_ERR_INVALID_ARGUMENT, "all modes must share wavelength_um, pixel_um and n_medium");
+        optics[m].n_medium != optics[0].n_medium || optics[m].absorption != optics[0].absorption)
+      return fail(OSOG_ERR_INVALID_ARGUMENT,
+                  "all modes must share wavelength_um, pixel_um, n_medium and absorption");
   }
   if (!workspace) return fail(OSOG_ERR_WORKSPACE, "workspace is NULL");
   const int th = tile_of(ctx, height, width, 0), tw = tile_of(ctx, height, width, 1);
@@ -403,9 +411,11 @@ osog_status osog_render_multi(osog_context* ctx, void* stream, int32_t height, i
   u.kx_n = lo <= hi ? hi - lo + 1 : 0;
   hipStream_t s = (hipStream_t)stream;
   float* opd = opd_out ? opd_out : b.opd;
+  float* tau = opd_out ? opd_out + (size_t)height * width : b.tau;
   if ((e = launch_binning(u, soa, b, s)) != hipSuccess) return hip_fail(e, "osog_render_multi: binning");
-  if ((e = launch_raster(u, b, opd, s)) != hipSuccess) return hip_fail(e, "osog_render_multi: raster");
-  if ((e = launch_pass1(u, opd, b, ctx->twiddle, s)) != hipSuccess) return hip_fail(e, "osog_render_multi: pass 1");
+  if ((e = launch_raster(u, b, opd, tau, s)) != hipSuccess) return hip_fail(e, "osog_render_multi: raster");
+  if ((e = launch_pass1(u, opd, tau, b, ctx->twiddle, s)) != hipSuccess)
+    return hip_fail(e, "osog_render_multi: pass 1");
   // passes 2 and 3 per mode, one after the other in the second band buffer
   for (int m = 0; m < n_modes; ++m) {
     FrameBufs bm = b;
@@ -448,10 +458,10 @@ osog_status osog_render_backward(osog_context* ctx, void* stream, int32_t height
   if ((e = launch_binning(p, soa, b, s)) != hipSuccess) return hip_fail(e, "backward: binning");
   profile_end(pr, OSOG_STAGE_BINNING, s);
   profile_begin(pr, OSOG_STAGE_RASTER, s);
-  if ((e = launch_raster(p, b, b.opd, s)) != hipSuccess) return hip_fail(e, "backward: raster");
+  if ((e = launch_raster(p, b, b.opd, b.tau, s)) != hipSuccess) return hip_fail(e, "backward: raster");
   profile_end(pr, OSOG_STAGE_RASTER, s);
   profile_begin(pr, OSOG_STAGE_PASS1, s);
-  if ((e = launch_pass1(p, b.opd, b, tw, s)) != hipSuccess) return hip_fail(e, "backward: pass 1");
+  if ((e = launch_pass1(p, b.opd, b.tau, b, tw, s)) != hipSuccess) return hip_fail(e, "backward: pass 1");
   profile_end(pr, OSOG_STAGE_PASS1, s);
   if (p.kx_n > 0) {
     profile_begin(pr, OSOG_STAGE_PASS2, s);
@@ -465,7 +475,8 @@ osog_status osog_render_backward(osog_context* ctx, void* stream, int32_t height
     profile_end(pr, OSOG_STAGE_ADJ_PASS2, s);
   }
   profile_begin(pr, OSOG_STAGE_ADJ_PASS1, s);
-  if ((e = launch_adj_pass1(p, b.opd, grad_opd, b, tw, s)) != hipSuccess) return hip_fail(e, "backward: adj pass 1");
+  if ((e = launch_adj_pass1(p, b.opd, b.tau, grad_opd, b, tw, s)) != hipSuccess)
+    return hip_fail(e, "backward: adj pass 1");
   profile_end(pr, OSOG_STAGE_ADJ_PASS1, s);
   if (grad_soa) {
     profile_begin(pr, OSOG_STAGE_ADJ_RASTER, s);

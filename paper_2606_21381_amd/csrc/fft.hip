@@ -63,10 +63,11 @@ __global__ void __launch_bounds__(kThreads) k_pass3(FrameDev F, const float2* __
     default: return hipErrorInvalidValue;                            \
   }
 
-hipError_t launch_pass1(const FramePlan& p, const float* opd, FrameBufs& b, const float2* tw,
+hipError_t launch_pass1(const FramePlan& p, const float* opd, const float* tau, FrameBufs& b, const float2* tw,
                         hipStream_t s) {
   FrameDev F = make_dev(p, b);
   F.opd = const_cast<float*>(opd);
+  F.tau = const_cast<float*>(tau);
   const int rbn = p.H / rows_per_fft_block(p.W), per = (rbn + kXcds - 1) / kXcds;
 #define L1(LG)                                                                              \
   if (p.fft_radix == 4) hipLaunchKernelGGL((k_pass1<LG, 4>), dim3(per * kXcds), dim3(kThreads), 0, s, F, tw, per); \

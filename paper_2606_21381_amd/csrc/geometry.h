@@ -118,9 +118,9 @@ __device__ __forceinline__ float prism_cover(const PRec& r, const float4& bb, in
   return prism_clip_area(r, i, j);
 }
 
-// Ellipsoid thickness times dn at the centre of pixel (i, j) with q recomputed
-// in FP64 (used within 2e-3 of the rim, where sqrt(1 - q) amplifies rounding).
-__device__ __forceinline__ float ellipsoid_rim(const PRec& r, int i, int j) {
+// q = (u/a)^2 + (v/b)^2 at the centre of pixel (i, j) in FP64 (used within 2e-3
+// of the rim, where sqrt(1 - q) amplifies rounding).
+__device__ __forceinline__ double ellipsoid_rim_q(const PRec& r, int i, int j) {
 #pragma clang fp contract(off)
   const float cx = r.f[0], cy = r.f[1];
   double cd = __hiloint2double(__float_as_int(r.f[11]), __float_as_int(r.f[10]));
@@ -128,7 +128,13 @@ __device__ __forceinline__ float ellipsoid_rim(const PRec& r, int i, int j) {
   double ddx = ((double)j + 0.5) - (double)cx, ddy = ((double)i + 0.5) - (double)cy;
   double uu = (cd * ddx + sd * ddy) / (double)r.f[6];
   double vv = (-sd * ddx + cd * ddy) / (double)r.f[7];
-  double qq = uu * uu + vv * vv;
+  return uu * uu + vv * vv;
+}
+
+// Ellipsoid thickness times dn at the centre of pixel (i, j) with q in FP64.
+__device__ __forceinline__ float ellipsoid_rim(const PRec& r, int i, int j) {
+#pragma clang fp contract(off)
+  const double qq = ellipsoid_rim_q(r, i, j);
   return qq < 1.0 ? (float)((double)r.f[14] * (double)r.f[15] * sqrt(1.0 - qq)) : 0.0f;
 }
 

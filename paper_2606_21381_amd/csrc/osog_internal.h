@@ -54,6 +54,7 @@ struct FramePlan {
   double dx_d, tfx_d, tfy_d;
   float photons;
   uint32_t seed_lo, seed_hi, frame;
+  int absorb;            // 1: Beer-Lambert amplitude from the absorbance canvas
 };
 
 // Carved views into the caller's workspace for one frame.
@@ -66,11 +67,14 @@ struct FrameBufs {
   int* tile_first;        // n_tiles: inspection only, prefix of the tile counts
   int* pids;              // n_tiles x bucket: particle ids per tile
   float* opd;             // H*W (used when the caller passes no opd_out)
+  float* tau;             // H*W absorbance (absorbing frames without opd_out)
+  float2* absr;           // n: (dmu * height, dmu) per particle (absorbing frames)
   float2* band;           // H * W complex (blocked layout, kx_n used)
   double* colsum;         // W
   // backward only
   float2* band2;          // H * W complex
   float* gopd;            // H*W
+  float* gtau;            // H*W: dL/dtau (absorbing frames)
   double* colgrad;        // 3 * W
 };
 
@@ -81,8 +85,10 @@ FrameBufs carve(void* ws, int H, int W, int64_t n, int tile_h, int tile_w, int p
 hipError_t launch_binning(const FramePlan& p, const float* soa, FrameBufs& b, hipStream_t s);
 hipError_t launch_bin_outputs(const FramePlan& p, FrameBufs& b, int* keys_out, int* pids_out, int64_t capacity,
                               int* tile_start, hipStream_t s);
-hipError_t launch_raster(const FramePlan& p, FrameBufs& b, float* opd, hipStream_t s);
-hipError_t launch_pass1(const FramePlan& p, const float* opd, FrameBufs& b, const float2* tw, hipStream_t s);
+// OPD into opd and, for absorbing frames, the absorbance into tau
+hipError_t launch_raster(const FramePlan& p, FrameBufs& b, float* opd, float* tau, hipStream_t s);
+hipError_t launch_pass1(const FramePlan& p, const float* opd, const float* tau, FrameBufs& b, const float2* tw,
+                        hipStream_t s);
 // pass 2 of a frame; band_in (if not null) is another band holding this frame's
 // columns inside its range [in_kx_lo, in_kx_lo + in_kx_n) (a shared pass 1)
 hipError_t launch_pass2(const FramePlan& p, const float* globals, FrameBufs& b, const float2* tw, hipStream_t s,
@@ -94,7 +100,8 @@ hipError_t launch_philox(const uint32_t* ctr, int64_t count, uint32_t k0, uint32
 hipError_t launch_pass2_keep(const FramePlan& p, const float* globals, FrameBufs& b, const float2* tw, hipStream_t s);
 hipError_t launch_adj_pass3(const FramePlan& p, FrameBufs& b, const float2* tw, const float* grad_i, hipStream_t s);
 hipError_t launch_adj_pass2(const FramePlan& p, const float* globals, FrameBufs& b, const float2* tw, hipStream_t s);
-hipError_t launch_adj_pass1(const FramePlan& p, const float* opd, const float* grad_opd, FrameBufs& b, const float2* tw, hipStream_t s);
+hipError_t launch_adj_pass1(const FramePlan& p, const float* opd, const float* tau, const float* grad_opd, FrameBufs& b,
+                            const float2* tw, hipStream_t s);
 hipError_t launch_raster_adjoint(const FramePlan& p, const float* soa, FrameBufs& b, float* grad_soa, hipStream_t s);
 hipError_t launch_global_grads(const FramePlan& p, FrameBufs& b, float* grad_globals, hipStream_t s);
 

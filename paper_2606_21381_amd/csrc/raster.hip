@@ -1,4 +1,7 @@
 // OPD rasterisation (step F5): one 64-lane wave per tile, four pixels per lane.
+// Absorbing frames also build the absorbance canvas tau = sum of dmu * thickness
+// from the same coverage values, in the same order (the Beer-Lambert exponent of
+// Eq. 4).
 // Every pixel adds dn * thickness of each of its tile's particles in ascending
 // particle id (the wave sorts its tile's ids first), so the sum order -- and the
 // canvas, bit for bit -- does not depend on the tiling, the launch order or the GPU.  This replaces the
@@ -17,17 +20,20 @@ namespace osog {
 // Workgroups are dealt to the 8 XCDs in turn (workgroup i to XCD i mod 8), so
 // the tile of workgroup i is chosen to give each XCD one contiguous band of
 // tiles: a particle spanning neighbouring tiles is then fetched into one L2.
+template <bool ABS>
 __global__ void __launch_bounds__(64) k_raster(FrameDev F, int per_xcd) {
   __shared__ int seg[kSegSort];
   const int tile = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
-  if (tile < F.n_tiles) raster_tile(F, tile, threadIdx.x, seg);
+  if (tile < F.n_tiles) raster_tile<ABS>(F, tile, threadIdx.x, seg);
 }
 
-hipError_t launch_raster(const FramePlan& p, FrameBufs& b, float* opd, hipStream_t s) {
+hipError_t launch_raster(const FramePlan& p, FrameBufs& b, float* opd, float* tau, hipStream_t s) {
   FrameDev F = make_dev(p, b);
   F.opd = opd;
+  F.tau = tau;
   const int per = (p.n_tiles + kXcds - 1) / kXcds;
-  hipLaunchKernelGGL(k_raster, dim3(per * kXcds), dim3(64), 0, s, F, per);
+  if (p.absorb) hipLaunchKernelGGL(k_raster<true>, dim3(per * kXcds), dim3(64), 0, s, F, per);
+  else hipLaunchKernelGGL(k_raster<false>, dim3(per * kXcds), dim3(64), 0, s, F, per);
   return hipGetLastError();
 }
 

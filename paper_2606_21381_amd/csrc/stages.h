@@ -29,6 +29,9 @@ struct FrameDev {
   const float* soa;
   const float* globals;
   float* opd;                      // caller's or workspace OPD canvas
+  float* tau;                      // absorbance canvas (absorbing frames)
+  float2* absr;                    // per particle (dmu * height, dmu) (absorbing frames)
+  int absorb;
   float* intensity;
   PRec* recs;
   int4* boxes;
@@ -76,6 +79,10 @@ __device__ __forceinline__ void bin_body(const FrameDev& F, int64_t p) {
   }
   F.recs[p] = r;
   F.boxes[p] = box;
+  if (F.absorb) {  // Beer-Lambert weight of the thickness (Eq. 4): row 8 holds dmu
+    const float dmu = ok ? soa[8 * ld + p] : 0.0f;
+    F.absr[p] = make_float2(dmu * h, dmu);
+  }
   if (ok) {
     const int tx0 = box.x / F.tile_w, tx1 = box.y / F.tile_w, ty0 = box.z / F.tile_h, ty1 = box.w / F.tile_h;
     const int nx = tx1 - tx0 + 1;
@@ -209,6 +216,7 @@ struct TileAcc {
   float sx0, sx1, sy0, sy1;  // pixel-edge bounds of that slot (canvas pixels)
   float scx, scy, shx, shy;  // centre of its pixel centres, half extents
   float acc[4];
+  float tacc[4];             // absorbance sums (absorbing frames)
 };
 
 // Adds one particle to the four pixel slots a lane owns.  The slot tests (does
@@ -226,8 +234,11 @@ struct TileAcc {
 // are multiples of the centre's ulp and the difference is small), so the rotated
 // offsets u, v carry ~1e-6 px of rounding and depend on the pixel and the
 // particle alone: the canvas is bitwise the same under every tiling.  Every
-// pixel receives exactly one term per particle, in particle order.
-__device__ __forceinline__ void add_particle(const PRec& r, TileAcc& T) {
+// pixel receives exactly one term per particle, in particle order.  ABS: the same
+// coverage (prism) or centre thickness (ellipsoid) also adds dmu * height times it
+// to the absorbance sums; ab = (dmu * height, dmu) of the particle.
+template <bool ABS>
+__device__ __forceinline__ void add_particle(const PRec& r, TileAcc& T, float2 ab) {
 #pragma clang fp contract(off)
   const float kind = r.f[3];
   const float amp = r.f[2];
@@ -255,6 +266,7 @@ __device__ __forceinline__ void add_particle(const PRec& r, TileAcc& T) {
       if (!((hit_m >> q) & 1u)) continue;
       if ((in_m >> q) & 1u) {
         T.acc[q] += amp;
+        if (ABS) T.tacc[q] += ab.x;
         continue;
       }
       // straight-line code: every case is a select.  A pixel two edges reach
@@ -281,6 +293,7 @@ __device__ __forceinline__ void add_particle(const PRec& r, TileAcc& T) {
       cover = sel(inside, 1.0f, cover);
       cover = sel(outside, 0.0f, cover);
       T.acc[q] += amp * cover;
+      if (ABS) T.tacc[q] += ab.x * cover;
       marks |= (unsigned)(!(outside | inside | edge)) << q;
     }
     while (marks) {
@@ -289,11 +302,19 @@ __device__ __forceinline__ void add_particle(const PRec& r, TileAcc& T) {
       // one call site; selects keep the slot arrays in registers
       const int ii = q == 0 ? T.pi[0] : (q == 1 ? T.pi[1] : (q == 2 ? T.pi[2] : T.pi[3]));
       const int jj = q == 0 ? T.pj[0] : (q == 1 ? T.pj[1] : (q == 2 ? T.pj[2] : T.pj[3]));
-      const float add = amp * prism_clip_area(r, ii, jj);
+      const float area = prism_clip_area(r, ii, jj);
+      const float add = amp * area;
       if (q == 0) T.acc[0] += add;
       else if (q == 1) T.acc[1] += add;
       else if (q == 2) T.acc[2] += add;
       else T.acc[3] += add;
+      if (ABS) {
+        const float tadd = ab.x * area;
+        if (q == 0) T.tacc[0] += tadd;
+        else if (q == 1) T.tacc[1] += tadd;
+        else if (q == 2) T.tacc[2] += tadd;
+        else T.tacc[3] += tadd;
+      }
     }
   } else if (kind == 1.0f) {
     // slot (lane & 3) meets the bounding box of the pixel centres the ellipse reaches
@@ -310,8 +331,9 @@ __device__ __forceinline__ void add_particle(const PRec& r, TileAcc& T) {
       const bool rim = (qv > 0.998f) & (qv < 1.002f);
       // 1 - q >= 0.002 where the value is kept, so the hardware square root
       // (within 1 ulp, no denormal scaling needed) serves
-      const float val = sel(qv <= 0.998f, amp * __builtin_amdgcn_sqrtf(fmaxf(1.0f - qv, 0.0f)), 0.0f);
-      T.acc[q] += val;
+      const float sq = sel(qv <= 0.998f, __builtin_amdgcn_sqrtf(fmaxf(1.0f - qv, 0.0f)), 0.0f);
+      T.acc[q] += amp * sq;
+      if (ABS) T.tacc[q] += ab.x * sq;
       marks |= (unsigned)rim << q;
     }
     while (marks) {
@@ -319,11 +341,21 @@ __device__ __forceinline__ void add_particle(const PRec& r, TileAcc& T) {
       marks &= marks - 1u;
       const int ii = q == 0 ? T.pi[0] : (q == 1 ? T.pi[1] : (q == 2 ? T.pi[2] : T.pi[3]));
       const int jj = q == 0 ? T.pj[0] : (q == 1 ? T.pj[1] : (q == 2 ? T.pj[2] : T.pj[3]));
-      const float add = ellipsoid_rim(r, ii, jj);
+      // h sqrt(1 - q) in FP64 with q recomputed in FP64, times dn (and dmu)
+      const double qq = ellipsoid_rim_q(r, ii, jj);
+      const double sq = qq < 1.0 ? sqrt(1.0 - qq) : 0.0;
+      const float add = (float)((double)r.f[14] * (double)r.f[15] * sq);
       if (q == 0) T.acc[0] += add;
       else if (q == 1) T.acc[1] += add;
       else if (q == 2) T.acc[2] += add;
       else T.acc[3] += add;
+      if (ABS) {
+        const float tadd = (float)((double)ab.y * (double)r.f[15] * sq);
+        if (q == 0) T.tacc[0] += tadd;
+        else if (q == 1) T.tacc[1] += tadd;
+        else if (q == 2) T.tacc[2] += tadd;
+        else T.tacc[3] += tadd;
+      }
     }
   }
 }
@@ -336,17 +368,25 @@ __device__ __forceinline__ void add_particle(const PRec& r, TileAcc& T) {
 // all particles in id order that keeps those whose box meets the tile.  All three visit the same
 // particles in the same order, so the sums are identical.  `seg`: kSegSort ints
 // of LDS; the workgroup is this single wave.
+template <bool ABS>
+__device__ __forceinline__ float2 absorb_weights(const FrameDev& F, int64_t id) {
+  return ABS ? F.absr[id] : make_float2(0.0f, 0.0f);
+}
+
+template <bool ABS>
 __device__ __forceinline__ void raster_ids(const FrameDev& F, TileAcc& T, int mine, int m) {
 #pragma clang fp contract(off)
   const PRec* __restrict__ recs = F.recs;
   PRec nxt = recs[__builtin_amdgcn_readlane(mine, 0)];
   for (int k = 0; k < m; ++k) {
     const PRec cur = nxt;
+    const float2 ab = absorb_weights<ABS>(F, __builtin_amdgcn_readlane(mine, k));
     if (k + 1 < m) nxt = recs[__builtin_amdgcn_readlane(mine, k + 1)];
-    add_particle(cur, T);
+    add_particle<ABS>(cur, T, ab);
   }
 }
 
+template <bool ABS>
 __device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int lane, int* seg) {
 #pragma clang fp contract(off)
   const int tile_w = F.tile_w, tile_h = F.tile_h;
@@ -360,6 +400,7 @@ __device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int lan
     T.px[k] = (float)T.pj[k] + 0.5f;
     T.py[k] = (float)T.pi[k] + 0.5f;
     T.acc[k] = 0.0f;
+    T.tacc[k] = 0.0f;
   }
   {
     const SubRect R = slot_rect(64 * (lane & 3), tile_w, tx, ty, tile_h);
@@ -379,7 +420,7 @@ __device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int lan
   if (!overflow && cnt <= 64) {
     if (cnt > 0) {
       const int mine = wave_sort64(lane < cnt ? pids[start + lane] : INT_MAX, lane);
-      raster_ids(F, T, mine, cnt);
+      raster_ids<ABS>(F, T, mine, cnt);
     }
   } else if (!overflow && cnt <= kSegSort) {
     int n2 = 128;
@@ -389,18 +430,21 @@ __device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int lan
     lds_sort(seg, n2, lane);
     for (int c0 = 0; c0 < cnt; c0 += 64) {
       const int m = min(64, cnt - c0);
-      raster_ids(F, T, lane < m ? seg[c0 + lane] : 0, m);
+      raster_ids<ABS>(F, T, lane < m ? seg[c0 + lane] : 0, m);
     }
   } else {
     const int x0 = tx * tile_w, x1 = x0 + tile_w - 1, y0 = ty * tile_h, y1 = y0 + tile_h - 1;
     for (int64_t p = 0; p < F.n; ++p) {
       const int4 b = F.boxes[p];
       if (b.x > b.y || b.x > x1 || b.y < x0 || b.z > y1 || b.w < y0) continue;
-      add_particle(F.recs[p], T);
+      add_particle<ABS>(F.recs[p], T, absorb_weights<ABS>(F, p));
     }
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) F.opd[(int64_t)T.pi[q] * F.W + T.pj[q]] = T.acc[q];
+  for (int q = 0; q < 4; ++q) {
+    F.opd[(int64_t)T.pi[q] * F.W + T.pj[q]] = T.acc[q];
+    if (ABS) F.tau[(int64_t)T.pi[q] * F.W + T.pj[q]] = T.tacc[q];
+  }
 }
 
 // ---- F6: pass 1, rows --------------------------------------------------------
@@ -414,10 +458,20 @@ __device__ __forceinline__ void pass1_body(const FrameDev& F, int g, const float
   const int t = threadIdx.x;
   const float* src = F.opd + (size_t)g * RPB * W;
   const float pk = F.phase_k;
-  for (int idx = t; idx < RPB * W; idx += kThreads) {
-    float s, c;
-    sincosf(pk * src[idx], &s, &c);
-    buf[idx] = make_float2(c, s);
+  if (F.absorb) {  // U = exp(-tau) exp(i phi): the Beer-Lambert amplitude of Eq. 4
+    const float* ta = F.tau + (size_t)g * RPB * W;
+    for (int idx = t; idx < RPB * W; idx += kThreads) {
+      float s, c;
+      sincosf(pk * src[idx], &s, &c);
+      const float am = expf(-ta[idx]);
+      buf[idx] = make_float2(am * c, am * s);
+    }
+  } else {
+    for (int idx = t; idx < RPB * W; idx += kThreads) {
+      float s, c;
+      sincosf(pk * src[idx], &s, &c);
+      buf[idx] = make_float2(c, s);
+    }
   }
   __syncthreads();
   Stages<W, RPB, -1, 1, LOGW, MAXR>::run(buf, tw);
@@ -659,6 +713,9 @@ inline FrameDev make_dev(const FramePlan& p, const FrameBufs& b) {
   F.band_in = b.band; F.in_kx_lo = p.kx_lo; F.in_kx_n = p.kx_n;
   F.fft_radix = p.fft_radix;
   F.opd = b.opd;
+  F.tau = b.tau;
+  F.absr = b.absr;
+  F.absorb = p.absorb;
   return F;
 }
 

@@ -49,9 +49,24 @@ def _ptr(t: Optional[torch.Tensor]):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
-def _check_soa(soa: torch.Tensor):
-    if soa.dim() != 2 or soa.shape[0] != 8 or soa.dtype != torch.float32 or not soa.is_cuda:
-        raise ValueError("soa must be a CUDA float32 tensor of shape [8, n]")
+def soa_rows(optics) -> int:
+    """Rows of the particle table these optics expect (9 with absorption)."""
+    return 9 if getattr(optics, "absorption", 0) else 8
+
+
+def _planes(optics) -> int:
+    """Planes of the OPD output (OPD, and the absorbance with absorption)."""
+    return 2 if getattr(optics, "absorption", 0) else 1
+
+
+def _opd_tensor(optics, H: int, W: int, device) -> torch.Tensor:
+    shape = (2, H, W) if _planes(optics) == 2 else (H, W)
+    return torch.empty(shape, dtype=torch.float32, device=device)
+
+
+def _check_soa(soa: torch.Tensor, rows: int = 8):
+    if soa.dim() != 2 or soa.shape[0] != rows or soa.dtype != torch.float32 or not soa.is_cuda:
+        raise ValueError("soa must be a CUDA float32 tensor of shape [%d, n]" % rows)
     if soa.shape[1] > 0 and soa.stride(1) != 1:
         raise ValueError("soa rows must be contiguous")
     n = soa.shape[1]
@@ -90,14 +105,17 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 def render(soa: torch.Tensor, H: int, W: int, optics, globals4: torch.Tensor, want_opd: bool = False,
            out: Optional[torch.Tensor] = None, opd_out: Optional[torch.Tensor] = None,
            workspace: Optional[torch.Tensor] = None, pairs_per_particle: int = 0):
-    """Render one frame.  Returns intensity [H, W] (and the OPD canvas if want_opd)."""
+    """Render one frame.  Returns intensity [H, W] (and the OPD canvas if want_opd:
+    [H, W], or [2, H, W] = OPD and absorbance with absorption)."""
     device = soa.device
-    n, ld = _check_soa(soa)
+    n, ld = _check_soa(soa, soa_rows(optics))
     _check_globals(globals4, device)
     if out is None:
         out = torch.empty((H, W), dtype=torch.float32, device=device)
     if want_opd and opd_out is None:
-        opd_out = torch.empty((H, W), dtype=torch.float32, device=device)
+        opd_out = _opd_tensor(optics, H, W, device)
+    if opd_out is not None and opd_out.numel() != _planes(optics) * H * W:
+        raise ValueError("opd_out must hold %d plane(s) of H x W" % _planes(optics))
     nb = workspace_size(H, W, n, False, pairs_per_particle, device)
     ws = workspace if workspace is not None else _workspace(nb, device)
     o = _lib.make_optics(optics)
@@ -114,13 +132,13 @@ def render_multi(soa: torch.Tensor, H: int, W: int, optics_list, globals_modes: 
     and row FFT): list of intensities [H, W] (and the OPD if want_opd).
     ``globals_modes``: CUDA float32 [n_modes, 4]."""
     device = soa.device
-    n, ld = _check_soa(soa)
+    n, ld = _check_soa(soa, soa_rows(optics_list[0]))
     m = len(optics_list)
     g = globals_modes.contiguous()
     if g.shape != (m, 4) or g.dtype != torch.float32 or g.device != device:
         raise ValueError("globals_modes must be a float32 [n_modes, 4] tensor on the particle table's device")
     outs = out if out is not None else [torch.empty((H, W), dtype=torch.float32, device=device) for _ in range(m)]
-    opd = torch.empty((H, W), dtype=torch.float32, device=device) if want_opd else None
+    opd = _opd_tensor(optics_list[0], H, W, device) if want_opd else None
     nb = workspace_size(H, W, n, True, 0, device)
     ws = workspace if workspace is not None else _workspace(nb, device)
     opts = (_lib.Optics * m)(*[_lib.make_optics(o) for o in optics_list])
@@ -135,13 +153,18 @@ def render_backward(soa: torch.Tensor, H: int, W: int, optics, globals4: torch.T
                     grad_intensity: torch.Tensor, grad_opd: Optional[torch.Tensor] = None,
                     need_soa: bool = True, need_globals: bool = True,
                     workspace: Optional[torch.Tensor] = None):
-    """Adjoint of the noiseless render: (grad_soa [8, n] or None, grad_globals [4] or None)."""
+    """Adjoint of the noiseless render: (grad_soa [rows, n] or None, grad_globals [4] or None).
+    With absorption the table and grad_soa have 9 rows and grad_opd (if given) is
+    [2, H, W]: dL/dOPD and dL/dtau."""
     device = soa.device
-    n, ld = _check_soa(soa)
+    rows = soa_rows(optics)
+    n, ld = _check_soa(soa, rows)
     _check_globals(globals4, device)
     gi = grad_intensity.contiguous()
     go = grad_opd.contiguous() if grad_opd is not None else None
-    gs = torch.empty((8, ld), dtype=torch.float32, device=device) if (need_soa and n) else None
+    if go is not None and go.numel() != _planes(optics) * H * W:
+        raise ValueError("grad_opd must hold %d plane(s) of H x W" % _planes(optics))
+    gs = torch.empty((rows, ld), dtype=torch.float32, device=device) if (need_soa and n) else None
     gg = torch.empty(4, dtype=torch.float32, device=device) if need_globals else None
     nb = workspace_size(H, W, n, True, 0, device)
     ws = workspace if workspace is not None else _workspace(nb, device)
@@ -183,9 +206,10 @@ def render_diff(soa: torch.Tensor, globals4: torch.Tensor, H: int, W: int, optic
 
 
 def bin_pairs(soa: torch.Tensor, H: int, W: int, capacity: Optional[int] = None):
-    """Binning steps only: (keys, pids, tile_start, counts, pair_count) as CUDA int32 tensors."""
+    """Binning steps only: (keys, pids, tile_start, counts, pair_count) as CUDA int32 tensors.
+    Binning reads the first 8 rows, so an absorbing table (9 rows) is accepted too."""
     device = soa.device
-    n, ld = _check_soa(soa)
+    n, ld = _check_soa(soa, 9 if soa.dim() == 2 and soa.shape[0] == 9 else 8)
     th, tw = get_tiling(device)
     n_tiles = (H // th) * (W // tw)
     if capacity is None:
@@ -225,7 +249,7 @@ def philox(ctr: torch.Tensor, key0: int, key1: int) -> torch.Tensor:
 class Batch:
     """A batch of frames rendered by one HIP graph launch (one kernel chain per frame).
 
-    ``frames``: list of (soa [8, n] CUDA float32, H, W, optics, globals [4] CUDA float32).
+    ``frames``: list of (soa [8 or 9, n] CUDA float32, H, W, optics, globals [4] CUDA float32).
     Outputs are allocated once; ``run()`` re-renders into them (replaying the
     captured graph after the first call) and returns the outputs.
     """
@@ -237,12 +261,11 @@ class Batch:
         self.inputs = frames
         self.out = out if out is not None else [torch.empty((H, W), dtype=torch.float32, device=self.device)
                                                 for (_, H, W, _, _) in frames]
-        self.opd = [torch.empty((H, W), dtype=torch.float32, device=self.device) if want_opd else None
-                    for (_, H, W, _, _) in frames]
+        self.opd = [_opd_tensor(o, H, W, self.device) if want_opd else None for (_, H, W, o, _) in frames]
         n = len(frames)
         self.c_frames = (_lib.Frame * n)()
         for f, (soa, H, W, optics, g) in enumerate(frames):
-            nn, ld = _check_soa(soa)
+            nn, ld = _check_soa(soa, soa_rows(optics))
             _check_globals(g, self.device)
             fr = self.c_frames[f]
             fr.height, fr.width = H, W

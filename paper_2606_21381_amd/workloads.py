@@ -7,12 +7,16 @@ FP64 with numpy's PCG64 generator and rounded to FP32.
 SoA table layout, [8][n] float32, one row per attribute:
   0 cx [px]  1 cy [px]  2 angle [rad]  3 a [px]  4 b [px]  5 height [um]  6 dn  7 shape
   (shape 0 = tetragonal prism with half-widths a, b; 1 = ellipsoid with semi-axes a, b)
+Absorbing tables (optics.absorption = 1) carry a ninth row, 8 dmu [1/um], the
+attenuation contrast mu_particle - mu_solvent of Beer-Lambert absorption.
 
 Recipes (sizes and distributions of the paper's workloads as used here):
   prism      a = b ~ U[3, 12] px, height ~ U[0.5, 3] um, angle ~ U[0, pi)
   ellipsoid  a, b ~ U[2, 10] px, height ~ U[0.5, 2] um (full central thickness), angle ~ U[0, pi)
   centres    uniform over the canvas; dn ~ U[0.01, 0.05]; n_medium 1.33
   optics     lambda 0.55 um, pixel 0.1 um
+  absorbing  dmu ~ U[0, 0.4] 1/um (the paper gives no values: up to ~70% amplitude
+             loss through the thickest particles)
 """
 from __future__ import annotations
 
@@ -23,6 +27,7 @@ import numpy as np
 
 BRIGHTFIELD, DIC, OBLIQUE = 0, 1, 2
 SOA_ROWS = 8
+SOA_ROWS_ABS = 9
 
 
 @dataclass
@@ -38,6 +43,7 @@ class OpticsSpec:
     tilt_fy: float = 0.0
     photons_mean: float = 0.0
     seed: int = 0
+    absorption: int = 0
 
 
 @dataclass
@@ -82,6 +88,12 @@ def mixed(rng: np.random.Generator, n: int, H: int, W: int) -> np.ndarray:
     npr = n // 2
     s = np.concatenate([prisms(rng, npr, H, W), ellipsoids(rng, n - npr, H, W)], axis=1)
     return s[:, rng.permutation(n)] if n else s
+
+
+def with_absorption(rng: np.random.Generator, s: np.ndarray, lo: float = 0.0, hi: float = 0.4) -> np.ndarray:
+    """The table with a ninth row, dmu ~ U[lo, hi] 1/um, appended."""
+    dmu = rng.uniform(lo, hi, s.shape[1])
+    return np.concatenate([s, dmu[None, :].astype(s.dtype)], axis=0)
 
 
 def f32(s: np.ndarray) -> np.ndarray:
