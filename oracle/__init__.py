@@ -7,7 +7,8 @@ may import it; the product path never does.
 
   binning.py  sorted (tile, particle) pairs (FP32-exact box recipe)
   raster.py   OPD canvas: exact-area prisms, centre-sampled ellipsoids (C, FP64)
-  optics.py   exit wave, DFT, pupil/defocus, BF / DIC / oblique, |E|^2, direct DFT
+  optics.py   exit wave (with absorption), DFT, pupil/defocus, BF / DIC / oblique, |E|^2,
+              Eq. 5's literal (incoherent) DIC, direct DFT
   noise.py    Philox4x32-10 and Poisson shot noise
   grad.py     central finite-difference gradients, solver loss
   cnn.py      the learned initializer's network in float64 PyTorch (autograd gradients)
@@ -17,7 +18,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import binning, grad, noise, optics, raster
-from .optics import BRIGHTFIELD, DIC, OBLIQUE, Optics
+from .optics import BRIGHTFIELD, DIC, DIC_INCOHERENT, OBLIQUE, Optics
 
 
 def render(soa, H: int, W: int, opt: Optics, globals4, with_noise: bool = False, frame: int = 0):
@@ -34,4 +35,4 @@ def render(soa, H: int, W: int, opt: Optics, globals4, with_noise: bool = False,
 
 
 __all__ = ["binning", "grad", "noise", "optics", "raster", "render", "Optics",
-           "BRIGHTFIELD", "DIC", "OBLIQUE"]
+           "BRIGHTFIELD", "DIC", "DIC_INCOHERENT", "OBLIQUE"]

@@ -16,6 +16,10 @@ Plain FP64 statement of what the renderer computes from an OPD canvas:
   oblique        E = IDFT(Ut P(f + f_t)): a tilted plane-wave illumination shifts the
                  spectrum against the pupil (the directional frequency-domain phase shift
                  of Sec. III.B, oblique modality)
+  DIC, Eq. 5     the literal form: D = U(r + ds) e^{i th} - U(r - ds) e^{-i th} at full
+  literal        resolution (D~ = Ut S, S the shear factor above without the pupil), then
+                 I = |D|^2 * |h_obj|^2 with h_obj = IDFT(P) and the intensity PSF scaled to
+                 unit sum (a uniform |D|^2 is reproduced): I = IDFT(DFT(|D|^2) OTF)
   noise          see ``noise.py`` (Sec. III.C, last paragraph)
 
 Frequencies follow numpy's fftfreq order, f = k / (N dx) cycles per micrometre.
@@ -27,7 +31,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-BRIGHTFIELD, DIC, OBLIQUE = 0, 1, 2
+BRIGHTFIELD, DIC, OBLIQUE, DIC_INCOHERENT = 0, 1, 2, 3
 
 
 @dataclass
@@ -90,13 +94,38 @@ def transfer(H: int, W: int, optics: Optics, defocus_um: float, shear_px: float,
     if optics.mode == BRIGHTFIELD or optics.mode == OBLIQUE:
         return P
     if optics.mode == DIC:
-        fy, fx = freqs(H, W, optics.pixel_um)
-        half = 0.5 * shear_px * optics.pixel_um          # |ds| in micrometres, total shear 2|ds|
-        dsx = half * np.cos(optics.shear_angle_rad)
-        dsy = half * np.sin(optics.shear_angle_rad)
-        ramp = 2.0 * np.pi * (fx[None, :] * dsx + fy[:, None] * dsy)
-        return P * (np.exp(1j * bias_rad) * np.exp(1j * ramp) - np.exp(-1j * bias_rad) * np.exp(-1j * ramp))
+        return P * shear_factor(H, W, optics, shear_px, bias_rad)
     raise ValueError("unknown mode %r" % optics.mode)
+
+
+def shear_factor(H: int, W: int, optics: Optics, shear_px: float, bias_rad: float) -> np.ndarray:
+    """S(f) = e^{i th} e^{+2 pi i f.ds} - e^{-i th} e^{-2 pi i f.ds} on the whole DFT grid:
+    the spectrum of U(r + ds) e^{i th} - U(r - ds) e^{-i th} is DFT(U) S (shift theorem),
+    ds = (shear_px / 2) dx (cos psi, sin psi), total shear 2 |ds| (Eq. 5)."""
+    fy, fx = freqs(H, W, optics.pixel_um)
+    half = 0.5 * shear_px * optics.pixel_um          # |ds| in micrometres, total shear 2|ds|
+    dsx = half * np.cos(optics.shear_angle_rad)
+    dsy = half * np.sin(optics.shear_angle_rad)
+    ramp = 2.0 * np.pi * (fx[None, :] * dsx + fy[:, None] * dsy)
+    return np.exp(1j * bias_rad) * np.exp(1j * ramp) - np.exp(-1j * bias_rad) * np.exp(-1j * ramp)
+
+
+def incoherent_otf(H: int, W: int, optics: Optics, defocus_um: float) -> np.ndarray:
+    """DFT of the intensity PSF |h_obj|^2, h_obj = IDFT(P) (Eq. 3's pupil, no tilt),
+    with the PSF scaled to unit sum, so the OTF is 1 at f = 0."""
+    h = np.fft.ifft2(pupil(H, W, optics, defocus_um, tilt=False))
+    psf = h.real * h.real + h.imag * h.imag
+    return np.fft.fft2(psf / psf.sum())
+
+
+def intensity_dic_incoherent(opd: np.ndarray, optics: Optics, defocus_um: float, shear_px: float,
+                             bias_rad: float, tau=None) -> np.ndarray:
+    """Eq. 5 as written: I = |U(r + ds) e^{i th} - U(r - ds) e^{-i th}|^2 * |h_obj|^2."""
+    H, W = opd.shape
+    U = exit_wave(opd, optics, tau)
+    D = np.fft.ifft2(np.fft.fft2(U) * shear_factor(H, W, optics, shear_px, bias_rad))
+    D2 = D.real * D.real + D.imag * D.imag
+    return np.fft.ifft2(np.fft.fft2(D2) * incoherent_otf(H, W, optics, defocus_um)).real
 
 
 def exit_wave(opd: np.ndarray, optics: Optics, tau=None) -> np.ndarray:
@@ -120,7 +149,10 @@ def field(opd: np.ndarray, optics: Optics, defocus_um: float, shear_px: float = 
 
 def intensity(opd: np.ndarray, optics: Optics, defocus_um: float, shear_px: float = 0.0,
               bias_rad: float = 0.0, dft=None, idft=None, tau=None) -> np.ndarray:
-    """Noiseless image I = |E|^2."""
+    """Noiseless image: I = |E|^2 (coherent modes) or Eq. 5's literal DIC."""
+    if optics.mode == DIC_INCOHERENT:
+        return intensity_dic_incoherent(np.asarray(opd, dtype=np.float64), optics, defocus_um, shear_px,
+                                        bias_rad, tau)
     E = field(opd, optics, defocus_um, shear_px, bias_rad, dft, idft, tau)
     return E.real * E.real + E.imag * E.imag
 
