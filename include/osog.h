@@ -42,9 +42,14 @@ typedef enum {
 } osog_status;
 
 /* Imaging modality (paper Sec. III.B): brightfield (Eq. 4's |U * h_obj|^2),
- * differential interference contrast (Eq. 5), oblique illumination (the
- * asymmetric Fourier pupil of the oblique modality). */
-typedef enum { OSOG_BRIGHTFIELD = 0, OSOG_DIC = 1, OSOG_OBLIQUE = 2 } osog_mode;
+ * differential interference contrast (Eq. 5 with the shear inside the coherent
+ * transfer function: |(U sheared and interfered) * h_obj|^2), oblique
+ * illumination (the asymmetric Fourier pupil of the oblique modality), and DIC
+ * as Eq. 5 writes it: the exit wave sheared and interfered at full resolution,
+ * squared, then blurred by the incoherent PSF |h_obj|^2 (scaled to unit sum).
+ * OSOG_DIC_INCOHERENT renders forward only (osog_render, osog_batch_render);
+ * it needs the larger workspace (osog_workspace_size with with_backward = 1). */
+typedef enum { OSOG_BRIGHTFIELD = 0, OSOG_DIC = 1, OSOG_OBLIQUE = 2, OSOG_DIC_INCOHERENT = 3 } osog_mode;
 
 /* The particle table is the SoA tensor S of paper Sec. III.A stored
  * attribute-major: float soa[OSOG_D][ld], row r holding attribute r of

@@ -25,7 +25,8 @@ def tune_frame(soa: torch.Tensor, H: int, W: int, optics, globals4: torch.Tensor
     n, ld = _check_soa(soa, soa_rows(optics))
     _check_globals(globals4, device)
     out = torch.empty((H, W), dtype=torch.float32, device=device)
-    ws = torch.empty(workspace_size(H, W, n, device=device), dtype=torch.uint8, device=device)
+    ws = torch.empty(workspace_size(H, W, n, int(optics.mode) == 3, device=device), dtype=torch.uint8,
+                     device=device)
     th, tw, rad = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     ms = ctypes.c_float()
     o = _lib.make_optics(optics)

@@ -99,6 +99,8 @@ static FrameBufs carve_impl(Carver& c, int H, int W, int64_t n, int tile_h, int 
     b.gopd = c.take<float>(hw);
     b.gtau = c.take<float>(hw);
     b.colgrad = c.take<double>(3 * (size_t)W);
+    b.otf = c.take<float2>(hw);
+    b.psum = c.take<double>(H);
   }
   if (cap_out) *cap_out = cap;
   return b;
@@ -117,7 +119,7 @@ FrameBufs carve(void* ws, int H, int W, int64_t n, int tile_h, int tile_w, int p
 }
 
 // ---- pupil band: signed kx columns with any bin inside the (shifted) disc ----
-static void band_range(int H, int W, const osog_optics& o, int* kx_lo, int* kx_n) {
+static void pupil_range(int H, int W, const osog_optics& o, int* kx_lo, int* kx_n) {
   const double vx = 1.0 / ((double)W * o.pixel_um), vy = 1.0 / ((double)H * o.pixel_um);
   const double tx = o.mode == OSOG_OBLIQUE ? o.tilt_fx : 0.0;
   const double ty = o.mode == OSOG_OBLIQUE ? o.tilt_fy : 0.0;
@@ -141,10 +143,32 @@ static void band_range(int H, int W, const osog_optics& o, int* kx_lo, int* kx_n
   else { *kx_lo = lo; *kx_n = hi - lo + 1; }
 }
 
+// Columns passes 1 and 2 carry: the pupil's, or every column for the incoherent
+// DIC (its shear acts before the pupil, on the whole spectrum).
+static void band_range(int H, int W, const osog_optics& o, int* kx_lo, int* kx_n) {
+  if (o.mode == OSOG_DIC_INCOHERENT) {
+    *kx_lo = -(W / 2);
+    *kx_n = W;
+    return;
+  }
+  pupil_range(H, W, o, kx_lo, kx_n);
+}
+
+// Incoherent DIC: the OTF is the pupil's autocorrelation, non-zero only for |kx|
+// up to twice the pupil's largest |kx|.
+static void otf_range(int W, int pup_lo, int pup_n, int* lo, int* n) {
+  if (pup_n == 0) { *lo = 0; *n = 0; return; }
+  const int kmax = std::max(-pup_lo, pup_lo + pup_n - 1);
+  if (4 * kmax + 1 >= W) { *lo = -(W / 2); *n = W; return; }
+  *lo = -2 * kmax;
+  *n = 4 * kmax + 1;
+}
+
 static osog_status check_optics(const osog_optics* o) {
   if (!o) return fail(OSOG_ERR_INVALID_ARGUMENT, "optics is NULL");
-  if (o->mode < OSOG_BRIGHTFIELD || o->mode > OSOG_OBLIQUE)
-    return fail(OSOG_ERR_INVALID_ARGUMENT, "optics.mode must be 0 (brightfield), 1 (DIC) or 2 (oblique)");
+  if (o->mode < OSOG_BRIGHTFIELD || o->mode > OSOG_DIC_INCOHERENT)
+    return fail(OSOG_ERR_INVALID_ARGUMENT,
+                "optics.mode must be 0 (brightfield), 1 (DIC), 2 (oblique) or 3 (incoherent DIC)");
   if (!(o->wavelength_um > 0.0) || !std::isfinite(o->wavelength_um))
     return fail(OSOG_ERR_INVALID_ARGUMENT, "optics.wavelength_um must be finite and > 0");
   if (!(o->pixel_um > 0.0) || !std::isfinite(o->pixel_um))
@@ -202,6 +226,10 @@ FramePlan make_plan(const osog_context* ctx, int H, int W, int64_t n, int64_t ld
   context_tiling(ctx, H, W, &p.tile_h, &p.tile_w);
   p.ntx = W / p.tile_w; p.nty = H / p.tile_h; p.n_tiles = p.ntx * p.nty;
   band_range(H, W, o, &p.kx_lo, &p.kx_n);
+  if (o.mode == OSOG_DIC_INCOHERENT) {
+    pupil_range(H, W, o, &p.pup_lo, &p.pup_n);
+    otf_range(W, p.pup_lo, p.pup_n, &p.otf_lo, &p.otf_n);
+  }
   p.rb = rows_per_block(W);
   p.fft_radix = context_radix(ctx, H, W);
   p.n = n; p.ld = ld; p.cap = cap;
@@ -257,7 +285,9 @@ hipError_t forward_frame(const osog_context* ctx, const FramePlan& p, const floa
     profile_end(pr, OSOG_STAGE_PASS2, s);
   }
   profile_begin(pr, OSOG_STAGE_PASS3, s);
-  if ((e = launch_pass3(p, b, ctx->twiddle, intensity, s)) != hipSuccess) return e;
+  if (p.mode == OSOG_DIC_INCOHERENT) e = launch_incoherent_tail(p, globals, b, ctx->twiddle, intensity, s);
+  else e = launch_pass3(p, b, ctx->twiddle, intensity, s);
+  if (e != hipSuccess) return e;
   profile_end(pr, OSOG_STAGE_PASS3, s);
   return hipSuccess;
 }
@@ -349,18 +379,21 @@ osog_status osog_render(osog_context* ctx, void* stream, int32_t height, int32_t
   if (st != OSOG_OK) return st;
   if (!intensity_out) return fail(OSOG_ERR_INVALID_ARGUMENT, "intensity_out is NULL");
   if (!workspace) return fail(OSOG_ERR_WORKSPACE, "workspace is NULL");
+  const bool big = optics->mode == OSOG_DIC_INCOHERENT;  // needs the spectra buffers of the larger carve
   // the largest pair capacity this workspace holds
   int ppp = 0;
   for (int cand = 1 << 20; cand >= 1; cand >>= 1)
-    if (frame_workspace_bytes(height, width, n, tile_of(ctx, height, width, 0), tile_of(ctx, height, width, 1), cand, false) <= workspace_bytes) {
+    if (frame_workspace_bytes(height, width, n, tile_of(ctx, height, width, 0), tile_of(ctx, height, width, 1), cand, big) <= workspace_bytes) {
       ppp = cand;
       break;
     }
-  if (ppp == 0) return fail(OSOG_ERR_WORKSPACE, "workspace smaller than osog_workspace_size()");
+  if (ppp == 0)
+    return fail(OSOG_ERR_WORKSPACE, big ? "incoherent DIC needs osog_workspace_size(with_backward=1) bytes"
+                                        : "workspace smaller than osog_workspace_size()");
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   int64_t cap = 0;
-  FrameBufs b = carve(workspace, height, width, n, tile_of(ctx, height, width, 0), tile_of(ctx, height, width, 1), ppp, false, &cap);
+  FrameBufs b = carve(workspace, height, width, n, tile_of(ctx, height, width, 0), tile_of(ctx, height, width, 1), ppp, big, &cap);
   FramePlan p = make_plan(ctx, height, width, n, ld, *optics, cap);
   e = forward_frame(ctx, p, soa, globals, b, opd_out, intensity_out, (hipStream_t)stream, true);
   if (e != hipSuccess) return hip_fail(e, "osog_render launch");
@@ -377,6 +410,8 @@ osog_status osog_render_multi(osog_context* ctx, void* stream, int32_t height, i
   for (int m = 0; m < n_modes; ++m) {
     osog_status st = check_frame(ctx, height, width, soa, n, ld, &optics[m], globals + 4 * m);
     if (st != OSOG_OK) return fail(st, "mode " + std::to_string(m) + ": " + g_last_error);
+    if (optics[m].mode == OSOG_DIC_INCOHERENT)
+      return fail(OSOG_ERR_UNSUPPORTED, "osog_render_multi: the incoherent DIC renders through osog_render");
     if (!intensity_out[m]) return fail(OSOG_ERR_INVALID_ARGUMENT, "intensity_out[" + std::to_string(m) + "] is NULL");
     if (optics[m].wavelength_um != optics[0].wavelength_um || optics[m].pixel_um != optics[0].pixel_um ||
         optics[m].n_medium != optics[0].n_medium || optics[m].absorption != optics[0].absorption)
@@ -436,6 +471,8 @@ osog_status osog_render_backward(osog_context* ctx, void* stream, int32_t height
                                  void* workspace, size_t workspace_bytes) {
   osog_status st = check_frame(ctx, height, width, soa, n, ld, optics, globals);
   if (st != OSOG_OK) return st;
+  if (optics->mode == OSOG_DIC_INCOHERENT)
+    return fail(OSOG_ERR_UNSUPPORTED, "osog_render_backward: the incoherent DIC has no adjoint");
   if (!grad_intensity) return fail(OSOG_ERR_INVALID_ARGUMENT, "grad_intensity is NULL");
   if (!workspace) return fail(OSOG_ERR_WORKSPACE, "workspace is NULL");
   int ppp = 0;

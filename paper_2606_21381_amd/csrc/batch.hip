@@ -92,7 +92,9 @@ static std::vector<size_t> batch_offsets(const osog_context* ctx, const osog_fra
     int th, tw;
     context_tiling(ctx, frames[f].height, frames[f].width, &th, &tw);
     off[f] = o;
-    o += al(frame_workspace_bytes(frames[f].height, frames[f].width, frames[f].n, th, tw, ppp, false));
+    // an incoherent DIC frame takes the larger carve (its spectra buffers)
+    o += al(frame_workspace_bytes(frames[f].height, frames[f].width, frames[f].n, th, tw, ppp,
+                                  frames[f].optics.mode == OSOG_DIC_INCOHERENT));
   }
   *total = o;
   return off;
@@ -133,7 +135,8 @@ static hipError_t record_batch(osog_context* ctx, BatchCache* c, const osog_fram
     int th, tw;
     context_tiling(ctx, fr.height, fr.width, &th, &tw);
     int64_t cap = 0;
-    FrameBufs bufs = carve(ws + off[f], fr.height, fr.width, fr.n, th, tw, ppp, false, &cap);
+    FrameBufs bufs = carve(ws + off[f], fr.height, fr.width, fr.n, th, tw, ppp,
+                           fr.optics.mode == OSOG_DIC_INCOHERENT, &cap);
     FramePlan p = make_plan(ctx, fr.height, fr.width, fr.n, fr.ld, fr.optics, cap);
     if ((e = forward_frame(ctx, p, fr.soa, fr.globals, bufs, fr.opd_out, fr.intensity_out, s, false)) != hipSuccess)
       return e;

@@ -96,9 +96,10 @@ hipError_t launch_pass2(const FramePlan& p, const float* globals, FrameBufs& b, 
 }
 
 hipError_t launch_pass3(const FramePlan& p, FrameBufs& b, const float2* tw, float* intensity,
-                        hipStream_t s) {
+                        hipStream_t s, int colsum_n) {
   FrameDev F = make_dev(p, b);
   F.intensity = intensity;
+  if (colsum_n >= 0) F.o.colsum_n = colsum_n;
   const int rbn = p.H / rows_per_fft_block(p.W), per = (rbn + kXcds - 1) / kXcds;
 #define L3(LG)                                                                              \
   if (p.fft_radix == 4) hipLaunchKernelGGL((k_pass3<LG, 4>), dim3(per * kXcds), dim3(kThreads), 0, s, F, tw, per); \

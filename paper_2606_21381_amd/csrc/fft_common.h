@@ -17,6 +17,7 @@ __host__ __device__ constexpr int rows_per_fft_block(int W) { return W >= 1024 ?
 // Kernel-argument copy of the optics a pass needs.
 struct OpticsArgs {
   int H, W, kx_lo, kx_n, rb, mode;
+  int colsum_n;                     // column sums pass 3 adds for the image mean
   float inv_wdx, inv_hdx, kn, tfx, tfy, dsx_per_px, dsy_per_px, inv_hw, photons;
   double vx, vy, tfx_d, tfy_d, r2;  // FP64 band predicate: f = k * v, (fx+tx)^2 + (fy+ty)^2 <= r2
   uint32_t seed_lo, seed_hi, frame;
@@ -25,6 +26,7 @@ struct OpticsArgs {
 inline OpticsArgs optics_args(const FramePlan& p) {
   OpticsArgs o;
   o.H = p.H; o.W = p.W; o.kx_lo = p.kx_lo; o.kx_n = p.kx_n; o.rb = p.rb; o.mode = p.mode;
+  o.colsum_n = p.kx_n;
   o.inv_wdx = p.inv_wdx; o.inv_hdx = p.inv_hdx; o.kn = p.kn; o.tfx = p.tfx; o.tfy = p.tfy;
   o.dsx_per_px = 0.5f * p.dx_um * p.cos_psi;  // ds = (shear/2) dx (cos psi, sin psi)
   o.dsy_per_px = 0.5f * p.dx_um * p.sin_psi;
@@ -141,11 +143,16 @@ struct Stages<N, ROWS, DIR, NS, 0, MAXR> {
 // dropped: it multiplies the whole field by one phase and leaves |E|^2 unchanged);
 // kz - k0 = -2 pi |g|^2 / (kn + sqrt(kn^2 - |g|^2)) without cancellation, g = f + f_t.
 // DIC: P (e^{i th} e^{+2 pi i f.ds} - e^{-i th} e^{-2 pi i f.ds}) = 2 i sin(2 pi f.ds + th) P.
+// Incoherent DIC: the shear factor alone, 2 i sin(2 pi f.ds + th), on every bin.
 __device__ __forceinline__ float2 transfer(const OpticsArgs& o, int kx, int ky, float dz,
                                            float shear, float bias) {
 #pragma clang fp contract(off)
   const float two_pi = 6.283185307179586f;
   const float fx = (float)kx * o.inv_wdx, fy = (float)ky * o.inv_hdx;
+  if (o.mode == OSOG_DIC_INCOHERENT) {
+    const float rho = two_pi * shear * (fx * o.dsx_per_px + fy * o.dsy_per_px);
+    return make_float2(0.0f, 2.0f * sinf(rho + bias));
+  }
   const float gx = fx + o.tfx, gy = fy + o.tfy;
   const float g2 = gx * gx + gy * gy;
   const float kzm = -two_pi * g2 / (o.kn + sqrtf(fmaxf(o.kn * o.kn - g2, 0.0f)));
@@ -196,6 +203,11 @@ __device__ __forceinline__ void transfer_grads(const OpticsArgs& o, int kx, int 
 // band bounds), so that no bin on the disc's edge can flip between passes.
 __device__ inline void band_chord(const OpticsArgs& o, int kx, int* lo_out, int* hi_out) {
 #pragma clang fp contract(off)
+  if (o.mode == OSOG_DIC_INCOHERENT) {  // the shear factor has no pupil: every row
+    *lo_out = -(o.H / 2);
+    *hi_out = o.H / 2 - 1;
+    return;
+  }
   const double gx = (double)kx * o.vx + o.tfx_d;
   const double gx2 = gx * gx;
   const int kmin = -(o.H / 2), kmax = o.H / 2 - 1;

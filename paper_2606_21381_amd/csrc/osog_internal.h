@@ -39,6 +39,8 @@ struct FramePlan {
   int H, W, logH, logW;
   int tile_h, tile_w, ntx, nty, n_tiles;
   int kx_lo, kx_n;       // in-band signed kx range [kx_lo, kx_lo + kx_n)
+  // incoherent DIC: the pupil's columns and the OTF's (|kx| up to twice the pupil's)
+  int pup_lo, pup_n, otf_lo, otf_n;
   int rb;                // rows per band block of the blocked spectrum layout
   int fft_radix;         // FFT plan: largest Stockham radix (8 or 4)
   int64_t n, ld, cap;    // particles, leading dimension, ids per tile bucket
@@ -76,6 +78,8 @@ struct FrameBufs {
   float* gopd;            // H*W
   float* gtau;            // H*W: dL/dtau (absorbing frames)
   double* colgrad;        // 3 * W
+  float2* otf;            // H*W: incoherent DIC spectra (blocked band layout)
+  double* psum;           // H: incoherent DIC per-row-group sums
 };
 
 size_t frame_workspace_bytes(int H, int W, int64_t n, int tile_h, int tile_w, int ppp, bool backward);
@@ -93,7 +97,12 @@ hipError_t launch_pass1(const FramePlan& p, const float* opd, const float* tau, 
 // columns inside its range [in_kx_lo, in_kx_lo + in_kx_n) (a shared pass 1)
 hipError_t launch_pass2(const FramePlan& p, const float* globals, FrameBufs& b, const float2* tw, hipStream_t s,
                         const float2* band_in = nullptr, int in_kx_lo = 0, int in_kx_n = 0);
-hipError_t launch_pass3(const FramePlan& p, FrameBufs& b, const float2* tw, float* intensity, hipStream_t s);
+hipError_t launch_pass3(const FramePlan& p, FrameBufs& b, const float2* tw, float* intensity, hipStream_t s,
+                        int colsum_n = -1);
+// incoherent DIC after passes 1 and 2 (full band, shear factor): |D|^2, its
+// spectrum times the OTF of |h_obj|^2 (built here from the pupil), the image
+hipError_t launch_incoherent_tail(const FramePlan& p, const float* globals, FrameBufs& b, const float2* tw,
+                                  float* intensity, hipStream_t s);
 hipError_t launch_philox(const uint32_t* ctr, int64_t count, uint32_t k0, uint32_t k1, uint32_t* out, hipStream_t s);
 
 // backward launchers

@@ -647,7 +647,7 @@ __device__ __forceinline__ void pass3_body(const FrameDev& F, int g, const float
   const bool noise = o.photons > 0.0f;
   if (noise) {
     double s = 0.0;
-    for (int b = t; b < o.kx_n; b += kThreads) s += F.colsum[b];
+    for (int b = t; b < o.colsum_n; b += kThreads) s += F.colsum[b];
     red[t] = s;
   }
   __syncthreads();
@@ -664,11 +664,14 @@ __device__ __forceinline__ void pass3_body(const FrameDev& F, int g, const float
   Stages<W, RPB, 1, 1, LOGW, MAXR>::run(buf, tw);
   const float inv = o.inv_hw;
   float* dst = F.intensity + (size_t)row0 * W;
+  // coherent modes: I = |E|^2; incoherent DIC: the band holds the spectrum of I
+  // itself (real up to rounding), so I = Re
+  const bool real_part = o.mode == OSOG_DIC_INCOHERENT;
   if (!(scale > 0.0f)) {
     for (int idx = t; idx < RPB * W; idx += kThreads) {
       const float2 e = buf[idx];
       const float er = e.x * inv, ei = e.y * inv;
-      dst[idx] = er * er + ei * ei;
+      dst[idx] = real_part ? er : er * er + ei * ei;
     }
     __syncthreads();
     return;
@@ -684,7 +687,7 @@ __device__ __forceinline__ void pass3_body(const FrameDev& F, int g, const float
       if (ml < NP) {
         const float2 e = buf[2 * ml + x];
         const float er = e.x * inv, ei = e.y * inv;
-        v = er * er + ei * ei;
+        v = real_part ? fmaxf(er, 0.0f) : er * er + ei * ei;  // a Poisson mean is >= 0
       }
       Ipix[2 * k + x] = v;
     }

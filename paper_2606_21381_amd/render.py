@@ -116,7 +116,8 @@ def render(soa: torch.Tensor, H: int, W: int, optics, globals4: torch.Tensor, wa
         opd_out = _opd_tensor(optics, H, W, device)
     if opd_out is not None and opd_out.numel() != _planes(optics) * H * W:
         raise ValueError("opd_out must hold %d plane(s) of H x W" % _planes(optics))
-    nb = workspace_size(H, W, n, False, pairs_per_particle, device)
+    # the incoherent DIC (mode 3) needs the larger workspace
+    nb = workspace_size(H, W, n, int(optics.mode) == 3, pairs_per_particle, device)
     ws = workspace if workspace is not None else _workspace(nb, device)
     o = _lib.make_optics(optics)
     lib = _lib.load()

@@ -25,7 +25,7 @@ from dataclasses import dataclass, field, replace
 
 import numpy as np
 
-BRIGHTFIELD, DIC, OBLIQUE = 0, 1, 2
+BRIGHTFIELD, DIC, OBLIQUE, DIC_INCOHERENT = 0, 1, 2, 3
 SOA_ROWS = 8
 SOA_ROWS_ABS = 9
 
