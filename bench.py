@@ -218,6 +218,7 @@ def main():
     }
     if not args.no_extras:
         res["multimodal"] = bench_multimodal(render, soa, fr, dev)
+        res["variants"] = bench_variants(render, fr, g, dev)
         res["backward"] = bench_backward(render, soa, g, fr, dev)
         res["batch"] = bench_batch(render, dev)
         res["inverse"] = bench_inverse(dev, learned=args.learned)
@@ -269,6 +270,37 @@ def bench_multimodal(render, soa, fr, dev, reps=20):
     return res
 
 
+def bench_variants(render, fr, g, dev, reps=20):
+    """The headline frame with Beer-Lambert absorption (a seeded dmu row) and as
+    Eq. 5's literal (incoherent) DIC: ms per frame of each, with the frame's noise."""
+    import numpy as np
+    import torch
+    from dataclasses import replace
+    from paper_2606_21381_amd import workloads
+    rng = np.random.Generator(np.random.PCG64(11))
+    soa8 = torch.from_numpy(fr.soa).to(dev)
+    soa9 = torch.from_numpy(workloads.f32(workloads.with_absorption(rng, fr.soa.astype(np.float64)))).to(dev)
+    cases = {"absorbing_dic": (soa9, replace(fr.optics, absorption=1)),
+             "incoherent_dic": (soa8, replace(fr.optics, mode=workloads.DIC_INCOHERENT))}
+    res = {"workload": "dic2048_n40000 (absorbing: dmu ~ U[0, 0.4] 1/um)"}
+    for name, (s, o) in cases.items():
+        out = torch.empty((fr.H, fr.W), dtype=torch.float32, device=dev)
+        ws = torch.empty(render.workspace_size(fr.H, fr.W, fr.soa.shape[1], o.mode == workloads.DIC_INCOHERENT),
+                         dtype=torch.uint8, device=dev)
+        for _ in range(3):
+            render.render(s, fr.H, fr.W, o, g, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            render.render(s, fr.H, fr.W, o, g, out=out, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[name] = {"ms_per_frame": round(ms, 4), "frames_per_s": round(1000.0 / ms, 1)}
+    return res
+
+
 def bench_backward(render, soa, g, fr, dev, reps=20):
     """ms per adjoint call (forward recompute + adjoint) at the headline frame."""
     import torch
@@ -286,7 +318,7 @@ def bench_backward(render, soa, g, fr, dev, reps=20):
 
 
 def bench_batch(render, dev, reps=10):
-    """64 frames of 512/1024/2048^2, 100..40000 particles, DIC + oblique, one persistent launch."""
+    """64 frames of 512/1024/2048^2, 100..40000 particles, DIC + oblique, one HIP graph launch."""
     import torch
     from paper_2606_21381_amd import autotune, workloads
     frs = workloads.config2()
