@@ -23,6 +23,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector peak (packed); scalar-issue FP32 FMA peaks at half
+# FP32 operations one exact evaluation of a candidate pixel needs at least (an FMA counts 2):
+#   prism      centre offsets 2, rotation 6, edge distances 2, four classifying compares,
+#              half-plane value 9 (select, |t| distance, clamp, square, scale, linear FMA, choice),
+#              accumulate 2                                                       = 25
+#   ellipsoid  centre offsets 2, rotation 6, axis scaling 2, q 3, 1 - q 1, rim compare 1,
+#              square root 1, accumulate 2                                        = 18
+RASTER_OPS = {"prism": 25.0, "ellipsoid": 18.0}
 METRIC = "frames/s at 2048²×40k-particle DIC"
 
 
@@ -44,6 +52,21 @@ def algorithmic_bytes(H, W, n, P, kx_n):
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "counters_dic2048_n40000.txt")
+
+
+def raster_candidates(soa, H, W):
+    """Candidate pixels of the raster: for each particle, the canvas pixels that meet the
+    axis-aligned bounding box of its footprint (the pixels any exact per-pixel method
+    must classify).  Returns (prism pixels, ellipsoid pixels)."""
+    cx, cy, ang, a, b = (soa[k].astype(np.float64) for k in range(5))
+    c, s = np.abs(np.cos(ang)), np.abs(np.sin(ang))
+    prism = soa[7] < 0.5
+    ex = np.where(prism, a * c + b * s, np.sqrt(a * a * c * c + b * b * s * s))
+    ey = np.where(prism, a * s + b * c, np.sqrt(a * a * s * s + b * b * c * c))
+    nx = np.clip(np.floor(cx + ex), 0, W - 1) - np.clip(np.floor(cx - ex), 0, W - 1) + 1
+    ny = np.clip(np.floor(cy + ey), 0, H - 1) - np.clip(np.floor(cy - ey), 0, H - 1) + 1
+    px = nx * ny
+    return float(px[prism].sum()), float(px[~prism].sum())
 
 
 def source_hash():
@@ -191,6 +214,17 @@ def main():
             "traffic": round(cnt["traffic"]) if cnt else None,
             "algorithmic_bytes": alg[dom], "avg_us": round(stage_us[dom], 2),
             "valu_busy": round(cnt["valu_busy"], 3) if cnt else None}
+    if dom == "raster":
+        # the raster is bound by vector ALU issue, not by HBM: its roofline is FP32 arithmetic
+        pp, pe = raster_candidates(fr.soa, H, W)
+        flops = pp * RASTER_OPS["prism"] + pe * RASTER_OPS["ellipsoid"]
+        tflops = flops / (stage_us[dom] * 1e-6) / 1e12
+        roof = {"bound": "alu", "kernel": dom, "achieved": round(tflops, 3), "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(tflops / FP32_PEAK_TFLOPS, 4),
+                "traffic": round(cnt["traffic"]) if cnt else None,
+                "algorithmic_flops": flops, "candidate_pixels": {"prism": pp, "ellipsoid": pe},
+                "avg_us": round(stage_us[dom], 2), "valu_busy": round(cnt["valu_busy"], 3) if cnt else None,
+                "hbm_frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes": alg[dom]}
     total_alg = sum(alg.values())
     res = {
         "metric": METRIC,
