@@ -11,13 +11,14 @@ may import it; the product path never does.
               Eq. 5's literal (incoherent) DIC, direct DFT
   noise.py    Philox4x32-10 and Poisson shot noise
   grad.py     central finite-difference gradients, solver loss
+  spectral.py the spectral (log-amplitude) loss of Eq. 8 and its gradient
   cnn.py      the learned initializer's network in float64 PyTorch (autograd gradients)
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import binning, grad, noise, optics, raster
+from . import binning, grad, noise, optics, raster, spectral
 from .optics import BRIGHTFIELD, DIC, DIC_INCOHERENT, OBLIQUE, Optics
 
 
@@ -34,5 +35,5 @@ def render(soa, H: int, W: int, opt: Optics, globals4, with_noise: bool = False,
     return opd, I
 
 
-__all__ = ["binning", "grad", "noise", "optics", "raster", "render", "Optics",
+__all__ = ["binning", "grad", "noise", "optics", "raster", "spectral", "render", "Optics",
            "BRIGHTFIELD", "DIC", "DIC_INCOHERENT", "OBLIQUE"]
