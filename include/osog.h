@@ -291,6 +291,28 @@ osog_status osog_conv3x3(osog_context* ctx, void* stream, int32_t mode, int32_t 
                          const uint16_t* y, const uint16_t* grad_y, const uint16_t* w, const float* bias,
                          uint16_t* out_bf16, float* out_f32, void* workspace, size_t workspace_bytes);
 
+/* ---- Spectral loss of Eq. 8 (targets that cannot be aligned pixel by pixel) -----
+ * With F the unnormalised 2-D DFT and eps > 0 inside the logarithms,
+ *   A(k) = log(|F(image)(k)| + eps) - log(|F(target)(k)| + eps),
+ *   L = (1/(H W)) sum over the H x W bins of A(k)^2,
+ *   dL/dimage = Re(DFT(g)), g(k) = (2/(H W)) A(k) conj(F(k)) / (|F(k)| (|F(k)| + eps)).
+ * The loss sees amplitudes only: a circular shift of the image leaves it
+ * unchanged.  height, width: powers of two in [32, 4096].  Asynchronous on
+ * `stream`; workspace: osog_spectral_workspace_size bytes (device). */
+osog_status osog_spectral_workspace_size(int32_t height, int32_t width, size_t* bytes);
+/* target_logamp (device float[height * width], written): log(|F(target)| + eps)
+ * in the library's spectrum layout (bin (ky, kx) at kx * height + ky, kx and ky
+ * in DFT order), computed once per target. */
+osog_status osog_spectral_target(osog_context* ctx, void* stream, int32_t height, int32_t width,
+                                 const float* target, float eps, float* target_logamp, void* workspace,
+                                 size_t workspace_bytes);
+/* loss_out (device float[1]): L of image (device float[height][width]) against a
+ * target_logamp from osog_spectral_target with the same eps; grad_out (device
+ * float[height][width] or NULL): dL/dimage. */
+osog_status osog_spectral_loss(osog_context* ctx, void* stream, int32_t height, int32_t width,
+                               const float* image, const float* target_logamp, float eps, float* loss_out,
+                               float* grad_out, void* workspace, size_t workspace_bytes);
+
 /* The in-band spectrum columns the chain carries for these optics: signed kx in
  * [*kx_lo, *kx_lo + *kx_n) are the columns with at least one DFT bin inside the
  * (oblique: shifted) pupil disc (Eq. 3).  Host only, no device work. */

@@ -23,7 +23,7 @@ EXPORTS = [
     "osog_batch_render", "osog_batch_error", "osog_set_batch_group", "osog_set_size_tiling", "osog_set_size_radix", "osog_autotune", "osog_bin", "osog_band_info", "osog_philox4x32_10", "osog_profile_enable",
     "osog_profile_read", "osog_cnn_param_count", "osog_cnn_workspace_size", "osog_cnn_forward",
     "osog_cnn_train_step", "osog_conv3x3_workspace_size", "osog_conv3x3", "osog_status_string",
-    "osog_last_error",
+    "osog_last_error", "osog_spectral_workspace_size", "osog_spectral_target", "osog_spectral_loss",
 ]
 
 
@@ -107,6 +107,9 @@ def load(path: str = LIB_PATH):
         "osog_cnn_train_step": [vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, i32, ctypes.c_float, vp, vp, vp, sz],
         "osog_conv3x3_workspace_size": [i32, i32, i32, i32, i32, i32, i32, ctypes.POINTER(sz)],
         "osog_conv3x3": [vp, vp, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, sz],
+        "osog_spectral_workspace_size": [i32, i32, ctypes.POINTER(sz)],
+        "osog_spectral_target": [vp, vp, i32, i32, vp, ctypes.c_float, vp, vp, sz],
+        "osog_spectral_loss": [vp, vp, i32, i32, vp, vp, ctypes.c_float, vp, vp, vp, sz],
         "osog_status_string": [ctypes.c_int],
         "osog_last_error": [],
     }

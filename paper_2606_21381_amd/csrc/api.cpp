@@ -525,6 +525,52 @@ osog_status osog_render_backward(osog_context* ctx, void* stream, int32_t height
   return OSOG_OK;
 }
 
+osog_status osog_spectral_workspace_size(int32_t height, int32_t width, size_t* bytes) {
+  if (!bytes) return fail(OSOG_ERR_INVALID_ARGUMENT, "bytes is NULL");
+  if (!pow2_in(height, 32, 4096) || !pow2_in(width, 32, 4096))
+    return fail(OSOG_ERR_UNSUPPORTED, "height and width must be powers of two in [32, 4096]");
+  *bytes = spectral_workspace_bytes(height, width);
+  return OSOG_OK;
+}
+
+static osog_status spectral_check(osog_context* ctx, int32_t height, int32_t width, float eps, void* workspace,
+                                  size_t workspace_bytes) {
+  if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
+  if (!pow2_in(height, 32, 4096) || !pow2_in(width, 32, 4096))
+    return fail(OSOG_ERR_UNSUPPORTED, "height and width must be powers of two in [32, 4096]");
+  if (!(eps > 0.0f) || !std::isfinite(eps)) return fail(OSOG_ERR_INVALID_ARGUMENT, "eps must be finite and > 0");
+  if (!workspace || workspace_bytes < spectral_workspace_bytes(height, width))
+    return fail(OSOG_ERR_WORKSPACE, "workspace smaller than osog_spectral_workspace_size()");
+  return OSOG_OK;
+}
+
+osog_status osog_spectral_target(osog_context* ctx, void* stream, int32_t height, int32_t width,
+                                 const float* target, float eps, float* target_logamp, void* workspace,
+                                 size_t workspace_bytes) {
+  osog_status st = spectral_check(ctx, height, width, eps, workspace, workspace_bytes);
+  if (st != OSOG_OK) return st;
+  if (!target || !target_logamp) return fail(OSOG_ERR_INVALID_ARGUMENT, "target or target_logamp is NULL");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  e = spectral_run(height, width, target, nullptr, target_logamp, eps, nullptr, nullptr, workspace, ctx->twiddle,
+                   (hipStream_t)stream);
+  return e == hipSuccess ? OSOG_OK : hip_fail(e, "osog_spectral_target launch");
+}
+
+osog_status osog_spectral_loss(osog_context* ctx, void* stream, int32_t height, int32_t width,
+                               const float* image, const float* target_logamp, float eps, float* loss_out,
+                               float* grad_out, void* workspace, size_t workspace_bytes) {
+  osog_status st = spectral_check(ctx, height, width, eps, workspace, workspace_bytes);
+  if (st != OSOG_OK) return st;
+  if (!image || !target_logamp || !loss_out)
+    return fail(OSOG_ERR_INVALID_ARGUMENT, "image, target_logamp or loss_out is NULL");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  e = spectral_run(height, width, image, target_logamp, nullptr, eps, loss_out, grad_out, workspace, ctx->twiddle,
+                   (hipStream_t)stream);
+  return e == hipSuccess ? OSOG_OK : hip_fail(e, "osog_spectral_loss launch");
+}
+
 osog_status osog_bin(osog_context* ctx, void* stream, int32_t height, int32_t width,
                      const float* soa, int64_t n, int64_t ld, int32_t* keys_out, int32_t* pids_out,
                      int64_t capacity, int32_t* pair_count_out, int32_t* tile_start_out,

@@ -116,6 +116,11 @@ hipError_t launch_global_grads(const FramePlan& p, FrameBufs& b, float* grad_glo
 
 void set_error(const std::string& msg);
 
+// spectral loss of Eq. 8 (spectral.hip)
+size_t spectral_workspace_bytes(int H, int W);
+hipError_t spectral_run(int H, int W, const float* img, const float* target, float* target_out, float eps,
+                        float* loss, float* grad, void* ws, const float2* tw, hipStream_t s);
+
 // learned initializer (cnn.hip)
 int64_t cnn_param_count();
 size_t cnn_workspace_bytes(int B, int H, int W);

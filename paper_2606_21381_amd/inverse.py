@@ -6,10 +6,19 @@ frame rendered from known prisms, and Adam recovers the shared dn, the defocus,
 the DIC shear and bias, and every prism's centre, angle and half-width from a
 perturbed start, minimising the mean squared image error.
 
-Schedule: for the first ``globals_first`` steps only the four globals move (the
+Schedule (a curriculum of stages, each naming the parameter groups that move):
+by default for the first ``globals_first`` steps only the four globals move (the
 per-particle parameters would otherwise drift to compensate for 20 % errors in
 dn, defocus, shear and bias, and some settle in other basins); then everything
 moves, with a cosine decay of every rate over the last part of the run.
+
+Losses: the mean squared image error for a pixel-aligned target, or the
+spectral loss of Eq. 8 (log amplitudes of the 2-D DFT, eps = ``spectral_eps``
+times the target's DC term) for a target that cannot be aligned pixel by pixel
+-- another placement of particles with the same statistics.  Against such a
+target only the optical globals are defined, so its curriculum freezes the
+geometry (the paper's calibration of blur-like optical parameters from
+unaligned micrographs, Sec. IV.B).
 
 Parameter error (how "1e-3 relative parameter error" is measured):
   e = max(e_glob, e_part)
@@ -52,6 +61,11 @@ class SolverConfig:
     target_error: float = 1e-3
     width_floor: float = 1.0   # half-width kept >= 1 px
     globals_first: int = 60    # steps during which only dn, dz, shear, bias move
+    # explicit curriculum: ((steps, groups), ...) with groups from GROUPS; overrides
+    # globals_first when given (the last stage lasts to the end)
+    curriculum: Optional[tuple] = None
+    loss: str = "mse"          # "mse" (pixel-aligned target) or "spectral" (Eq. 8)
+    spectral_eps: float = 1e-4 # eps of the spectral loss, relative to the target's DC term
 
 
 @dataclass
@@ -122,6 +136,26 @@ def parameter_error(p: Params, truth: Truth) -> torch.Tensor:
     return torch.maximum(e_glob, e_part)
 
 
+GROUPS = ("position", "angle", "width", "dn", "dz", "shear", "bias")
+
+
+def stage_groups(cfg: SolverConfig, k: int) -> frozenset:
+    """Parameter groups that move at step k."""
+    if cfg.curriculum is None:
+        return frozenset(GROUPS[3:]) if k < cfg.globals_first else frozenset(GROUPS)
+    end = 0
+    for n, groups in cfg.curriculum:
+        end += n
+        if k < end:
+            return frozenset(groups)
+    return frozenset(cfg.curriculum[-1][1])
+
+
+def _params_of(p: "Params", group: str):
+    return {"position": (p.x, p.y), "angle": (p.angle,), "width": (p.width,), "dn": (p.dn,),
+            "dz": (p.dz,), "shear": (p.shear,), "bias": (p.bias,)}[group]
+
+
 def _lr_groups(p: Params, cfg: SolverConfig):
     return [
         {"params": [p.x, p.y], "lr": cfg.lr_pos},
@@ -137,7 +171,8 @@ def _lr_groups(p: Params, cfg: SolverConfig):
 def solve(target: torch.Tensor, start: Params, truth: Optional[Truth], H: int, W: int, optics,
           cfg: SolverConfig = SolverConfig(),
           render_fn: Optional[Callable] = None) -> SolveResult:
-    """Adam on L = mean((I(theta) - target)^2); returns error/loss/time traces.
+    """Adam on L = mean((I(theta) - target)^2) (or the spectral loss, cfg.loss);
+    returns error/loss/time traces.
 
     ``start`` is modified in place.  Errors and losses stay on the GPU during
     the loop (no host synchronisation per step); per-step GPU times come from
@@ -149,6 +184,18 @@ def solve(target: torch.Tensor, start: Params, truth: Optional[Truth], H: int, W
         def render_fn(soa, g):
             return render_diff(soa, g, H, W, optics)
 
+    if cfg.loss == "spectral":
+        from .render import spectral_loss_diff, spectral_target
+        eps = cfg.spectral_eps * float(target.double().sum())
+        tl = spectral_target(target, eps)
+
+        def loss_fn(I):
+            return spectral_loss_diff(I, tl, eps)
+    elif cfg.loss == "mse":
+        def loss_fn(I):
+            return torch.mean((I - target) ** 2)
+    else:
+        raise ValueError("loss must be 'mse' or 'spectral'")
     opt = torch.optim.Adam(_lr_groups(start, cfg), betas=cfg.betas)
     base = [g["lr"] for g in opt.param_groups]
     dev = target.device
@@ -172,11 +219,13 @@ def solve(target: torch.Tensor, start: Params, truth: Optional[Truth], H: int, W
                 g["lr"] = b * mult
         opt.zero_grad(set_to_none=True)
         I = render_fn(start.soa(), start.globals4())
-        loss = torch.mean((I - target) ** 2)
+        loss = loss_fn(I)
         loss.backward()
-        if k < cfg.globals_first:  # per-particle parameters wait until the globals have settled
-            for q in (start.x, start.y, start.angle, start.width):
-                q.grad = None
+        moving = stage_groups(cfg, k)
+        for grp in GROUPS:  # frozen groups keep their values (and Adam state)
+            if grp not in moving:
+                for q in _params_of(start, grp):
+                    q.grad = None
         opt.step()
         with torch.no_grad():
             start.width.clamp_(min=cfg.width_floor)

@@ -305,3 +305,61 @@ def set_batch_group(group: int, device=None):
 
 def set_size_tiling(H: int, W: int, tile_h: int, tile_w: int, device=None):
     _lib.check(_lib.load().osog_set_size_tiling(context(device), H, W, tile_h, tile_w), "osog_set_size_tiling")
+
+
+# ---- spectral loss of Eq. 8 -------------------------------------------------------
+def _spectral_ws(H: int, W: int, device, workspace=None) -> torch.Tensor:
+    b = ctypes.c_size_t()
+    _lib.check(_lib.load().osog_spectral_workspace_size(H, W, ctypes.byref(b)), "osog_spectral_workspace_size")
+    return workspace if workspace is not None else _workspace(b.value, device)
+
+
+def spectral_target(target: torch.Tensor, eps: float, workspace=None) -> torch.Tensor:
+    """log(|DFT(target)| + eps) in the library's spectrum layout (float32 [H * W])."""
+    t = target.contiguous()
+    if t.dim() != 2 or t.dtype != torch.float32 or not t.is_cuda:
+        raise ValueError("target must be a CUDA float32 [H, W] tensor")
+    H, W = t.shape
+    out = torch.empty(H * W, dtype=torch.float32, device=t.device)
+    ws = _spectral_ws(H, W, t.device, workspace)
+    _lib.check(_lib.load().osog_spectral_target(context(t.device), _stream(t.device), H, W, _ptr(t), float(eps),
+                                                 _ptr(out), _ptr(ws), ws.numel()), "osog_spectral_target")
+    return out
+
+
+def spectral_loss(image: torch.Tensor, target_logamp: torch.Tensor, eps: float, want_grad: bool = True,
+                  workspace=None):
+    """(loss as a CUDA float32 [1] tensor, dL/dimage [H, W] or None) of Eq. 8's spectral loss."""
+    im = image.contiguous()
+    if im.dim() != 2 or im.dtype != torch.float32 or not im.is_cuda:
+        raise ValueError("image must be a CUDA float32 [H, W] tensor")
+    H, W = im.shape
+    if target_logamp.numel() != H * W:
+        raise ValueError("target_logamp must come from spectral_target of an H x W target")
+    loss = torch.empty(1, dtype=torch.float32, device=im.device)
+    grad = torch.empty((H, W), dtype=torch.float32, device=im.device) if want_grad else None
+    ws = _spectral_ws(H, W, im.device, workspace)
+    _lib.check(_lib.load().osog_spectral_loss(context(im.device), _stream(im.device), H, W, _ptr(im),
+                                               _ptr(target_logamp), float(eps), _ptr(loss), _ptr(grad), _ptr(ws),
+                                               ws.numel()), "osog_spectral_loss")
+    return loss, grad
+
+
+class SpectralLossFn(torch.autograd.Function):
+    """L = spectral loss of Eq. 8 (image against a fixed target's log amplitudes),
+    with the library's gradient image as backward."""
+
+    @staticmethod
+    def forward(ctx, image, target_logamp, eps):
+        loss, grad = spectral_loss(image.detach(), target_logamp, eps, want_grad=image.requires_grad)
+        ctx.save_for_backward(grad if grad is not None else loss)
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        return grad * g, None, None
+
+
+def spectral_loss_diff(image: torch.Tensor, target_logamp: torch.Tensor, eps: float) -> torch.Tensor:
+    return SpectralLossFn.apply(image, target_logamp, eps)

@@ -64,3 +64,15 @@ def test_solver_converges_on_a_smooth_toy_model():
     assert res.time_to_target_s == res.time_s[res.steps_to_target - 1]
     assert np.all(np.diff(res.time_s) >= 0)
     assert res.loss[-1] < 1e-3 * res.loss[0]
+
+
+def test_curriculum_stages():
+    from paper_2606_21381_amd import inverse
+    cfg = inverse.SolverConfig(globals_first=60)
+    assert inverse.stage_groups(cfg, 0) == frozenset(("dn", "dz", "shear", "bias"))
+    assert inverse.stage_groups(cfg, 60) == frozenset(inverse.GROUPS)
+    cur = inverse.SolverConfig(curriculum=((10, ("dz",)), (5, ("position", "width")), (1, ("bias",))))
+    assert inverse.stage_groups(cur, 9) == frozenset(("dz",))
+    assert inverse.stage_groups(cur, 10) == frozenset(("position", "width"))
+    assert inverse.stage_groups(cur, 15) == frozenset(("bias",))
+    assert inverse.stage_groups(cur, 1000) == frozenset(("bias",))
