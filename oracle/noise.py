@@ -13,6 +13,9 @@ words 0,1 belong to the even pixel, words 2,3 to the odd one; any further words
 of pixel p come from its own blocks at counter (p, frame, round, 1), round =
 1, 2, ...  uniform = ((x >> 9) + 0.5) * 2^-23 in FP32 (every value exact, never
 0 or 1).
+Gaussian read noise (optional): read_noise * z counts added to each count, z
+from Box-Muller on the first two words of the block at counter (m, frame, 0, 2)
+of pixels 2m and 2m+1 (read_normals).
 Poisson variates: mean < 10 by inversion with sequential search on the pixel's
 first word (at most 40 steps); mean >= 10 by Hoermann's transformed rejection
 with squeeze "PTRS" (Insurance: Math. and Econ. 12, 1993), two uniforms per
@@ -141,9 +144,23 @@ def poisson_one(mu: float, pixel: int, frame: int, seed: int) -> int:
     return int(math.floor(float(mu)))
 
 
+def read_normals(pair: int, frame: int, seed: int):
+    """Two standard normal variates for pixels 2 pair and 2 pair + 1 (Box and Muller,
+    Ann. Math. Statist. 29, 1958) from the first two words u1, u2 of the Philox block
+    at counter (pair, frame, 0, 2): r = sqrt(-2 ln u1), (r cos 2 pi u2, r sin 2 pi u2).
+    FP64 on the FP32 uniforms."""
+    key = (seed & MASK, (seed >> 32) & MASK)
+    w = philox4x32_10((pair, frame, 0, 2), key)
+    u1, u2 = float(uniform_f32(w[0])), float(uniform_f32(w[1]))
+    r = math.sqrt(-2.0 * math.log(u1))
+    return r * math.cos(2.0 * math.pi * u2), r * math.sin(2.0 * math.pi * u2)
+
+
 def add_noise(I: np.ndarray, photons_mean: float, seed: int, frame: int = 0,
-              mean_I: float | None = None) -> np.ndarray:
-    """counts/s with counts ~ Poisson(s I), s = photons_mean / mean(I).  Slow: small frames."""
+              mean_I: float | None = None, read_noise: float = 0.0) -> np.ndarray:
+    """(counts + read_noise z) / s with counts ~ Poisson(s I), s = photons_mean / mean(I),
+    z standard normal (read_normals): the heteroscedastic sensor model of Sec. III.C,
+    Poisson shot noise plus Gaussian read noise of read_noise counts.  Slow: small frames."""
     I = np.asarray(I, dtype=np.float64)
     m = float(I.mean()) if mean_I is None else float(mean_I)
     if not (photons_mean > 0) or not (m > 0):
@@ -152,5 +169,8 @@ def add_noise(I: np.ndarray, photons_mean: float, seed: int, frame: int = 0,
     flat = I.reshape(-1)
     out = np.empty_like(flat)
     for p in range(flat.shape[0]):
-        out[p] = poisson_one(s * flat[p], p, frame, seed) / s
+        k = float(poisson_one(s * flat[p], p, frame, seed))
+        if read_noise > 0:
+            k += read_noise * read_normals(p >> 1, frame, seed)[p & 1]
+        out[p] = k / s
     return out.reshape(I.shape)
