@@ -88,6 +88,12 @@ typedef struct {
    *    OSOG_D_ABS rows and A = exp(-tau) with the absorbance canvas
    *    tau = sum over particles of dmu * thickness, built like the OPD. */
   int32_t absorption;
+  /* Gaussian read noise of the sensor (Sec. III.C: Poisson shot noise plus a
+   * Gaussian term), standard deviation in photon counts, >= 0; needs
+   * photons_mean > 0.  Pixels 2m and 2m+1 take z from Box-Muller on the first two
+   * words of the Philox block at counter (m, noise_frame, 0, 2); the output is
+   * (counts + read_noise z) / s. */
+  double read_noise;
 } osog_optics;
 
 /* Differentiable per-frame globals live in DEVICE memory, float[4]:

@@ -41,6 +41,7 @@ class Optics(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("noise_frame", ctypes.c_uint32),
         ("absorption", ctypes.c_int32),
+        ("read_noise", ctypes.c_double),
     ]
 
 
@@ -148,4 +149,5 @@ def make_optics(spec) -> Optics:
     o.seed = int(spec.seed) & 0xFFFFFFFFFFFFFFFF
     o.noise_frame = int(getattr(spec, "noise_frame", 0)) & 0xFFFFFFFF
     o.absorption = 1 if getattr(spec, "absorption", 0) else 0
+    o.read_noise = float(getattr(spec, "read_noise", 0.0))
     return o

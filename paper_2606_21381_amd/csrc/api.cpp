@@ -181,6 +181,10 @@ static osog_status check_optics(const osog_optics* o) {
     return fail(OSOG_ERR_INVALID_ARGUMENT, "optics shear angle and tilt must be finite");
   if (!(o->photons_mean >= 0.0) || !std::isfinite(o->photons_mean))
     return fail(OSOG_ERR_INVALID_ARGUMENT, "optics.photons_mean must be finite and >= 0");
+  if (!(o->read_noise >= 0.0) || !std::isfinite(o->read_noise))
+    return fail(OSOG_ERR_INVALID_ARGUMENT, "optics.read_noise must be finite and >= 0");
+  if (o->read_noise > 0.0 && !(o->photons_mean > 0.0))
+    return fail(OSOG_ERR_INVALID_ARGUMENT, "optics.read_noise needs photons_mean > 0 (it is in photon counts)");
   if (o->absorption != 0 && o->absorption != 1)
     return fail(OSOG_ERR_INVALID_ARGUMENT, "optics.absorption must be 0 or 1");
   return OSOG_OK;
@@ -247,6 +251,7 @@ FramePlan make_plan(const osog_context* ctx, int H, int W, int64_t n, int64_t ld
   p.dx_d = o.pixel_um;
   p.na_over_lambda = o.na / o.wavelength_um;
   p.photons = (float)o.photons_mean;
+  p.read_sigma = (float)o.read_noise;
   p.seed_lo = (uint32_t)(o.seed & 0xffffffffu);
   p.seed_hi = (uint32_t)(o.seed >> 32);
   p.frame = o.noise_frame;

@@ -18,7 +18,7 @@ __host__ __device__ constexpr int rows_per_fft_block(int W) { return W >= 1024 ?
 struct OpticsArgs {
   int H, W, kx_lo, kx_n, rb, mode;
   int colsum_n;                     // column sums pass 3 adds for the image mean
-  float inv_wdx, inv_hdx, kn, tfx, tfy, dsx_per_px, dsy_per_px, inv_hw, photons;
+  float inv_wdx, inv_hdx, kn, tfx, tfy, dsx_per_px, dsy_per_px, inv_hw, photons, read_sigma;
   double vx, vy, tfx_d, tfy_d, r2;  // FP64 band predicate: f = k * v, (fx+tx)^2 + (fy+ty)^2 <= r2
   uint32_t seed_lo, seed_hi, frame;
 };
@@ -32,6 +32,7 @@ inline OpticsArgs optics_args(const FramePlan& p) {
   o.dsy_per_px = 0.5f * p.dx_um * p.sin_psi;
   o.inv_hw = 1.0f / ((float)p.H * (float)p.W);
   o.photons = p.photons;
+  o.read_sigma = p.read_sigma;
   o.vx = 1.0 / ((double)p.W * p.dx_d);
   o.vy = 1.0 / ((double)p.H * p.dx_d);
   o.tfx_d = p.tfx_d; o.tfy_d = p.tfy_d;

@@ -55,6 +55,7 @@ struct FramePlan {
   double na_over_lambda; // pupil radius, FP64 (the band predicate is FP64)
   double dx_d, tfx_d, tfy_d;
   float photons;
+  float read_sigma;      // Gaussian read noise [photon counts]
   uint32_t seed_lo, seed_hi, frame;
   int absorb;            // 1: Beer-Lambert amplitude from the absorbance canvas
 };

@@ -621,7 +621,18 @@ __device__ __forceinline__ void noise_rows(const FrameDev& F, float scale, int64
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       const int ml = t + kThreads * (k0 + c);
-      if (ml < NP) out[ml] = make_float2(res[2 * c] / scale, res[2 * c + 1] / scale);
+      if (ml >= NP) continue;
+      float a = res[2 * c], b = res[2 * c + 1];
+      if (o.read_sigma > 0.0f) {  // Gaussian read noise: Box-Muller on the pair's own block
+        const uint32_t m = (uint32_t)((pix0 + 2 * ml) >> 1);
+        const uint4 w = philox4x32_10(make_uint4(m, o.frame, 0u, 2u), o.seed_lo, o.seed_hi);
+        const float r = sqrtf(-2.0f * logf(u01(w.x)));
+        float sn, cs;
+        sincosf(6.283185307179586f * u01(w.y), &sn, &cs);
+        a = a + o.read_sigma * (r * cs);
+        b = b + o.read_sigma * (r * sn);
+      }
+      out[ml] = make_float2(a / scale, b / scale);
     }
     __syncthreads();  // the queue is reused by the next round
   }

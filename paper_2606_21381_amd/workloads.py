@@ -44,6 +44,7 @@ class OpticsSpec:
     photons_mean: float = 0.0
     seed: int = 0
     absorption: int = 0
+    read_noise: float = 0.0   # Gaussian read noise, photon counts (needs photons_mean > 0)
 
 
 @dataclass
