@@ -11,7 +11,10 @@ that any correct implementation reproduces it exactly:
 
     ext = max(a, b) * 1.41421366f + 1   for a prism (1.41421366f is the float just above sqrt 2:
                                           it bounds the footprint's circumradius sqrt(a^2+b^2))
-    ext = max(a, b) + 1                 for an ellipsoid
+    ext = max(a, b) + 1                 for an ellipsoid (0.5 <= shape < 1.5)
+    ext = max(a, b) * R_k + 1           for a polyhedral habit k = floor(shape + 0.5) - 2 with
+                                          the habit's bounding radius R_k (FP32); no pairs for a
+                                          habit index the frame does not define
     x0 = floor(cx - ext), x1 = floor(cx + ext)   (same for y), clamped to the canvas
     no pairs if a <= 0, b <= 0, any bound is NaN, or the box misses the canvas.
 
@@ -26,15 +29,24 @@ import numpy as np
 SQRT2_UP = np.float32(1.41421366)
 
 
-def pixel_boxes(soa: np.ndarray, H: int, W: int):
-    """Per-particle clamped pixel box (x0, x1, y0, y1) and a validity mask (FP32 recipe)."""
+def pixel_boxes(soa: np.ndarray, H: int, W: int, habit_radius=None):
+    """Per-particle clamped pixel box (x0, x1, y0, y1) and a validity mask (FP32 recipe).
+    habit_radius: FP32 bounding radii of the frame's polyhedral habits (or None)."""
     soa = np.asarray(soa, dtype=np.float32)
     cx, cy, a, b, shape = soa[0], soa[1], soa[3], soa[4], soa[7]
     one = np.float32(1.0)
+    R = np.asarray(habit_radius if habit_radius is not None else [], dtype=np.float32)
     with np.errstate(invalid="ignore", over="ignore"):
         valid = (a > 0) & (b > 0)
         m = np.where(valid, np.maximum(a, b), np.float32(0.0)).astype(np.float32)
-        ext = np.where(shape < np.float32(0.5), m * SQRT2_UP + one, m + one).astype(np.float32)
+        hab = shape >= np.float32(1.5)
+        k = np.where(hab, np.floor(shape + np.float32(0.5)) - np.float32(2.0), np.float32(0.0))
+        known = hab & (k >= 0) & (k < R.size)
+        valid &= ~hab | known
+        Rk = np.where(known, R[np.clip(k, 0, max(R.size - 1, 0)).astype(np.int64)] if R.size else np.float32(0),
+                      np.float32(0.0)).astype(np.float32)
+        ext = np.where(shape < np.float32(0.5), m * SQRT2_UP + one,
+                       np.where(hab, (m * Rk).astype(np.float32) + one, m + one)).astype(np.float32)
         fx0 = np.floor(cx - ext)
         fx1 = np.floor(cx + ext)
         fy0 = np.floor(cy - ext)
@@ -48,7 +60,7 @@ def pixel_boxes(soa: np.ndarray, H: int, W: int):
     return x0, x1, y0, y1, valid
 
 
-def bin_pairs(soa: np.ndarray, H: int, W: int, tile_h: int, tile_w: int):
+def bin_pairs(soa: np.ndarray, H: int, W: int, tile_h: int, tile_w: int, habit_radius=None):
     """Sorted (tile key, particle id) pairs of the particle table.
 
     Returns a dict with int32 arrays ``keys``, ``pids``, ``tile_start``
@@ -58,7 +70,7 @@ def bin_pairs(soa: np.ndarray, H: int, W: int, tile_h: int, tile_w: int):
     """
     assert H % tile_h == 0 and W % tile_w == 0
     ntx, nty = W // tile_w, H // tile_h
-    x0, x1, y0, y1, valid = pixel_boxes(soa, H, W)
+    x0, x1, y0, y1, valid = pixel_boxes(soa, H, W, habit_radius)
     n = x0.shape[0]
     keys, pids, counts = [], [], np.zeros(n, dtype=np.int64)
     for p in range(n):

@@ -49,7 +49,7 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def opd(soa: np.ndarray, H: int, W: int) -> np.ndarray:
+def opd(soa: np.ndarray, H: int, W: int, habits=None, topo_seed: int = 0) -> np.ndarray:
     """OPD canvas [H][W] in micrometres, FP64.
 
     ``soa`` is the [8][ld] particle table (rows: cx, cy, angle, a, b, height, dn,
@@ -68,10 +68,13 @@ def opd(soa: np.ndarray, H: int, W: int) -> np.ndarray:
         lib.oracle_opd_f64(H, W, _ptr(soa), n, n, _ptr(out))
     else:
         raise TypeError("soa must be float32 or float64")
+    if habits:
+        from . import habits as _habits
+        _habits.add_habits(out, soa, habits, topo_seed, row=6)
     return out
 
 
-def absorbance(soa: np.ndarray, H: int, W: int) -> np.ndarray:
+def absorbance(soa: np.ndarray, H: int, W: int, habits=None, topo_seed: int = 0) -> np.ndarray:
     """Absorbance canvas tau [H][W], FP64, of a [9][n] table whose row 8 is the
     attenuation contrast dmu = mu_particle - mu_solvent [1/um].
 
@@ -84,7 +87,11 @@ def absorbance(soa: np.ndarray, H: int, W: int) -> np.ndarray:
     assert soa.ndim == 2 and soa.shape[0] == 9
     t = np.array(soa[:8], copy=True)
     t[6] = soa[8]
-    return opd(t, H, W)
+    out = opd(t, H, W)
+    if habits:
+        from . import habits as _habits
+        _habits.add_habits(out, soa, habits, topo_seed, row=8)
+    return out
 
 
 def opd_at(soa: np.ndarray, H: int, W: int, rows, cols) -> np.ndarray:

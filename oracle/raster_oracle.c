@@ -72,10 +72,11 @@ static long lmax(long a, long b) { return a > b ? a : b; }
 static long lmin(long a, long b) { return a < b ? a : b; }
 
 /* Thickness-weighted OPD of one particle added into opd[H][W] (row-major).
- * soa rows: 0 cx 1 cy 2 angle 3 a 4 b 5 height 6 dn 7 shape (>= 0.5: ellipsoid). */
+ * soa rows: 0 cx 1 cy 2 angle 3 a 4 b 5 height 6 dn 7 shape (< 0.5 prism, < 1.5
+ * ellipsoid; >= 1.5 polyhedral habits, added by the Python side, habits.py). */
 static void add_particle(int H, int W, double cx, double cy, double ang, double a, double b,
                          double h, double dn, double shape, double* opd) {
-  if (!(a > 0.0) || !(b > 0.0)) return;
+  if (!(a > 0.0) || !(b > 0.0) || shape >= 1.5) return;
   double c = cos(ang), s = sin(ang);
   if (shape < 0.5) {
     /* footprint corners, counter-clockwise in the local frame */
@@ -140,7 +141,7 @@ void oracle_opd_at(int H, int W, const float* soa, int64_t n, int64_t ld,
     double cx = soa[0 * ld + p], cy = soa[1 * ld + p], ang = soa[2 * ld + p];
     double a = soa[3 * ld + p], b = soa[4 * ld + p], h = soa[5 * ld + p];
     double dn = soa[6 * ld + p], shape = soa[7 * ld + p];
-    if (!(a > 0.0) || !(b > 0.0)) continue;
+    if (!(a > 0.0) || !(b > 0.0) || shape >= 1.5) continue;
     double r = (a > b ? a : b) * 1.5 + 2.0;
     double c = cos(ang), s = sin(ang);
     for (int64_t k = 0; k < m; ++k) {
