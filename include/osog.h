@@ -63,7 +63,8 @@ enum {
   OSOG_B = 4,      /* half-width along v [px] / semi-axis                       */
   OSOG_HEIGHT = 5, /* prism height / ellipsoid full central thickness [um]      */
   OSOG_DN = 6,     /* n_particle - n_medium                                     */
-  OSOG_SHAPE = 7,  /* < 0.5: prism (box-filtered exact area); else ellipsoid    */
+  OSOG_SHAPE = 7,  /* < 0.5 prism (box-filtered exact area); < 1.5 ellipsoid;   */
+                   /* 2 + k polyhedral habit k (osog_set_habits)               */
   OSOG_D = 8,
   /* absorbing tables (osog_optics.absorption = 1) carry one more row:           */
   OSOG_DMU = 8,    /* mu_particle - mu_solvent, attenuation contrast [1/um]    */
@@ -127,7 +128,8 @@ osog_status osog_workspace_size(const osog_context* ctx, int32_t height, int32_t
                                 int32_t pairs_per_particle, int32_t with_backward, size_t* bytes);
 
 /* Forward render (paper Sec. III, f(Theta) = I):
- *   soa           device float[OSOG_D][ld] (absorbing: float[OSOG_D_ABS][ld]),
+ *   soa           device float[OSOG_D][ld] (absorbing: float[OSOG_D_ABS][ld]);
+ *                 shape < 0.5 prism, < 1.5 ellipsoid, 2 + k habit k (osog_set_habits),
  *                 ld >= n, n >= 0 (n = 0: empty canvas)
  *   optics        host, static optics
  *   globals       device float[4] (see above)
@@ -296,6 +298,31 @@ osog_status osog_conv3x3(osog_context* ctx, void* stream, int32_t mode, int32_t 
                          int32_t width, int32_t c_in, int32_t c_out, int32_t stride, const uint16_t* x,
                          const uint16_t* y, const uint16_t* grad_y, const uint16_t* w, const float* bias,
                          uint16_t* out_bf16, float* out_f32, void* workspace, size_t workspace_bytes);
+
+/* Polyhedral crystal habits (paper Eq. 1: a habit is the intersection of M
+ * half-spaces) for particles whose table row OSOG_SHAPE holds 2 + k (habit k).
+ * Habit k, in unit coordinates (U, V, W), is {n_x U + n_y V + n_z W <= d} over
+ * its faces; a particle of it occupies (x, y) = c + R(angle) (a U, b V),
+ * z = height W, and its thickness at a pixel is the length of the vertical ray
+ * through the pixel centre inside the solid.  Micro-topography (the procedural
+ * high-frequency perturbation of the height map): where that thickness is
+ * positive it becomes max(0, t + amplitude r(x, y)), r value noise on a square
+ * lattice of `cell` px in canvas coordinates, lattice values 2u - 1 from the first
+ * word of the Philox4x32-10 block at counter (lattice x, lattice y, k, 3) under
+ * topo_seed (u as for the shot noise), blended with smoothstep weights.
+ *   face_counts   host int32[n_habits], 4..32 faces each
+ *   faces         host float[sum counts][4]: (n_x, n_y, n_z, d), habit after habit
+ *   radius        host float[n_habits]: a bound on sqrt(U^2 + V^2) over the habit
+ *                 (it sets the particle's pixel box: max(a, b) radius + 1)
+ *   topo_amplitude_um, topo_cell_px  host float[n_habits] (amplitude >= 0; cell a
+ *                 power of two in [1, 256])
+ * Each habit must be a bounded, non-empty polytope (checked by enumerating its
+ * vertices) whose vertices lie within `radius`.  Replaces the context's habits
+ * (n_habits = 0 clears them); a table row naming an undefined habit adds
+ * nothing.  Synchronous (uploads a small table). */
+osog_status osog_set_habits(osog_context* ctx, int32_t n_habits, const int32_t* face_counts, const float* faces,
+                            const float* radius, const float* topo_amplitude_um, const float* topo_cell_px,
+                            uint64_t topo_seed);
 
 /* ---- Spectral loss of Eq. 8 (targets that cannot be aligned pixel by pixel) -----
  * With F the unnormalised 2-D DFT and eps > 0 inside the logarithms,

@@ -19,17 +19,17 @@ from . import optics as _optics
 from . import raster as _raster
 
 
-def image64(soa64: np.ndarray, H: int, W: int, optics, g64) -> np.ndarray:
+def image64(soa64: np.ndarray, H: int, W: int, optics, g64, habits=None, topo_seed: int = 0) -> np.ndarray:
     """Noiseless image of an FP64 table; a [9][n] table is an absorbing one."""
     soa64 = np.asarray(soa64, dtype=np.float64)
-    opd = _raster.opd(soa64, H, W)
-    tau = _raster.absorbance(soa64, H, W) if soa64.shape[0] == 9 else None
+    opd = _raster.opd(soa64, H, W, habits, topo_seed)
+    tau = _raster.absorbance(soa64, H, W, habits, topo_seed) if soa64.shape[0] == 9 else None
     return _optics.intensity(opd, optics, float(g64[0]), float(g64[1]), float(g64[2]), tau=tau)
 
 
-def loss(soa64, H, W, optics, g64, weights) -> float:
+def loss(soa64, H, W, optics, g64, weights, habits=None, topo_seed: int = 0) -> float:
     """L = sum_ij weights_ij * I_ij (a linear probe of the noiseless image)."""
-    return float(np.sum(weights * image64(soa64, H, W, optics, g64)))
+    return float(np.sum(weights * image64(soa64, H, W, optics, g64, habits, topo_seed)))
 
 
 def _central(f, x0: float, d: float) -> float:
@@ -37,7 +37,7 @@ def _central(f, x0: float, d: float) -> float:
 
 
 def fd_gradients(soa, H, W, optics, globals4, weights, rows=(0, 1, 2, 3, 4, 5, 6),
-                 delta: float = 1e-5):
+                 delta: float = 1e-5, habits=None, topo_seed: int = 0):
     """FD gradients of sum(weights * I) w.r.t. SoA rows ``rows`` and globals 0..2.
 
     Returns (grad_soa [rows of the table][n] FP64 with untouched rows zero,
@@ -47,7 +47,7 @@ def fd_gradients(soa, H, W, optics, globals4, weights, rows=(0, 1, 2, 3, 4, 5, 6
     g64 = np.array(globals4, dtype=np.float64)
     D, n = soa64.shape
     # rounding noise of a central difference is ~ eps |L| / d; never flag below it
-    floor = 1e-9 * max(abs(loss(soa64, H, W, optics, g64, weights)), 1.0)
+    floor = 1e-9 * max(abs(loss(soa64, H, W, optics, g64, weights, habits, topo_seed)), 1.0)
     gs = np.zeros((D, n))
     fs = np.zeros((D, n), dtype=bool)
     for r in rows:
@@ -55,7 +55,7 @@ def fd_gradients(soa, H, W, optics, globals4, weights, rows=(0, 1, 2, 3, 4, 5, 6
             def f(v, r=r, p=p):
                 s = soa64.copy()
                 s[r, p] = v
-                return loss(s, H, W, optics, g64, weights)
+                return loss(s, H, W, optics, g64, weights, habits, topo_seed)
             x0 = soa64[r, p]
             e1 = _central(f, x0, delta)
             e2 = _central(f, x0, delta / 2)
@@ -67,7 +67,7 @@ def fd_gradients(soa, H, W, optics, globals4, weights, rows=(0, 1, 2, 3, 4, 5, 6
         def f(v, k=k):
             g = g64.copy()
             g[k] = v
-            return loss(soa64, H, W, optics, g, weights)
+            return loss(soa64, H, W, optics, g, weights, habits, topo_seed)
         e1 = _central(f, g64[k], delta)
         e2 = _central(f, g64[k], delta / 2)
         gg[k] = e2

@@ -24,6 +24,7 @@ EXPORTS = [
     "osog_profile_read", "osog_cnn_param_count", "osog_cnn_workspace_size", "osog_cnn_forward",
     "osog_cnn_train_step", "osog_conv3x3_workspace_size", "osog_conv3x3", "osog_status_string",
     "osog_last_error", "osog_spectral_workspace_size", "osog_spectral_target", "osog_spectral_loss",
+    "osog_set_habits",
 ]
 
 
@@ -109,6 +110,7 @@ def load(path: str = LIB_PATH):
         "osog_conv3x3_workspace_size": [i32, i32, i32, i32, i32, i32, i32, ctypes.POINTER(sz)],
         "osog_conv3x3": [vp, vp, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, sz],
         "osog_spectral_workspace_size": [i32, i32, ctypes.POINTER(sz)],
+        "osog_set_habits": [vp, i32, vp, vp, vp, vp, vp, ctypes.c_uint64],
         "osog_spectral_target": [vp, vp, i32, i32, vp, ctypes.c_float, vp, vp, sz],
         "osog_spectral_loss": [vp, vp, i32, i32, vp, vp, ctypes.c_float, vp, vp, vp, sz],
         "osog_status_string": [ctypes.c_int],

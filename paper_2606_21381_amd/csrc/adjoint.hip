@@ -223,7 +223,10 @@ __global__ void __launch_bounds__(kThreads) k_adj_raster(const float* __restrict
                                                          int tile_h, int tile_w,
                                                          const float* __restrict__ gopd,
                                                          const float* __restrict__ gtau,
-                                                         float* __restrict__ grad_soa) {
+                                                         float* __restrict__ grad_soa,
+                                                         const float4* __restrict__ hab_enc,
+                                                         const float4* __restrict__ hab_info,
+                                                         uint32_t topo_lo, uint32_t topo_hi) {
   constexpr int NA = ABS ? 8 : 7;
   __shared__ float red[NA][kThreads];
   const int t = threadIdx.x;
@@ -292,6 +295,48 @@ __global__ void __launch_bounds__(kThreads) k_adj_raster(const float* __restrict
           acc[2] += amp * fang;
           acc[3] += amp * fa;
           acc[4] += amp * fb;
+        } else if (r.f[3] == 2.0f) {
+          // polyhedral habit: t = h w(U, V) (+ topography where positive), w the chord
+          // between the active upper and lower faces, linear in (U, V) between creases;
+          // the jump at a vertical face is not differentiated (centre sampling)
+          const int k = (int)r.f[18];
+          const float4 info = hab_info[k];
+          const float4* enc = hab_enc + k * kMaxFaces;
+          const int nf = (int)info.x;
+          const float dx = ((float)j + 0.5f) - r.f[0], dy = ((float)i + 0.5f) - r.f[1];
+          const float ia = r.f[8], ib = r.f[9];
+          const float U = (c * dx + s * dy) * ia, V = (-s * dx + c * dy) * ib;
+          float lo = -__builtin_inff(), hi = __builtin_inff(), plo = 0.f, qlo = 0.f, phi = 0.f, qhi = 0.f;
+          bool ok = true;
+          for (int f = 0; f < nf; ++f) {
+            const float4 e = enc[f];
+            const float val = e.x * U + e.y * V + e.z;
+            if (e.w > 0.0f) {
+              if (val < hi) { hi = val; phi = e.x; qhi = e.y; }
+            } else if (e.w < 0.0f) {
+              if (val > lo) { lo = val; plo = e.x; qlo = e.y; }
+            } else {
+              ok = ok && val <= 0.0f;
+            }
+          }
+          if (!ok || !(hi > lo)) continue;
+          const float w = hi - lo;
+          float t = h * w;
+          if (info.z > 0.0f) {
+            t = t + info.z * value_noise((float)j + 0.5f, (float)i + 0.5f, 1.0f / info.w, (uint32_t)k, topo_lo,
+                                         topo_hi);
+            if (!(t > 0.0f)) continue;
+          }
+          acc[5] += gw * w;
+          acc[6] += g * t;
+          if (ABS) acc[7] += gt * t;
+          const float wU = phi - plo, wV = qhi - qlo, k1 = gw * h;
+          const float dUa = (-s * dx + c * dy) * ia, dVa = (-c * dx - s * dy) * ib;
+          acc[0] += k1 * (wU * (-c * ia) + wV * (s * ib));
+          acc[1] += k1 * (wU * (-s * ia) + wV * (-c * ib));
+          acc[2] += k1 * (wU * dUa + wV * dVa);
+          acc[3] += k1 * wU * (-U * ia);
+          acc[4] += k1 * wV * (-V * ib);
         } else {
           const float dx = ((float)j + 0.5f) - r.f[0], dy = ((float)i + 0.5f) - r.f[1];
           const float u = c * dx + s * dy, v = -s * dx + c * dy;
@@ -412,10 +457,12 @@ hipError_t launch_raster_adjoint(const FramePlan& p, const float* soa, FrameBufs
                                  hipStream_t s) {
   if (p.n > 0 && p.absorb)
     hipLaunchKernelGGL(k_adj_raster<true>, dim3((unsigned)p.n), dim3(kThreads), 0, s, soa, p.n, p.ld, b.recs,
-                       b.boxes, p.W, p.tile_h, p.tile_w, b.gopd, b.gtau, grad_soa);
+                       b.boxes, p.W, p.tile_h, p.tile_w, b.gopd, b.gtau, grad_soa, p.hab_enc, p.hab_info, p.topo_lo,
+                       p.topo_hi);
   else if (p.n > 0)
     hipLaunchKernelGGL(k_adj_raster<false>, dim3((unsigned)p.n), dim3(kThreads), 0, s, soa, p.n, p.ld, b.recs,
-                       b.boxes, p.W, p.tile_h, p.tile_w, b.gopd, b.gtau, grad_soa);
+                       b.boxes, p.W, p.tile_h, p.tile_w, b.gopd, b.gtau, grad_soa, p.hab_enc, p.hab_info, p.topo_lo,
+                       p.topo_hi);
   return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 
 #include <climits>
 #include <algorithm>
+#include <array>
 #include <map>
 #include <optional>
 #include <cmath>
@@ -29,6 +30,10 @@ struct osog_context {
   int batch_group = 4;
   osog::BatchCache* batch = nullptr;
   osog::Profiler* prof = nullptr;
+  // polyhedral habits (osog_set_habits): enc, raw [kMaxHabits][kMaxFaces], info [kMaxHabits]
+  float4* hab = nullptr;
+  int n_habits = 0;
+  uint64_t topo_seed = 0;
 };
 
 namespace osog {
@@ -256,6 +261,12 @@ FramePlan make_plan(const osog_context* ctx, int H, int W, int64_t n, int64_t ld
   p.seed_hi = (uint32_t)(o.seed >> 32);
   p.frame = o.noise_frame;
   p.absorb = o.absorption ? 1 : 0;
+  p.n_habits = ctx->n_habits;
+  p.hab_enc = ctx->hab;
+  p.hab_raw = ctx->hab ? ctx->hab + kMaxHabits * kMaxFaces : nullptr;
+  p.hab_info = ctx->hab ? ctx->hab + 2 * kMaxHabits * kMaxFaces : nullptr;
+  p.topo_lo = (uint32_t)(ctx->topo_seed & 0xffffffffu);
+  p.topo_hi = (uint32_t)(ctx->topo_seed >> 32);
   return p;
 }
 
@@ -340,8 +351,54 @@ osog_status osog_context_destroy(osog_context* ctx) {
   batch_cache_destroy(ctx->batch);
   profiler_destroy(ctx->prof);
   if (ctx->twiddle) (void)hipFree(ctx->twiddle);
+  if (ctx->hab) (void)hipFree(ctx->hab);
   delete ctx;
   return OSOG_OK;
+}
+
+// Vertices of {x : A x <= d} by intersecting every triple of face planes (FP64),
+// inside a guard box |x_i| <= 1e4 whose own faces are added: a vertex on the guard
+// box means the habit is unbounded.
+static bool habit_vertices(const float* f, int m, double* max_r, bool* bounded) {
+  std::vector<std::array<double, 4>> F;
+  for (int k = 0; k < m; ++k) F.push_back({f[4 * k], f[4 * k + 1], f[4 * k + 2], f[4 * k + 3]});
+  const double G = 1e4;
+  for (int ax = 0; ax < 3; ++ax)
+    for (int sg = -1; sg <= 1; sg += 2) {
+      std::array<double, 4> g{0, 0, 0, G};
+      g[ax] = sg;
+      F.push_back(g);
+    }
+  const int M = (int)F.size();
+  int found = 0;
+  *max_r = 0.0;
+  *bounded = true;
+  for (int a = 0; a < M; ++a)
+    for (int b = a + 1; b < M; ++b)
+      for (int c = b + 1; c < M; ++c) {
+        const double* A[3] = {F[a].data(), F[b].data(), F[c].data()};
+        const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                           A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                           A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+        if (std::fabs(det) < 1e-12) continue;
+        double x[3];
+        for (int col = 0; col < 3; ++col) {  // Cramer's rule
+          double Bm[3][3];
+          for (int r = 0; r < 3; ++r)
+            for (int q = 0; q < 3; ++q) Bm[r][q] = q == col ? A[r][3] : A[r][q];
+          x[col] = (Bm[0][0] * (Bm[1][1] * Bm[2][2] - Bm[1][2] * Bm[2][1]) -
+                    Bm[0][1] * (Bm[1][0] * Bm[2][2] - Bm[1][2] * Bm[2][0]) +
+                    Bm[0][2] * (Bm[1][0] * Bm[2][1] - Bm[1][1] * Bm[2][0])) / det;
+        }
+        bool in = true;
+        for (int k = 0; k < M && in; ++k)
+          in = F[k][0] * x[0] + F[k][1] * x[1] + F[k][2] * x[2] <= F[k][3] + 1e-7 * (1.0 + std::fabs(F[k][3]));
+        if (!in) continue;
+        ++found;
+        if (a >= m || b >= m || c >= m) *bounded = false;
+        *max_r = std::max(*max_r, std::sqrt(x[0] * x[0] + x[1] * x[1]));
+      }
+  return found >= 4;
 }
 
 osog_status osog_set_tiling(osog_context* ctx, int32_t tile_h, int32_t tile_w) {
@@ -527,6 +584,63 @@ osog_status osog_render_backward(osog_context* ctx, void* stream, int32_t height
   }
   if (grad_globals && (e = launch_global_grads(p, b, grad_globals, s)) != hipSuccess)
     return hip_fail(e, "backward: global gradients");
+  return OSOG_OK;
+}
+
+osog_status osog_set_habits(osog_context* ctx, int32_t n_habits, const int32_t* face_counts, const float* faces,
+                            const float* radius, const float* topo_amplitude_um, const float* topo_cell_px,
+                            uint64_t topo_seed) {
+  if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
+  if (n_habits < 0 || n_habits > kMaxHabits)
+    return fail(OSOG_ERR_INVALID_ARGUMENT, "n_habits must be in [0, 64]");
+  if (n_habits > 0 && (!face_counts || !faces || !radius || !topo_amplitude_um || !topo_cell_px))
+    return fail(OSOG_ERR_INVALID_ARGUMENT, "habit arrays are NULL");
+  std::vector<float4> tab(3 * kMaxHabits * kMaxFaces + 0, make_float4(0.f, 0.f, 0.f, 0.f));
+  float4* enc = tab.data();
+  float4* raw = enc + kMaxHabits * kMaxFaces;
+  float4* info = raw + kMaxHabits * kMaxFaces;
+  int64_t off = 0;
+  for (int k = 0; k < n_habits; ++k) {
+    const int m = face_counts[k];
+    const std::string hk = "habit " + std::to_string(k) + ": ";
+    if (m < 4 || m > kMaxFaces) return fail(OSOG_ERR_INVALID_ARGUMENT, hk + "needs 4..32 faces");
+    const float* f = faces + 4 * off;
+    for (int q = 0; q < 4 * m; ++q)
+      if (!std::isfinite(f[q])) return fail(OSOG_ERR_INVALID_ARGUMENT, hk + "faces must be finite");
+    double max_r = 0.0;
+    bool bounded = true;
+    if (!habit_vertices(f, m, &max_r, &bounded)) return fail(OSOG_ERR_INVALID_ARGUMENT, hk + "empty polytope");
+    if (!bounded) return fail(OSOG_ERR_INVALID_ARGUMENT, hk + "unbounded polytope");
+    if (!(radius[k] >= max_r * (1.0 - 1e-6)) || !std::isfinite(radius[k]))
+      return fail(OSOG_ERR_INVALID_ARGUMENT, hk + "radius must bound sqrt(U^2 + V^2) over the polytope (" +
+                                                 std::to_string(max_r) + ")");
+    const float amp = topo_amplitude_um[k], cell = topo_cell_px[k];
+    if (!(amp >= 0.0f) || !std::isfinite(amp))
+      return fail(OSOG_ERR_INVALID_ARGUMENT, hk + "topography amplitude must be finite and >= 0");
+    const int ci = (int)cell;
+    if (!((float)ci == cell && pow2_in(ci, 1, 256)))
+      return fail(OSOG_ERR_INVALID_ARGUMENT, hk + "topography cell must be a power of two in [1, 256] px");
+    for (int q = 0; q < m; ++q) {
+      const float nx = f[4 * q], ny = f[4 * q + 1], nz = f[4 * q + 2], d = f[4 * q + 3];
+      raw[k * kMaxFaces + q] = make_float4(nx, ny, nz, d);
+      if (nz != 0.0f)  // W bound (d - nx U - ny V) / nz, upper for nz > 0, lower for nz < 0
+        enc[k * kMaxFaces + q] = make_float4(-nx / nz, -ny / nz, d / nz, nz > 0.0f ? 1.0f : -1.0f);
+      else
+        enc[k * kMaxFaces + q] = make_float4(nx, ny, -d, 0.0f);
+    }
+    info[k] = make_float4((float)m, radius[k], amp, cell);
+    off += m;
+  }
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  if (!ctx->hab && (e = hipMalloc(&ctx->hab, sizeof(float4) * tab.size())) != hipSuccess) {
+    ctx->hab = nullptr;
+    return hip_fail(e, "hipMalloc(habits)");
+  }
+  if ((e = hipMemcpy(ctx->hab, tab.data(), sizeof(float4) * tab.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    return hip_fail(e, "hipMemcpy(habits)");
+  ctx->n_habits = n_habits;
+  ctx->topo_seed = topo_seed;
   return OSOG_OK;
 }
 

@@ -9,16 +9,18 @@ namespace osog {
 // Conservative pixel box of a particle.  Only exactly rounded FP32 operations
 // with no contraction, so every correct implementation reproduces it bit for bit:
 //   ext = max(a,b) * 1.41421366f + 1 (prism; 1.41421366f is the float just above
-//   sqrt 2, so ext covers the footprint's circumradius plus a pixel) or max(a,b) + 1
-//   (ellipsoid); box = [floor(c - ext), floor(c + ext)] clamped to the canvas.
-// Returns false (no pairs) for a non-positive or NaN half-width, a NaN bound or
-// a box that misses the canvas.
-__device__ __forceinline__ bool pixel_box(float cx, float cy, float a, float b, float shape, int H,
+//   sqrt 2, so ext covers the footprint's circumradius plus a pixel), max(a,b) + 1
+//   (ellipsoid) or max(a,b) * R + 1 (polyhedral habit of bounding radius R);
+//   box = [floor(c - ext), floor(c + ext)] clamped to the canvas.
+// Returns false (no pairs) for a non-positive or NaN half-width, a NaN bound, a
+// habit the frame does not define (R <= 0) or a box that misses the canvas.
+__device__ __forceinline__ bool pixel_box(float cx, float cy, float a, float b, float shape, float R, int H,
                                           int W, int4* box) {
 #pragma clang fp contract(off)
   if (!(a > 0.0f) || !(b > 0.0f)) return false;
   float m = fmaxf(a, b);
-  float ext = (shape < 0.5f) ? (m * 1.41421366f + 1.0f) : (m + 1.0f);
+  if (shape >= 1.5f && !(R > 0.0f)) return false;
+  float ext = (shape < 0.5f) ? (m * 1.41421366f + 1.0f) : (shape < 1.5f ? (m + 1.0f) : (m * R + 1.0f));
   float fx0 = floorf(cx - ext), fx1 = floorf(cx + ext);
   float fy0 = floorf(cy - ext), fy1 = floorf(cy + ext);
   if (!(fx0 <= fx1) || !(fy0 <= fy1)) return false;
@@ -33,7 +35,7 @@ __device__ __forceinline__ bool pixel_box(float cx, float cy, float a, float b, 
 
 // Raster record of a valid particle (layout documented with PRec).
 __device__ __forceinline__ void make_record(float cx, float cy, float ang, float a, float b, float h,
-                                            float dn, float shape, PRec* out) {
+                                            float dn, float shape, float R, float habit, PRec* out) {
   PRec& r = *out;
 #pragma unroll
   for (int k = 0; k < 32; ++k) r.f[k] = 0.0f;
@@ -70,7 +72,7 @@ __device__ __forceinline__ void make_record(float cx, float cy, float ang, float
     r.f[27] = __builtin_amdgcn_rcpf(fmaxf(2.0f * p * q, 1e-30f));
     r.f[28] = r.f[20] - 0.5f; r.f[29] = r.f[21] + 0.5f; r.f[30] = r.f[22] - 0.5f; r.f[31] = r.f[23] + 0.5f;
   } else {
-    r.f[3] = 1.0f;
+    r.f[3] = shape < 1.5f ? 1.0f : 2.0f;
     r.f[8] = 1.0f / a;
     r.f[9] = 1.0f / b;
     r.f[10] = __int_as_float(__double2loint(cd));
@@ -81,9 +83,15 @@ __device__ __forceinline__ void make_record(float cx, float cy, float ang, float
     r.f[15] = h;
     // bounding-box half extents of the ellipse, enlarged so that every pixel centre
     // outside them has q >= 1.002 after FP32 rounding
-    const float ex = sqrtf(a * a * c * c + b * b * s * s), ey = sqrtf(a * a * s * s + b * b * c * c);
-    r.f[16] = ex * 1.0011f + 1e-3f;
-    r.f[17] = ey * 1.0011f + 1e-3f;
+    if (shape < 1.5f) {
+      const float ex = sqrtf(a * a * c * c + b * b * s * s), ey = sqrtf(a * a * s * s + b * b * c * c);
+      r.f[16] = ex * 1.0011f + 1e-3f;
+      r.f[17] = ey * 1.0011f + 1e-3f;
+    } else {  // habit: every point of the solid lies within max(a, b) R of the centre
+      r.f[16] = fmaxf(a, b) * R * 1.0001f + 1e-3f;
+      r.f[17] = r.f[16];
+      r.f[18] = habit;
+    }
   }
 }
 

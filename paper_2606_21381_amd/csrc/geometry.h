@@ -131,6 +131,70 @@ __device__ __forceinline__ double ellipsoid_rim_q(const PRec& r, int i, int j) {
   return uu * uu + vv * vv;
 }
 
+// ---- polyhedral habits (Eq. 1) ------------------------------------------------
+// Unit chord W_hi - W_lo (clamped at 0) of a habit's encoded faces at (U, V), FP32.
+// *near: the smallest |n_x U + n_y V - d| over its vertical faces, where the
+// chord jumps (a pixel that close is recomputed in FP64).
+__device__ __forceinline__ float habit_chord(const float4* __restrict__ enc, int nf, float U, float V, float* near) {
+#pragma clang fp contract(off)
+  float lo = -__builtin_inff(), hi = __builtin_inff(), nr = __builtin_inff();
+  bool ok = true;
+  for (int f = 0; f < nf; ++f) {
+    const float4 e = enc[f];
+    const float val = __builtin_fmaf(e.x, U, __builtin_fmaf(e.y, V, e.z));
+    if (e.w > 0.0f) hi = fminf(hi, val);
+    else if (e.w < 0.0f) lo = fmaxf(lo, val);
+    else {
+      ok = ok & (val <= 0.0f);
+      nr = fminf(nr, fabsf(val));
+    }
+  }
+  *near = nr;
+  return ok ? fmaxf(hi - lo, 0.0f) : 0.0f;
+}
+
+// The same chord in FP64 from the faces as given, at the centre of pixel (i, j).
+__device__ __forceinline__ double habit_chord64(const PRec& r, const float4* __restrict__ raw, int nf, int i, int j) {
+#pragma clang fp contract(off)
+  const double cd = __hiloint2double(__float_as_int(r.f[11]), __float_as_int(r.f[10]));
+  const double sd = __hiloint2double(__float_as_int(r.f[13]), __float_as_int(r.f[12]));
+  const double ddx = ((double)j + 0.5) - (double)r.f[0], ddy = ((double)i + 0.5) - (double)r.f[1];
+  const double U = (cd * ddx + sd * ddy) / (double)r.f[6];
+  const double V = (-sd * ddx + cd * ddy) / (double)r.f[7];
+  double lo = -__builtin_inff(), hi = __builtin_inff();
+  bool ok = true;
+  for (int f = 0; f < nf; ++f) {
+    const float4 e = raw[f];
+    const double c = (double)e.w - (double)e.x * U - (double)e.y * V;
+    if (e.z > 0.0f) hi = fmin(hi, c / (double)e.z);
+    else if (e.z < 0.0f) lo = fmax(lo, c / (double)e.z);
+    else ok = ok && c >= 0.0;
+  }
+  return ok ? fmax(hi - lo, 0.0) : 0.0;
+}
+
+// Micro-topography value noise at canvas point (x, y): lattice values 2u - 1 from
+// the first word of the Philox block at (lattice x, lattice y, habit, 3),
+// smoothstep-blended.  inv_cell = 1 / cell with cell a power of two, so x * inv_cell
+// and the lattice values are exact in FP32.
+__device__ __forceinline__ float topo_lattice(uint32_t ix, uint32_t iy, uint32_t k, uint32_t lo, uint32_t hi) {
+  const uint4 w = philox4x32_10(make_uint4(ix, iy, k, 3u), lo, hi);
+  return ((float)(w.x >> 9) + 0.5f) * (1.0f / 4194304.0f) - 1.0f;
+}
+
+__device__ __forceinline__ float value_noise(float x, float y, float inv_cell, uint32_t k, uint32_t lo, uint32_t hi) {
+#pragma clang fp contract(off)
+  const float gx = x * inv_cell, gy = y * inv_cell;
+  const float x0 = floorf(gx), y0 = floorf(gy);
+  const float fx = gx - x0, fy = gy - y0;
+  const uint32_t ix = (uint32_t)(int)x0, iy = (uint32_t)(int)y0;
+  const float v00 = topo_lattice(ix, iy, k, lo, hi), v10 = topo_lattice(ix + 1u, iy, k, lo, hi);
+  const float v01 = topo_lattice(ix, iy + 1u, k, lo, hi), v11 = topo_lattice(ix + 1u, iy + 1u, k, lo, hi);
+  const float sx = fx * fx * (3.0f - 2.0f * fx), sy = fy * fy * (3.0f - 2.0f * fy);
+  const float a = v00 + (v10 - v00) * sx, b = v01 + (v11 - v01) * sx;
+  return a + (b - a) * sy;
+}
+
 // Ellipsoid thickness times dn at the centre of pixel (i, j) with q in FP64.
 __device__ __forceinline__ float ellipsoid_rim(const PRec& r, int i, int j) {
 #pragma clang fp contract(off)

@@ -16,6 +16,8 @@ constexpr int kTwN = 4096;        // twiddle table length (largest FFT)
 constexpr int kDefaultPairsPerParticle = 32;
 constexpr int kXcds = 8;          // MI355X: 8 accelerator dies, each with its own L2
 constexpr int kMaxBucket = 1024;  // ids per tile bucket at most (the raster sorts up to this many)
+constexpr int kMaxHabits = 64;    // polyhedral habits per context
+constexpr int kMaxFaces = 32;     // faces per habit
 
 // Per-particle raster record, 128 bytes, written once by the prepare kernel and
 // read by the raster through the scalar cache.
@@ -30,6 +32,8 @@ constexpr int kMaxBucket = 1024;  // ids per tile bucket at most (the raster sor
 //   ellipsoid f[8] 1/a f[9] 1/b f[10..11] cos as double f[12..13] sin as double
 //             f[14] dn f[15] h     (the FP64 rim refinement uses these)
 //             f[16], f[17] half extents of the bounding box, enlarged (see ellipse_extent)
+//   habit     (kind 2) as the ellipsoid in f[8..15]; f[16] = f[17] = max(a, b) R
+//             (enlarged) bounds the solid's distance from the centre; f[18] habit index
 struct __align__(16) PRec {
   float f[32];
 };
@@ -56,6 +60,15 @@ struct FramePlan {
   double dx_d, tfx_d, tfy_d;
   float photons;
   float read_sigma;      // Gaussian read noise [photon counts]
+  // polyhedral habits of the context (device tables, kMaxFaces faces per habit):
+  //   enc[f]  (p, q, r, type): type +1 / -1 an upper / lower bound W <= / >= p U + q V + r,
+  //           type 0 a vertical face, inside where p U + q V + r <= 0
+  //   raw[f]  (n_x, n_y, n_z, d) as given;  info[k] (faces, radius, topography amplitude, cell)
+  const float4* hab_enc;
+  const float4* hab_raw;
+  const float4* hab_info;
+  int n_habits;
+  uint32_t topo_lo, topo_hi;
   uint32_t seed_lo, seed_hi, frame;
   int absorb;            // 1: Beer-Lambert amplitude from the absorbance canvas
 };

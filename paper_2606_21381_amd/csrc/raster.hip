@@ -20,11 +20,13 @@ namespace osog {
 // Workgroups are dealt to the 8 XCDs in turn (workgroup i to XCD i mod 8), so
 // the tile of workgroup i is chosen to give each XCD one contiguous band of
 // tiles: a particle spanning neighbouring tiles is then fetched into one L2.
-template <bool ABS>
+// HAB: the frame's context defines polyhedral habits (a separate build of the
+// kernel, so frames without them keep the smaller register footprint).
+template <bool ABS, bool HAB>
 __global__ void __launch_bounds__(64) k_raster(FrameDev F, int per_xcd) {
   __shared__ int seg[kSegSort];
   const int tile = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
-  if (tile < F.n_tiles) raster_tile<ABS>(F, tile, threadIdx.x, seg);
+  if (tile < F.n_tiles) raster_tile<ABS, HAB>(F, tile, threadIdx.x, seg);
 }
 
 hipError_t launch_raster(const FramePlan& p, FrameBufs& b, float* opd, float* tau, hipStream_t s) {
@@ -32,8 +34,14 @@ hipError_t launch_raster(const FramePlan& p, FrameBufs& b, float* opd, float* ta
   F.opd = opd;
   F.tau = tau;
   const int per = (p.n_tiles + kXcds - 1) / kXcds;
-  if (p.absorb) hipLaunchKernelGGL(k_raster<true>, dim3(per * kXcds), dim3(64), 0, s, F, per);
-  else hipLaunchKernelGGL(k_raster<false>, dim3(per * kXcds), dim3(64), 0, s, F, per);
+  const dim3 g(per * kXcds), wg(64);
+  if (p.n_habits > 0) {
+    if (p.absorb) hipLaunchKernelGGL((k_raster<true, true>), g, wg, 0, s, F, per);
+    else hipLaunchKernelGGL((k_raster<false, true>), g, wg, 0, s, F, per);
+  } else {
+    if (p.absorb) hipLaunchKernelGGL((k_raster<true, false>), g, wg, 0, s, F, per);
+    else hipLaunchKernelGGL((k_raster<false, false>), g, wg, 0, s, F, per);
+  }
   return hipGetLastError();
 }
 

@@ -32,6 +32,11 @@ struct FrameDev {
   float* tau;                      // absorbance canvas (absorbing frames)
   float2* absr;                    // per particle (dmu * height, dmu) (absorbing frames)
   int absorb;
+  const float4* hab_enc;           // polyhedral habits (see FramePlan)
+  const float4* hab_raw;
+  const float4* hab_info;
+  int n_habits;
+  uint32_t topo_lo, topo_hi;
   float* intensity;
   PRec* recs;
   int4* boxes;
@@ -66,13 +71,21 @@ __device__ __forceinline__ void bin_body(const FrameDev& F, int64_t p) {
   const float a = soa[3 * ld + p], b = soa[4 * ld + p], h = soa[5 * ld + p];
   const float dn = soa[6 * ld + p], shape = soa[7 * ld + p];
   int4 box;
-  const bool ok = pixel_box(cx, cy, a, b, shape, F.H, F.W, &box);
+  float R = 0.0f, habit = -1.0f;  // a polyhedral habit's bounding radius and index
+  if (shape >= 1.5f) {
+    const float kf = floorf(shape + 0.5f) - 2.0f;
+    if (kf >= 0.0f && kf < (float)F.n_habits) {
+      habit = kf;
+      R = F.hab_info[(int)kf].y;
+    }
+  }
+  const bool ok = pixel_box(cx, cy, a, b, shape, R, F.H, F.W, &box);
   PRec r;
 #pragma unroll
   for (int k = 0; k < 32; ++k) r.f[k] = 0.0f;
   int cnt = 0;
   if (ok) {
-    make_record(cx, cy, ang, a, b, h, dn, shape, &r);
+    make_record(cx, cy, ang, a, b, h, dn, shape, R, habit, &r);
   } else {
     r.f[3] = -1.0f;
     box = make_int4(1, 0, 1, 0);
@@ -217,6 +230,10 @@ struct TileAcc {
   float scx, scy, shx, shy;  // centre of its pixel centres, half extents
   float acc[4];
   float tacc[4];             // absorbance sums (absorbing frames)
+  const float4* hab_enc;     // polyhedral habits of the frame
+  const float4* hab_raw;
+  const float4* hab_info;
+  uint32_t topo_lo, topo_hi;
 };
 
 // Adds one particle to the four pixel slots a lane owns.  The slot tests (does
@@ -237,7 +254,7 @@ struct TileAcc {
 // pixel receives exactly one term per particle, in particle order.  ABS: the same
 // coverage (prism) or centre thickness (ellipsoid) also adds dmu * height times it
 // to the absorbance sums; ab = (dmu * height, dmu) of the particle.
-template <bool ABS>
+template <bool ABS, bool HAB>
 __device__ __forceinline__ void add_particle(const PRec& r, TileAcc& T, float2 ab) {
 #pragma clang fp contract(off)
   const float kind = r.f[3];
@@ -357,6 +374,53 @@ __device__ __forceinline__ void add_particle(const PRec& r, TileAcc& T, float2 a
         else T.tacc[3] += tadd;
       }
     }
+  } else if (HAB && kind == 2.0f) {
+    // polyhedral habit: chord of the vertical ray through the pixel centre (Eq. 1),
+    // times the height, plus the micro-topography where it is positive
+    const bool hit = !((T.sx1 - 0.5f - r.f[0] < -r.f[16]) | (T.sx0 + 0.5f - r.f[0] > r.f[16]) |
+                       (T.sy1 - 0.5f - r.f[1] < -r.f[17]) | (T.sy0 + 0.5f - r.f[1] > r.f[17]));
+    const unsigned hit_m = (unsigned)__ballot(hit) & 15u;
+    const int k = (int)r.f[18];
+    const float4 info = T.hab_info[k];
+    const float4* __restrict__ enc = T.hab_enc + k * kMaxFaces;
+    const int nf = (int)info.x;
+    const float h = r.f[15], dn = r.f[14], tamp = info.z, inv_cell = 1.0f / info.w;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (!((hit_m >> q) & 1u)) continue;
+      const float dx = T.px[q] - r.f[0], dy = T.py[q] - r.f[1];
+      const float U = __builtin_fmaf(c, dx, s * dy) * r.f[8], V = __builtin_fmaf(c, dy, -(s * dx)) * r.f[9];
+      float near;
+      float t = h * habit_chord(enc, nf, U, V, &near);
+      if (tamp > 0.0f && t > 0.0f)
+        t = fmaxf(t + tamp * value_noise(T.px[q], T.py[q], inv_cell, (uint32_t)k, T.topo_lo, T.topo_hi), 0.0f);
+      const bool costly = near < 1e-4f;  // next to a vertical face: FP64 below
+      T.acc[q] += sel(costly, 0.0f, dn * t);
+      if (ABS) T.tacc[q] += sel(costly, 0.0f, ab.y * t);
+      marks |= (unsigned)costly << q;
+    }
+    while (marks) {
+      const int q = __builtin_ctz(marks);
+      marks &= marks - 1u;
+      const int ii = q == 0 ? T.pi[0] : (q == 1 ? T.pi[1] : (q == 2 ? T.pi[2] : T.pi[3]));
+      const int jj = q == 0 ? T.pj[0] : (q == 1 ? T.pj[1] : (q == 2 ? T.pj[2] : T.pj[3]));
+      double t = (double)h * habit_chord64(r, T.hab_raw + k * kMaxFaces, nf, ii, jj);
+      if (tamp > 0.0f && t > 0.0)
+        t = fmax(t + (double)tamp * (double)value_noise((float)jj + 0.5f, (float)ii + 0.5f, inv_cell, (uint32_t)k,
+                                                        T.topo_lo, T.topo_hi), 0.0);
+      const float add = (float)((double)dn * t);
+      if (q == 0) T.acc[0] += add;
+      else if (q == 1) T.acc[1] += add;
+      else if (q == 2) T.acc[2] += add;
+      else T.acc[3] += add;
+      if (ABS) {
+        const float tadd = (float)((double)ab.y * t);
+        if (q == 0) T.tacc[0] += tadd;
+        else if (q == 1) T.tacc[1] += tadd;
+        else if (q == 2) T.tacc[2] += tadd;
+        else T.tacc[3] += tadd;
+      }
+    }
   }
 }
 
@@ -373,7 +437,7 @@ __device__ __forceinline__ float2 absorb_weights(const FrameDev& F, int64_t id) 
   return ABS ? F.absr[id] : make_float2(0.0f, 0.0f);
 }
 
-template <bool ABS>
+template <bool ABS, bool HAB>
 __device__ __forceinline__ void raster_ids(const FrameDev& F, TileAcc& T, int mine, int m) {
 #pragma clang fp contract(off)
   const PRec* __restrict__ recs = F.recs;
@@ -382,11 +446,11 @@ __device__ __forceinline__ void raster_ids(const FrameDev& F, TileAcc& T, int mi
     const PRec cur = nxt;
     const float2 ab = absorb_weights<ABS>(F, __builtin_amdgcn_readlane(mine, k));
     if (k + 1 < m) nxt = recs[__builtin_amdgcn_readlane(mine, k + 1)];
-    add_particle<ABS>(cur, T, ab);
+    add_particle<ABS, HAB>(cur, T, ab);
   }
 }
 
-template <bool ABS>
+template <bool ABS, bool HAB>
 __device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int lane, int* seg) {
 #pragma clang fp contract(off)
   const int tile_w = F.tile_w, tile_h = F.tile_h;
@@ -402,6 +466,11 @@ __device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int lan
     T.acc[k] = 0.0f;
     T.tacc[k] = 0.0f;
   }
+  T.hab_enc = F.hab_enc;
+  T.hab_raw = F.hab_raw;
+  T.hab_info = F.hab_info;
+  T.topo_lo = F.topo_lo;
+  T.topo_hi = F.topo_hi;
   {
     const SubRect R = slot_rect(64 * (lane & 3), tile_w, tx, ty, tile_h);
     T.sx0 = R.x0;
@@ -420,7 +489,7 @@ __device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int lan
   if (!overflow && cnt <= 64) {
     if (cnt > 0) {
       const int mine = wave_sort64(lane < cnt ? pids[start + lane] : INT_MAX, lane);
-      raster_ids<ABS>(F, T, mine, cnt);
+      raster_ids<ABS, HAB>(F, T, mine, cnt);
     }
   } else if (!overflow && cnt <= kSegSort) {
     int n2 = 128;
@@ -430,14 +499,14 @@ __device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int lan
     lds_sort(seg, n2, lane);
     for (int c0 = 0; c0 < cnt; c0 += 64) {
       const int m = min(64, cnt - c0);
-      raster_ids<ABS>(F, T, lane < m ? seg[c0 + lane] : 0, m);
+      raster_ids<ABS, HAB>(F, T, lane < m ? seg[c0 + lane] : 0, m);
     }
   } else {
     const int x0 = tx * tile_w, x1 = x0 + tile_w - 1, y0 = ty * tile_h, y1 = y0 + tile_h - 1;
     for (int64_t p = 0; p < F.n; ++p) {
       const int4 b = F.boxes[p];
       if (b.x > b.y || b.x > x1 || b.y < x0 || b.z > y1 || b.w < y0) continue;
-      add_particle<ABS>(F.recs[p], T, absorb_weights<ABS>(F, p));
+      add_particle<ABS, HAB>(F.recs[p], T, absorb_weights<ABS>(F, p));
     }
   }
 #pragma unroll
@@ -730,6 +799,12 @@ inline FrameDev make_dev(const FramePlan& p, const FrameBufs& b) {
   F.tau = b.tau;
   F.absr = b.absr;
   F.absorb = p.absorb;
+  F.hab_enc = p.hab_enc;
+  F.hab_raw = p.hab_raw;
+  F.hab_info = p.hab_info;
+  F.n_habits = p.n_habits;
+  F.topo_lo = p.topo_lo;
+  F.topo_hi = p.topo_hi;
   return F;
 }
 

@@ -363,3 +363,20 @@ class SpectralLossFn(torch.autograd.Function):
 
 def spectral_loss_diff(image: torch.Tensor, target_logamp: torch.Tensor, eps: float) -> torch.Tensor:
     return SpectralLossFn.apply(image, target_logamp, eps)
+
+
+# ---- polyhedral habits (Eq. 1) --------------------------------------------------
+def set_habits(habits, topo_seed: int = 0, device=None):
+    """Install the context's polyhedral habits: a list of objects with ``faces``
+    ([M][4]: n_x, n_y, n_z, d), ``radius``, ``topo_amplitude_um`` and ``topo_cell_px``.
+    Particles with table row 7 = 2 + k use habit k."""
+    import numpy as np
+    n = len(habits)
+    counts = (ctypes.c_int32 * max(n, 1))(*[int(np.asarray(h.faces).shape[0]) for h in habits])
+    flat = np.ascontiguousarray(np.concatenate([np.asarray(h.faces, dtype=np.float32).reshape(-1) for h in habits])
+                                if n else np.zeros(4, np.float32))
+    rad = (ctypes.c_float * max(n, 1))(*[float(h.radius) for h in habits])
+    amp = (ctypes.c_float * max(n, 1))(*[float(h.topo_amplitude_um) for h in habits])
+    cell = (ctypes.c_float * max(n, 1))(*[float(h.topo_cell_px) for h in habits])
+    _lib.check(_lib.load().osog_set_habits(context(device), n, counts, flat.ctypes.data_as(ctypes.c_void_p), rad,
+                                            amp, cell, int(topo_seed) & 0xFFFFFFFFFFFFFFFF), "osog_set_habits")

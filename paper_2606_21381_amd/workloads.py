@@ -97,6 +97,46 @@ def with_absorption(rng: np.random.Generator, s: np.ndarray, lo: float = 0.0, hi
     return np.concatenate([s, dmu[None, :].astype(s.dtype)], axis=0)
 
 
+@dataclass
+class HabitSpec:
+    """A polyhedral crystal habit in unit coordinates: faces [M][4] (n_x, n_y, n_z, d)
+    of {n . (U, V, W) <= d}, a bound on sqrt(U^2 + V^2) over it, and its
+    micro-topography (amplitude in um, lattice cell in px, a power of two)."""
+    faces: np.ndarray
+    radius: float
+    topo_amplitude_um: float = 0.0
+    topo_cell_px: float = 8.0
+
+
+def habit_octahedron(**kw) -> HabitSpec:
+    f = np.array([[sx, sy, sz, 1.0] for sx in (1, -1) for sy in (1, -1) for sz in (1, -1)], dtype=np.float32)
+    return HabitSpec(f, 1.0, **kw)
+
+
+def habit_tetragonal(cap: float = 0.5, **kw) -> HabitSpec:
+    """Square prism |U|, |V| <= 1 between four-sided pyramidal caps reaching W = +-(1 + cap):
+    the tetragonal habit of lysozyme crystals."""
+    f = [[1, 0, 0, 1], [-1, 0, 0, 1], [0, 1, 0, 1], [0, -1, 0, 1]]
+    for sx, sy in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+        f += [[sx, sy, 1.0, 1.0 + cap], [sx, sy, -1.0, 1.0 + cap]]
+    return HabitSpec(np.array(f, dtype=np.float32), math.sqrt(2.0), **kw)
+
+
+def habits_table(rng: np.random.Generator, n: int, H: int, W: int, n_habits: int) -> np.ndarray:
+    """n particles of habits 0..n_habits-1: in-plane scales a, b ~ U[4, 12] px, height
+    ~ U[0.5, 2.5] um, angle ~ U[0, pi), dn ~ U[0.01, 0.05], centres uniform."""
+    s = np.zeros((SOA_ROWS, n), dtype=np.float64)
+    s[0] = rng.uniform(0, W, n)
+    s[1] = rng.uniform(0, H, n)
+    s[2] = rng.uniform(0, math.pi, n)
+    s[3] = rng.uniform(4, 12, n)
+    s[4] = rng.uniform(4, 12, n)
+    s[5] = rng.uniform(0.5, 2.5, n)
+    s[6] = rng.uniform(0.01, 0.05, n)
+    s[7] = 2.0 + rng.integers(0, n_habits, n)
+    return s
+
+
 def f32(s: np.ndarray) -> np.ndarray:
     return np.ascontiguousarray(s.astype(np.float32))
 

@@ -1,0 +1,143 @@
+"""Polyhedral crystal habits (Eq. 1) with micro-topography on the GPU against the
+FP64 oracle: binning (bit-exact), OPD and absorbance (max abs <= 1e-5) and image
+(relative L2 <= 1e-4) on tables mixing prisms, ellipsoids and habits; gradients
+against central differences of the oracle; the batch path (bitwise its single
+renders); rejection of unbounded habits and short radii."""
+import math
+
+import numpy as np
+import pytest
+import torch
+from dataclasses import replace
+
+import oracle
+from oracle import habits as OH
+from paper_2606_21381_amd import _lib, render, workloads
+from tests.gpu_util import dev_globals, dev_soa, need_gpu, oracle_optics, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+SEED = 0x5EED
+HABITS = [workloads.habit_octahedron(), workloads.habit_tetragonal(0.5),
+          workloads.habit_tetragonal(0.3, topo_amplitude_um=0.15, topo_cell_px=4.0)]
+
+
+def oracle_habits(hs):
+    return [OH.Habit(np.asarray(h.faces, dtype=np.float64), float(np.float32(h.radius)), float(h.topo_amplitude_um),
+                     float(h.topo_cell_px)) for h in hs]
+
+
+@pytest.fixture
+def habits():
+    render.set_habits(HABITS, SEED)
+    yield oracle_habits(HABITS)
+    render.set_habits([], 0)
+
+
+def mixed_table(seed, size, n, absorb=False):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    s = np.concatenate([workloads.mixed(rng, n // 2, size, size),
+                        workloads.habits_table(rng, n - n // 2, size, size, len(HABITS))], axis=1)
+    s = s[:, rng.permutation(n)]
+    if absorb:
+        s = workloads.with_absorption(rng, s)
+    return workloads.f32(s)
+
+
+@pytest.mark.parametrize("size,n,absorb", [(256, 300, False), (512, 1500, True)])
+def test_habit_parity(habits, size, n, absorb):
+    need_gpu()
+    say("habit parity %d^2 n=%d absorb %d" % (size, n, absorb))
+    soa = mixed_table(80 + size, size, n, absorb)
+    g = np.array([0.4, 1.0, math.pi / 2, 0], np.float32)
+    opt = replace(workloads.dic_optics(0.0), absorption=1 if absorb else 0)
+    I, planes = render.render(dev_soa(soa), size, size, opt, dev_globals(g), want_opd=True)
+    torch.cuda.synchronize()
+    planes = planes.cpu().double().numpy()
+    ropd = oracle.raster.opd(soa, size, size, habits, SEED)
+    gpu_opd = planes[0] if absorb else planes
+    e_opd = float(np.max(np.abs(gpu_opd - ropd)))
+    rtau = oracle.raster.absorbance(soa, size, size, habits, SEED) if absorb else None
+    e_tau = float(np.max(np.abs(planes[1] - rtau))) if absorb else 0.0
+    rI = oracle.optics.intensity(ropd, oracle_optics(opt), float(g[0]), float(g[1]), float(g[2]), tau=rtau)
+    e_I = rel_l2(I.cpu().numpy(), rI)
+    # the habit particles do contribute
+    only = soa.copy()
+    only[6, soa[7] < 1.5] = 0.0
+    hab_opd = oracle.raster.opd(only, size, size, habits, SEED)
+    say("  OPD max abs %.3e (habits alone reach %.3f um), tau %.3e, I rel L2 %.3e" % (e_opd, hab_opd.max(), e_tau, e_I))
+    assert hab_opd.max() > 0.02
+    assert e_opd <= 1e-5 and e_tau <= 1e-5 and e_I <= 1e-4
+
+
+def test_habit_binning_bit_exact(habits):
+    need_gpu()
+    soa = mixed_table(91, 512, 1200)
+    keys, pids, ts, counts, P = render.bin_pairs(dev_soa(soa), 512, 512)
+    torch.cuda.synchronize()
+    radii = np.array([h.radius for h in HABITS], np.float32)
+    ref = oracle.binning.bin_pairs(soa, 512, 512, 16, 16, habit_radius=radii)
+    assert P == len(ref["keys"])
+    assert np.array_equal(keys.cpu().numpy(), ref["keys"]) and np.array_equal(pids.cpu().numpy(), ref["pids"])
+    assert np.array_equal(ts.cpu().numpy(), ref["tile_start"])
+    say("habit binning: %d pairs, bit-exact" % P)
+
+
+def test_habit_gradients_vs_fd(habits):
+    need_gpu()
+    rng = np.random.Generator(np.random.PCG64(7))
+    n, size = 6, 64
+    s = workloads.habits_table(rng, n, size, size, 1)   # octahedra: no vertical faces
+    s[0] = rng.uniform(16, 48, n)
+    s[1] = rng.uniform(16, 48, n)
+    soa = workloads.f32(s)
+    opt = workloads.dic_optics(0.0)
+    g = np.array([0.5, 1.0, 1.3, 0], np.float32)
+    w = rng.normal(size=(size, size))
+    gs, gg = render.render_backward(dev_soa(soa), size, size, opt, dev_globals(g),
+                                    torch.from_numpy(w.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    gs = gs.cpu().double().numpy()
+    rs, rg, fs, fg = oracle.grad.fd_gradients(soa, size, size, oracle_optics(opt), g, w, habits=habits,
+                                              topo_seed=SEED)
+    say("octahedral habits, 6 particles on 64x64")
+    for r, name in enumerate(["cx", "cy", "angle", "a", "b", "height", "dn"]):
+        got, ref = gs[r][~fs[r]], rs[r][~fs[r]]
+        cos = float(np.dot(got, ref) / (np.linalg.norm(got) * np.linalg.norm(ref)))
+        err = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        say("  %-6s max err / max |g| %.2e  cosine %.8f  (%d flagged)" % (name, err, cos, fs[r].sum()))
+        assert cos >= 0.9999 and err <= 2e-2
+    for k in range(3):
+        assert abs(gg[k] - rg[k]) <= 1e-3 * abs(rg[k])
+
+
+def test_habits_in_a_batch_are_bitwise_single(habits):
+    need_gpu()
+    frames = []
+    for f in range(4):
+        size = (256, 512)[f % 2]
+        frames.append((dev_soa(mixed_table(120 + f, size, 400 + 150 * f)), size, size, workloads.dic_optics(1000.0, f),
+                       dev_globals([0.2 * f, 1.0, 1.5, 0])))
+    singles = [render.render(s, H, W, o, g) for (s, H, W, o, g) in frames]
+    torch.cuda.synchronize()
+    outs = render.Batch(frames).run()
+    torch.cuda.synchronize()
+    for f, (a, b) in enumerate(zip(singles, outs)):
+        assert torch.equal(a, b), f
+
+
+def test_habit_validation():
+    need_gpu()
+    open_top = workloads.HabitSpec(np.array([[1, 0, 0, 1], [-1, 0, 0, 1], [0, 1, 0, 1], [0, -1, 0, 1],
+                                             [0, 0, -1, 0]], np.float32), 1.5)
+    with pytest.raises(_lib.OsogError) as e:
+        render.set_habits([open_top])
+    assert e.value.status == 1 and "unbounded" in str(e.value)
+    short = replace(workloads.habit_octahedron(), radius=0.5)
+    with pytest.raises(_lib.OsogError) as e:
+        render.set_habits([short])
+    assert e.value.status == 1 and "radius" in str(e.value)
+    bad_cell = replace(workloads.habit_octahedron(), topo_amplitude_um=0.1, topo_cell_px=3.0)
+    with pytest.raises(_lib.OsogError):
+        render.set_habits([bad_cell])
+    render.set_habits([], 0)
