@@ -305,8 +305,9 @@ def bench_multimodal(render, soa, fr, dev, reps=20):
 
 
 def bench_variants(render, fr, g, dev, reps=20):
-    """The headline frame with Beer-Lambert absorption (a seeded dmu row) and as
-    Eq. 5's literal (incoherent) DIC: ms per frame of each, with the frame's noise."""
+    """The headline frame with Beer-Lambert absorption (a seeded dmu row), as Eq. 5's
+    literal (incoherent) DIC, and with a third of its particles as polyhedral habits:
+    ms per frame of each, with the frame's noise."""
     import numpy as np
     import torch
     from dataclasses import replace
@@ -314,10 +315,21 @@ def bench_variants(render, fr, g, dev, reps=20):
     rng = np.random.Generator(np.random.PCG64(11))
     soa8 = torch.from_numpy(fr.soa).to(dev)
     soa9 = torch.from_numpy(workloads.f32(workloads.with_absorption(rng, fr.soa.astype(np.float64)))).to(dev)
+    # a third of the particles as polyhedral habits (octahedra, tetragonal bipyramids, one with topography)
+    hab = fr.soa.astype(np.float64).copy()
+    sel = rng.permutation(hab.shape[1])[: hab.shape[1] // 3]
+    hab[:, sel] = workloads.habits_table(rng, sel.size, fr.H, fr.W, 3)
+    soa_h = torch.from_numpy(workloads.f32(hab)).to(dev)
+    habits = [workloads.habit_octahedron(), workloads.habit_tetragonal(0.5),
+              workloads.habit_tetragonal(0.3, topo_amplitude_um=0.15, topo_cell_px=4.0)]
     cases = {"absorbing_dic": (soa9, replace(fr.optics, absorption=1)),
-             "incoherent_dic": (soa8, replace(fr.optics, mode=workloads.DIC_INCOHERENT))}
-    res = {"workload": "dic2048_n40000 (absorbing: dmu ~ U[0, 0.4] 1/um)"}
+             "incoherent_dic": (soa8, replace(fr.optics, mode=workloads.DIC_INCOHERENT)),
+             "habits_dic": (soa_h, fr.optics)}
+    res = {"workload": "dic2048_n40000 (absorbing: dmu ~ U[0, 0.4] 1/um; habits: a third of the particles "
+                       "as octahedra / tetragonal bipyramids, one habit with micro-topography)"}
     for name, (s, o) in cases.items():
+        if name == "habits_dic":
+            render.set_habits(habits, 7)
         out = torch.empty((fr.H, fr.W), dtype=torch.float32, device=dev)
         ws = torch.empty(render.workspace_size(fr.H, fr.W, fr.soa.shape[1], o.mode == workloads.DIC_INCOHERENT),
                          dtype=torch.uint8, device=dev)
@@ -332,6 +344,8 @@ def bench_variants(render, fr, g, dev, reps=20):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         res[name] = {"ms_per_frame": round(ms, 4), "frames_per_s": round(1000.0 / ms, 1)}
+        if name == "habits_dic":
+            render.set_habits([], 0)
     return res
 
 

@@ -137,6 +137,38 @@ def habits_table(rng: np.random.Generator, n: int, H: int, W: int, n_habits: int
     return s
 
 
+def artifacts(rng: np.random.Generator, H: int, W: int, organics: int = 0, debris: int = 0,
+              fouling: int = 0) -> np.ndarray:
+    """Artifact particles of the paper's physical-regularisation pipeline (Sec. III.C:
+    out-of-focus organics, slide debris, objective fouling) as rows of an absorbing
+    [9][m] table, to be appended to one.  The paper gives no models; readings:
+      organics  large faint phase objects: ellipsoids a, b ~ U[20, 60] px, height ~ U[1, 3] um,
+                dn ~ U[0.002, 0.006], dmu ~ U[0, 0.02] 1/um (smooth, low-frequency structure)
+      debris    small dense absorbers: ellipsoids a, b ~ U[3, 12] px, height ~ U[0.3, 1] um,
+                dn ~ U[0.05, 0.15], dmu ~ U[1, 4] 1/um
+      fouling   broad faint absorbing smudges: ellipsoids a, b ~ U[80, 250] px, height ~ U[1, 2] um,
+                dn = 0, dmu ~ U[0.01, 0.05] 1/um
+    Centres are uniform over the canvas, angles U[0, pi)."""
+    rows = []
+    for count, ab, hh, dn, dmu in ((organics, (20, 60), (1, 3), (0.002, 0.006), (0.0, 0.02)),
+                                  (debris, (3, 12), (0.3, 1), (0.05, 0.15), (1.0, 4.0)),
+                                  (fouling, (80, 250), (1, 2), (0.0, 0.0), (0.01, 0.05))):
+        if count <= 0:
+            continue
+        s = np.zeros((SOA_ROWS_ABS, count), dtype=np.float64)
+        s[0] = rng.uniform(0, W, count)
+        s[1] = rng.uniform(0, H, count)
+        s[2] = rng.uniform(0, math.pi, count)
+        s[3] = rng.uniform(*ab, count)
+        s[4] = rng.uniform(*ab, count)
+        s[5] = rng.uniform(*hh, count)
+        s[6] = rng.uniform(*dn, count) if dn[1] > 0 else 0.0
+        s[7] = 1.0
+        s[8] = rng.uniform(*dmu, count)
+        rows.append(s)
+    return np.concatenate(rows, axis=1) if rows else np.zeros((SOA_ROWS_ABS, 0))
+
+
 def f32(s: np.ndarray) -> np.ndarray:
     return np.ascontiguousarray(s.astype(np.float32))
 
