@@ -228,24 +228,40 @@ __global__ void __launch_bounds__(kThreads) k_adj_raster(const float* __restrict
                                                          const float4* __restrict__ hab_info,
                                                          uint32_t topo_lo, uint32_t topo_hi) {
   constexpr int NA = ABS ? 8 : 7;
-  __shared__ float red[NA][kThreads];
-  const int t = threadIdx.x;
-  const int64_t p = blockIdx.x;
+  // one wave per particle: its pixel box is dealt to the 64 lanes row-major
+  const int lane = threadIdx.x & 63;
+  // wave-uniform particle index: the record and table rows come through the scalar cache
+  const int64_t p = (int64_t)blockIdx.x * (kThreads / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if (p >= n) return;  // the whole wave
   const PRec r = recs[p];
   const int4 box = boxes[p];
   const float h = soa[5 * ld + p], dn = soa[6 * ld + p];
   const float dmu = ABS ? soa[8 * ld + p] : 0.0f;
   float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (r.f[3] >= 0.0f && box.x <= box.y) {
-    const int tx0 = box.x / tile_w, tx1 = box.y / tile_w, ty0 = box.z / tile_h, ty1 = box.w / tile_h;
-    const int li = t / tile_w, lj = t - li * tile_w;
+    // the pixels that can see the particle: prism, pixel squares meeting its footprint
+    // bounds; ellipsoid or habit, pixel centres within its enlarged extents -- inside the box
+    float fx0, fx1, fy0, fy1;
+    if (r.f[3] == 0.0f) {
+      fx0 = floorf(r.f[20]); fx1 = ceilf(r.f[21]) - 1.0f; fy0 = floorf(r.f[22]); fy1 = ceilf(r.f[23]) - 1.0f;
+    } else {
+      fx0 = floorf(r.f[0] - r.f[16] - 0.5f); fx1 = ceilf(r.f[0] + r.f[16] - 0.5f);
+      fy0 = floorf(r.f[1] - r.f[17] - 0.5f); fy1 = ceilf(r.f[1] + r.f[17] - 0.5f);
+    }
+    const int x0 = (int)fmaxf(fx0, (float)box.x), x1 = (int)fminf(fx1, (float)box.y);
+    const int y0 = (int)fmaxf(fy0, (float)box.z), y1 = (int)fminf(fy1, (float)box.w);
+    const int bw = x1 - x0 + 1, cnt = (bw > 0 && y1 >= y0) ? bw * (y1 - y0 + 1) : 0;
+    const float inv_bw = cnt > 0 ? 1.0f / (float)bw : 0.0f;
     const bool prism = r.f[3] == 0.0f;
     const float4 bb = prism ? prism_bounds(r) : make_float4(0.f, 0.f, 0.f, 0.f);
     const float c = r.f[4], s = r.f[5], a = r.f[6], b = r.f[7];
-    for (int ty = ty0; ty <= ty1; ++ty)
-      for (int tx = tx0; tx <= tx1; ++tx) {
-        const int i = ty * tile_h + li, j = tx * tile_w + lj;
-        if (j < box.x || j > box.y || i < box.z || i > box.w) continue;
+    for (int base = 0; base < cnt; base += 64) {
+        const int k = base + lane;
+        if (k >= cnt) continue;
+        int row = (int)((float)k * inv_bw);  // then corrected to the exact quotient
+        if (row * bw > k) --row;
+        if ((row + 1) * bw <= k) ++row;
+        const int i = y0 + row, j = x0 + (k - row * bw);
         const float g = gopd[(int64_t)i * W + j];
         const float gt = ABS ? gtau[(int64_t)i * W + j] : 0.0f;
         if (g == 0.0f && gt == 0.0f) continue;
@@ -357,18 +373,19 @@ __global__ void __launch_bounds__(kThreads) k_adj_raster(const float* __restrict
         }
       }
   }
+  // fixed-order butterfly across the wave: bitwise reproducible
 #pragma unroll
-  for (int k = 0; k < NA; ++k) red[k][t] = acc[k];
-  __syncthreads();
-  for (int st = kThreads / 2; st > 0; st >>= 1) {
-    if (t < st) {
-#pragma unroll
-      for (int k = 0; k < NA; ++k) red[k][t] += red[k][t + st];
-    }
-    __syncthreads();
-  }
+  for (int k = 0; k < NA; ++k)
+    for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
   // rows 0-6 from acc[0..6], row 7 (shape) = 0, row 8 (dmu) = acc[7]
-  if (t < NA + 1) grad_soa[(int64_t)t * ld + p] = t < 7 ? red[t][0] : (t == 7 ? 0.0f : red[NA - 1][0]);
+  if (lane < NA + 1) {
+    float v = 0.0f;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) v = (lane == k) ? acc[k] : v;
+    if (lane == 7) v = 0.0f;
+    if (ABS && lane == 8) v = acc[7];
+    grad_soa[(int64_t)lane * ld + p] = v;
+  }
 }
 
 // grad_globals[k] = sum over columns of colgrad[k][col], fixed order; [3] = 0
@@ -455,12 +472,13 @@ hipError_t launch_adj_pass1(const FramePlan& p, const float* opd, const float* t
 
 hipError_t launch_raster_adjoint(const FramePlan& p, const float* soa, FrameBufs& b, float* grad_soa,
                                  hipStream_t s) {
+  const unsigned groups = (unsigned)((p.n + kThreads / 64 - 1) / (kThreads / 64));  // a wave per particle
   if (p.n > 0 && p.absorb)
-    hipLaunchKernelGGL(k_adj_raster<true>, dim3((unsigned)p.n), dim3(kThreads), 0, s, soa, p.n, p.ld, b.recs,
+    hipLaunchKernelGGL(k_adj_raster<true>, dim3(groups), dim3(kThreads), 0, s, soa, p.n, p.ld, b.recs,
                        b.boxes, p.W, p.tile_h, p.tile_w, b.gopd, b.gtau, grad_soa, p.hab_enc, p.hab_info, p.topo_lo,
                        p.topo_hi);
   else if (p.n > 0)
-    hipLaunchKernelGGL(k_adj_raster<false>, dim3((unsigned)p.n), dim3(kThreads), 0, s, soa, p.n, p.ld, b.recs,
+    hipLaunchKernelGGL(k_adj_raster<false>, dim3(groups), dim3(kThreads), 0, s, soa, p.n, p.ld, b.recs,
                        b.boxes, p.W, p.tile_h, p.tile_w, b.gopd, b.gtau, grad_soa, p.hab_enc, p.hab_info, p.topo_lo,
                        p.topo_hi);
   return hipGetLastError();
