@@ -1,0 +1,73 @@
+"""The widened paths at the largest canvas, 4096^2 (one row or column per
+transform workgroup, the full band of 4096 columns), checked by closed forms:
+the incoherent DIC's empty field 4 sin^2(theta), a canvas-filling absorber's
+exp(-2 dmu h), the spectral loss's invariance under circular shifts, and a
+habit particle's binning against the oracle's box recipe."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2606_21381_amd import render, workloads
+from tests.gpu_util import dev_globals, dev_soa, need_gpu, say
+
+pytestmark = pytest.mark.gpu
+N = 4096
+
+
+def test_incoherent_dic_empty_field_4096():
+    need_gpu()
+    soa = torch.zeros((8, 0), dtype=torch.float32, device="cuda")
+    opt = workloads.OpticsSpec(mode=workloads.DIC_INCOHERENT, na=0.5, shear_angle_rad=math.pi / 4)
+    I = render.render(soa, N, N, opt, dev_globals([0.6, 1.0, 1.2, 0]))
+    want = 4 * math.sin(1.2) ** 2
+    err = float((I.double() - want).abs().max()) / want
+    say("incoherent DIC 4096^2 empty field: max rel err %.2e" % err)
+    assert err <= 1e-5
+
+
+def test_canvas_filling_absorber_4096():
+    need_gpu()
+    h, dmu = 1.2, 0.25
+    soa = np.array([[N / 2], [N / 2], [0.0], [5000.0], [5000.0], [h], [0.0], [0.0], [dmu]], np.float32)
+    opt = workloads.OpticsSpec(mode=workloads.BRIGHTFIELD, na=0.5, absorption=1)
+    I = render.render(dev_soa(soa), N, N, opt, dev_globals([0.5, 0, 0, 0]))
+    want = math.exp(-2 * dmu * h)
+    err = float((I.double() - want).abs().max()) / want
+    say("absorber 4096^2: max rel err %.2e" % err)
+    assert err <= 1e-5
+
+
+def test_spectral_loss_shift_invariance_4096():
+    need_gpu()
+    rng = np.random.Generator(np.random.PCG64(3))
+    soa = dev_soa(workloads.f32(workloads.mixed(rng, 20000, N, N)))
+    I = render.render(soa, N, N, workloads.dic_optics(1000.0, 3), dev_globals([0.3, 1.0, 1.5, 0]))
+    T = torch.roll(I, (7, 123), dims=(0, 1)).contiguous()
+    eps = 1e-4 * float(T.double().sum())
+    tl = render.spectral_target(T, eps)
+    loss, grad = render.spectral_loss(I, tl, eps)
+    torch.cuda.synchronize()
+    say("spectral loss 4096^2 of a shifted copy: %.3e, |grad| max %.3e" % (float(loss), float(grad.abs().max())))
+    assert float(loss) < 1e-9
+
+
+def test_habit_binning_4096():
+    need_gpu()
+    habits = [workloads.habit_tetragonal(0.5)]
+    render.set_habits(habits, 1)
+    try:
+        rng = np.random.Generator(np.random.PCG64(4))
+        s = workloads.habits_table(rng, 5000, N, N, 1)
+        s[3] = rng.uniform(4, 40, 5000)   # some particles spanning several tiles
+        soa = workloads.f32(s)
+        keys, pids, ts, counts, P = render.bin_pairs(dev_soa(soa), N, N)
+        torch.cuda.synchronize()
+        ref = oracle.binning.bin_pairs(soa, N, N, 16, 16, habit_radius=np.array([h.radius for h in habits], np.float32))
+        say("habit binning 4096^2: %d pairs" % P)
+        assert P == len(ref["keys"]) and np.array_equal(keys.cpu().numpy(), ref["keys"])
+        assert np.array_equal(pids.cpu().numpy(), ref["pids"])
+    finally:
+        render.set_habits([], 0)
