@@ -86,7 +86,8 @@ hipError_t launch_binning(const FramePlan& p, const float* soa, FrameBufs& b, hi
   FrameDev F = make_dev(p, b);
   F.soa = soa;
   const unsigned gt = (unsigned)((p.n_tiles + kThreads - 1) / kThreads);
-  const unsigned gp = (unsigned)(p.n > 0 ? (p.n + kThreads - 1) / kThreads : 1);
+  const int64_t lanes = p.n * kBinGroup;
+  const unsigned gp = (unsigned)(lanes > 0 ? (lanes + kThreads - 1) / kThreads : 1);
   hipLaunchKernelGGL(k_bin_clear, dim3(gt), dim3(kThreads), 0, s, F);
   hipLaunchKernelGGL(k_bin, dim3(gp), dim3(kThreads), 0, s, F);
   return hipGetLastError();

@@ -60,10 +60,17 @@ struct FrameDev {
 // tiles' true pair counts, which may exceed the bucket (the reader then falls
 // back to an id-ordered scan for that tile, and scal[1] counts such tiles).  The
 // order of ids inside a bucket is restored by the reader, which sorts it.
-// Up to kFillBatch cursor increments are issued before their results are used.
-constexpr int kFillBatch = 8;
+// A group of kBinGroup lanes shares one particle: its first lane writes the
+// record, box and count, and the group deals the particle's tiles round robin,
+// each lane issuing up to kFillBatch cursor increments before their results are
+// used (a particle meets ~5 tiles on average, so most lanes wait on one
+// increment instead of one lane on all of them).
+constexpr int kBinGroup = 8;
+constexpr int kFillBatch = 4;
 
-__device__ __forceinline__ void bin_body(const FrameDev& F, int64_t p) {
+__device__ __forceinline__ void bin_body(const FrameDev& F, int64_t gid) {
+  const int64_t p = gid / kBinGroup;
+  const int sub = (int)(gid - p * kBinGroup);
   if (p >= F.n) return;
   const float* soa = F.soa;
   const int64_t ld = F.ld;
@@ -80,32 +87,38 @@ __device__ __forceinline__ void bin_body(const FrameDev& F, int64_t p) {
     }
   }
   const bool ok = pixel_box(cx, cy, a, b, shape, R, F.H, F.W, &box);
-  PRec r;
-#pragma unroll
-  for (int k = 0; k < 32; ++k) r.f[k] = 0.0f;
   int cnt = 0;
   if (ok) {
-    make_record(cx, cy, ang, a, b, h, dn, shape, R, habit, &r);
-  } else {
-    r.f[3] = -1.0f;
-    box = make_int4(1, 0, 1, 0);
+    const int tx0 = box.x / F.tile_w, tx1 = box.y / F.tile_w, ty0 = box.z / F.tile_h, ty1 = box.w / F.tile_h;
+    cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
   }
-  F.recs[p] = r;
-  F.boxes[p] = box;
-  if (F.absorb) {  // Beer-Lambert weight of the thickness (Eq. 4): row 8 holds dmu
-    const float dmu = ok ? soa[8 * ld + p] : 0.0f;
-    F.absr[p] = make_float2(dmu * h, dmu);
+  if (sub == 0) {
+    PRec r;
+#pragma unroll
+    for (int k = 0; k < 32; ++k) r.f[k] = 0.0f;
+    if (ok) {
+      make_record(cx, cy, ang, a, b, h, dn, shape, R, habit, &r);
+    } else {
+      r.f[3] = -1.0f;
+      box = make_int4(1, 0, 1, 0);
+    }
+    F.recs[p] = r;
+    F.boxes[p] = box;
+    if (F.absorb) {  // Beer-Lambert weight of the thickness (Eq. 4): row 8 holds dmu
+      const float dmu = ok ? soa[8 * ld + p] : 0.0f;
+      F.absr[p] = make_float2(dmu * h, dmu);
+    }
+    F.counts[p] = cnt;
   }
   if (ok) {
     const int tx0 = box.x / F.tile_w, tx1 = box.y / F.tile_w, ty0 = box.z / F.tile_h, ty1 = box.w / F.tile_h;
     const int nx = tx1 - tx0 + 1;
-    cnt = nx * (ty1 - ty0 + 1);
     const int cap = (int)F.cap;
-    for (int e0 = 0; e0 < cnt; e0 += kFillBatch) {
+    for (int e0 = sub; e0 < cnt; e0 += kBinGroup * kFillBatch) {
       int key[kFillBatch], pos[kFillBatch];
 #pragma unroll
       for (int u = 0; u < kFillBatch; ++u) {
-        const int e = e0 + u;
+        const int e = e0 + u * kBinGroup;
         key[u] = e < cnt ? (ty0 + e / nx) * F.ntx + tx0 + e % nx : -1;
         pos[u] = key[u] >= 0 ? atomicAdd(&F.tile_count[key[u]], 1) : 0;
       }
@@ -117,7 +130,6 @@ __device__ __forceinline__ void bin_body(const FrameDev& F, int64_t p) {
       }
     }
   }
-  F.counts[p] = cnt;
 }
 
 // ---- inspection: exclusive prefix of the tile counts (one workgroup) -----------
