@@ -646,6 +646,7 @@ __device__ __forceinline__ void noise_rows(const FrameDev& F, float scale, int64
   const OpticsArgs& o = F.o;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   uint4* queue = reinterpret_cast<uint4*>(lds) + wave * (64 * 2 * CH);
+  const float inv_scale = 1.0f / scale;  // counts / s as one multiply (within two ulps of the quotient)
   float2* out = reinterpret_cast<float2*>(dst);
   for (int k0 = 0; k0 < PP; k0 += CH) {
     float res[2 * CH];
@@ -713,7 +714,7 @@ __device__ __forceinline__ void noise_rows(const FrameDev& F, float scale, int64
         a = a + o.read_sigma * (r * cs);
         b = b + o.read_sigma * (r * sn);
       }
-      out[ml] = make_float2(a / scale, b / scale);
+      out[ml] = make_float2(a * inv_scale, b * inv_scale);
     }
     __syncthreads();  // the queue is reused by the next round
   }
