@@ -251,6 +251,7 @@ def main():
         "paper_context": "paper: 40,000 particles in under 50 ms on one NVIDIA A100 (1024^2 canvas)",
     }
     if not args.no_extras:
+        res["fft_vs_rocfft"] = bench_fft_vs_rocfft(render, lib, ctx, soa, fr, g, dev)
         res["multimodal"] = bench_multimodal(render, soa, fr, dev)
         res["variants"] = bench_variants(render, fr, g, dev)
         res["backward"] = bench_backward(render, soa, g, fr, dev)
@@ -267,6 +268,59 @@ def main():
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(fr)
     print(json.dumps(res), flush=True)
+
+
+def bench_fft_vs_rocfft(render, lib, ctx, soa, fr, g, dev, reps=50):
+    """The imaging chain of a noiseless headline frame (passes 1-3: exp(i k OPD), banded
+    row DFT, column DFT x transfer x inverse column DFT, inverse row DFT, |E|^2) against
+    the same chain through torch.fft (rocFFT): exp(i k OPD), dense FFT2, multiply by a
+    full-grid transfer array, IFFT2, |E|^2.  The transfer values do not change the
+    library FFT's time, so a unit-modulus array stands in for them here (the numerics of
+    the two chains are compared in the forward tests)."""
+    import ctypes
+    from dataclasses import replace
+
+    import torch
+    from paper_2606_21381_amd import _lib
+    H, W = fr.H, fr.W
+    opt0 = replace(fr.optics, photons_mean=0.0)
+    out = torch.empty((H, W), dtype=torch.float32, device=dev)
+    _, opd = render.render(soa, H, W, opt0, g, want_opd=True)
+    for _ in range(5):
+        render.render(soa, H, W, opt0, g, out=out)
+    torch.cuda.synchronize()
+    _lib.check(lib.osog_profile_enable(ctx, 1), "profile_enable")
+    for _ in range(reps):
+        render.render(soa, H, W, opt0, g, out=out)
+    st_ms = (ctypes.c_double * 10)()
+    st_n = (ctypes.c_int64 * 10)()
+    _lib.check(lib.osog_profile_read(ctx, st_ms, st_n), "profile_read")
+    _lib.check(lib.osog_profile_enable(ctx, 0), "profile_disable")
+    us = {_lib.STAGES[k]: 1000.0 * st_ms[k] / st_n[k] for k in range(5) if st_n[k]}
+    chain_us = us["pass1"] + us["pass2"] + us["pass3"]
+    k = 2.0 * math.pi / fr.optics.wavelength_um
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    Hf = torch.polar(torch.ones((H, W), device=dev),
+                     (2.0 * math.pi) * torch.rand((H, W), device=dev, generator=gen))
+
+    def chain():
+        E = torch.fft.ifft2(torch.fft.fft2(torch.polar(torch.ones_like(opd), k * opd)) * Hf)
+        return E.real * E.real + E.imag * E.imag
+
+    for _ in range(5):
+        chain()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        chain()
+    e1.record()
+    torch.cuda.synchronize()
+    roc_us = 1000.0 * e0.elapsed_time(e1) / reps
+    return {"workload": "dic2048_n40000 noiseless imaging chain", "library_passes_us": round(chain_us, 2),
+            "library_stage_us": {k2: round(us[k2], 2) for k2 in ("pass1", "pass2", "pass3")},
+            "rocfft_chain_us": round(roc_us, 2), "speedup": round(roc_us / chain_us, 2)}
 
 
 def bench_multimodal(render, soa, fr, dev, reps=20):

@@ -33,10 +33,12 @@ __global__ void __launch_bounds__(kThreads) k_pass2_keep(const float2* __restric
                                                          const float* __restrict__ globals,
                                                          const float2* __restrict__ tw) {
   constexpr int H = 1 << LOGH;
-  __shared__ float2 buf[H];
+  __shared__ float2 buf[fft_lds_f2(H)];
   __shared__ int chord[2];
   const int t = threadIdx.x, b = blockIdx.x, kx = o.kx_lo + b, RB = o.rb;
-  for (int i = t; i < H; i += kThreads) buf[i] = band[((size_t)(i / RB) * o.kx_n + b) * RB + (i % RB)];
+  gather_lds<8>(
+      H, [&](int i) { return band[((size_t)(i / RB) * o.kx_n + b) * RB + (i % RB)]; },
+      [&](int i, float2 v) { buf[i] = v; });
   if (t == 0) band_chord(o, kx, &chord[0], &chord[1]);
   __syncthreads();
   Stages<H, 1, -1, 1, LOGH>::run(buf, tw);
@@ -58,23 +60,36 @@ __global__ void __launch_bounds__(kThreads) k_adj_pass3(float2* __restrict__ ban
                                                         const float* __restrict__ grad_i,
                                                         const float2* __restrict__ tw) {
   constexpr int W = 1 << LOGW, RB = rows_per_block(W);
-  __shared__ float2 buf[RB * W];
+  __shared__ float2 buf[fft_lds_f2(RB * W)];
   const int t = threadIdx.x, rb = blockIdx.x;
   for (int idx = t; idx < RB * W; idx += kThreads) buf[idx] = make_float2(0.0f, 0.0f);
   __syncthreads();
   float2* blk = band2 + (size_t)rb * o.kx_n * RB;
-  for (int idx = t; idx < o.kx_n * RB; idx += kThreads) {
-    const int b = idx / RB, r = idx - b * RB;
-    buf[r * W + ((o.kx_lo + b) & (W - 1))] = blk[idx];
-  }
+  gather_lds<4>(
+      o.kx_n * RB, [&](int idx) { return blk[idx]; },
+      [&](int idx, float2 v) {
+        const int b = idx / RB, r = idx - b * RB;
+        buf[r * W + ((o.kx_lo + b) & (W - 1))] = v;
+      });
   __syncthreads();
   Stages<W, RB, 1, 1, LOGW>::run(buf, tw);
   const float inv = o.inv_hw;
   const float* gi = grad_i + (size_t)rb * RB * W;
-  for (int idx = t; idx < RB * W; idx += kThreads) {
-    const float2 e = buf[idx];
-    const float g2 = 2.0f * gi[idx] * inv;
-    buf[idx] = make_float2(g2 * e.x * inv, g2 * e.y * inv);  // g_E / (HW), E = B~/(HW)
+  constexpr int NP = RB * W, LB = 8;
+  for (int i0 = t; i0 < NP; i0 += LB * kThreads) {
+    float gv[LB];
+#pragma unroll
+    for (int u = 0; u < LB; ++u)
+      if (i0 + u * kThreads < NP) gv[u] = gi[i0 + u * kThreads];
+#pragma unroll
+    for (int u = 0; u < LB; ++u) {
+      const int idx = i0 + u * kThreads;
+      if (idx < NP) {
+        const float2 e = buf[idx];
+        const float g2 = 2.0f * gv[u] * inv;
+        buf[idx] = make_float2(g2 * e.x * inv, g2 * e.y * inv);  // g_E / (HW), E = B~/(HW)
+      }
+    }
   }
   __syncthreads();
   Stages<W, RB, -1, 1, LOGW>::run(buf, tw);
@@ -92,16 +107,17 @@ __global__ void __launch_bounds__(kThreads) k_adj_pass2(const float2* __restrict
                                                         const float2* __restrict__ tw,
                                                         double* __restrict__ colgrad) {
   constexpr int H = 1 << LOGH;
-  __shared__ float2 ua[H];
-  __shared__ float2 gb[H];
+  __shared__ float2 ua[fft_lds_f2(H)];
+  __shared__ float2 gb[fft_lds_f2(H)];
   __shared__ int chord[2];
   __shared__ double red[3][kThreads];
   const int t = threadIdx.x, b = blockIdx.x, kx = o.kx_lo + b, RB = o.rb;
-  for (int i = t; i < H; i += kThreads) {
-    const size_t at = ((size_t)(i / RB) * o.kx_n + b) * RB + (i % RB);
-    ua[i] = band[at];
-    gb[i] = band2[at];
-  }
+  gather_lds<4>(
+      H, [&](int i) { return band[((size_t)(i / RB) * o.kx_n + b) * RB + (i % RB)]; },
+      [&](int i, float2 v) { ua[i] = v; });
+  gather_lds<4>(
+      H, [&](int i) { return band2[((size_t)(i / RB) * o.kx_n + b) * RB + (i % RB)]; },
+      [&](int i, float2 v) { gb[i] = v; });
   if (t == 0) band_chord(o, kx, &chord[0], &chord[1]);
   __syncthreads();
   Stages<H, 1, -1, 1, LOGH>::run(ua, tw);  // U~
@@ -153,35 +169,52 @@ __global__ void __launch_bounds__(kThreads) k_adj_pass1(const float2* __restrict
                                                         float* __restrict__ gopd, float* __restrict__ gtau,
                                                         int64_t plane) {
   constexpr int W = 1 << LOGW, RB = rows_per_block(W);
-  __shared__ float2 buf[RB * W];
+  __shared__ float2 buf[fft_lds_f2(RB * W)];
   const int t = threadIdx.x, rb = blockIdx.x;
   for (int idx = t; idx < RB * W; idx += kThreads) buf[idx] = make_float2(0.0f, 0.0f);
   __syncthreads();
   const float2* blk = band2 + (size_t)rb * o.kx_n * RB;
-  for (int idx = t; idx < o.kx_n * RB; idx += kThreads) {
-    const int b = idx / RB, r = idx - b * RB;
-    buf[r * W + ((o.kx_lo + b) & (W - 1))] = blk[idx];
-  }
+  gather_lds<4>(
+      o.kx_n * RB, [&](int idx) { return blk[idx]; },
+      [&](int idx, float2 v) {
+        const int b = idx / RB, r = idx - b * RB;
+        buf[r * W + ((o.kx_lo + b) & (W - 1))] = v;
+      });
   __syncthreads();
   Stages<W, RB, 1, 1, LOGW>::run(buf, tw);  // g_U
   const size_t off = (size_t)rb * RB * W;
-  for (int idx = t; idx < RB * W; idx += kThreads) {
-    float s, c;
-    sincosf(phase_k * opd[off + idx], &s, &c);
-    if (tau) {  // U = e^{-tau} (c + i s), as pass 1 forms it
-      const float am = expf(-tau[off + idx]);
-      c = am * c;
-      s = am * s;
+  constexpr int NP = RB * W, LB = 8;
+  for (int i0 = t; i0 < NP; i0 += LB * kThreads) {
+    float ov[LB], tv[LB];
+#pragma unroll
+    for (int u = 0; u < LB; ++u) {
+      const int idx = i0 + u * kThreads;
+      if (idx < NP) {
+        ov[u] = opd[off + idx];
+        tv[u] = tau ? tau[off + idx] : 0.0f;
+      }
     }
-    const float2 g = buf[idx];
-    // Im(conj(U) g_U) with U = c + i s
-    float go = phase_k * (c * g.y - s * g.x);
-    if (grad_opd) go += grad_opd[off + idx];
-    gopd[off + idx] = go;
-    if (tau) {  // -Re(conj(U) g_U)
-      float gt = -(c * g.x + s * g.y);
-      if (grad_opd) gt += grad_opd[plane + off + idx];
-      gtau[off + idx] = gt;
+#pragma unroll
+    for (int u = 0; u < LB; ++u) {
+      const int idx = i0 + u * kThreads;
+      if (idx >= NP) continue;
+      float s, c;
+      sincosf(phase_k * ov[u], &s, &c);
+      if (tau) {  // U = e^{-tau} (c + i s), as pass 1 forms it
+        const float am = expf(-tv[u]);
+        c = am * c;
+        s = am * s;
+      }
+      const float2 g = buf[idx];
+      // Im(conj(U) g_U) with U = c + i s
+      float go = phase_k * (c * g.y - s * g.x);
+      if (grad_opd) go += grad_opd[off + idx];
+      gopd[off + idx] = go;
+      if (tau) {  // -Re(conj(U) g_U)
+        float gt = -(c * g.x + s * g.y);
+        if (grad_opd) gt += grad_opd[plane + off + idx];
+        gtau[off + idx] = gt;
+      }
     }
   }
 }

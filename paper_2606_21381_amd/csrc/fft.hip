@@ -27,7 +27,7 @@ namespace osog {
 // of row groups and the halves meet in one L2.  per_xcd * 8 >= groups.
 template <int LOGW, int MAXR>
 __global__ void __launch_bounds__(kThreads) k_pass1(FrameDev F, const float2* __restrict__ tw, int per_xcd) {
-  __shared__ __align__(16) char lds[rows_per_fft_block(1 << LOGW) * (1 << LOGW) * sizeof(float2)];
+  __shared__ __align__(16) char lds[fft_lds_f2(rows_per_fft_block(1 << LOGW) * (1 << LOGW)) * sizeof(float2)];
   const int g = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
   if (g * rows_per_fft_block(1 << LOGW) < F.H) pass1_body<LOGW, MAXR>(F, g, tw, lds);
 }
@@ -37,7 +37,7 @@ __global__ void __launch_bounds__(kThreads) k_pass1(FrameDev F, const float2* __
 // i mod 8) takes one contiguous run of columns, and a line is fetched once.
 template <int LOGH, int MAXR>
 __global__ void __launch_bounds__(kThreads) k_pass2(FrameDev F, const float2* __restrict__ tw, int per_xcd) {
-  __shared__ __align__(16) char lds[(1 << LOGH) * sizeof(float2) + kThreads * sizeof(double) + 16];
+  __shared__ __align__(16) char lds[fft_lds_f2(1 << LOGH) * sizeof(float2) + kThreads * sizeof(double) + 16];
   const int b = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
   if (b < F.o.kx_n) pass2_body<LOGH, MAXR>(F, b, tw, lds);
 }

@@ -82,12 +82,54 @@ __device__ __forceinline__ void dft(float2* v) {
   }
 }
 
+// LDS bank spreading of the Stockham stages.  A stage writes its butterfly
+// outputs r NS apart; with NS = 1 or 8 (radix 8) or NS = 1 or 4 (radix 4) a
+// half-wave's 32 float2 stores would fall on a quarter or an eighth of the 64
+// banks.  Such a stage writes point i at i + q (i / 32) instead (q = stage_pad),
+// which gives each half-wave's stores 32 distinct bank pairs, and the next stage
+// reads with the same q (its reads, 32 consecutive points per half-wave, stay
+// spread).  The first stage reads and the last stage writes the plain layout, so
+// callers never see the padding; a buffer holding n points for the stages needs
+// fft_lds_f2(n) float2s.  Rows shorter than 256 points are not padded.
+constexpr int kFftPadMax = 4;
+__host__ __device__ constexpr int fft_lds_f2(int n) { return n + (n >> 5) * kFftPadMax; }
+
+template <int N, int R, int NS>
+__host__ __device__ constexpr int stage_pad() {
+  return N < 256 ? 0 : (R == 8 ? (NS == 1 ? 1 : (NS == 8 ? 4 : 0)) : (R == 4 ? (NS == 1 ? 1 : (NS == 4 ? 4 : 0)) : 0));
+}
+
+template <int Q>
+__device__ __forceinline__ int lds_at(int i) {
+  return Q ? i + (i >> 5) * Q : i;
+}
+
+// Copy n elements load(i) -> store(i, .) for i = threadIdx.x + k kThreads with LB
+// loads in flight per thread before the first is stored, so a workgroup waits on
+// memory once per LB elements instead of once per element.
+template <int LB, class Load, class Store>
+__device__ __forceinline__ void gather_lds(int n, const Load& load, const Store& store) {
+  for (int i0 = threadIdx.x; i0 < n; i0 += LB * kThreads) {
+    float2 v[LB];
+#pragma unroll
+    for (int u = 0; u < LB; ++u) {
+      const int i = i0 + u * kThreads;
+      if (i < n) v[u] = load(i);
+    }
+#pragma unroll
+    for (int u = 0; u < LB; ++u) {
+      const int i = i0 + u * kThreads;
+      if (i < n) store(i, v[u]);
+    }
+  }
+}
+
 // One Stockham autosort stage over ROWS rows of N points held in LDS, then the
 // remaining stages.  NS = product of the radices done so far, REM = log2 of the
 // part still to transform, MAXR = the plan's largest radix (8: radix-8 stages
 // then one radix-4 or -2 stage; 4: radix-4 stages then one radix-2 stage).  Butterfly j of radix R reads x[j + r N/R],
 // twiddles by W^(r (j mod NS) N/(NS R)), and writes to (j/NS) NS R + (j mod NS) + r NS.
-template <int N, int ROWS, int DIR, int NS, int REM, int MAXR = 8>
+template <int N, int ROWS, int DIR, int NS, int REM, int MAXR = 8, int QIN = 0>
 struct Stages {
   static __device__ __forceinline__ void run(float2* buf, const float2* __restrict__ tw) {
 #pragma clang fp contract(off)
@@ -95,6 +137,8 @@ struct Stages {
     constexpr int LR = R == 8 ? 3 : (R == 4 ? 2 : 1);
     constexpr int NB = N / R, TOT = ROWS * NB, BPT = (TOT + kThreads - 1) / kThreads;
     constexpr int TSTRIDE = kTwN / N;
+    constexpr int QOUT = REM == LR ? 0 : stage_pad<N, R, NS>();
+    static_assert(QIN <= kFftPadMax && QOUT <= kFftPadMax, "LDS padding beyond fft_lds_f2");
     float2 v[BPT][R];
     const int t = threadIdx.x;
 #pragma unroll
@@ -102,9 +146,8 @@ struct Stages {
       const int idx = t + q * kThreads;
       if (TOT % kThreads == 0 || idx < TOT) {
         const int row = idx / NB, j = idx % NB;
-        const float2* rb = buf + row * N;
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[q][r] = rb[j + r * NB];
+        for (int r = 0; r < R; ++r) v[q][r] = buf[lds_at<QIN>(row * N + j + r * NB)];
         if constexpr (NS > 1) {
           const int k = j & (NS - 1);
 #pragma unroll
@@ -123,19 +166,18 @@ struct Stages {
       const int idx = t + q * kThreads;
       if (TOT % kThreads == 0 || idx < TOT) {
         const int row = idx / NB, j = idx % NB;
-        float2* rb = buf + row * N;
-        const int d = (j / NS) * NS * R + (j & (NS - 1));
+        const int d = row * N + (j / NS) * NS * R + (j & (NS - 1));
 #pragma unroll
-        for (int r = 0; r < R; ++r) rb[d + r * NS] = v[q][r];
+        for (int r = 0; r < R; ++r) buf[lds_at<QOUT>(d + r * NS)] = v[q][r];
       }
     }
     __syncthreads();
-    Stages<N, ROWS, DIR, NS * R, REM - LR, MAXR>::run(buf, tw);
+    Stages<N, ROWS, DIR, NS * R, REM - LR, MAXR, QOUT>::run(buf, tw);
   }
 };
 
-template <int N, int ROWS, int DIR, int NS, int MAXR>
-struct Stages<N, ROWS, DIR, NS, 0, MAXR> {
+template <int N, int ROWS, int DIR, int NS, int MAXR, int QIN>
+struct Stages<N, ROWS, DIR, NS, 0, MAXR, QIN> {
   static __device__ __forceinline__ void run(float2*, const float2* __restrict__) {}
 };
 

@@ -38,7 +38,7 @@ template <int LOGH>
 __global__ void __launch_bounds__(kThreads) k_inc_pupil(OpticsArgs o, const float* __restrict__ globals,
                                                         float2* __restrict__ out, const float2* __restrict__ tw) {
   constexpr int H = 1 << LOGH;
-  __shared__ float2 buf[H];
+  __shared__ float2 buf[fft_lds_f2(H)];
   __shared__ int chord[2];
   const int t = threadIdx.x, b = blockIdx.x, kx = o.kx_lo + b;
   if (t == 0) band_chord(o, kx, &chord[0], &chord[1]);
@@ -62,15 +62,21 @@ __global__ void __launch_bounds__(kThreads) k_inc_abs2(const float2* __restrict_
                                                        float scale, double* __restrict__ psum,
                                                        const float2* __restrict__ tw) {
   constexpr int W = 1 << LOGW, RPB = rows_per_fft_block(W);
-  __shared__ __align__(16) float2 buf[RPB * W];
+  __shared__ __align__(16) float2 buf[fft_lds_f2(RPB * W)];
   __shared__ double red[kThreads];
   const int t = threadIdx.x, g = blockIdx.x, row0 = g * RPB;
   for (int idx = t; idx < RPB * W; idx += kThreads) buf[idx] = make_float2(0.0f, 0.0f);
   __syncthreads();
-  for (int idx = t; idx < in_n * RPB; idx += kThreads) {
-    const int b = idx / RPB, r = idx - b * RPB;
-    buf[r * W + ((in_lo + b) & (W - 1))] = in[band_at(row0 + r, b, in_n, rb)];
-  }
+  gather_lds<4>(
+      in_n * RPB,
+      [&](int idx) {
+        const int b = idx / RPB, r = idx - b * RPB;
+        return in[band_at(row0 + r, b, in_n, rb)];
+      },
+      [&](int idx, float2 v) {
+        const int b = idx / RPB, r = idx - b * RPB;
+        buf[r * W + ((in_lo + b) & (W - 1))] = v;
+      });
   __syncthreads();
   Stages<W, RPB, 1, 1, LOGW>::run(buf, tw);
   double part = 0.0;
@@ -100,10 +106,11 @@ __global__ void __launch_bounds__(kThreads) k_inc_otf(const float2* __restrict__
                                                       const double* __restrict__ psum, int groups,
                                                       float2* __restrict__ otf, const float2* __restrict__ tw) {
   constexpr int H = 1 << LOGH;
-  __shared__ float2 buf[H];
+  __shared__ float2 buf[fft_lds_f2(H)];
   __shared__ double red[kThreads];
   const int t = threadIdx.x, b = blockIdx.x;
-  for (int i = t; i < H; i += kThreads) buf[i] = in[band_at(i, b, n, rb)];
+  gather_lds<8>(
+      H, [&](int i) { return in[band_at(i, b, n, rb)]; }, [&](int i, float2 v) { buf[i] = v; });
   double s = 0.0;
   for (int k = t; k < groups; k += kThreads) s += psum[k];
   red[t] = s;
@@ -124,12 +131,14 @@ __global__ void __launch_bounds__(kThreads) k_inc_mul(float2* __restrict__ band,
                                                       const float2* __restrict__ otf,
                                                       const float2* __restrict__ tw) {
   constexpr int H = 1 << LOGH;
-  __shared__ float2 buf[H];
+  __shared__ float2 buf[fft_lds_f2(H)];
   const int t = threadIdx.x, b = blockIdx.x;
-  for (int i = t; i < H; i += kThreads) buf[i] = band[band_at(i, b, n, rb)];
+  gather_lds<8>(
+      H, [&](int i) { return band[band_at(i, b, n, rb)]; }, [&](int i, float2 v) { buf[i] = v; });
   __syncthreads();
   Stages<H, 1, -1, 1, LOGH>::run(buf, tw);
-  for (int m = t; m < H; m += kThreads) buf[m] = cmul(buf[m], otf[(size_t)b * H + m]);
+  gather_lds<8>(
+      H, [&](int m) { return otf[(size_t)b * H + m]; }, [&](int m, float2 v) { buf[m] = cmul(buf[m], v); });
   __syncthreads();
   Stages<H, 1, 1, 1, LOGH>::run(buf, tw);
   for (int i = t; i < H; i += kThreads) band[band_at(i, b, n, rb)] = buf[i];

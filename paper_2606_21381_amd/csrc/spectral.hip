@@ -25,9 +25,11 @@ template <int LOGW>
 __global__ void __launch_bounds__(kThreads) k_spec_rows(const float* __restrict__ img, float2* __restrict__ band,
                                                         const float2* __restrict__ tw) {
   constexpr int W = 1 << LOGW, RPB = rows_per_fft_block(W), RB = rows_per_block(W);
-  __shared__ __align__(16) float2 buf[RPB * W];
+  __shared__ __align__(16) float2 buf[fft_lds_f2(RPB * W)];
   const int t = threadIdx.x, row0 = blockIdx.x * RPB;
-  for (int idx = t; idx < RPB * W; idx += kThreads) buf[idx] = make_float2(img[(size_t)row0 * W + idx], 0.0f);
+  gather_lds<8>(
+      RPB * W, [&](int idx) { return make_float2(img[(size_t)row0 * W + idx], 0.0f); },
+      [&](int idx, float2 v) { buf[idx] = v; });
   __syncthreads();
   Stages<W, RPB, -1, 1, LOGW>::run(buf, tw);
   for (int idx = t; idx < RPB * W; idx += kThreads) {
@@ -46,10 +48,11 @@ __global__ void __launch_bounds__(kThreads) k_spec_cols(float2* __restrict__ ban
                                                         double* __restrict__ colsum, const float2* __restrict__ tw) {
 #pragma clang fp contract(off)
   constexpr int H = 1 << LOGH;
-  __shared__ float2 buf[H];
+  __shared__ float2 buf[fft_lds_f2(H)];
   __shared__ double red[kThreads];
   const int t = threadIdx.x, b = blockIdx.x, RB = W >= 1024 ? 8192 / W : 8;
-  for (int i = t; i < H; i += kThreads) buf[i] = band[spec_at(i, b, W, RB)];
+  gather_lds<8>(
+      H, [&](int i) { return band[spec_at(i, b, W, RB)]; }, [&](int i, float2 v) { buf[i] = v; });
   __syncthreads();
   Stages<H, 1, -1, 1, LOGH>::run(buf, tw);
   if (target_out) {
@@ -87,12 +90,18 @@ template <int LOGW>
 __global__ void __launch_bounds__(kThreads) k_spec_grad(const float2* __restrict__ band, float* __restrict__ grad,
                                                         const float2* __restrict__ tw) {
   constexpr int W = 1 << LOGW, RPB = rows_per_fft_block(W), RB = rows_per_block(W);
-  __shared__ __align__(16) float2 buf[RPB * W];
+  __shared__ __align__(16) float2 buf[fft_lds_f2(RPB * W)];
   const int t = threadIdx.x, row0 = blockIdx.x * RPB;
-  for (int idx = t; idx < RPB * W; idx += kThreads) {
-    const int b = idx / RPB, r = idx - b * RPB;
-    buf[r * W + b] = band[spec_at(row0 + r, b, W, RB)];
-  }
+  gather_lds<8>(
+      RPB * W,
+      [&](int idx) {
+        const int b = idx / RPB, r = idx - b * RPB;
+        return band[spec_at(row0 + r, b, W, RB)];
+      },
+      [&](int idx, float2 v) {
+        const int b = idx / RPB, r = idx - b * RPB;
+        buf[r * W + b] = v;
+      });
   __syncthreads();
   Stages<W, RPB, -1, 1, LOGW>::run(buf, tw);
   for (int idx = t; idx < RPB * W; idx += kThreads) grad[(size_t)row0 * W + idx] = buf[idx].x;

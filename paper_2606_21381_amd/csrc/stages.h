@@ -4,8 +4,9 @@
 // rendered alone or inside a batch goes through identical arithmetic.
 //
 // Every body is executed by one 256-thread workgroup (the raster body by one
-// 64-lane wave) and receives a pointer to LDS scratch of at least kStageLds
-// bytes; bodies that synchronise call __syncthreads() uniformly.
+// 64-lane wave) and receives a pointer to the LDS scratch its kernel declares
+// (FFT buffers sized by fft_lds_f2); bodies that synchronise call
+// __syncthreads() uniformly.
 #pragma once
 
 #include "bin_common.h"
@@ -15,9 +16,6 @@
 
 namespace osog {
 
-// LDS one stage body may use: the largest is pass 3 at RB * W = 8192 points
-// plus a 256-entry double reduction array.
-constexpr int kStageLds = 8192 * 8 + kThreads * 8;  // >= pass3_buf_bytes(W) + kThreads * 8 for every W
 
 // Everything a stage needs to know about one frame, in device-readable form.
 struct FrameDev {
@@ -539,19 +537,31 @@ __device__ __forceinline__ void pass1_body(const FrameDev& F, int g, const float
   const int t = threadIdx.x;
   const float* src = F.opd + (size_t)g * RPB * W;
   const float pk = F.phase_k;
+  // every load of the row block is issued before the first is used, so the
+  // workgroup waits on memory once rather than once per point it handles
+  constexpr int PER = RPB * W / kThreads;
+  static_assert(RPB * W % kThreads == 0, "row block not a multiple of the workgroup");
+  float ph[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) ph[u] = src[t + u * kThreads];
   if (F.absorb) {  // U = exp(-tau) exp(i phi): the Beer-Lambert amplitude of Eq. 4
     const float* ta = F.tau + (size_t)g * RPB * W;
-    for (int idx = t; idx < RPB * W; idx += kThreads) {
+    float tv[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) tv[u] = ta[t + u * kThreads];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
       float s, c;
-      sincosf(pk * src[idx], &s, &c);
-      const float am = expf(-ta[idx]);
-      buf[idx] = make_float2(am * c, am * s);
+      sincosf(pk * ph[u], &s, &c);
+      const float am = expf(-tv[u]);
+      buf[t + u * kThreads] = make_float2(am * c, am * s);
     }
   } else {
-    for (int idx = t; idx < RPB * W; idx += kThreads) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
       float s, c;
-      sincosf(pk * src[idx], &s, &c);
-      buf[idx] = make_float2(c, s);
+      sincosf(pk * ph[u], &s, &c);
+      buf[t + u * kThreads] = make_float2(c, s);
     }
   }
   __syncthreads();
@@ -572,15 +582,28 @@ __device__ __forceinline__ void pass2_body(const FrameDev& F, int b, const float
 #pragma clang fp contract(off)
   constexpr int H = 1 << LOGH;
   float2* buf = reinterpret_cast<float2*>(lds);
-  double* red = reinterpret_cast<double*>(lds + H * sizeof(float2));
-  int* chord = reinterpret_cast<int*>(lds + H * sizeof(float2) + kThreads * sizeof(double));
+  double* red = reinterpret_cast<double*>(lds + fft_lds_f2(H) * sizeof(float2));
+  int* chord = reinterpret_cast<int*>(lds + fft_lds_f2(H) * sizeof(float2) + kThreads * sizeof(double));
   const OpticsArgs& o = F.o;
   const int t = threadIdx.x, kx = o.kx_lo + b;
   const int RB = o.rb;
   float2* band = F.band;
   const float2* src = F.band_in;
   const int bi = kx - F.in_kx_lo, in_n = F.in_kx_n;
-  for (int i = t; i < H; i += kThreads) buf[i] = src[((size_t)(i / RB) * in_n + bi) * RB + (i % RB)];
+  {  // the column's loads all in flight before the first is used
+    constexpr int PER = (H + kThreads - 1) / kThreads;
+    float2 v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int i = t + u * kThreads;
+      if (H % kThreads == 0 || i < H) v[u] = src[((size_t)(i / RB) * in_n + bi) * RB + (i % RB)];
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int i = t + u * kThreads;
+      if (H % kThreads == 0 || i < H) buf[i] = v[u];
+    }
+  }
   if (t == 0) band_chord(o, kx, &chord[0], &chord[1]);
   __syncthreads();
   Stages<H, 1, -1, 1, LOGH, MAXR>::run(buf, tw);
@@ -624,7 +647,8 @@ constexpr int kNoiseChunk = 4;                                   // pairs per la
 constexpr int kNoiseQueueBytes = kThreads * 2 * kNoiseChunk * 16;  // uint4 entries, 32 KB
 
 __host__ __device__ constexpr int pass3_buf_bytes(int W) {
-  return rows_per_fft_block(W) * W * 8 > kNoiseQueueBytes ? rows_per_fft_block(W) * W * 8 : kNoiseQueueBytes;
+  return fft_lds_f2(rows_per_fft_block(W) * W) * 8 > kNoiseQueueBytes ? fft_lds_f2(rows_per_fft_block(W) * W) * 8
+                                                                       : kNoiseQueueBytes;
 }
 
 // Inclusive prefix sum over the 64 lanes of a wave.
@@ -733,9 +757,20 @@ __device__ __forceinline__ void pass3_body(const FrameDev& F, int g, const float
   __syncthreads();
   const int row0 = g * RPB, blk = row0 / RB, r0 = row0 % RB;
   const float2* src = F.band + (size_t)blk * o.kx_n * RB + r0;
-  for (int idx = t; idx < o.kx_n * RPB; idx += kThreads) {
-    const int b = idx / RPB, r = idx - b * RPB;
-    buf[r * W + ((o.kx_lo + b) & (W - 1))] = src[(size_t)b * RB + r];
+  constexpr int LB = 4;  // band loads in flight per thread
+  const int nb = o.kx_n * RPB;
+  for (int i0 = t; i0 < nb; i0 += LB * kThreads) {
+    float2 v[LB];
+#pragma unroll
+    for (int u = 0; u < LB; ++u) {
+      const int idx = i0 + u * kThreads, b = idx / RPB, r = idx - b * RPB;
+      if (idx < nb) v[u] = src[(size_t)b * RB + r];
+    }
+#pragma unroll
+    for (int u = 0; u < LB; ++u) {
+      const int idx = i0 + u * kThreads, b = idx / RPB, r = idx - b * RPB;
+      if (idx < nb) buf[r * W + ((o.kx_lo + b) & (W - 1))] = v[u];
+    }
   }
   const bool noise = o.photons > 0.0f;
   if (noise) {
