@@ -124,6 +124,33 @@ __device__ __forceinline__ void gather_lds(int n, const Load& load, const Store&
   }
 }
 
+// Twiddles of the Stockham stage that follows NS transformed points with REM
+// bits left (none for the first stage).  Each stage loads the next stage's
+// twiddles right after its butterflies, so they arrive while the workgroup
+// passes the stage's barriers and LDS writes.
+template <int N, int ROWS, int NS, int REM, int MAXR>
+struct StageTw {
+  static constexpr int R = (REM >= 3 && MAXR == 8) ? 8 : (REM >= 2 ? 4 : 2);
+  static constexpr int NB = N / R, TOT = ROWS * NB, BPT = (TOT + kThreads - 1) / kThreads;
+  static constexpr bool kHas = NS > 1 && REM > 0;
+  float2 w[kHas ? BPT : 1][kHas ? R : 1];
+  __device__ __forceinline__ void load(const float2* __restrict__ tw) {
+    if constexpr (kHas) {
+      constexpr int TSTRIDE = kTwN / N;  // index r k N/(NS R) TSTRIDE < N TSTRIDE = kTwN
+      const int t = threadIdx.x;
+#pragma unroll
+      for (int q = 0; q < BPT; ++q) {
+        const int idx = t + q * kThreads;
+        if (TOT % kThreads == 0 || idx < TOT) {
+          const int k = (idx % NB) & (NS - 1);
+#pragma unroll
+          for (int r = 1; r < R; ++r) w[q][r] = tw[(r * k * (N / (NS * R))) * TSTRIDE];
+        }
+      }
+    }
+  }
+};
+
 // One Stockham autosort stage over ROWS rows of N points held in LDS, then the
 // remaining stages.  NS = product of the radices done so far, REM = log2 of the
 // part still to transform, MAXR = the plan's largest radix (8: radix-8 stages
@@ -131,12 +158,16 @@ __device__ __forceinline__ void gather_lds(int n, const Load& load, const Store&
 // twiddles by W^(r (j mod NS) N/(NS R)), and writes to (j/NS) NS R + (j mod NS) + r NS.
 template <int N, int ROWS, int DIR, int NS, int REM, int MAXR = 8, int QIN = 0>
 struct Stages {
+  using Tw = StageTw<N, ROWS, NS, REM, MAXR>;
   static __device__ __forceinline__ void run(float2* buf, const float2* __restrict__ tw) {
+    Tw none;
+    run(buf, tw, none);
+  }
+  static __device__ __forceinline__ void run(float2* buf, const float2* __restrict__ tw, const Tw& cw) {
 #pragma clang fp contract(off)
-    constexpr int R = (REM >= 3 && MAXR == 8) ? 8 : (REM >= 2 ? 4 : 2);
+    constexpr int R = Tw::R;
     constexpr int LR = R == 8 ? 3 : (R == 4 ? 2 : 1);
     constexpr int NB = N / R, TOT = ROWS * NB, BPT = (TOT + kThreads - 1) / kThreads;
-    constexpr int TSTRIDE = kTwN / N;
     constexpr int QOUT = REM == LR ? 0 : stage_pad<N, R, NS>();
     static_assert(QIN <= kFftPadMax && QOUT <= kFftPadMax, "LDS padding beyond fft_lds_f2");
     float2 v[BPT][R];
@@ -148,11 +179,10 @@ struct Stages {
         const int row = idx / NB, j = idx % NB;
 #pragma unroll
         for (int r = 0; r < R; ++r) v[q][r] = buf[lds_at<QIN>(row * N + j + r * NB)];
-        if constexpr (NS > 1) {
-          const int k = j & (NS - 1);
+        if constexpr (Tw::kHas) {
 #pragma unroll
           for (int r = 1; r < R; ++r) {
-            float2 w = tw[(r * k * (N / (NS * R))) * TSTRIDE];
+            float2 w = cw.w[q][r];
             if (DIR < 0) w.y = -w.y;
             v[q][r] = cmul(v[q][r], w);
           }
@@ -160,6 +190,9 @@ struct Stages {
         dft<R, DIR>(v[q]);
       }
     }
+    using Next = Stages<N, ROWS, DIR, NS * R, REM - LR, MAXR, QOUT>;
+    typename Next::Tw nw;
+    nw.load(tw);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < BPT; ++q) {
@@ -172,13 +205,14 @@ struct Stages {
       }
     }
     __syncthreads();
-    Stages<N, ROWS, DIR, NS * R, REM - LR, MAXR, QOUT>::run(buf, tw);
+    Next::run(buf, tw, nw);
   }
 };
 
 template <int N, int ROWS, int DIR, int NS, int MAXR, int QIN>
 struct Stages<N, ROWS, DIR, NS, 0, MAXR, QIN> {
-  static __device__ __forceinline__ void run(float2*, const float2* __restrict__) {}
+  using Tw = StageTw<N, ROWS, NS, 0, MAXR>;
+  static __device__ __forceinline__ void run(float2*, const float2* __restrict__, const Tw&) {}
 };
 
 // ---- transfer function ------------------------------------------------------
