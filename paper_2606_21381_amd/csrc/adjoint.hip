@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(kThreads) k_adj_pass2(const float2* __restrict
   __shared__ float2 ua[fft_lds_f2(H)];
   __shared__ float2 gb[fft_lds_f2(H)];
   __shared__ int chord[2];
-  __shared__ double red[3][kThreads];
+  __shared__ double red[kThreads / 64];
   const int t = threadIdx.x, b = blockIdx.x, kx = o.kx_lo + b, RB = o.rb;
   gather_lds<4>(
       H, [&](int i) { return band[((size_t)(i / RB) * o.kx_n + b) * RB + (i % RB)]; },
@@ -140,19 +140,13 @@ __global__ void __launch_bounds__(kThreads) k_adj_pass2(const float2* __restrict
     }
     gb[m] = out;
   }
-  red[0][t] = p0;
-  red[1][t] = p1;
-  red[2][t] = p2;
-  __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (t < s) {
-      red[0][t] += red[0][t + s];
-      red[1][t] += red[1][t + s];
-      red[2][t] += red[2][t + s];
-    }
-    __syncthreads();
+  // fixed-order column sums; their barriers also order gb for the stages
+  const double s0 = block_sum(p0, red), s1 = block_sum(p1, red), s2 = block_sum(p2, red);
+  if (t == 0) {
+    colgrad[b] = s0;
+    colgrad[(size_t)o.kx_n + b] = s1;
+    colgrad[2 * (size_t)o.kx_n + b] = s2;
   }
-  if (t < 3) colgrad[(size_t)t * o.kx_n + b] = red[t][0];
   Stages<H, 1, 1, 1, LOGH>::run(gb, tw);  // g_A
   for (int i = t; i < H; i += kThreads) band2[((size_t)(i / RB) * o.kx_n + b) * RB + (i % RB)] = gb[i];
 }

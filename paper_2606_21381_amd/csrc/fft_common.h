@@ -104,6 +104,23 @@ __device__ __forceinline__ int lds_at(int i) {
   return Q ? i + (i >> 5) * Q : i;
 }
 
+// Workgroup sum of one double per thread in a fixed order: an xor butterfly over
+// each wave's lanes (lane 0's result is kept), then the waves' sums in wave order.
+// Returns the total to every thread; `red` holds kThreads / 64 doubles of LDS and
+// is free again on return.  Contains barriers: call uniformly.
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  const int t = threadIdx.x;
+  if ((t & 63) == 0) red[t >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
 // Copy n elements load(i) -> store(i, .) for i = threadIdx.x + k kThreads with LB
 // loads in flight per thread before the first is stored, so a workgroup waits on
 // memory once per LB elements instead of once per element.

@@ -86,13 +86,8 @@ __global__ void __launch_bounds__(kThreads) k_inc_abs2(const float2* __restrict_
     buf[idx] = make_float2(v, 0.0f);
     part += (double)v;
   }
-  red[t] = part;
-  __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] += red[t + s];
-    __syncthreads();
-  }
-  if (t == 0) psum[g] = red[0];
+  const double ps = block_sum(part, red);  // its barriers also order buf for the stages
+  if (t == 0) psum[g] = ps;
   Stages<W, RPB, -1, 1, LOGW>::run(buf, tw);
   for (int idx = t; idx < out_n * RPB; idx += kThreads) {
     const int b = idx / RPB, r = idx - b * RPB;
@@ -113,13 +108,7 @@ __global__ void __launch_bounds__(kThreads) k_inc_otf(const float2* __restrict__
       H, [&](int i) { return in[band_at(i, b, n, rb)]; }, [&](int i, float2 v) { buf[i] = v; });
   double s = 0.0;
   for (int k = t; k < groups; k += kThreads) s += psum[k];
-  red[t] = s;
-  __syncthreads();
-  for (int st = kThreads / 2; st > 0; st >>= 1) {
-    if (t < st) red[t] += red[t + st];
-    __syncthreads();
-  }
-  const double total = red[0];
+  const double total = block_sum(s, red);  // its barriers also order buf for the stages
   const float inv = total > 0.0 ? (float)(1.0 / total) : 0.0f;  // an empty pupil passes nothing
   Stages<H, 1, -1, 1, LOGH>::run(buf, tw);
   for (int m = t; m < H; m += kThreads) otf[(size_t)b * H + m] = cscale(buf[m], inv);

@@ -74,13 +74,8 @@ __global__ void __launch_bounds__(kThreads) k_spec_cols(float2* __restrict__ ban
       buf[m] = make_float2(s * f.x, -s * f.y);  // s conj(F)
     }
   }
-  red[t] = part;
-  __syncthreads();
-  for (int st = kThreads / 2; st > 0; st >>= 1) {
-    if (t < st) red[t] += red[t + st];
-    __syncthreads();
-  }
-  if (t == 0) colsum[b] = red[0];
+  const double cs = block_sum(part, red);  // its barriers also order buf for the stages
+  if (t == 0) colsum[b] = cs;
   if (!with_grad) return;
   Stages<H, 1, -1, 1, LOGH>::run(buf, tw);
   for (int i = t; i < H; i += kThreads) band[spec_at(i, b, W, RB)] = buf[i];

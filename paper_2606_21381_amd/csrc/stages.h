@@ -619,13 +619,8 @@ __device__ __forceinline__ void pass2_body(const FrameDev& F, int b, const float
     }
     buf[m] = g;
   }
-  red[t] = part;
-  __syncthreads();
-  for (int s = kThreads / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] += red[t + s];
-    __syncthreads();
-  }
-  if (t == 0) F.colsum[b] = red[0];
+  const double colsum = block_sum(part, red);  // its barriers also order buf for the stages
+  if (t == 0) F.colsum[b] = colsum;
   Stages<H, 1, 1, 1, LOGH, MAXR>::run(buf, tw);
   for (int i = t; i < H; i += kThreads) band[((size_t)(i / RB) * o.kx_n + b) * RB + (i % RB)] = buf[i];
   __syncthreads();
@@ -773,20 +768,13 @@ __device__ __forceinline__ void pass3_body(const FrameDev& F, int g, const float
     }
   }
   const bool noise = o.photons > 0.0f;
-  if (noise) {
-    double s = 0.0;
-    for (int b = t; b < o.colsum_n; b += kThreads) s += F.colsum[b];
-    red[t] = s;
-  }
   __syncthreads();
   float scale = 0.0f;
-  if (noise) {
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-      if (t < s) red[t] += red[t + s];
-      __syncthreads();
-    }
+  if (noise) {  // o.photons is uniform over the workgroup, so the barriers inside are too
+    double s = 0.0;
+    for (int b = t; b < o.colsum_n; b += kThreads) s += F.colsum[b];
     const double hw = (double)o.H * (double)W;
-    const double mean = red[0] / (hw * hw);
+    const double mean = block_sum(s, red) / (hw * hw);
     scale = mean > 0.0 ? (float)((double)o.photons / mean) : 0.0f;
   }
   Stages<W, RPB, 1, 1, LOGW, MAXR>::run(buf, tw);
