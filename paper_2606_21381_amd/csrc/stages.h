@@ -646,6 +646,14 @@ __host__ __device__ constexpr int pass3_buf_bytes(int W) {
                                                                        : kNoiseQueueBytes;
 }
 
+// Orders LDS accesses among the lanes of one wave: enough for a wave-private
+// region, where a workgroup barrier would also wait for the other waves.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Inclusive prefix sum over the 64 lanes of a wave.
 __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
 #pragma unroll
@@ -708,13 +716,13 @@ __device__ __forceinline__ void noise_rows(const FrameDev& F, float scale, int64
 #pragma unroll
     for (int e = 0; e < 2 * CH; ++e)
       if (pend & (1u << e)) queue[pos++] = ent[e];
-    __syncthreads();
+    wave_sync();
     for (int q = lane; q < total; q += 64) {
       const uint4 en = queue[q];
       const int k = poisson_large(__uint_as_float(en.y), en.z, en.w, en.x, o.frame, o.seed_lo, o.seed_hi);
       queue[q].y = (uint32_t)k;
     }
-    __syncthreads();
+    wave_sync();
     pos = incl - cnt;
 #pragma unroll
     for (int e = 0; e < 2 * CH; ++e)
@@ -735,7 +743,7 @@ __device__ __forceinline__ void noise_rows(const FrameDev& F, float scale, int64
       }
       out[ml] = make_float2(a * inv_scale, b * inv_scale);
     }
-    __syncthreads();  // the queue is reused by the next round
+    wave_sync();  // the wave's queue is reused by the next round
   }
 }
 
