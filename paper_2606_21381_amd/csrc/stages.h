@@ -805,15 +805,12 @@ __device__ __forceinline__ void pass3_body(const FrameDev& F, int g, const float
 #pragma unroll
   for (int k = 0; k < PP; ++k) {
     const int ml = t + kThreads * k;
+    // the pair's two fields in one 16-byte read (consecutive lanes, consecutive banks)
+    const float4 e2 = ml < NP ? reinterpret_cast<const float4*>(buf)[ml] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll
     for (int x = 0; x < 2; ++x) {
-      float v = 0.0f;
-      if (ml < NP) {
-        const float2 e = buf[2 * ml + x];
-        const float er = e.x * inv, ei = e.y * inv;
-        v = real_part ? fmaxf(er, 0.0f) : er * er + ei * ei;  // a Poisson mean is >= 0
-      }
-      Ipix[2 * k + x] = v;
+      const float er = (x ? e2.z : e2.x) * inv, ei = (x ? e2.w : e2.y) * inv;
+      Ipix[2 * k + x] = ml < NP ? (real_part ? fmaxf(er, 0.0f) : er * er + ei * ei) : 0.0f;  // a Poisson mean is >= 0
     }
   }
   __syncthreads();
