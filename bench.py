@@ -69,29 +69,24 @@ def raster_candidates(soa, H, W):
     return float(px[prism].sum()), float(px[~prism].sum())
 
 
-def source_hash():
-    """sha1 over the library's kernel sources (names and bytes, sorted by name)."""
-    import glob
+def kernel_hash():
+    """sha1 of the built library, whose device code is what a counter summary measured
+    (comment-only source edits leave it unchanged)."""
     import hashlib
-    h = hashlib.sha1()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2606_21381_amd", "csrc", "*"))):
-        if f.endswith((".hip", ".h", ".cpp")):
-            h.update(os.path.basename(f).encode())
-            with open(f, "rb") as fh:
-                h.update(fh.read())
-    return h.hexdigest()
+    with open(os.path.join(ROOT, "paper_2606_21381_amd", "lib", "libosog.so"), "rb") as fh:
+        return hashlib.sha1(fh.read()).hexdigest()
 
 
 def measured_counters(kernel):
     """HBM bytes (scaled FETCH_SIZE + WRITE_SIZE) and VALU busy share of `kernel`
     from the committed rocprofv3 counter summary, or None when that summary was
-    taken on other kernel sources than the ones built now."""
+    taken on another build of the library than the one loaded now."""
     try:
         lines = open(COUNTERS).read().splitlines()
     except OSError:
         return None
-    stamp = [l for l in lines if l.startswith("# kernel sources: sha1 ")]
-    if not stamp or stamp[0].split()[4] != source_hash():
+    stamp = [l for l in lines if l.startswith("# kernel library: sha1 ")]
+    if not stamp or stamp[0].split()[4] != kernel_hash():
         return None
     head = [l.split() for l in lines if l.startswith("kernel ")]
     if not head:

@@ -7,11 +7,13 @@
 
 namespace osog {
 
-// Rows of the blocked band layout (and rows per pass-1/pass-3 workgroup): keeps
-// one workgroup's LDS at <= 64 KB for W >= 1024.
+// Rows of the blocked band layout (and rows per adjoint row-pass workgroup): keeps
+// one such workgroup's transform at 8192 points (72 KB of LDS with the stage
+// padding) for W >= 1024.
 __host__ __device__ constexpr int rows_per_block(int W) { return W >= 1024 ? 8192 / W : 8; }
 // Rows one pass-1 / pass-3 workgroup transforms: half a band row block from
-// W = 1024 up (32 KB of LDS, so four workgroups share a CU), else a full one.
+// W = 1024 up (4096 points, 36 KB of LDS with the stage padding, so four
+// workgroups share a CU), else a full one.
 __host__ __device__ constexpr int rows_per_fft_block(int W) { return W >= 1024 ? 4096 / W : 8; }
 
 // Kernel-argument copy of the optics a pass needs.
