@@ -66,6 +66,10 @@ class SolverConfig:
     curriculum: Optional[tuple] = None
     loss: str = "mse"          # "mse" (pixel-aligned target) or "spectral" (Eq. 8)
     spectral_eps: float = 1e-4 # eps of the spectral loss, relative to the target's DC term
+    # replay each step as one captured HIP graph (one per curriculum stage) when the
+    # target is on the GPU; the eager loop issues ~50 launches per step and is bound by
+    # the host.  The steps compute the same values either way.
+    graph: bool = True
 
 
 @dataclass
@@ -90,6 +94,7 @@ class SolveResult:
     error_part: Optional[np.ndarray] = None   # e_part per step, len = steps + 1
     steps_to_glob_target: Optional[int] = None
     time_to_glob_target_s: Optional[float] = None
+    graphed: bool = False                     # steps replayed from captured graphs
 
 
 class Params(torch.nn.Module):
@@ -119,10 +124,18 @@ class Params(torch.nn.Module):
         return torch.cat([self.dn, self.dz, self.shear, self.bias])
 
 
-def parameter_errors(p: Params, truth: Truth):
-    """(e_glob, e_part) on the device (see the module docstring)."""
+def error_floor(device) -> torch.Tensor:
+    """Denominator floor of e_glob per global (dn, dz, shear, bias)."""
+    return torch.tensor([0.0, 0.5, 0.0, 0.0], device=device, dtype=torch.float32)
+
+
+def parameter_errors(p: Params, truth: Truth, floor: Optional[torch.Tensor] = None):
+    """(e_glob, e_part) on the device (see the module docstring).  ``floor``: a
+    precomputed error_floor (needed inside a graph capture, which allows no
+    host-to-device copy)."""
     g = p.glob()
-    floor = torch.tensor([0.0, 0.5, 0.0, 0.0], device=g.device, dtype=g.dtype)
+    if floor is None:
+        floor = error_floor(g.device)
     e_glob = ((g - truth.globals4).abs() / torch.maximum(truth.globals4.abs(), floor)).max()
     da = torch.remainder(p.angle - truth.angle + math.pi / 4, math.pi / 2) - math.pi / 4
     e_part = torch.stack([((p.x - truth.x).abs() / 3.0).max(), ((p.y - truth.y).abs() / 3.0).max(),
@@ -168,6 +181,28 @@ def _lr_groups(p: Params, cfg: SolverConfig):
     ]
 
 
+def _graph_memsets(g) -> int:
+    """Memset nodes in a captured graph.  A step graph must hold kernels and copies
+    only (a memset node is replayed as recorded, and such nodes have left wrong
+    values on replays after the first), so one that holds a memset is not used."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    graph = ctypes.c_void_p(g.raw_cuda_graph())
+    n = ctypes.c_size_t(0)
+    if hip.hipGraphGetNodes(graph, None, ctypes.byref(n)) != 0:
+        raise RuntimeError("hipGraphGetNodes failed")
+    nodes = (ctypes.c_void_p * max(n.value, 1))()
+    if hip.hipGraphGetNodes(graph, nodes, ctypes.byref(n)) != 0:
+        raise RuntimeError("hipGraphGetNodes failed")
+    kinds = ctypes.c_int(-1)
+    memsets = 0
+    for i in range(n.value):
+        if hip.hipGraphNodeGetType(ctypes.c_void_p(nodes[i]), ctypes.byref(kinds)) != 0:
+            raise RuntimeError("hipGraphNodeGetType failed")
+        memsets += kinds.value == 2  # hipGraphNodeTypeMemset
+    return memsets
+
+
 def solve(target: torch.Tensor, start: Params, truth: Optional[Truth], H: int, W: int, optics,
           cfg: SolverConfig = SolverConfig(),
           render_fn: Optional[Callable] = None) -> SolveResult:
@@ -176,7 +211,12 @@ def solve(target: torch.Tensor, start: Params, truth: Optional[Truth], H: int, W
 
     ``start`` is modified in place.  Errors and losses stay on the GPU during
     the loop (no host synchronisation per step); per-step GPU times come from
-    events recorded on the current stream.
+    events recorded on the current stream.  On the GPU (``cfg.graph``) every
+    step is one replay of a captured graph of the whole step (forward, loss,
+    adjoint, Adam, clamp, errors), captured once per curriculum stage after
+    three eager warm-up steps whose effect on the parameters and on Adam's state
+    is undone; the rates of the cosine decay live in a device tensor that each
+    step rewrites.  If a captured graph holds a memset node the solve runs eager.
     """
     if render_fn is None:
         from .render import render_diff
@@ -192,16 +232,90 @@ def solve(target: torch.Tensor, start: Params, truth: Optional[Truth], H: int, W
         def loss_fn(I):
             return spectral_loss_diff(I, tl, eps)
     elif cfg.loss == "mse":
-        def loss_fn(I):
-            return torch.mean((I - target) ** 2)
+        inv_n = 1.0 / target.numel()
+
+        def loss_fn(I):  # row sums, then their sum: no grid-wide reduction
+            return torch.sum(torch.sum((I - target) ** 2, dim=-1)) * inv_n
     else:
         raise ValueError("loss must be 'mse' or 'spectral'")
-    opt = torch.optim.Adam(_lr_groups(start, cfg), betas=cfg.betas)
-    base = [g["lr"] for g in opt.param_groups]
     dev = target.device
+    on_gpu = target.is_cuda
+    groups = _lr_groups(start, cfg)
+    base = [g["lr"] for g in groups]
+    if on_gpu:  # rates as views of one device tensor, rewritten in place by the decay
+        base_t = torch.tensor(base, dtype=torch.float32, device=dev)
+        lr_all = base_t.clone()
+        for k, g in enumerate(groups):
+            g["lr"] = lr_all[k]
+        opt = torch.optim.Adam(groups, betas=cfg.betas, capturable=True, foreach=True)
+    else:
+        opt = torch.optim.Adam(groups, betas=cfg.betas)
     losses = torch.zeros(cfg.steps, device=dev)
     errors = torch.zeros((cfg.steps + 1, 2), device=dev)
-    timing = target.is_cuda
+    static_loss = torch.zeros((), device=dev)
+    static_err = torch.zeros(2, device=dev)
+    floor = error_floor(dev)
+    k0 = int(cfg.decay_after * cfg.steps)
+
+    def rate_mult(k):  # cosine decay of every group's rate over the last part of the run
+        if k < k0:
+            return 1.0
+        f = (k - k0) / max(1, cfg.steps - k0)
+        return cfg.decay_to + (1 - cfg.decay_to) * 0.5 * (1 + math.cos(math.pi * f))
+
+    def set_rates(k):
+        m = rate_mult(k)
+        if on_gpu:
+            torch.mul(base_t, m, out=lr_all)
+        else:
+            for g, b in zip(opt.param_groups, base):
+                g["lr"] = b * m
+
+    def body(moving):
+        opt.zero_grad(set_to_none=True)
+        I = render_fn(start.soa(), start.globals4())
+        loss = loss_fn(I)
+        loss.backward()
+        for grp in GROUPS:  # frozen groups keep their values (and Adam state)
+            if grp not in moving:
+                for q in _params_of(start, grp):
+                    q.grad = None
+        opt.step()
+        with torch.no_grad():
+            start.width.clamp_(min=cfg.width_floor)
+            static_loss.copy_(loss.detach())
+            if truth is not None:
+                static_err.copy_(torch.stack(parameter_errors(start, truth, floor)))
+
+    graphs = None
+    stages = sorted({stage_groups(cfg, k) for k in range(cfg.steps)}, key=lambda f: sorted(f))
+    if on_gpu and cfg.graph and cfg.steps > 0:
+        saved = [q.detach().clone() for q in start.parameters()]
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):  # warm-up: creates Adam's state and the allocator's blocks
+            for _ in range(3):
+                body(frozenset(GROUPS))
+        torch.cuda.current_stream(dev).wait_stream(side)
+        graphs, pool = {}, None
+        for moving in stages:
+            g = torch.cuda.CUDAGraph(keep_graph=True)
+            with torch.cuda.graph(g, pool=pool):
+                body(moving)
+            pool = g.pool()
+            g.instantiate()
+            if _graph_memsets(g):
+                graphs = None
+                break
+            graphs[moving] = g
+        with torch.no_grad():  # undo the warm-up and capture steps
+            for q, v in zip(start.parameters(), saved):
+                q.copy_(v)
+            for st in opt.state.values():
+                for v in st.values():
+                    if torch.is_tensor(v):
+                        v.zero_()
+    timing = on_gpu
     events = [torch.cuda.Event(enable_timing=True) for _ in range(cfg.steps + 1)] if timing else None
     t_host = []
     with torch.no_grad():
@@ -210,28 +324,16 @@ def solve(target: torch.Tensor, start: Params, truth: Optional[Truth], H: int, W
     if timing:
         events[0].record()
     t0 = time.perf_counter()
-    k0 = int(cfg.decay_after * cfg.steps)
     for k in range(cfg.steps):
-        if k >= k0:  # cosine decay of every group's rate over the last part of the run
-            f = (k - k0) / max(1, cfg.steps - k0)
-            mult = cfg.decay_to + (1 - cfg.decay_to) * 0.5 * (1 + math.cos(math.pi * f))
-            for g, b in zip(opt.param_groups, base):
-                g["lr"] = b * mult
-        opt.zero_grad(set_to_none=True)
-        I = render_fn(start.soa(), start.globals4())
-        loss = loss_fn(I)
-        loss.backward()
-        moving = stage_groups(cfg, k)
-        for grp in GROUPS:  # frozen groups keep their values (and Adam state)
-            if grp not in moving:
-                for q in _params_of(start, grp):
-                    q.grad = None
-        opt.step()
-        with torch.no_grad():
-            start.width.clamp_(min=cfg.width_floor)
-            losses[k] = loss.detach()
-            if truth is not None:
-                errors[k + 1] = torch.stack(parameter_errors(start, truth))
+        if k >= k0 or k == 0:
+            set_rates(k)
+        if graphs is not None:
+            graphs[stage_groups(cfg, k)].replay()
+        else:
+            body(stage_groups(cfg, k))
+        losses[k].copy_(static_loss)
+        if truth is not None:
+            errors[k + 1].copy_(static_err)
         if timing:
             events[k + 1].record()
         else:
@@ -249,7 +351,7 @@ def solve(target: torch.Tensor, start: Params, truth: Optional[Truth], H: int, W
                        int(hit[0]) + 1 if hit.size else None, float(times[hit[0]]) if hit.size else None,
                        {k: float(v) for k, v in zip(GLOBAL_NAMES, start.glob().detach().cpu().numpy())},
                        eg[:, 0], eg[:, 1], int(hitg[0]) + 1 if hitg.size else None,
-                       float(times[hitg[0]]) if hitg.size else None)
+                       float(times[hitg[0]]) if hitg.size else None, graphs is not None)
 
 
 def problem_tensors(prob, device):
