@@ -141,6 +141,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-extras", action="store_true", help="skip the backward, batch and inverse-solve legs")
+    ap.add_argument("--legs", default="fft_vs_rocfft,multimodal,variants,backward,batch,inverse",
+                    help="comma-separated extra legs to run (default: all)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed run, one plain device-to-device copy of this many MiB "
                          "(reference dispatch for hardware byte counters)")
@@ -246,12 +248,19 @@ def main():
         "paper_context": "paper: 40,000 particles in under 50 ms on one NVIDIA A100 (1024^2 canvas)",
     }
     if not args.no_extras:
-        res["fft_vs_rocfft"] = bench_fft_vs_rocfft(render, lib, ctx, soa, fr, g, dev)
-        res["multimodal"] = bench_multimodal(render, soa, fr, dev)
-        res["variants"] = bench_variants(render, fr, g, dev)
-        res["backward"] = bench_backward(render, soa, g, fr, dev)
-        res["batch"] = bench_batch(render, dev)
-        res["inverse"] = bench_inverse(dev, learned=args.learned)
+        legs = set(args.legs.split(","))
+        if "fft_vs_rocfft" in legs:
+            res["fft_vs_rocfft"] = bench_fft_vs_rocfft(render, lib, ctx, soa, fr, g, dev)
+        if "multimodal" in legs:
+            res["multimodal"] = bench_multimodal(render, soa, fr, dev)
+        if "variants" in legs:
+            res["variants"] = bench_variants(render, fr, g, dev)
+        if "backward" in legs:
+            res["backward"] = bench_backward(render, soa, g, fr, dev)
+        if "batch" in legs:
+            res["batch"] = bench_batch(render, dev)
+        if "inverse" in legs:
+            res["inverse"] = bench_inverse(dev, learned=args.learned)
     if args.calib_copy_mib > 0:
         nb = args.calib_copy_mib << 20
         src = torch.ones(nb, dtype=torch.uint8, device=dev)
