@@ -141,7 +141,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=50)
     ap.add_argument("--no-extras", action="store_true", help="skip the backward, batch and inverse-solve legs")
-    ap.add_argument("--legs", default="fft_vs_rocfft,multimodal,variants,backward,batch,inverse",
+    ap.add_argument("--legs", default="fft_vs_rocfft,multimodal,variants,backward,batch,stream,inverse",
                     help="comma-separated extra legs to run (default: all)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed run, one plain device-to-device copy of this many MiB "
@@ -259,6 +259,8 @@ def main():
             res["backward"] = bench_backward(render, soa, g, fr, dev)
         if "batch" in legs:
             res["batch"] = bench_batch(render, dev)
+        if "stream" in legs:
+            res["stream"] = bench_stream(render, fr, dev)
         if "inverse" in legs:
             res["inverse"] = bench_inverse(dev, learned=args.learned)
     if args.calib_copy_mib > 0:
@@ -460,6 +462,30 @@ def bench_batch(render, dev, reps=10):
             "latency_p50_ms": round(float(np.percentile(lat, 50)), 4),
             "latency_p99_ms": round(float(np.percentile(lat, 99)), 4),
             "error_flag": b.error_flag(), "autotune": choices}
+
+
+def bench_stream(render, fr, dev, frames=8, reps=10):
+    """The headline frame rendered as a stream: `frames` copies of it (each with its own
+    noise seed) per batch graph launch, so one frame's binning and raster overlap another's
+    FFT passes on the concurrent branches.  Reported beside the single-render rate, which
+    stays the headline value."""
+    import torch
+    from dataclasses import replace
+    soa = torch.from_numpy(fr.soa).to(dev)
+    g = torch.from_numpy(fr.globals4).to(dev)
+    items = [(soa, fr.H, fr.W, replace(fr.optics, seed=fr.optics.seed + k), g) for k in range(frames)]
+    b = render.Batch(items)
+    b.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.run()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"workload": "dic2048_n40000 x %d per batch launch" % frames, "ms_per_batch": round(ms, 4),
+            "frames_per_s": round(frames * 1000.0 / ms, 1), "error_flag": b.error_flag()}
 
 
 def bench_inverse(dev, learned=False):
