@@ -102,6 +102,31 @@ def measured_counters(kernel):
     return None
 
 
+def frame_valu_floor_us():
+    """Time the headline frame's kernels need at the chip's full VALU issue rate (their
+    wave instructions x 4 cycles over 1024 SIMDs at 2.4 GHz), from the committed counter
+    summary; None when that summary belongs to another build of the library."""
+    frame = ("k_bin", "k_bin_clear", "k_raster<false, false>", "k_pass1<11, 8>", "k_pass2<11, 8>",
+             "k_pass3<11, 8>")
+    try:
+        lines = open(COUNTERS).read().splitlines()
+    except OSError:
+        return None
+    stamp = [l for l in lines if l.startswith("# kernel library: sha1 ")]
+    head = [l.split() for l in lines if l.startswith("kernel ")]
+    if not stamp or stamp[0].split()[4] != kernel_hash() or not head:
+        return None
+    cols = head[0][1:]
+    winst = {}
+    for l in lines:
+        f = l.split()
+        if f and not l.startswith("#") and not l.startswith("kernel ") and len(f) > len(cols):
+            winst[" ".join(f[:-len(cols)])] = dict(zip(cols, map(float, f[-len(cols):])))["valu_winst"]
+    if not all(k in winst for k in frame):
+        return None
+    return sum(winst[k] for k in frame) * 4.0 / (1024 * 2.4e3)
+
+
 def cpu_baseline(fr, budget_s=20.0):
     """The FP64 oracle on a bounded sample of the same workload, scaled to frames/s.
 
@@ -223,6 +248,7 @@ def main():
                 "avg_us": round(stage_us[dom], 2), "valu_busy": round(cnt["valu_busy"], 3) if cnt else None,
                 "hbm_frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes": alg[dom]}
     total_alg = sum(alg.values())
+    vf = frame_valu_floor_us()
     res = {
         "metric": METRIC,
         "value": round(1000.0 / ms, 2),
@@ -244,6 +270,10 @@ def main():
         "frame_alg_bytes": total_alg,
         "frame_alg_gbs": round(total_alg / (ms * 1e-3) / 1e9, 1),
         "frame_hbm_frac": round(total_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        # the frame is bound by vector issue: its kernels' VALU instructions at the full issue
+        # rate, and that floor as a share of the measured frame time
+        "frame_valu_floor_us": round(vf, 1) if vf else None,
+        "frame_valu_frac": round(vf / (ms * 1e3), 4) if vf else None,
         "roofline": roof,
         "paper_context": "paper: 40,000 particles in under 50 ms on one NVIDIA A100 (1024^2 canvas)",
     }
