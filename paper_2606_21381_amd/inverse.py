@@ -181,6 +181,18 @@ def _lr_groups(p: Params, cfg: SolverConfig):
     ]
 
 
+_side_streams = {}
+
+
+def _warmup_stream(dev) -> "torch.cuda.Stream":
+    """One warm-up stream per device, reused by every solve (the renderer keeps a
+    workspace per stream, so a fresh stream per solve would add one each time)."""
+    key = torch.device(dev).index
+    if key not in _side_streams:
+        _side_streams[key] = torch.cuda.Stream(device=dev)
+    return _side_streams[key]
+
+
 def _graph_memsets(g) -> int:
     """Memset nodes in a captured graph.  A step graph must hold kernels and copies
     only (a memset node is replayed as recorded, and such nodes have left wrong
@@ -291,7 +303,7 @@ def solve(target: torch.Tensor, start: Params, truth: Optional[Truth], H: int, W
     stages = sorted({stage_groups(cfg, k) for k in range(cfg.steps)}, key=lambda f: sorted(f))
     if on_gpu and cfg.graph and cfg.steps > 0:
         saved = [q.detach().clone() for q in start.parameters()]
-        side = torch.cuda.Stream(device=dev)
+        side = _warmup_stream(dev)
         side.wait_stream(torch.cuda.current_stream(dev))
         with torch.cuda.stream(side):  # warm-up: creates Adam's state and the allocator's blocks
             for _ in range(3):
