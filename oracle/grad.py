@@ -79,3 +79,44 @@ def mse(I: np.ndarray, target: np.ndarray) -> float:
     """Inverse-rendering loss: mean squared error against a pixel-aligned target."""
     d = np.asarray(I, dtype=np.float64) - np.asarray(target, dtype=np.float64)
     return float(np.mean(d * d))
+
+
+def directional_fd(soa, H, W, optics, globals4, weights, v_soa, v_glob, delta: float = 1e-5):
+    """Central differences of L = sum(weights * I) along one direction of the whole
+    parameter vector (every table entry and the three globals at once):
+    (L(p + d v) - L(p - d v)) / (2 d), at d and at d/2.  This is J v for the linear
+    probe, the left side of the dot-product identity <J v, w> = <v, J^T w>."""
+    soa64 = np.array(soa, dtype=np.float64)
+    g64 = np.array(globals4, dtype=np.float64)
+    v_soa = np.asarray(v_soa, dtype=np.float64)
+    v_glob = np.asarray(v_glob, dtype=np.float64)
+
+    def L(t):
+        g = g64.copy()
+        g[:3] += t * v_glob[:3]
+        return loss(soa64 + t * v_soa, H, W, optics, g, weights)
+
+    return (L(delta) - L(-delta)) / (2 * delta), (L(delta / 2) - L(-delta / 2)) / delta
+
+
+def ellipsoid_rim_margin(soa, H: int, W: int) -> np.ndarray:
+    """Per particle: min over canvas pixel centres of |1 - q|, q = (u/a)^2 + (v/b)^2
+    the centre's normalised radius in the ellipsoid's frame (FP64); inf for other
+    shapes.  The centre-sampled thickness h sqrt(1 - q) has unbounded slope at the
+    rim, so a finite difference is well conditioned only where no pixel centre lies
+    close to it."""
+    s = np.asarray(soa, dtype=np.float64)
+    out = np.full(s.shape[1], np.inf)
+    for p in np.nonzero(s[7] == 1.0)[0]:
+        cx, cy, ang, a, b = s[0, p], s[1, p], s[2, p], s[3, p], s[4, p]
+        r = max(a, b) + 2.0
+        x = np.arange(max(0, int(np.floor(cx - r))), min(W - 1, int(np.floor(cx + r))) + 1) + 0.5
+        y = np.arange(max(0, int(np.floor(cy - r))), min(H - 1, int(np.floor(cy + r))) + 1) + 0.5
+        if x.size == 0 or y.size == 0:
+            continue
+        dx, dy = np.meshgrid(x - cx, y - cy)
+        c, sn = np.cos(ang), np.sin(ang)
+        u, v = c * dx + sn * dy, -sn * dx + c * dy
+        q = (u / a) ** 2 + (v / b) ** 2
+        out[p] = float(np.min(np.abs(1.0 - q)))
+    return out
