@@ -34,6 +34,7 @@ struct osog_context {
   float4* hab = nullptr;
   int n_habits = 0;
   uint64_t topo_seed = 0;
+  uint64_t habit_gen = 0;  // bumped by every osog_set_habits: part of a captured batch's signature
 };
 
 namespace osog {
@@ -227,6 +228,7 @@ int context_radix(const osog_context* ctx, int H, int W) {
 const float2* context_twiddle(const osog_context* ctx) { return ctx->twiddle; }
 int context_device(const osog_context* ctx) { return ctx->device; }
 BatchCache* context_batch(osog_context* ctx) { return ctx->batch; }
+uint64_t context_habit_generation(const osog_context* ctx) { return ctx->habit_gen; }
 
 FramePlan make_plan(const osog_context* ctx, int H, int W, int64_t n, int64_t ld,
                     const osog_optics& o, int64_t cap) {
@@ -633,6 +635,8 @@ osog_status osog_set_habits(osog_context* ctx, int32_t n_habits, const int32_t* 
   }
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  // work already queued may still read the old table
+  if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
   if (!ctx->hab && (e = hipMalloc(&ctx->hab, sizeof(float4) * tab.size())) != hipSuccess) {
     ctx->hab = nullptr;
     return hip_fail(e, "hipMalloc(habits)");
@@ -641,6 +645,7 @@ osog_status osog_set_habits(osog_context* ctx, int32_t n_habits, const int32_t* 
     return hip_fail(e, "hipMemcpy(habits)");
   ctx->n_habits = n_habits;
   ctx->topo_seed = topo_seed;
+  ctx->habit_gen++;
   return OSOG_OK;
 }
 

@@ -10,9 +10,11 @@
 // the device's hardware queues, so small frames overlap large ones.  Every
 // dependency is a graph edge: no workgroup ever waits for another.
 //
-// Kernel arguments (frame pointers, sizes, optics) are fixed at capture, so the
-// signature is the raw frame descriptors plus the workspace, the timestamp
-// buffer, the per-size tiling and FFT radix, and the branch count.
+// Kernel arguments (frame pointers, sizes, optics, the habit count and
+// topography seed) and the raster build are fixed at capture, so the signature
+// is the raw frame descriptors plus the workspace, the timestamp buffer, the
+// per-size tiling and FFT radix, the branch count and the context's habit
+// generation (which osog_set_habits advances).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -82,6 +84,7 @@ void context_tiling(const osog_context* ctx, int H, int W, int* th, int* tw);
 int context_radix(const osog_context* ctx, int H, int W);
 int context_device(const osog_context* ctx);
 BatchCache* context_batch(osog_context* ctx);
+uint64_t context_habit_generation(const osog_context* ctx);
 
 // Workspace: the flags, then each frame's single-frame workspace.
 static std::vector<size_t> batch_offsets(const osog_context* ctx, const osog_frame* frames, int nf, int ppp,
@@ -161,6 +164,8 @@ hipError_t batch_render(osog_context* ctx, hipStream_t stream, const osog_frame*
   std::string sig(reinterpret_cast<const char*>(frames), sizeof(osog_frame) * (size_t)nf);
   const void* extra[2] = {workspace, frame_done_ns};
   sig.append(reinterpret_cast<const char*>(extra), sizeof(extra));
+  const uint64_t gen = context_habit_generation(ctx);
+  sig.append(reinterpret_cast<const char*>(&gen), sizeof(gen));
   std::vector<int> ints = {ppp, branches};
   for (int f = 0; f < nf; ++f) {
     int th, tw;

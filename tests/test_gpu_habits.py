@@ -126,6 +126,34 @@ def test_habits_in_a_batch_are_bitwise_single(habits):
         assert torch.equal(a, b), f
 
 
+def test_batch_replayed_after_the_habits_change(habits):
+    """A captured batch graph bakes the habit count, topography seed and raster build
+    into its kernels: after osog_set_habits the same Batch (same buffers) must not
+    replay the stale graph."""
+    need_gpu()
+    frames = []
+    for f in range(3):
+        size = (256, 512)[f % 2]
+        frames.append((dev_soa(mixed_table(140 + f, size, 500 + 100 * f)), size, size,
+                       workloads.dic_optics(0.0, f), dev_globals([0.3 * f, 1.0, 1.5, 0])))
+    b = render.Batch(frames)
+    first = [x.clone() for x in b.run()]
+    torch.cuda.synchronize()
+    # fewer habits, another topography seed: ids 2 + k >= 2 + 1 now name no habit
+    render.set_habits(HABITS[:1], SEED + 1)
+    try:
+        singles = [render.render(s, H, W, o, g) for (s, H, W, o, g) in frames]
+        outs = b.run()
+        torch.cuda.synchronize()
+        for f, (a, c) in enumerate(zip(singles, outs)):
+            say("frame %d: replay after set_habits bitwise the single render: %s; differs from before: %s" % (
+                f, bool(torch.equal(a, c)), not torch.equal(first[f], c)))
+            assert torch.equal(a, c), f
+            assert not torch.equal(first[f], c), f
+    finally:
+        render.set_habits(HABITS, SEED)
+
+
 def test_habit_validation():
     need_gpu()
     open_top = workloads.HabitSpec(np.array([[1, 0, 0, 1], [-1, 0, 0, 1], [0, 1, 0, 1], [0, -1, 0, 1],
