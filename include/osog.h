@@ -144,6 +144,24 @@ osog_status osog_render(osog_context* ctx, void* stream, int32_t height, int32_t
                         const float* globals, float* opd_out, float* intensity_out,
                         void* workspace, size_t workspace_bytes);
 
+/* osog_render without a workspace, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  It calls no hipMalloc, hipFree or allocating library routine: the
+ * frame's buffers (records, tile buckets, band spectrum, and the OPD and
+ * absorbance planes when opd_out is NULL) live in one fixed 64 MiB device array
+ * inside the library, one copy per GPU, held until the process ends.  Arguments
+ * and outputs are those of osog_render (same kernels, bitwise the same images);
+ * the caller still passes soa, globals, opd_out and intensity_out.
+ *   Limit: frames whose packed buffers exceed 64 MiB return OSOG_ERR_WORKSPACE
+ *   with the size they need (2048 x 2048 with 40,000 particles needs about 30 MiB
+ *   without opd_out); the incoherent DIC (mode 3) returns OSOG_ERR_UNSUPPORTED.
+ *   Every call on one GPU shares that GPU's array, whatever the context or
+ *   stream: calls that overlap in time on one GPU race and give wrong images.
+ *   Serialise them (one stream, or events between streams). */
+osog_status osog_render_noalloc(osog_context* ctx, void* stream, int32_t height, int32_t width,
+                                const float* soa, int64_t n, int64_t ld, const osog_optics* optics,
+                                const float* globals, float* opd_out, float* intensity_out);
+
 /* Several imaging modalities of one particle table, pixel-aligned (paper Sec.
  * III, the multi-modal output of one geometry buffer): binning, rasterisation
  * and the row FFT run once over the union of the modes' in-band spectrum

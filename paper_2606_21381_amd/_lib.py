@@ -19,7 +19,7 @@ STAGES = ["binning", "raster", "pass1", "pass2", "pass3", "adj_pass3", "adj_pass
 # Every symbol include/osog.h declares.
 EXPORTS = [
     "osog_context_create", "osog_context_destroy", "osog_set_tiling", "osog_get_tiling",
-    "osog_workspace_size", "osog_render", "osog_render_multi", "osog_render_backward", "osog_batch_workspace_size",
+    "osog_workspace_size", "osog_render", "osog_render_noalloc", "osog_render_multi", "osog_render_backward", "osog_batch_workspace_size",
     "osog_batch_render", "osog_batch_error", "osog_set_batch_group", "osog_set_size_tiling", "osog_set_size_radix", "osog_autotune", "osog_bin", "osog_band_info", "osog_philox4x32_10", "osog_profile_enable",
     "osog_profile_read", "osog_cnn_param_count", "osog_cnn_workspace_size", "osog_cnn_forward",
     "osog_cnn_train_step", "osog_conv3x3_workspace_size", "osog_conv3x3", "osog_status_string",
@@ -86,6 +86,7 @@ def load(path: str = LIB_PATH):
         "osog_get_tiling": [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "osog_workspace_size": [vp, i32, i32, i64, i32, i32, ctypes.POINTER(sz)],
         "osog_render": [vp, vp, i32, i32, vp, i64, i64, ctypes.POINTER(Optics), vp, vp, vp, vp, sz],
+        "osog_render_noalloc": [vp, vp, i32, i32, vp, i64, i64, ctypes.POINTER(Optics), vp, vp, vp],
         "osog_render_multi": [vp, vp, i32, i32, vp, i64, i64, i32, ctypes.POINTER(Optics), vp,
                               ctypes.POINTER(vp), vp, vp, sz],
         "osog_render_backward": [vp, vp, i32, i32, vp, i64, i64, ctypes.POINTER(Optics), vp, vp, vp,

@@ -35,7 +35,19 @@ struct osog_context {
   int n_habits = 0;
   uint64_t topo_seed = 0;
   uint64_t habit_gen = 0;  // bumped by every osog_set_habits: part of a captured batch's signature
+  // device address of this GPU's copy of `scratch` (osog_render_noalloc), or NULL with the
+  // error hipGetSymbolAddress returned
+  void* scratch = nullptr;
+  hipError_t scratch_err = hipSuccess;
 };
+
+// Fixed device scratch of osog_render_noalloc, for callers that cannot allocate.
+// Every GPU that loads the library holds its own copy until the process ends.  In
+// host code the name is only a stand-in for the symbol: kernels receive the device
+// address that hipGetSymbolAddress returns for the current device (taken once per
+// context in osog_context_create), never the name itself.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace osog {
 
@@ -122,6 +134,29 @@ FrameBufs carve(void* ws, int H, int W, int64_t n, int tile_h, int tile_w, int p
                 int64_t* cap_out) {
   Carver c{static_cast<char*>(ws)};
   return carve_impl(c, H, W, n, tile_h, tile_w, ppp, backward, cap_out);
+}
+
+// Forward-only buffers of one frame, packed for the fixed scratch: the band keeps
+// only the in-band columns, the OPD and absorbance planes exist only when the
+// caller passes no opd_out, and the inspection prefix is left out.
+static FrameBufs carve_compact(Carver& c, const FramePlan& p, int64_t cap, bool own_opd) {
+  const size_t hw = (size_t)p.H * p.W, nn = p.n > 0 ? (size_t)p.n : 1;
+  const size_t kx = p.kx_n > 0 ? (size_t)p.kx_n : 1;
+  FrameBufs b{};
+  b.recs = c.take<PRec>(nn);
+  b.boxes = c.take<int4>(nn);
+  b.counts = c.take<int>(nn);
+  b.scal = c.take<int>(64);
+  b.tile_count = c.take<int>(p.n_tiles);
+  b.pids = c.take<int>((size_t)p.n_tiles * cap);
+  if (own_opd) {
+    b.opd = c.take<float>(hw);
+    if (p.absorb) b.tau = c.take<float>(hw);
+  }
+  if (p.absorb) b.absr = c.take<float2>(nn);
+  b.band = c.take<float2>((size_t)p.H * kx);
+  b.colsum = c.take<double>(kx);
+  return b;
 }
 
 // ---- pupil band: signed kx columns with any bin inside the (shifted) disc ----
@@ -341,6 +376,12 @@ osog_status osog_context_create(osog_context** out, int device) {
     delete ctx;
     return hip_fail(e, "hipMemcpy(twiddle)");
   }
+  // this device's copy of the no-allocation scratch (the device is current here)
+  ctx->scratch_err = hipGetSymbolAddress(&ctx->scratch, HIP_SYMBOL(scratch));
+  if (ctx->scratch_err != hipSuccess) {
+    ctx->scratch = nullptr;
+    (void)hipGetLastError();  // keep the failure out of later launch checks
+  }
   ctx->batch = batch_cache_create();
   ctx->prof = profiler_create();
   *out = ctx;
@@ -461,6 +502,45 @@ osog_status osog_render(osog_context* ctx, void* stream, int32_t height, int32_t
   FramePlan p = make_plan(ctx, height, width, n, ld, *optics, cap);
   e = forward_frame(ctx, p, soa, globals, b, opd_out, intensity_out, (hipStream_t)stream, true);
   if (e != hipSuccess) return hip_fail(e, "osog_render launch");
+  return OSOG_OK;
+}
+
+osog_status osog_render_noalloc(osog_context* ctx, void* stream, int32_t height, int32_t width,
+                                const float* soa, int64_t n, int64_t ld, const osog_optics* optics,
+                                const float* globals, float* opd_out, float* intensity_out) {
+  osog_status st = check_frame(ctx, height, width, soa, n, ld, optics, globals);
+  if (st != OSOG_OK) return st;
+  if (!intensity_out) return fail(OSOG_ERR_INVALID_ARGUMENT, "intensity_out is NULL");
+  if (optics->mode == OSOG_DIC_INCOHERENT)
+    return fail(OSOG_ERR_UNSUPPORTED, "osog_render_noalloc does not render the incoherent DIC "
+                                      "(its full spectra need osog_render's workspace)");
+  if (!ctx->scratch)
+    return fail(OSOG_ERR_HIP, std::string("no device address for the scratch: ") + hipGetErrorString(ctx->scratch_err));
+  FramePlan p = make_plan(ctx, height, width, n, ld, *optics, 0);
+  const bool own_opd = opd_out == nullptr;
+  // the largest pair capacity that fits (results do not depend on it)
+  int64_t cap = 0;
+  size_t need = 0;
+  for (int cand = 1 << 20; cand >= 1; cand >>= 1) {
+    const int64_t c = bucket_capacity(n, p.n_tiles, cand);
+    Carver probe{nullptr};
+    carve_compact(probe, p, c, own_opd);
+    need = probe.off;
+    if (need <= kScratchBytes) {
+      cap = c;
+      break;
+    }
+  }
+  if (cap == 0)
+    return fail(OSOG_ERR_WORKSPACE, "frame needs " + std::to_string(need) + " bytes of scratch; osog_render_noalloc holds " +
+                                        std::to_string(kScratchBytes) + " (use osog_render with a workspace)");
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  Carver c{static_cast<char*>(ctx->scratch)};
+  FrameBufs b = carve_compact(c, p, cap, own_opd);
+  p.cap = cap;
+  e = forward_frame(ctx, p, soa, globals, b, opd_out, intensity_out, (hipStream_t)stream, false);
+  if (e != hipSuccess) return hip_fail(e, "osog_render_noalloc launch");
   return OSOG_OK;
 }
 

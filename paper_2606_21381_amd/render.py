@@ -127,6 +127,25 @@ def render(soa: torch.Tensor, H: int, W: int, optics, globals4: torch.Tensor, wa
     return (out, opd_out) if want_opd else out
 
 
+def render_noalloc(soa: torch.Tensor, H: int, W: int, optics, globals4: torch.Tensor,
+                   out: torch.Tensor, opd_out: Optional[torch.Tensor] = None):
+    """osog_render_noalloc: the frame of render() in the library's fixed device scratch,
+    with no workspace and no device allocation (out, and opd_out if given, are the
+    caller's).  Calls on one GPU share that scratch: they must not overlap."""
+    device = soa.device
+    n, ld = _check_soa(soa, soa_rows(optics))
+    _check_globals(globals4, device)
+    if out.shape != (H, W) or out.dtype != torch.float32 or out.device != device or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 [H, W] tensor on the particle table's device")
+    if opd_out is not None and opd_out.numel() != _planes(optics) * H * W:
+        raise ValueError("opd_out must hold %d plane(s) of H x W" % _planes(optics))
+    o = _lib.make_optics(optics)
+    _lib.check(_lib.load().osog_render_noalloc(context(device), _stream(device), H, W, _ptr(soa) if n else None,
+                                                n, ld, ctypes.byref(o), _ptr(globals4), _ptr(opd_out), _ptr(out)),
+               "osog_render_noalloc")
+    return out
+
+
 def render_multi(soa: torch.Tensor, H: int, W: int, optics_list, globals_modes: torch.Tensor,
                  want_opd: bool = False, out=None, workspace: Optional[torch.Tensor] = None):
     """Several modalities of one particle table, pixel-aligned (one binning, raster
