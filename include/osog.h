@@ -113,17 +113,19 @@ osog_status osog_context_create(osog_context** out, int device);
 osog_status osog_context_destroy(osog_context* ctx);
 
 /* Tiling used for binning and rasterisation: tile_h x tile_w pixels, both
- * powers of two with tile_h * tile_w == 256.  Changing it changes the pair
- * list but not the OPD (each pixel always sums its particles in ascending id). */
+ * powers of two with 256 <= tile_h * tile_w <= 1024.  Changing it changes the
+ * pair list but not the OPD (each pixel's value depends only on the pixel and
+ * the particles that reach it). */
 osog_status osog_set_tiling(osog_context* ctx, int32_t tile_h, int32_t tile_w);
 osog_status osog_get_tiling(const osog_context* ctx, int32_t* tile_h, int32_t* tile_w);
 
 /* Bytes of device workspace needed by osog_render (with_backward = 0) or by
  * osog_render_backward (with_backward = 1) for an H x W canvas and n particles.
- * pairs_per_particle sizes the per-tile pair buckets: (pairs_per_particle * n +
- * tiles) / tiles ids per tile, rounded up to a multiple of 8, in [8, 1024]
- * (0 selects 32).  A tile with more pairs than its bucket holds stays correct
- * and bitwise identical but is rasterised by a slow scan of all particles. */
+ * pairs_per_particle sizes the (tile, particle) pair list: pairs_per_particle * n
+ * + tiles entries (0 selects 32).  The list is grouped by tile with exact
+ * offsets, so a crowded tile costs only its own pairs.  A frame whose pairs
+ * exceed the list stays correct and bitwise identical: the tiles whose segments
+ * do not fit are rasterised by a slower id-ordered scan of all particles. */
 osog_status osog_workspace_size(const osog_context* ctx, int32_t height, int32_t width, int64_t n,
                                 int32_t pairs_per_particle, int32_t with_backward, size_t* bytes);
 
@@ -147,7 +149,7 @@ osog_status osog_render(osog_context* ctx, void* stream, int32_t height, int32_t
 /* osog_render without a workspace, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc).  It calls no hipMalloc, hipFree or allocating library routine: the
- * frame's buffers (records, tile buckets, band spectrum, and the OPD and
+ * frame's buffers (records, tile pair list, band spectrum, and the OPD and
  * absorbance planes when opd_out is NULL) live in one fixed 64 MiB device array
  * inside the library, one copy per GPU, held until the process ends.  Arguments
  * and outputs are those of osog_render (same kernels, bitwise the same images);
@@ -234,9 +236,10 @@ osog_status osog_batch_render(osog_context* ctx, void* stream, const osog_frame*
                               int32_t n_frames, void* workspace, size_t workspace_bytes,
                               uint64_t* frame_done_ns);
 
-/* Number of frames of the last batch on this workspace in which some tile's
- * pair bucket overflowed (those tiles were rendered by the slower all-particle
- * scan, with the same result), into *flag (host).  Waits for the device. */
+/* Number of frames of the last batch on this workspace in which some tile was
+ * rasterised by the slower id-ordered scan of all particles (a segment of more
+ * than 512 ids, or one past the pair list's capacity; the result is the same),
+ * into *flag (host).  Waits for the device. */
 osog_status osog_batch_error(osog_context* ctx, void* workspace, int32_t* flag);
 
 /* Batch scheduling: the number of concurrent branches of the batch graph,
@@ -270,8 +273,8 @@ osog_status osog_autotune(osog_context* ctx, void* stream, int32_t height, int32
  *   tile_start_out      device int32[n_tiles + 1]; counts_out device int32[n] or NULL
  * n_tiles = (height / tile_h) * (width / tile_w).  *pair_count_out is the full
  * pair count; if it exceeds `capacity`, keys_out and pids_out are not written.
- * workspace: as for osog_render (its buckets are filled as a render fills them;
- * an overflowing tile's ids are produced by the same id-ordered scan). */
+ * workspace: as for osog_render (its pair list is filled as a render fills it;
+ * a tile the raster would scan is produced by the same id-ordered scan). */
 osog_status osog_bin(osog_context* ctx, void* stream, int32_t height, int32_t width,
                      const float* soa, int64_t n, int64_t ld, int32_t* keys_out,
                      int32_t* pids_out, int64_t capacity, int32_t* pair_count_out,

@@ -66,6 +66,11 @@ static osog_status hip_fail(hipError_t e, const char* where) {
 
 static bool pow2_in(int v, int lo, int hi) { return v >= lo && v <= hi && (v & (v - 1)) == 0; }
 
+// Raster tiles: power-of-two sides, kMinTile..kMaxTile pixels (the raster's LDS sums)
+static bool tile_shape_ok(int th, int tw) {
+  return pow2_in(th, 1, kMaxTile) && pow2_in(tw, 1, kMaxTile) && th * tw >= kMinTile && th * tw <= kMaxTile;
+}
+
 static int ilog2(int v) {
   int l = 0;
   while ((1 << l) < v) ++l;
@@ -86,18 +91,17 @@ struct Carver {
   }
 };
 
-// Ids per tile bucket: the pair capacity ppp * n + n_tiles spread evenly over the
-// tiles, rounded up to a multiple of 8, in [8, kMaxBucket].
-static int64_t bucket_capacity(int64_t n, int n_tiles, int ppp) {
-  int64_t per = (n * (int64_t)ppp + n_tiles + n_tiles - 1) / n_tiles;
-  per = (per + 7) / 8 * 8;
-  return per < 8 ? 8 : (per > kMaxBucket ? kMaxBucket : per);
+// Entries of the pair list: ppp pairs per particle plus one per tile (the
+// tile-aligned part of every particle's box), at least one.
+int64_t pair_capacity(int64_t n, int n_tiles, int ppp) {
+  const int64_t c = n * (int64_t)ppp + n_tiles;
+  return c < 1 ? 1 : (c > INT_MAX ? INT_MAX : c);
 }
 
 static FrameBufs carve_impl(Carver& c, int H, int W, int64_t n, int tile_h, int tile_w, int ppp,
-                            bool backward, int64_t* cap_out) {
+                            bool backward, int64_t* pair_cap_out) {
   const int n_tiles = (H / tile_h) * (W / tile_w);
-  const int64_t cap = bucket_capacity(n, n_tiles, ppp);
+  const int64_t pcap = pair_capacity(n, n_tiles, ppp);
   const size_t hw = (size_t)H * W;
   FrameBufs b{};
   b.recs = c.take<PRec>(n > 0 ? n : 1);
@@ -105,8 +109,9 @@ static FrameBufs carve_impl(Carver& c, int H, int W, int64_t n, int tile_h, int 
   b.counts = c.take<int>(n > 0 ? n : 1);
   b.scal = c.take<int>(64);
   b.tile_count = c.take<int>(n_tiles);
-  b.tile_first = c.take<int>(n_tiles);
-  b.pids = c.take<int>((size_t)n_tiles * cap);
+  b.tile_start = c.take<int>(n_tiles + 1);
+  b.cursor = c.take<int>(n_tiles);
+  b.pids = c.take<int>((size_t)pcap);
   b.opd = c.take<float>(hw);
   b.tau = c.take<float>(hw);
   b.absr = c.take<float2>(n > 0 ? n : 1);
@@ -120,7 +125,7 @@ static FrameBufs carve_impl(Carver& c, int H, int W, int64_t n, int tile_h, int 
     b.otf = c.take<float2>(hw);
     b.psum = c.take<double>(H);
   }
-  if (cap_out) *cap_out = cap;
+  if (pair_cap_out) *pair_cap_out = pcap;
   return b;
 }
 
@@ -131,15 +136,15 @@ size_t frame_workspace_bytes(int H, int W, int64_t n, int tile_h, int tile_w, in
 }
 
 FrameBufs carve(void* ws, int H, int W, int64_t n, int tile_h, int tile_w, int ppp, bool backward,
-                int64_t* cap_out) {
+                int64_t* pair_cap_out) {
   Carver c{static_cast<char*>(ws)};
-  return carve_impl(c, H, W, n, tile_h, tile_w, ppp, backward, cap_out);
+  return carve_impl(c, H, W, n, tile_h, tile_w, ppp, backward, pair_cap_out);
 }
 
 // Forward-only buffers of one frame, packed for the fixed scratch: the band keeps
 // only the in-band columns, the OPD and absorbance planes exist only when the
 // caller passes no opd_out, and the inspection prefix is left out.
-static FrameBufs carve_compact(Carver& c, const FramePlan& p, int64_t cap, bool own_opd) {
+static FrameBufs carve_compact(Carver& c, const FramePlan& p, int64_t pair_cap, bool own_opd) {
   const size_t hw = (size_t)p.H * p.W, nn = p.n > 0 ? (size_t)p.n : 1;
   const size_t kx = p.kx_n > 0 ? (size_t)p.kx_n : 1;
   FrameBufs b{};
@@ -148,7 +153,9 @@ static FrameBufs carve_compact(Carver& c, const FramePlan& p, int64_t cap, bool 
   b.counts = c.take<int>(nn);
   b.scal = c.take<int>(64);
   b.tile_count = c.take<int>(p.n_tiles);
-  b.pids = c.take<int>((size_t)p.n_tiles * cap);
+  b.tile_start = c.take<int>(p.n_tiles + 1);
+  b.cursor = c.take<int>(p.n_tiles);
+  b.pids = c.take<int>((size_t)pair_cap);
   if (own_opd) {
     b.opd = c.take<float>(hw);
     if (p.absorb) b.tau = c.take<float>(hw);
@@ -266,7 +273,7 @@ BatchCache* context_batch(osog_context* ctx) { return ctx->batch; }
 uint64_t context_habit_generation(const osog_context* ctx) { return ctx->habit_gen; }
 
 FramePlan make_plan(const osog_context* ctx, int H, int W, int64_t n, int64_t ld,
-                    const osog_optics& o, int64_t cap) {
+                    const osog_optics& o, int64_t pair_cap) {
   FramePlan p{};
   p.H = H; p.W = W; p.logH = ilog2(H); p.logW = ilog2(W);
   context_tiling(ctx, H, W, &p.tile_h, &p.tile_w);
@@ -278,7 +285,7 @@ FramePlan make_plan(const osog_context* ctx, int H, int W, int64_t n, int64_t ld
   }
   p.rb = rows_per_block(W);
   p.fft_radix = context_radix(ctx, H, W);
-  p.n = n; p.ld = ld; p.cap = cap;
+  p.n = n; p.ld = ld; p.pair_cap = pair_cap;
   p.mode = o.mode;
   p.phase_k = (float)(2.0 * M_PI / o.wavelength_um);
   p.inv_wdx = (float)(1.0 / ((double)W * o.pixel_um));
@@ -446,8 +453,8 @@ static bool habit_vertices(const float* f, int m, double* max_r, bool* bounded) 
 
 osog_status osog_set_tiling(osog_context* ctx, int32_t tile_h, int32_t tile_w) {
   if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
-  if (!pow2_in(tile_h, 1, 256) || !pow2_in(tile_w, 1, 256) || tile_h * tile_w != kThreads)
-    return fail(OSOG_ERR_UNSUPPORTED, "tile sides must be powers of two with tile_h * tile_w == 256");
+  if (!tile_shape_ok(tile_h, tile_w))
+    return fail(OSOG_ERR_UNSUPPORTED, "tile sides must be powers of two with 256 <= tile_h * tile_w <= 1024");
   ctx->tile_h = tile_h;
   ctx->tile_w = tile_w;
   return OSOG_OK;
@@ -518,11 +525,11 @@ osog_status osog_render_noalloc(osog_context* ctx, void* stream, int32_t height,
     return fail(OSOG_ERR_HIP, std::string("no device address for the scratch: ") + hipGetErrorString(ctx->scratch_err));
   FramePlan p = make_plan(ctx, height, width, n, ld, *optics, 0);
   const bool own_opd = opd_out == nullptr;
-  // the largest pair capacity that fits (results do not depend on it)
+  // the largest pair list that fits (results do not depend on it), up to 1024 pairs per particle
   int64_t cap = 0;
   size_t need = 0;
-  for (int cand = 1 << 20; cand >= 1; cand >>= 1) {
-    const int64_t c = bucket_capacity(n, p.n_tiles, cand);
+  for (int cand = 1024; cand >= 1; cand >>= 1) {
+    const int64_t c = pair_capacity(n, p.n_tiles, cand);
     Carver probe{nullptr};
     carve_compact(probe, p, c, own_opd);
     need = probe.off;
@@ -538,7 +545,7 @@ osog_status osog_render_noalloc(osog_context* ctx, void* stream, int32_t height,
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   Carver c{static_cast<char*>(ctx->scratch)};
   FrameBufs b = carve_compact(c, p, cap, own_opd);
-  p.cap = cap;
+  p.pair_cap = cap;
   e = forward_frame(ctx, p, soa, globals, b, opd_out, intensity_out, (hipStream_t)stream, false);
   if (e != hipSuccess) return hip_fail(e, "osog_render_noalloc launch");
   return OSOG_OK;
@@ -896,9 +903,9 @@ osog_status osog_set_batch_group(osog_context* ctx, int32_t group) {
 
 osog_status osog_set_size_tiling(osog_context* ctx, int32_t height, int32_t width, int32_t tile_h, int32_t tile_w) {
   if (!ctx) return fail(OSOG_ERR_NOT_INITIALIZED, "context is NULL");
-  if (!pow2_in(tile_h, 1, 256) || !pow2_in(tile_w, 1, 256) || tile_h * tile_w != kThreads ||
-      !pow2_in(height, 32, 4096) || !pow2_in(width, 32, 4096) || height % tile_h || width % tile_w)
-    return fail(OSOG_ERR_UNSUPPORTED, "tiling must divide the canvas, powers of two, tile_h * tile_w == 256");
+  if (!tile_shape_ok(tile_h, tile_w) || !pow2_in(height, 32, 4096) || !pow2_in(width, 32, 4096) ||
+      height % tile_h || width % tile_w)
+    return fail(OSOG_ERR_UNSUPPORTED, "tiling must divide the canvas, powers of two, 256 <= tile_h * tile_w <= 1024");
   ctx->size_tiling[{height, width}] = {tile_h, tile_w};
   return OSOG_OK;
 }
@@ -1023,7 +1030,8 @@ osog_status osog_autotune(osog_context* ctx, void* stream, int32_t height, int32
                            ? std::optional<std::pair<int, int>>(ctx->size_tiling[key]) : std::nullopt;
   const auto saved_r = ctx->size_radix.find(key) != ctx->size_radix.end()
                            ? std::optional<int>(ctx->size_radix[key]) : std::nullopt;
-  const int cand_t[3][2] = {{16, 16}, {8, 32}, {32, 8}};
+  const int cand_t[][2] = {{16, 16}, {32, 32}, {32, 16}, {16, 32}, {64, 16}};
+  constexpr int n_cand_t = (int)(sizeof(cand_t) / sizeof(cand_t[0]));
   const int cand_r[2] = {8, 4};
   float best = 1e30f;
   int bt = -1, br = -1;
@@ -1033,7 +1041,7 @@ osog_status osog_autotune(osog_context* ctx, void* stream, int32_t height, int32
   if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
   if ((e = hipEventCreate(&e1)) != hipSuccess) { (void)hipEventDestroy(e0); return hip_fail(e, "hipEventCreate"); }
   osog_status out = OSOG_OK;
-  for (int ti = 0; ti < 3 && out == OSOG_OK; ++ti) {
+  for (int ti = 0; ti < n_cand_t && out == OSOG_OK; ++ti) {
     if (height % cand_t[ti][0] || width % cand_t[ti][1]) continue;
     for (int ri = 0; ri < 2 && out == OSOG_OK; ++ri) {
       ctx->size_tiling[key] = {cand_t[ti][0], cand_t[ti][1]};

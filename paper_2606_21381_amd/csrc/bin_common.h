@@ -33,6 +33,10 @@ __device__ __forceinline__ bool pixel_box(float cx, float cy, float a, float b, 
   return true;
 }
 
+// A pixel index from an integral float, clamped far outside any canvas (the raster
+// clamps it to its tile).
+__device__ __forceinline__ int pixel_index(float v) { return (int)fminf(fmaxf(v, -2.0f), 65536.0f); }
+
 // Raster record of a valid particle (layout documented with PRec).
 __device__ __forceinline__ void make_record(float cx, float cy, float ang, float a, float b, float h,
                                             float dn, float shape, float R, float habit, PRec* out) {
@@ -70,7 +74,11 @@ __device__ __forceinline__ void make_record(float cx, float cy, float ang, float
     r.f[25] = 0.5f * (p - q);
     r.f[26] = __builtin_amdgcn_rcpf(p);
     r.f[27] = __builtin_amdgcn_rcpf(fmaxf(2.0f * p * q, 1e-30f));
-    r.f[28] = r.f[20] - 0.5f; r.f[29] = r.f[21] + 0.5f; r.f[30] = r.f[22] - 0.5f; r.f[31] = r.f[23] + 0.5f;
+    // candidate pixels: those whose square meets the bounds
+    r.f[28] = __int_as_float(pixel_index(floorf(r.f[20])));
+    r.f[29] = __int_as_float(pixel_index(ceilf(r.f[21]) - 1.0f));
+    r.f[30] = __int_as_float(pixel_index(floorf(r.f[22])));
+    r.f[31] = __int_as_float(pixel_index(ceilf(r.f[23]) - 1.0f));
   } else {
     r.f[3] = shape < 1.5f ? 1.0f : 2.0f;
     r.f[8] = 1.0f / a;
@@ -92,6 +100,11 @@ __device__ __forceinline__ void make_record(float cx, float cy, float ang, float
       r.f[17] = r.f[16];
       r.f[18] = habit;
     }
+    // candidate pixels: those whose centre lies inside the enlarged box
+    r.f[28] = __int_as_float(pixel_index(ceilf((cx - r.f[16]) - 0.5f)));
+    r.f[29] = __int_as_float(pixel_index(floorf((cx + r.f[16]) - 0.5f)));
+    r.f[30] = __int_as_float(pixel_index(ceilf((cy - r.f[17]) - 0.5f)));
+    r.f[31] = __int_as_float(pixel_index(floorf((cy + r.f[17]) - 0.5f)));
   }
 }
 

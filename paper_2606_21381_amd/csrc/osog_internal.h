@@ -15,7 +15,8 @@ constexpr int kThreads = 256;     // every kernel runs 256-thread workgroups (4 
 constexpr int kTwN = 4096;        // twiddle table length (largest FFT)
 constexpr int kDefaultPairsPerParticle = 32;
 constexpr int kXcds = 8;          // MI355X: 8 accelerator dies, each with its own L2
-constexpr int kMaxBucket = 1024;  // ids per tile bucket at most (the raster sorts up to this many)
+constexpr int kMinTile = 256;     // pixels per tile: a power of two in [kMinTile, kMaxTile]
+constexpr int kMaxTile = 1024;
 constexpr int kMaxHabits = 64;    // polyhedral habits per context
 constexpr int kMaxFaces = 32;     // faces per habit
 
@@ -28,12 +29,16 @@ constexpr int kMaxFaces = 32;     // faces per habit
 //             f[20..23] footprint bounds xmin, xmax, ymin, ymax in canvas pixels
 //             f[24..27] half-plane filter constants (p+q)/2, (p-q)/2, 1/p, 1/(2pq)
 //                       with p = max(|cos|,|sin|), q = min (1/(2pq) kept finite)
-//             f[28..31] the bounds widened by half a pixel (xmin-1/2, xmax+1/2, ...)
+//             f[28..31] candidate pixels (int bits): columns [jlo, jhi], rows [ilo, ihi] whose
+//                       pixel square meets the bounds (not clamped to the canvas)
 //   ellipsoid f[8] 1/a f[9] 1/b f[10..11] cos as double f[12..13] sin as double
 //             f[14] dn f[15] h     (the FP64 rim refinement uses these)
 //             f[16], f[17] half extents of the bounding box, enlarged (see ellipse_extent)
+//             f[28..31] candidate pixels (int bits): columns [jlo, jhi], rows [ilo, ihi] whose
+//                       centre lies inside the enlarged box (every other centre has q >= 1.002)
 //   habit     (kind 2) as the ellipsoid in f[8..15]; f[16] = f[17] = max(a, b) R
-//             (enlarged) bounds the solid's distance from the centre; f[18] habit index
+//             (enlarged) bounds the solid's distance from the centre; f[18] habit index;
+//             f[28..31] candidate pixels as for the ellipsoid
 struct __align__(16) PRec {
   float f[32];
 };
@@ -47,7 +52,8 @@ struct FramePlan {
   int pup_lo, pup_n, otf_lo, otf_n;
   int rb;                // rows per band block of the blocked spectrum layout
   int fft_radix;         // FFT plan: largest Stockham radix (8 or 4)
-  int64_t n, ld, cap;    // particles, leading dimension, ids per tile bucket
+  int64_t n, ld;         // particles, leading dimension
+  int64_t pair_cap;      // entries of the pair list (pairs beyond it are not stored)
   // optics in the precision the kernels use
   int mode;
   float phase_k;         // 2 pi / lambda  [rad/um]
@@ -78,10 +84,11 @@ struct FrameBufs {
   PRec* recs;
   int4* boxes;
   int* counts;            // pairs per particle
-  int* scal;              // [1] tiles whose bucket overflowed, [3] total pairs (inspection)
-  int* tile_count;        // n_tiles: pairs per tile
-  int* tile_first;        // n_tiles: inspection only, prefix of the tile counts
-  int* pids;              // n_tiles x bucket: particle ids per tile
+  int* scal;              // [1] tiles rasterised by the id-ordered scan, [3] total pairs
+  int* tile_count;        // n_tiles: pairs per tile (histogram)
+  int* tile_start;        // n_tiles + 1: exclusive prefix of the tile counts
+  int* cursor;            // n_tiles: next free entry of each tile's segment (emit)
+  int* pids;              // pair_cap: particle ids, grouped by tile (segments at tile_start)
   float* opd;             // H*W (used when the caller passes no opd_out)
   float* tau;             // H*W absorbance (absorbing frames without opd_out)
   float2* absr;           // n: (dmu * height, dmu) per particle (absorbing frames)
@@ -97,7 +104,10 @@ struct FrameBufs {
 };
 
 size_t frame_workspace_bytes(int H, int W, int64_t n, int tile_h, int tile_w, int ppp, bool backward);
-FrameBufs carve(void* ws, int H, int W, int64_t n, int tile_h, int tile_w, int ppp, bool backward, int64_t* cap_out);
+FrameBufs carve(void* ws, int H, int W, int64_t n, int tile_h, int tile_w, int ppp, bool backward,
+                int64_t* pair_cap_out);
+// entries of the pair list: ppp pairs per particle plus one per tile
+int64_t pair_capacity(int64_t n, int n_tiles, int ppp);
 
 // launchers (return hipError_t of the last launch)
 hipError_t launch_binning(const FramePlan& p, const float* soa, FrameBufs& b, hipStream_t s);
@@ -151,7 +161,7 @@ size_t conv3x3_workspace_bytes(int mode, int B, int Hi, int Wi, int Ci, int Co, 
 struct Profiler;
 // host helpers shared by the entry points (api.cpp)
 FramePlan make_plan(const osog_context* ctx, int H, int W, int64_t n, int64_t ld, const osog_optics& o,
-                    int64_t cap);
+                    int64_t pair_cap);
 hipError_t forward_frame(const osog_context* ctx, const FramePlan& p, const float* soa,
                          const float* globals, FrameBufs& b, float* opd_out, float* intensity,
                          hipStream_t s, bool profile);

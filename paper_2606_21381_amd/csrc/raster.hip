@@ -1,15 +1,14 @@
-// OPD rasterisation (step F5): one 64-lane wave per tile, four pixels per lane.
-// Absorbing frames also build the absorbance canvas tau = sum of dmu * thickness
-// from the same coverage values, in the same order (the Beer-Lambert exponent of
-// Eq. 4).
-// Every pixel adds dn * thickness of each of its tile's particles in ascending
-// particle id (the wave sorts its tile's ids first), so the sum order -- and the
-// canvas, bit for bit -- does not depend on the tiling, the launch order or the GPU.  This replaces the
-// paper's atomic scatter-add (Sec. III.C, Eq. 7) by a gather over the sorted
-// pair list.  The particle id and its 128-byte record are wave-uniform and are
-// read through the scalar cache; each 64-pixel slot first tests the particle
-// against its own pixel rectangle (skip / full coverage), and both shortcuts
-// return exactly what the per-pixel code would.  Body: raster_tile (stages.h).
+// OPD rasterisation (step F5): one 64-lane wave per tile, the tile's pixel sums
+// in LDS.  Absorbing frames also build the absorbance canvas tau = sum of
+// dmu * thickness from the same coverage values, in the same order (the
+// Beer-Lambert exponent of Eq. 4).
+// Each particle of the tile, in ascending id, deals the candidate pixels of its
+// record that lie in the tile to the lanes, 64 at a time; the costly pixels (two
+// prism edges, ellipse rim, habit face) are queued and evaluated 64 at a time.
+// Every pixel's value depends only on the pixel and the particles that reach it,
+// so the canvas is bitwise the same under every tiling, launch order and GPU.
+// This replaces the paper's atomic scatter-add (Sec. III.C, Eq. 7) by a gather
+// over the tile-sorted pair list.  Body: raster_tile (stages.h).
 #include <hip/hip_runtime.h>
 
 #include "osog_internal.h"
@@ -24,9 +23,9 @@ namespace osog {
 // kernel, so frames without them keep the smaller register footprint).
 template <bool ABS, bool HAB>
 __global__ void __launch_bounds__(64) k_raster(FrameDev F, int per_xcd) {
-  __shared__ int seg[kSegSort];
+  extern __shared__ char lds_raster[];
   const int tile = (int)(blockIdx.x % kXcds) * per_xcd + (int)(blockIdx.x / kXcds);
-  if (tile < F.n_tiles) raster_tile<ABS, HAB>(F, tile, threadIdx.x, seg);
+  if (tile < F.n_tiles) raster_tile<ABS, HAB>(F, tile, threadIdx.x, lds_raster);
 }
 
 hipError_t launch_raster(const FramePlan& p, FrameBufs& b, float* opd, float* tau, hipStream_t s) {
@@ -35,12 +34,14 @@ hipError_t launch_raster(const FramePlan& p, FrameBufs& b, float* opd, float* ta
   F.tau = tau;
   const int per = (p.n_tiles + kXcds - 1) / kXcds;
   const dim3 g(per * kXcds), wg(64);
+  const int area = p.tile_h * p.tile_w;
+  const size_t lds = (size_t)raster_lds_bytes(area, p.absorb != 0);
   if (p.n_habits > 0) {
-    if (p.absorb) hipLaunchKernelGGL((k_raster<true, true>), g, wg, 0, s, F, per);
-    else hipLaunchKernelGGL((k_raster<false, true>), g, wg, 0, s, F, per);
+    if (p.absorb) hipLaunchKernelGGL((k_raster<true, true>), g, wg, lds, s, F, per);
+    else hipLaunchKernelGGL((k_raster<false, true>), g, wg, lds, s, F, per);
   } else {
-    if (p.absorb) hipLaunchKernelGGL((k_raster<true, false>), g, wg, 0, s, F, per);
-    else hipLaunchKernelGGL((k_raster<false, false>), g, wg, 0, s, F, per);
+    if (p.absorb) hipLaunchKernelGGL((k_raster<true, false>), g, wg, lds, s, F, per);
+    else hipLaunchKernelGGL((k_raster<false, false>), g, wg, lds, s, F, per);
   }
   return hipGetLastError();
 }

@@ -21,7 +21,8 @@ namespace osog {
 struct FrameDev {
   int H, W, logH, logW, tile_h, tile_w, ntx, n_tiles;
   int fft_radix;                   // FFT plan: largest Stockham radix (8 or 4)
-  int64_t n, ld, cap;              // cap: ids per tile bucket
+  int64_t n, ld;
+  int64_t pair_cap;                // entries of the pair list
   OpticsArgs o;
   float phase_k;
   const float* soa;
@@ -39,10 +40,11 @@ struct FrameDev {
   PRec* recs;
   int4* boxes;
   int* counts;                     // pairs per particle
-  int* scal;                       // [1] tiles whose bucket overflowed, [3] total pairs (inspection)
-  int* tile_count;                 // pairs per tile (the fill cursor; may exceed the bucket)
-  int* tile_first;                 // inspection only: exclusive prefix of the tile counts
-  int* pids;                       // n_tiles buckets of `cap` particle ids
+  int* scal;                       // [1] tiles rasterised by the id-ordered scan, [3] total pairs
+  int* tile_count;                 // pairs per tile (histogram)
+  int* tile_start;                 // n_tiles + 1: first pair of each tile's segment
+  int* cursor;                     // next free entry of each segment (emit)
+  int* pids;                       // the pair list: particle ids grouped by tile
   float2* band;
   double* colsum;
   // pass 2 reads its columns from band_in, whose in-band range is [in_kx_lo, in_kx_lo + in_kx_n)
@@ -51,20 +53,13 @@ struct FrameDev {
   int in_kx_lo, in_kx_n;
 };
 
-// ---- F1-F3: records, pixel boxes, pairs per particle; tile buckets -----------
-// A one-digit counting sort on the tile key with fixed-size buckets: every pair
-// (tile, particle) takes the next slot of its tile's bucket through an atomic
-// cursor.  The counters must be zero on entry (k_bin_clear); they end as the
-// tiles' true pair counts, which may exceed the bucket (the reader then falls
-// back to an id-ordered scan for that tile, and scal[1] counts such tiles).  The
-// order of ids inside a bucket is restored by the reader, which sorts it.
+// ---- F1: records, pixel boxes, pairs per particle, tile histogram ----------------
 // A group of kBinGroup lanes shares one particle: its first lane writes the
-// record, box and count, and the group deals the particle's tiles round robin,
-// each lane issuing up to kFillBatch cursor increments before their results are
-// used (a particle meets ~5 tiles on average, so most lanes wait on one
-// increment instead of one lane on all of them).
+// record, box and pair count, and the group deals the particle's tiles round
+// robin, each lane adding one to the count of its tiles (integer atomics: the
+// histogram does not depend on their order).  The histogram must be zero on
+// entry (k_bin_clear).
 constexpr int kBinGroup = 8;
-constexpr int kFillBatch = 4;
 
 __device__ __forceinline__ void bin_body(const FrameDev& F, int64_t gid) {
   const int64_t p = gid / kBinGroup;
@@ -72,9 +67,8 @@ __device__ __forceinline__ void bin_body(const FrameDev& F, int64_t gid) {
   if (p >= F.n) return;
   const float* soa = F.soa;
   const int64_t ld = F.ld;
-  const float cx = soa[0 * ld + p], cy = soa[1 * ld + p], ang = soa[2 * ld + p];
-  const float a = soa[3 * ld + p], b = soa[4 * ld + p], h = soa[5 * ld + p];
-  const float dn = soa[6 * ld + p], shape = soa[7 * ld + p];
+  const float cx = soa[0 * ld + p], cy = soa[1 * ld + p];
+  const float a = soa[3 * ld + p], b = soa[4 * ld + p], shape = soa[7 * ld + p];
   int4 box;
   float R = 0.0f, habit = -1.0f;  // a polyhedral habit's bounding radius and index
   if (shape >= 1.5f) {
@@ -85,18 +79,22 @@ __device__ __forceinline__ void bin_body(const FrameDev& F, int64_t gid) {
     }
   }
   const bool ok = pixel_box(cx, cy, a, b, shape, R, F.H, F.W, &box);
-  int cnt = 0;
+  int tx0 = 0, ty0 = 0, nx = 0, cnt = 0;
   if (ok) {
-    const int tx0 = box.x / F.tile_w, tx1 = box.y / F.tile_w, ty0 = box.z / F.tile_h, ty1 = box.w / F.tile_h;
-    cnt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+    tx0 = box.x / F.tile_w;
+    ty0 = box.z / F.tile_h;
+    nx = box.y / F.tile_w - tx0 + 1;
+    cnt = nx * (box.w / F.tile_h - ty0 + 1);
   }
+  for (int e = sub; e < cnt; e += kBinGroup) atomicAdd(&F.tile_count[(ty0 + e / nx) * F.ntx + tx0 + e % nx], 1);
   if (sub == 0) {
+    const float ang = soa[2 * ld + p], h = soa[5 * ld + p], dn = soa[6 * ld + p];
     PRec r;
-#pragma unroll
-    for (int k = 0; k < 32; ++k) r.f[k] = 0.0f;
     if (ok) {
       make_record(cx, cy, ang, a, b, h, dn, shape, R, habit, &r);
     } else {
+#pragma unroll
+      for (int k = 0; k < 32; ++k) r.f[k] = 0.0f;
       r.f[3] = -1.0f;
       box = make_int4(1, 0, 1, 0);
     }
@@ -108,75 +106,132 @@ __device__ __forceinline__ void bin_body(const FrameDev& F, int64_t gid) {
     }
     F.counts[p] = cnt;
   }
-  if (ok) {
-    const int tx0 = box.x / F.tile_w, tx1 = box.y / F.tile_w, ty0 = box.z / F.tile_h, ty1 = box.w / F.tile_h;
-    const int nx = tx1 - tx0 + 1;
-    const int cap = (int)F.cap;
-    for (int e0 = sub; e0 < cnt; e0 += kBinGroup * kFillBatch) {
-      int key[kFillBatch], pos[kFillBatch];
-#pragma unroll
-      for (int u = 0; u < kFillBatch; ++u) {
-        const int e = e0 + u * kBinGroup;
-        key[u] = e < cnt ? (ty0 + e / nx) * F.ntx + tx0 + e % nx : -1;
-        pos[u] = key[u] >= 0 ? atomicAdd(&F.tile_count[key[u]], 1) : 0;
-      }
-#pragma unroll
-      for (int u = 0; u < kFillBatch; ++u) {
-        if (key[u] < 0) continue;
-        if (pos[u] < cap) F.pids[(int64_t)key[u] * cap + pos[u]] = (int)p;
-        else if (pos[u] == cap) atomicAdd(&F.scal[1], 1);
-      }
-    }
-  }
 }
 
-// ---- inspection: exclusive prefix of the tile counts (one workgroup) -----------
-// tile_first = prefix of the true counts; total pairs -> scal[3].  The counts
-// pass through LDS in chunks of kScanChunk, read and written coalesced.
+// ---- F2: exclusive prefix of the tile histogram (one workgroup) -----------------
+// tile_start[t] = pairs of tiles 0..t-1, tile_start[n_tiles] = all pairs (also
+// scal[3]), and the emit cursors start at tile_start.  The counts pass through LDS
+// in chunks of kScanChunk, read and written coalesced; each thread sums
+// kScanChunk / kScanThreads consecutive counts, the threads' sums are scanned
+// across the wave with shuffles and across the waves in LDS.  Integer sums: the
+// result is exact in any order.
 constexpr int kScanThreads = 1024;
-constexpr int kScanChunk = 8192;
+constexpr int kScanPer = 16;                         // counts per thread and chunk
+constexpr int kScanChunk = kScanThreads * kScanPer;  // 16384 tiles per pass
 
-__device__ __forceinline__ void tile_scan_body(const FrameDev& F, long long* buf, long long* part) {
-  const int t = threadIdx.x;
+__device__ __forceinline__ long long wave_incl_scan(long long v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const long long u = __shfl_up(v, o, 64);
+    if (lane >= o) v += u;
+  }
+  return v;
+}
+
+// Each thread holds kScanPer consecutive counts in registers (read as int4), so a
+// chunk costs one round trip to memory.  wsum: 2 * kScanThreads / 64 + 1 long longs of LDS.
+__device__ __forceinline__ void tile_scan_body(const FrameDev& F, long long* wsum) {
+  constexpr int NW = kScanThreads / 64;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int nt = F.n_tiles;
   long long carry = 0;
   for (int c0 = 0; c0 < nt; c0 += kScanChunk) {
-    const int cn = min(kScanChunk, nt - c0);
-    for (int i = t; i < cn; i += kScanThreads) buf[i] = F.tile_count[c0 + i];
-    __syncthreads();
-    const int per = (cn + kScanThreads - 1) / kScanThreads;
-    const int b0 = min(cn, t * per), b1 = min(cn, b0 + per);
+    const int i0 = c0 + t * kScanPer;
+    int loc[kScanPer];
+    if (i0 + kScanPer <= nt) {  // n_tiles and c0 are multiples of 16 except on tiny canvases
+      const int4* src = reinterpret_cast<const int4*>(F.tile_count + i0);
+#pragma unroll
+      for (int q = 0; q < kScanPer / 4; ++q) {
+        const int4 v = src[q];
+        loc[4 * q] = v.x; loc[4 * q + 1] = v.y; loc[4 * q + 2] = v.z; loc[4 * q + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kScanPer; ++k) loc[k] = i0 + k < nt ? F.tile_count[i0 + k] : 0;
+    }
     long long s = 0;
-    for (int k = b0; k < b1; ++k) s += buf[k];
-    part[t] = s;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) s += loc[k];
+    const long long incl = wave_incl_scan(s, lane);
+    if (lane == 63) wsum[wv] = incl;
     __syncthreads();
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-      const long long v = t >= off ? part[t - off] : 0;
-      __syncthreads();
-      part[t] += v;
-      __syncthreads();
+    if (wv == 0) {
+      const long long w = lane < NW ? wsum[lane] : 0;
+      const long long wi = wave_incl_scan(w, lane);
+      if (lane < NW) wsum[NW + lane] = wi - w;  // exclusive per wave
+      if (lane == NW - 1) wsum[2 * NW] = wi;    // chunk total
     }
-    long long run = carry + part[t] - s;
-    for (int k = b0; k < b1; ++k) {
-      const long long c = buf[k];
-      buf[k] = run;
-      run += c;
+    __syncthreads();
+    long long run = carry + wsum[NW + wv] + incl - s;
+    carry += wsum[2 * NW];
+    int out[kScanPer];
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      out[k] = run < INT_MAX ? (int)run : INT_MAX;
+      run += loc[k];
     }
-    const long long chunk_total = part[kScanThreads - 1];
-    __syncthreads();
-    for (int i = t; i < cn; i += kScanThreads) F.tile_first[c0 + i] = (int)(buf[i] < INT_MAX ? buf[i] : INT_MAX);
-    carry += chunk_total;
-    __syncthreads();
+    if (i0 + kScanPer <= nt) {
+      int4* d0 = reinterpret_cast<int4*>(F.tile_start + i0);  // tile_start is 16-byte aligned
+      int4* d1 = reinterpret_cast<int4*>(F.cursor + i0);
+#pragma unroll
+      for (int q = 0; q < kScanPer / 4; ++q) {
+        const int4 v = make_int4(out[4 * q], out[4 * q + 1], out[4 * q + 2], out[4 * q + 3]);
+        d0[q] = v;
+        d1[q] = v;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kScanPer; ++k)
+        if (i0 + k < nt) {
+          F.tile_start[i0 + k] = out[k];
+          F.cursor[i0 + k] = out[k];
+        }
+    }
+    __syncthreads();  // wsum is rewritten by the next chunk
   }
-  if (t == 0) F.scal[3] = carry < INT_MAX ? (int)carry : INT_MAX;
+  if (t == 0) {
+    const int tot = carry < INT_MAX ? (int)carry : INT_MAX;
+    F.tile_start[nt] = tot;
+    F.scal[3] = tot;
+  }
 }
 
-// ---- F4: a tile's particle ids in ascending order, for one 64-lane wave -------
-// The fill leaves each tile's ids in arbitrary order.  Up to 64 ids are sorted
-// in registers (bitonic network over the lanes); up to kSegSort in LDS; a
-// longer list is not materialised: the caller visits all particles in id order
-// and keeps those whose box meets the tile (the same ids, the same order).
-constexpr int kSegSort = kMaxBucket;
+// ---- F3: emit each pair into its tile's segment -----------------------------------
+// A group of kBinGroup lanes shares one particle and deals its tiles round robin;
+// every pair takes the next entry of its tile's segment through the tile's
+// cursor.  The order inside a segment depends on the atomics; the reader restores
+// ascending id.  Pairs past the list's capacity are not stored (their tiles are
+// rasterised by the id-ordered scan instead).
+constexpr int kFillBatch = 4;
+
+__device__ __forceinline__ void emit_body(const FrameDev& F, int64_t gid) {
+  const int64_t p = gid / kBinGroup;
+  const int sub = (int)(gid - p * kBinGroup);
+  if (p >= F.n) return;
+  const int4 box = F.boxes[p];
+  if (box.x > box.y) return;
+  const int tx0 = box.x / F.tile_w, tx1 = box.y / F.tile_w, ty0 = box.z / F.tile_h, ty1 = box.w / F.tile_h;
+  const int nx = tx1 - tx0 + 1, cnt = nx * (ty1 - ty0 + 1);
+  for (int e0 = sub; e0 < cnt; e0 += kBinGroup * kFillBatch) {
+    int pos[kFillBatch];
+#pragma unroll
+    for (int u = 0; u < kFillBatch; ++u) {
+      const int e = e0 + u * kBinGroup;
+      const int key = e < cnt ? (ty0 + e / nx) * F.ntx + tx0 + e % nx : -1;
+      pos[u] = key >= 0 ? atomicAdd(&F.cursor[key], 1) : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kFillBatch; ++u)
+      if (pos[u] >= 0 && pos[u] < F.pair_cap) F.pids[pos[u]] = (int)p;
+  }
+}
+
+// ---- F4: a segment's particle ids in ascending order, for one 64-lane wave ------
+// Up to 64 ids are sorted in registers (bitonic network over the lanes), up to
+// kSegSort in LDS.  A longer segment, or one cut short by the list's capacity, is
+// not sorted: the reader visits all particles in id order and keeps those whose
+// box meets the tile (the same ids in the same order).
+constexpr int kSegSort = 512;
 
 __device__ __forceinline__ int wave_sort64(int v, int lane) {
 #pragma unroll
@@ -208,22 +263,116 @@ __device__ __forceinline__ void lds_sort(int* seg, int n2, int lane) {
     }
 }
 
+// Does particle p's box meet the tile [x0, x1] x [y0, y1]?
+__device__ __forceinline__ bool box_meets(const FrameDev& F, int64_t p, int x0, int x1, int y0, int y1) {
+  const int4 b = F.boxes[p];
+  return !(b.x > b.y || b.x > x1 || b.y < x0 || b.z > y1 || b.w < y0);
+}
+
+// Visits the ids of tile `tile` in ascending order, up to 64 at a time: visit(ids
+// held by the lanes, count).  `seg`: kSegSort ints of LDS.  Returns true when the
+// segment was read by the id-ordered scan.  (It writes no global memory, so the
+// records it reads stay provably unclobbered and load through the scalar cache.)
+template <class Visit>
+__device__ __forceinline__ bool for_tile_ids(const FrameDev& F, int tile, int lane, int* seg, Visit&& visit) {
+  const int start = F.tile_start[tile], end = F.tile_start[tile + 1];
+  const int cnt = end - start;
+  const bool stored = end <= F.pair_cap;
+  const int* __restrict__ pids = F.pids + start;
+  if (stored && cnt <= 64) {
+    if (cnt > 0) visit(wave_sort64(lane < cnt ? pids[lane] : INT_MAX, lane), cnt);
+  } else if (stored && cnt <= kSegSort) {
+    int n2 = 128;
+    while (n2 < cnt) n2 <<= 1;
+    for (int i = lane; i < n2; i += 64) seg[i] = i < cnt ? pids[i] : INT_MAX;
+    __syncthreads();
+    lds_sort(seg, n2, lane);
+    for (int c0 = 0; c0 < cnt; c0 += 64) {
+      const int m = min(64, cnt - c0);
+      visit(lane < m ? seg[c0 + lane] : 0, m);
+    }
+  } else {
+    const int ty = tile / F.ntx, tx = tile - ty * F.ntx;
+    const int x0 = tx * F.tile_w, x1 = x0 + F.tile_w - 1, y0 = ty * F.tile_h, y1 = y0 + F.tile_h - 1;
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    for (int64_t p0 = 0; p0 < F.n; p0 += 64) {
+      const int64_t p = p0 + lane;
+      const bool hit = p < F.n && box_meets(F, p, x0, x1, y0, y1);
+      const uint64_t m = __ballot(hit);
+      if (!m) continue;
+      // compact the hits into the low lanes, keeping their order
+      if (hit) seg[__popcll(m & below)] = (int)p;
+      __syncthreads();
+      const int c = __popcll(m);
+      const int mine = lane < c ? seg[lane] : 0;
+      __syncthreads();
+      visit(mine, c);
+    }
+    return true;
+  }
+  return false;
+}
+
 // ---- F5: rasterise one tile with one 64-lane wave ------------------------------
-struct SubRect {
-  float x0, x1, y0, y1;  // pixel-edge bounds of the 64 pixels one lane slot covers
+// The tile's pixel sums live in LDS.  Each particle of the tile, in ascending id,
+// deals its candidate pixels (the pixels of its record's candidate rectangle that
+// lie in the tile) to the 64 lanes, 64 at a time; each lane evaluates its pixel
+// without branching for the common cases -- outside, inside, one edge (the
+// half-plane box filter) for a prism; the centre sample for an ellipsoid; the
+// vertical chord for a habit -- and adds dn * thickness to the pixel's LDS sum.  A
+// particle's candidates are distinct pixels and its adds complete before the next
+// particle's, so every pixel sums its terms in ascending particle id.
+// The costly pixels -- a prism pixel two edges reach (the clipped-polygon area),
+// an ellipsoid pixel within 2e-3 of the rim and a habit pixel next to a vertical
+// face (both FP64) -- are queued as (pixel, particle) in particle order and
+// evaluated 64 at a time with every lane busy; their terms go to a second LDS sum
+// per pixel, again in ascending particle id.  The canvas value is the first sum
+// plus the second: a function of the pixel and of the particles that reach it
+// alone, so it is bitwise the same under every tiling.
+// The offset of a pixel centre from the particle centre is exact in FP32 (both
+// are multiples of the centre's ulp and the difference is small), so the rotated
+// offsets u, v carry ~1e-6 px of rounding and depend on the pixel and the
+// particle alone.  ABS: the same coverage (prism) or centre thickness (ellipsoid,
+// habit) also adds dmu * height times it (or dmu times the habit thickness) to
+// the absorbance sums; ab = (dmu * height, dmu) of the particle.
+constexpr int kQueue = 128;  // queued costly pixels per wave: 64 plus one batch of appends
+
+// LDS of one raster wave, for a tile of `area` pixels (layout of raster_lds_bytes)
+struct RasterLds {
+  float* acc;   // [area] terms in ascending particle id
+  float* cacc;  // [area] costly terms in ascending particle id
+  float* tacc;  // [area] absorbance (ABS)
+  float* ctacc; // [area]
+  int* qpix;    // [kQueue] tile pixel index of a queued pixel
+  int* qpid;    // [kQueue] its particle
+  int* seg;     // [kSegSort] a long segment's ids
 };
 
-__device__ __forceinline__ SubRect slot_rect(int first, int tile_w, int tx, int ty, int tile_h) {
-  const int w0 = first, w1 = first + 63;
-  int r0 = w0 / tile_w, r1 = w1 / tile_w, c0 = 0, c1 = tile_w - 1;
-  if (tile_w > 64) { c0 = w0 % tile_w; c1 = w1 % tile_w; }
-  SubRect R;
-  R.x0 = (float)(tx * tile_w + c0);
-  R.x1 = (float)(tx * tile_w + c1 + 1);
-  R.y0 = (float)(ty * tile_h + r0);
-  R.y1 = (float)(ty * tile_h + r1 + 1);
-  return R;
+__host__ __device__ constexpr int raster_lds_bytes(int area, bool abs) {
+  return 4 * area * (abs ? 4 : 2) + 8 * kQueue + 4 * kSegSort;
 }
+
+__device__ __forceinline__ RasterLds raster_lds(char* base, int area, bool abs) {
+  RasterLds L;
+  float* f = reinterpret_cast<float*>(base);
+  L.acc = f;
+  L.cacc = f + area;
+  L.tacc = f + 2 * area;
+  L.ctacc = f + 3 * area;
+  int* q = reinterpret_cast<int*>(f + area * (abs ? 4 : 2));
+  L.qpix = q;
+  L.qpid = q + kQueue;
+  L.seg = q + 2 * kQueue;
+  return L;
+}
+
+struct TileGeom {
+  int X0, Y0, tw, th;  // tile origin (canvas pixels) and sides
+  const float4* hab_enc;
+  const float4* hab_raw;
+  const float4* hab_info;
+  uint32_t topo_lo, topo_hi;
+};
 
 // A select the compiler keeps as v_cndmask (both operands already computed)
 // rather than turning into a divergent branch.
@@ -231,80 +380,148 @@ __device__ __forceinline__ float sel(bool c, float x, float y) {
   return __builtin_unpredictable(c) ? x : y;
 }
 
-struct TileAcc {
-  int pi[4], pj[4];          // canvas row and column of the lane's pixel in each slot
-  float px[4], py[4];        // that pixel's centre, j + 1/2 and i + 1/2
-  // every lane also holds the bounds of slot (lane & 3), so that the four
-  // wave-uniform slot tests of a particle run as one vector instruction each
-  float sx0, sx1, sy0, sy1;  // pixel-edge bounds of that slot (canvas pixels)
-  float scx, scy, shx, shy;  // centre of its pixel centres, half extents
-  float acc[4];
-  float tacc[4];             // absorbance sums (absorbing frames)
-  const float4* hab_enc;     // polyhedral habits of the frame
-  const float4* hab_raw;
-  const float4* hab_info;
-  uint32_t topo_lo, topo_hi;
-};
+// A load through the scalar cache of a value that no work of the running kernel
+// writes (the address space of kernel-constant memory; the address is the same).
+__device__ __forceinline__ PRec const_load(const PRec* p) {
+  typedef const __attribute__((address_space(4))) float cfloat;
+  cfloat* q = (cfloat*)(p->f);
+  PRec r;
+#pragma unroll
+  for (int k = 0; k < 32; ++k) r.f[k] = q[k];
+  return r;
+}
 
-// Adds one particle to the four pixel slots a lane owns.  The slot tests (does
-// the particle reach the slot; is every pixel centre of the slot deep inside a
-// prism) are evaluated for the four slots at once, one slot per lane, and read
-// back as wave-uniform bit masks: a slot the particle misses is skipped and a
-// slot inside its footprint takes the full amplitude.  In any other slot every
-// lane evaluates its pixel without branching for the common cases -- outside,
-// inside, one edge (the half-plane box filter) for a prism; the centre sample for
-// an ellipsoid -- and only marks the rare costly pixels: a prism pixel two edges
-// reach (the clipped-polygon area) and an ellipsoid pixel within 2e-3 of the rim
-// (FP64).  Those are evaluated after the four slots, each lane serving its own
-// marks, so the costly code runs once per particle rather than once per slot.
-// The offset of a pixel centre from the particle centre is exact in FP32 (both
-// are multiples of the centre's ulp and the difference is small), so the rotated
-// offsets u, v carry ~1e-6 px of rounding and depend on the pixel and the
-// particle alone: the canvas is bitwise the same under every tiling.  Every
-// pixel receives exactly one term per particle, in particle order.  ABS: the same
-// coverage (prism) or centre thickness (ellipsoid) also adds dmu * height times it
-// to the absorbance sums; ab = (dmu * height, dmu) of the particle.
+__device__ __forceinline__ void lds_add(float* p, float v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Evaluates the first `count` queued costly pixels, one per lane, and adds their
+// terms to the costly sums in queue (= particle) order: the entries are sorted by
+// (pixel, queue position) and added in rounds, round r adding the r-th term of
+// every pixel, so a pixel queued twice in one batch still sums in particle order.
 template <bool ABS, bool HAB>
-__device__ __forceinline__ void add_particle(const PRec& r, TileAcc& T, float2 ab) {
+__device__ __forceinline__ void flush_costly(const FrameDev& F, const TileGeom& G, const RasterLds& L, int count,
+                                          int lane) {
 #pragma clang fp contract(off)
+  const bool valid = lane < count;
+  const int pix = valid ? L.qpix[lane] : 0;
+  const int pid = valid ? L.qpid[lane] : 0;
+  float val = 0.0f, tval = 0.0f;
+  if (valid) {
+    const PRec& r = F.recs[pid];
+    const int ii = G.Y0 + pix / G.tw, jj = G.X0 + pix % G.tw;
+    const float kind = r.f[3];
+    if (kind == 0.0f) {
+      const float area = prism_clip_area(r, ii, jj);
+      val = r.f[2] * area;
+      if (ABS) tval = F.absr[pid].x * area;
+    } else if (kind == 1.0f) {
+      // h sqrt(1 - q) in FP64 with q recomputed in FP64, times dn (and dmu)
+      const double qq = ellipsoid_rim_q(r, ii, jj);
+      const double sq = qq < 1.0 ? sqrt(1.0 - qq) : 0.0;
+      val = (float)((double)r.f[14] * (double)r.f[15] * sq);
+      if (ABS) tval = (float)((double)F.absr[pid].y * (double)r.f[15] * sq);
+    } else if (HAB) {
+      const int k = (int)r.f[18];
+      const float4 info = G.hab_info[k];
+      const float tamp = info.z, inv_cell = 1.0f / info.w;
+      double t = (double)r.f[15] * habit_chord64(r, G.hab_raw + k * kMaxFaces, (int)info.x, ii, jj);
+      if (tamp > 0.0f && t > 0.0)
+        t = fmax(t + (double)tamp * (double)value_noise((float)jj + 0.5f, (float)ii + 0.5f, inv_cell, (uint32_t)k,
+                                                        G.topo_lo, G.topo_hi), 0.0);
+      val = (float)((double)r.f[14] * t);
+      if (ABS) tval = (float)((double)F.absr[pid].y * t);
+    }
+  }
+  const int key = valid ? (pix << 6) | lane : INT_MAX;
+  const int sk = wave_sort64(key, lane);
+  const bool sv = sk != INT_MAX;
+  const int src = sk & 63, spix = sk >> 6;
+  const float sval = __shfl(val, src, 64);
+  const float stval = ABS ? __shfl(tval, src, 64) : 0.0f;
+  const int prev = __shfl_up(spix, 1, 64);
+  const bool first = sv && (lane == 0 || prev != spix);
+  const uint64_t fm = __ballot(first);
+  const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  const uint64_t mine = fm & upto;
+  const int rank = mine ? lane - (63 - __clzll((long long)mine)) : 0;
+  for (int rd = 0;; ++rd) {
+    const bool act = sv && rank == rd;
+    if (!__ballot(act)) break;
+    if (act) {  // distinct pixels within a round
+      L.cacc[spix] += sval;
+      if (ABS) L.ctacc[spix] += stval;
+    }
+    __syncthreads();
+  }
+}
+
+// Appends the lanes' costly pixels to the queue (qn entries held, wave-uniform);
+// evaluates a full batch of 64 when the queue holds at least that many.
+template <bool ABS, bool HAB>
+__device__ __forceinline__ void queue_costly(const FrameDev& F, const TileGeom& G, const RasterLds& L, bool costly,
+                                             int pix, int pid, int lane, int& qn) {
+  const uint64_t cm = __ballot(costly);
+  if (!cm) return;
+  if (costly) {
+    const int slot = qn + __builtin_amdgcn_mbcnt_hi((uint32_t)(cm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)cm, 0u));
+    L.qpix[slot] = pix;
+    L.qpid[slot] = pid;
+  }
+  qn += __popcll(cm);
+  if (qn >= 64) {
+    __syncthreads();
+    flush_costly<ABS, HAB>(F, G, L, 64, lane);
+    // keep the rest (fewer than 64) at the head of the queue
+    const int rest = qn - 64;
+    const int mp = lane < rest ? L.qpix[64 + lane] : 0, md = lane < rest ? L.qpid[64 + lane] : 0;
+    __syncthreads();
+    if (lane < rest) {
+      L.qpix[lane] = mp;
+      L.qpid[lane] = md;
+    }
+    __syncthreads();
+    qn = rest;
+  }
+}
+
+// Adds particle `pid` (record r, uniform) to the tile sums.
+template <bool ABS, bool HAB>
+__device__ __forceinline__ void raster_particle(const FrameDev& F, const TileGeom& G, const RasterLds& L,
+                                                const PRec& r, int pid, int lane, int& qn) {
+#pragma clang fp contract(off)
+  const int jlo = max(__float_as_int(r.f[28]), G.X0), jhi = min(__float_as_int(r.f[29]), G.X0 + G.tw - 1);
+  const int ilo = max(__float_as_int(r.f[30]), G.Y0), ihi = min(__float_as_int(r.f[31]), G.Y0 + G.th - 1);
+  if (jlo > jhi || ilo > ihi) return;
+  const int w = jhi - jlo + 1, m = w * (ihi - ilo + 1);
+  const float inv_w = __builtin_amdgcn_rcpf((float)w);  // row = floor((k + 1/2) / w), exact for k < 1024
   const float kind = r.f[3];
-  const float amp = r.f[2];
-  unsigned marks = 0u;
-  const float c = r.f[4], s = r.f[5];
+  const float cx = r.f[0], cy = r.f[1], amp = r.f[2], c = r.f[4], s = r.f[5];
+  const float2 ab = ABS ? F.absr[pid] : make_float2(0.0f, 0.0f);
+  const int lx = jlo - G.X0, ly = ilo - G.Y0;
+  // pixel centre offsets from the particle centre, measured from the particle's
+  // own first candidate (not the tile's): dx = dx0 + (j - cj0) is then a function
+  // of the pixel and the particle alone, whatever the tiling (and exact wherever
+  // the centre's ulp is at least 2^-24 of the offset)
+  const int cj0 = __float_as_int(r.f[28]), ci0 = __float_as_int(r.f[30]);
+  const float dx0 = ((float)cj0 + 0.5f) - cx, dy0 = ((float)ci0 + 0.5f) - cy;
+  const int ox = jlo - cj0, oy = ilo - ci0;
   if (kind == 0.0f) {
     const float a = r.f[6], b = r.f[7];
     // half-plane box filter constants (as in halfplane_cover; (c, s) and (s, c) share them)
     const float hp_h = r.f[24], hp_l = r.f[25], hp_rp = r.f[26], hp_r2 = r.f[27];
     const float hd = hp_h + 1e-4f;  // pixel_half_extent(c, s)
     const bool a_ok = a >= hd, b_ok = b >= hd;  // the pixel cannot reach both edges of a pair
-    unsigned hit_m, in_m;
-    {  // slot (lane & 3): reached at all; every pixel centre deep inside both slabs
-      const bool hit = !((r.f[21] <= T.sx0) | (r.f[20] >= T.sx1) | (r.f[23] <= T.sy0) | (r.f[22] >= T.sy1));
-      const float sdx = T.scx - r.f[0], sdy = T.scy - r.f[1];
-      const float uc = __builtin_fmaf(c, sdx, s * sdy), vc = __builtin_fmaf(c, sdy, -(s * sdx));
-      const float ux = fabsf(uc) + fabsf(c) * T.shx + fabsf(s) * T.shy;
-      const float vy = fabsf(vc) + fabsf(s) * T.shx + fabsf(c) * T.shy;
-      const bool deep = (ux < a - hd) & (vy < b - hd);
-      hit_m = (unsigned)__ballot(hit) & 15u;
-      in_m = (unsigned)__ballot(hit & deep) & 15u;
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (!((hit_m >> q) & 1u)) continue;
-      if ((in_m >> q) & 1u) {
-        T.acc[q] += amp;
-        if (ABS) T.tacc[q] += ab.x;
-        continue;
-      }
-      // straight-line code: every case is a select.  A pixel two edges reach
-      // takes 0 here and its clipped-polygon area below.
-      const bool off_box = (T.px[q] >= r.f[29]) | (T.px[q] <= r.f[28]) | (T.py[q] >= r.f[31]) | (T.py[q] <= r.f[30]);
-      const float dx = T.px[q] - r.f[0], dy = T.py[q] - r.f[1];
+    for (int k0 = 0; k0 < m; k0 += 64) {
+      const int k = k0 + lane;
+      const bool valid = k < m;
+      const int row = (int)(((float)k + 0.5f) * inv_w), col = k - __mul24(row, w);
+      const float dx = dx0 + (float)(ox + col), dy = dy0 + (float)(oy + row);
       const float u = __builtin_fmaf(c, dx, s * dy), v = __builtin_fmaf(c, dy, -(s * dx));
       const float du = fabsf(u) - a, dv = fabsf(v) - b;  // signed distances to the nearer edges
       const bool in_u = du < -hd, in_v = dv < -hd;
       const bool inside = in_u & in_v;
-      const bool outside = off_box | (du > hd) | (dv > hd);
+      const bool outside = (du > hd) | (dv > hd);
       const bool edge_u = in_v & a_ok;
       const bool edge = edge_u | (in_u & b_ok);
       // halfplane_cover(t, .) with t = -du (edge_u) or -dv; beyond the pixel's
@@ -316,214 +533,118 @@ __device__ __forceinline__ void add_particle(const PRec& r, TileAcc& T, float2 a
       const float lin = 0.5f + t * hp_rp;
       float cover = sel(t > 0.0f, 1.0f - tri, tri);
       cover = sel(at <= hp_l, lin, cover);
-      cover = sel(edge, cover, 0.0f);
       cover = sel(inside, 1.0f, cover);
-      cover = sel(outside, 0.0f, cover);
-      T.acc[q] += amp * cover;
-      if (ABS) T.tacc[q] += ab.x * cover;
-      marks |= (unsigned)(!(outside | inside | edge)) << q;
-    }
-    while (marks) {
-      const int q = __builtin_ctz(marks);
-      marks &= marks - 1u;
-      // one call site; selects keep the slot arrays in registers
-      const int ii = q == 0 ? T.pi[0] : (q == 1 ? T.pi[1] : (q == 2 ? T.pi[2] : T.pi[3]));
-      const int jj = q == 0 ? T.pj[0] : (q == 1 ? T.pj[1] : (q == 2 ? T.pj[2] : T.pj[3]));
-      const float area = prism_clip_area(r, ii, jj);
-      const float add = amp * area;
-      if (q == 0) T.acc[0] += add;
-      else if (q == 1) T.acc[1] += add;
-      else if (q == 2) T.acc[2] += add;
-      else T.acc[3] += add;
-      if (ABS) {
-        const float tadd = ab.x * area;
-        if (q == 0) T.tacc[0] += tadd;
-        else if (q == 1) T.tacc[1] += tadd;
-        else if (q == 2) T.tacc[2] += tadd;
-        else T.tacc[3] += tadd;
+      const int pix = __mul24(ly + row, G.tw) + lx + col;
+      if (valid & (inside | (edge & !outside))) {
+        lds_add(L.acc + pix, amp * cover);
+        if (ABS) lds_add(L.tacc + pix, ab.x * cover);
       }
+      queue_costly<ABS, HAB>(F, G, L, valid & !(outside | inside | edge), pix, pid, lane, qn);
     }
   } else if (kind == 1.0f) {
-    // slot (lane & 3) meets the bounding box of the pixel centres the ellipse reaches
-    const bool hit = !((T.sx1 - 0.5f - r.f[0] < -r.f[16]) | (T.sx0 + 0.5f - r.f[0] > r.f[16]) |
-                       (T.sy1 - 0.5f - r.f[1] < -r.f[17]) | (T.sy0 + 0.5f - r.f[1] > r.f[17]));
-    const unsigned hit_m = (unsigned)__ballot(hit) & 15u;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (!((hit_m >> q) & 1u)) continue;
-      const float dx = T.px[q] - r.f[0], dy = T.py[q] - r.f[1];
-      const float u = __builtin_fmaf(c, dx, s * dy) * r.f[8], v = __builtin_fmaf(c, dy, -(s * dx)) * r.f[9];
+    const float ia = r.f[8], ib = r.f[9];
+    for (int k0 = 0; k0 < m; k0 += 64) {
+      const int k = k0 + lane;
+      const bool valid = k < m;
+      const int row = (int)(((float)k + 0.5f) * inv_w), col = k - __mul24(row, w);
+      const float dx = dx0 + (float)(ox + col), dy = dy0 + (float)(oy + row);
+      const float u = __builtin_fmaf(c, dx, s * dy) * ia, v = __builtin_fmaf(c, dy, -(s * dx)) * ib;
       const float qv = u * u + v * v;
-      // outside: 0; within 2e-3 of the rim: 0 here and the FP64 value below
+      // inside: the centre sample; within 2e-3 of the rim: queued for FP64
       const bool rim = (qv > 0.998f) & (qv < 1.002f);
       // 1 - q >= 0.002 where the value is kept, so the hardware square root
       // (within 1 ulp, no denormal scaling needed) serves
-      const float sq = sel(qv <= 0.998f, __builtin_amdgcn_sqrtf(fmaxf(1.0f - qv, 0.0f)), 0.0f);
-      T.acc[q] += amp * sq;
-      if (ABS) T.tacc[q] += ab.x * sq;
-      marks |= (unsigned)rim << q;
-    }
-    while (marks) {
-      const int q = __builtin_ctz(marks);
-      marks &= marks - 1u;
-      const int ii = q == 0 ? T.pi[0] : (q == 1 ? T.pi[1] : (q == 2 ? T.pi[2] : T.pi[3]));
-      const int jj = q == 0 ? T.pj[0] : (q == 1 ? T.pj[1] : (q == 2 ? T.pj[2] : T.pj[3]));
-      // h sqrt(1 - q) in FP64 with q recomputed in FP64, times dn (and dmu)
-      const double qq = ellipsoid_rim_q(r, ii, jj);
-      const double sq = qq < 1.0 ? sqrt(1.0 - qq) : 0.0;
-      const float add = (float)((double)r.f[14] * (double)r.f[15] * sq);
-      if (q == 0) T.acc[0] += add;
-      else if (q == 1) T.acc[1] += add;
-      else if (q == 2) T.acc[2] += add;
-      else T.acc[3] += add;
-      if (ABS) {
-        const float tadd = (float)((double)ab.y * (double)r.f[15] * sq);
-        if (q == 0) T.tacc[0] += tadd;
-        else if (q == 1) T.tacc[1] += tadd;
-        else if (q == 2) T.tacc[2] += tadd;
-        else T.tacc[3] += tadd;
+      const float sq = __builtin_amdgcn_sqrtf(fmaxf(1.0f - qv, 0.0f));
+      const int pix = __mul24(ly + row, G.tw) + lx + col;
+      if (valid & (qv <= 0.998f)) {
+        lds_add(L.acc + pix, amp * sq);
+        if (ABS) lds_add(L.tacc + pix, ab.x * sq);
       }
+      queue_costly<ABS, HAB>(F, G, L, valid & rim, pix, pid, lane, qn);
     }
   } else if (HAB && kind == 2.0f) {
     // polyhedral habit: chord of the vertical ray through the pixel centre (Eq. 1),
     // times the height, plus the micro-topography where it is positive
-    const bool hit = !((T.sx1 - 0.5f - r.f[0] < -r.f[16]) | (T.sx0 + 0.5f - r.f[0] > r.f[16]) |
-                       (T.sy1 - 0.5f - r.f[1] < -r.f[17]) | (T.sy0 + 0.5f - r.f[1] > r.f[17]));
-    const unsigned hit_m = (unsigned)__ballot(hit) & 15u;
-    const int k = (int)r.f[18];
-    const float4 info = T.hab_info[k];
-    const float4* __restrict__ enc = T.hab_enc + k * kMaxFaces;
+    const int hk = (int)r.f[18];
+    const float4 info = G.hab_info[hk];
+    const float4* __restrict__ enc = G.hab_enc + hk * kMaxFaces;
     const int nf = (int)info.x;
     const float h = r.f[15], dn = r.f[14], tamp = info.z, inv_cell = 1.0f / info.w;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (!((hit_m >> q) & 1u)) continue;
-      const float dx = T.px[q] - r.f[0], dy = T.py[q] - r.f[1];
-      const float U = __builtin_fmaf(c, dx, s * dy) * r.f[8], V = __builtin_fmaf(c, dy, -(s * dx)) * r.f[9];
+    const float ia = r.f[8], ib = r.f[9];
+    for (int k0 = 0; k0 < m; k0 += 64) {
+      const int k = k0 + lane;
+      const bool valid = k < m;
+      const int row = (int)(((float)k + 0.5f) * inv_w), col = k - __mul24(row, w);
+      const float px = (float)(jlo + col) + 0.5f, py = (float)(ilo + row) + 0.5f;
+      const float dx = dx0 + (float)(ox + col), dy = dy0 + (float)(oy + row);
+      const float U = __builtin_fmaf(c, dx, s * dy) * ia, V = __builtin_fmaf(c, dy, -(s * dx)) * ib;
       float near;
       float t = h * habit_chord(enc, nf, U, V, &near);
       if (tamp > 0.0f && t > 0.0f)
-        t = fmaxf(t + tamp * value_noise(T.px[q], T.py[q], inv_cell, (uint32_t)k, T.topo_lo, T.topo_hi), 0.0f);
-      const bool costly = near < 1e-4f;  // next to a vertical face: FP64 below
-      T.acc[q] += sel(costly, 0.0f, dn * t);
-      if (ABS) T.tacc[q] += sel(costly, 0.0f, ab.y * t);
-      marks |= (unsigned)costly << q;
-    }
-    while (marks) {
-      const int q = __builtin_ctz(marks);
-      marks &= marks - 1u;
-      const int ii = q == 0 ? T.pi[0] : (q == 1 ? T.pi[1] : (q == 2 ? T.pi[2] : T.pi[3]));
-      const int jj = q == 0 ? T.pj[0] : (q == 1 ? T.pj[1] : (q == 2 ? T.pj[2] : T.pj[3]));
-      double t = (double)h * habit_chord64(r, T.hab_raw + k * kMaxFaces, nf, ii, jj);
-      if (tamp > 0.0f && t > 0.0)
-        t = fmax(t + (double)tamp * (double)value_noise((float)jj + 0.5f, (float)ii + 0.5f, inv_cell, (uint32_t)k,
-                                                        T.topo_lo, T.topo_hi), 0.0);
-      const float add = (float)((double)dn * t);
-      if (q == 0) T.acc[0] += add;
-      else if (q == 1) T.acc[1] += add;
-      else if (q == 2) T.acc[2] += add;
-      else T.acc[3] += add;
-      if (ABS) {
-        const float tadd = (float)((double)ab.y * t);
-        if (q == 0) T.tacc[0] += tadd;
-        else if (q == 1) T.tacc[1] += tadd;
-        else if (q == 2) T.tacc[2] += tadd;
-        else T.tacc[3] += tadd;
+        t = fmaxf(t + tamp * value_noise(px, py, inv_cell, (uint32_t)hk, G.topo_lo, G.topo_hi), 0.0f);
+      const bool costly = valid & (near < 1e-4f);  // next to a vertical face: FP64 in the queue
+      const int pix = __mul24(ly + row, G.tw) + lx + col;
+      if (valid & !costly & (t != 0.0f)) {
+        lds_add(L.acc + pix, dn * t);
+        if (ABS) lds_add(L.tacc + pix, ab.y * t);
       }
+      queue_costly<ABS, HAB>(F, G, L, costly, pix, pid, lane, qn);
     }
   }
 }
 
-// Lane `lane` of the wave owns pixels lane, lane+64, lane+128, lane+192 of the
-// tile.  The particle loop, the record load (scalar cache) and the kind dispatch
-// run once per (tile, particle); ids are fetched 64 at a time and broadcast.
-// Particles are visited in ascending id: the tile's bucket is sorted on the fly
-// (wave_sort64 / lds_sort); a tile whose bucket overflowed is served by a scan of
-// all particles in id order that keeps those whose box meets the tile.  All three visit the same
-// particles in the same order, so the sums are identical.  `seg`: kSegSort ints
-// of LDS; the workgroup is this single wave.
-template <bool ABS>
-__device__ __forceinline__ float2 absorb_weights(const FrameDev& F, int64_t id) {
-  return ABS ? F.absr[id] : make_float2(0.0f, 0.0f);
-}
-
 template <bool ABS, bool HAB>
-__device__ __forceinline__ void raster_ids(const FrameDev& F, TileAcc& T, int mine, int m) {
+__device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int lane, char* lds) {
 #pragma clang fp contract(off)
-  const PRec* __restrict__ recs = F.recs;
-  PRec nxt = recs[__builtin_amdgcn_readlane(mine, 0)];
-  for (int k = 0; k < m; ++k) {
-    const PRec cur = nxt;
-    const float2 ab = absorb_weights<ABS>(F, __builtin_amdgcn_readlane(mine, k));
-    if (k + 1 < m) nxt = recs[__builtin_amdgcn_readlane(mine, k + 1)];
-    add_particle<ABS, HAB>(cur, T, ab);
-  }
-}
-
-template <bool ABS, bool HAB>
-__device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int lane, int* seg) {
-#pragma clang fp contract(off)
-  const int tile_w = F.tile_w, tile_h = F.tile_h;
+  TileGeom G;
+  G.tw = F.tile_w;
+  G.th = F.tile_h;
   const int ty = tile / F.ntx, tx = tile - ty * F.ntx;
-  TileAcc T;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int q = lane + 64 * k, li = q / tile_w, lj = q - li * tile_w;
-    T.pi[k] = ty * tile_h + li;
-    T.pj[k] = tx * tile_w + lj;
-    T.px[k] = (float)T.pj[k] + 0.5f;
-    T.py[k] = (float)T.pi[k] + 0.5f;
-    T.acc[k] = 0.0f;
-    T.tacc[k] = 0.0f;
-  }
-  T.hab_enc = F.hab_enc;
-  T.hab_raw = F.hab_raw;
-  T.hab_info = F.hab_info;
-  T.topo_lo = F.topo_lo;
-  T.topo_hi = F.topo_hi;
-  {
-    const SubRect R = slot_rect(64 * (lane & 3), tile_w, tx, ty, tile_h);
-    T.sx0 = R.x0;
-    T.sx1 = R.x1;
-    T.sy0 = R.y0;
-    T.sy1 = R.y1;
-    T.scx = 0.5f * (R.x0 + R.x1);
-    T.scy = 0.5f * (R.y0 + R.y1);
-    T.shx = 0.5f * (R.x1 - R.x0 - 1.0f);
-    T.shy = 0.5f * (R.y1 - R.y0 - 1.0f);
-  }
-  const int cnt = F.tile_count[tile];
-  const bool overflow = cnt > (int)F.cap;     // the bucket could not hold the tile's ids
-  const int* __restrict__ pids = F.pids + (int64_t)tile * F.cap;
-  const int start = 0;
-  if (!overflow && cnt <= 64) {
-    if (cnt > 0) {
-      const int mine = wave_sort64(lane < cnt ? pids[start + lane] : INT_MAX, lane);
-      raster_ids<ABS, HAB>(F, T, mine, cnt);
-    }
-  } else if (!overflow && cnt <= kSegSort) {
-    int n2 = 128;
-    while (n2 < cnt) n2 <<= 1;
-    for (int i = lane; i < n2; i += 64) seg[i] = i < cnt ? pids[start + i] : INT_MAX;
-    __syncthreads();
-    lds_sort(seg, n2, lane);
-    for (int c0 = 0; c0 < cnt; c0 += 64) {
-      const int m = min(64, cnt - c0);
-      raster_ids<ABS, HAB>(F, T, lane < m ? seg[c0 + lane] : 0, m);
-    }
-  } else {
-    const int x0 = tx * tile_w, x1 = x0 + tile_w - 1, y0 = ty * tile_h, y1 = y0 + tile_h - 1;
-    for (int64_t p = 0; p < F.n; ++p) {
-      const int4 b = F.boxes[p];
-      if (b.x > b.y || b.x > x1 || b.y < x0 || b.z > y1 || b.w < y0) continue;
-      add_particle<ABS, HAB>(F.recs[p], T, absorb_weights<ABS>(F, p));
+  G.X0 = tx * G.tw;
+  G.Y0 = ty * G.th;
+  G.hab_enc = F.hab_enc;
+  G.hab_raw = F.hab_raw;
+  G.hab_info = F.hab_info;
+  G.topo_lo = F.topo_lo;
+  G.topo_hi = F.topo_hi;
+  const int area = G.tw * G.th;
+  const RasterLds L = raster_lds(lds, area, ABS);
+  for (int q = lane; q < area; q += 64) {
+    L.acc[q] = 0.0f;
+    L.cacc[q] = 0.0f;
+    if (ABS) {
+      L.tacc[q] = 0.0f;
+      L.ctacc[q] = 0.0f;
     }
   }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    F.opd[(int64_t)T.pi[q] * F.W + T.pj[q]] = T.acc[q];
-    if (ABS) F.tau[(int64_t)T.pi[q] * F.W + T.pj[q]] = T.tacc[q];
+  __syncthreads();
+  int qn = 0;
+  const PRec* __restrict__ recs = F.recs;
+  const bool scanned = for_tile_ids(F, tile, lane, L.seg, [&](int mine, int m) {
+    // wave-uniform records through the scalar cache, the next one requested
+    // before the current one is rasterised
+    int pid = __builtin_amdgcn_readlane(mine, 0);
+    PRec nxt = const_load(recs + pid);
+    for (int k = 0; k < m; ++k) {
+      const PRec cur = nxt;
+      const int cpid = pid;
+      if (k + 1 < m) {
+        pid = __builtin_amdgcn_readlane(mine, k + 1);
+        nxt = const_load(recs + pid);
+      }
+      raster_particle<ABS, HAB>(F, G, L, cur, cpid, lane, qn);
+    }
+  });
+  __syncthreads();
+  if (qn > 0) flush_costly<ABS, HAB>(F, G, L, qn, lane);
+  __syncthreads();
+  for (int q = lane; q < area; q += 64) {
+    const int i = q / G.tw, j = q - i * G.tw;
+    const int64_t o = (int64_t)(G.Y0 + i) * F.W + G.X0 + j;
+    F.opd[o] = L.acc[q] + L.cacc[q];
+    if (ABS) F.tau[o] = L.tacc[q] + L.ctacc[q];
   }
+  if (scanned && lane == 0) atomicAdd(&F.scal[1], 1);
 }
 
 // ---- F6: pass 1, rows --------------------------------------------------------
@@ -827,11 +948,11 @@ inline FrameDev make_dev(const FramePlan& p, const FrameBufs& b) {
   FrameDev F{};
   F.H = p.H; F.W = p.W; F.logH = p.logH; F.logW = p.logW;
   F.tile_h = p.tile_h; F.tile_w = p.tile_w; F.ntx = p.ntx; F.n_tiles = p.n_tiles;
-  F.n = p.n; F.ld = p.ld; F.cap = p.cap;
+  F.n = p.n; F.ld = p.ld; F.pair_cap = p.pair_cap;
   F.o = optics_args(p);
   F.phase_k = p.phase_k;
   F.recs = b.recs; F.boxes = b.boxes; F.counts = b.counts; F.scal = b.scal;
-  F.tile_count = b.tile_count; F.tile_first = b.tile_first;
+  F.tile_count = b.tile_count; F.tile_start = b.tile_start; F.cursor = b.cursor;
   F.pids = b.pids;
   F.band = b.band; F.colsum = b.colsum;
   F.band_in = b.band; F.in_kx_lo = p.kx_lo; F.in_kx_n = p.kx_n;

@@ -57,7 +57,7 @@ def mid_frame(seed, size, n, mode):
     return workloads.Frame(size, size, soa, opt, np.array(g, np.float32), "mid")
 
 
-@pytest.mark.parametrize("tiling", [(16, 16), (8, 32), (32, 8)])
+@pytest.mark.parametrize("tiling", [(16, 16), (8, 32), (32, 8), (32, 32), (16, 64)])
 def test_binning_bit_exact(tiling):
     r = R()
     fr = workloads.config1(n=5000, size=1024)
@@ -125,7 +125,7 @@ def test_deterministic_and_tiling_invariant():
     a_opd, a_I = gpu_frame(fr)
     b_opd, b_I = gpu_frame(fr)
     assert np.array_equal(a_opd, b_opd) and np.array_equal(a_I, b_I)
-    for tl in [(8, 32), (32, 8), (64, 4)]:
+    for tl in [(8, 32), (32, 8), (64, 4), (32, 32), (32, 16), (4, 256)]:
         r.set_tiling(*tl)
         try:
             c_opd, c_I = gpu_frame(fr)
@@ -148,20 +148,20 @@ def test_pair_overflow_fallback_is_bitwise_identical():
 
 def crowded_frame(seed=11):
     """256^2 brightfield frame whose particles crowd into a few tiles: 700 small
-    prisms and ellipsoids in a 48x48 px patch (tiles of 100-400 particles: the
-    LDS sort) and 500 more centred in one 16x16 tile (more than its bucket of
-    ceil((32 * 1200 + 256) / 256) = 152 ids: the id-ordered scan)."""
+    prisms and ellipsoids in a 48x48 px patch (tiles of 65-512 particles: the
+    LDS sort) and 700 more centred in one 16x16 tile (a segment of more than 512
+    ids: the id-ordered scan)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     a = workloads.mixed(rng, 700, 256, 256)
     a[0] = rng.uniform(100, 148, 700)
     a[1] = rng.uniform(60, 108, 700)
     a[3] = rng.uniform(1.5, 4, 700)
     a[4] = np.where(a[7] > 0.5, rng.uniform(1.5, 4, 700), a[3])
-    b = workloads.mixed(rng, 500, 256, 256)
-    b[0] = rng.uniform(200, 208, 500)
-    b[1] = rng.uniform(200, 208, 500)
-    b[3] = rng.uniform(1, 3, 500)
-    b[4] = np.where(b[7] > 0.5, rng.uniform(1, 3, 500), b[3])
+    b = workloads.mixed(rng, 700, 256, 256)
+    b[0] = rng.uniform(200, 208, 700)
+    b[1] = rng.uniform(200, 208, 700)
+    b[3] = rng.uniform(1, 3, 700)
+    b[4] = np.where(b[7] > 0.5, rng.uniform(1, 3, 700), b[3])
     soa = workloads.f32(np.concatenate([a, b], axis=1))
     opt = workloads.OpticsSpec(mode=workloads.BRIGHTFIELD, na=0.4)
     return workloads.Frame(256, 256, soa, opt, np.array([1.0, 0, 0, 0], np.float32), "crowded")
@@ -174,9 +174,9 @@ def test_crowded_tiles_sorted_and_scanned_paths():
     keys, pids, ts, counts, P = r.bin_pairs(soa, fr.H, fr.W)
     ref = oracle.binning.bin_pairs(fr.soa, fr.H, fr.W, 16, 16)
     per_tile = np.diff(ref["tile_start"])
-    say("crowded: pairs %d, max per tile %d, tiles over 64: %d, over 152: %d" % (
-        P, per_tile.max(), (per_tile > 64).sum(), (per_tile > 152).sum()))
-    assert (per_tile > 64).sum() > 0 and (per_tile > 152).sum() > 0
+    say("crowded: pairs %d, max per tile %d, tiles over 64: %d, over 512: %d" % (
+        P, per_tile.max(), (per_tile > 64).sum(), (per_tile > 512).sum()))
+    assert ((per_tile > 64) & (per_tile <= 512)).sum() > 0 and (per_tile > 512).sum() > 0
     assert P == len(ref["keys"])
     assert np.array_equal(keys.cpu().numpy(), ref["keys"])
     assert np.array_equal(pids.cpu().numpy(), ref["pids"])
@@ -300,7 +300,8 @@ def test_radix4_plan_and_autotuner():
     e = rel_l2(I.cpu().numpy(), rI)
     say("radix-4 plan rel L2 %.2e; autotuner chose %s, rel L2 %.2e" % (e4, choice, e))
     assert e4 <= I_TOL and e <= I_TOL
-    assert (choice["tile_h"], choice["tile_w"]) in [(16, 16), (8, 32), (32, 8)] and choice["fft_radix"] in (4, 8)
+    assert (choice["tile_h"], choice["tile_w"]) in [(16, 16), (32, 32), (32, 16), (16, 32), (64, 16)]
+    assert choice["fft_radix"] in (4, 8)
     # back to the defaults for the other tests
     render._lib.check(lib.osog_set_size_tiling(render.context(), 512, 512, 16, 16), "tiling")
     render._lib.check(lib.osog_set_size_radix(render.context(), 512, 512, 8), "radix")
