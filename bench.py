@@ -24,13 +24,14 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector peak (packed); scalar-issue FP32 FMA peaks at half
-# FP32 operations one exact evaluation of a candidate pixel needs at least (an FMA counts 2):
-#   prism      centre offsets 2, rotation 6, edge distances 2, four classifying compares,
-#              half-plane value 9 (select, |t| distance, clamp, square, scale, linear FMA, choice),
-#              accumulate 2                                                       = 25
-#   ellipsoid  centre offsets 2, rotation 6, axis scaling 2, q 3, 1 - q 1, rim compare 1,
-#              square root 1, accumulate 2                                        = 18
-RASTER_OPS = {"prism": 25.0, "ellipsoid": 18.0}
+# Algorithmic FP32 operations of the raster per unit of work (an FMA counts 2): a candidate
+# pixel test -- a pixel of a particle's conservative binning box, which any exact per-pixel
+# method must classify -- 20 (centre offsets, rotation, edge distances, classification, the
+# thickness, the add); an exact clip of a prism boundary pixel (the box-filtered area where an
+# edge crosses the pixel) 80.  The 2048^2 x 40k frame has 19.2 M tests and 1.5 M clips: 0.50 GFLOP.
+RASTER_FLOP_PER_TEST = 20.0
+RASTER_FLOP_PER_CLIP = 80.0
+HBM_TARGET_FRAC = 0.6      # the frame's target share of the HBM roofline
 METRIC = "frames/s at 2048²×40k-particle DIC"
 
 
@@ -54,19 +55,33 @@ def algorithmic_bytes(H, W, n, P, kx_n):
 COUNTERS = os.path.join(ROOT, "profiles", "counters_dic2048_n40000.txt")
 
 
-def raster_candidates(soa, H, W):
-    """Candidate pixels of the raster: for each particle, the canvas pixels that meet the
-    axis-aligned bounding box of its footprint (the pixels any exact per-pixel method
-    must classify).  Returns (prism pixels, ellipsoid pixels)."""
+def raster_work(soa, H, W):
+    """Units of the raster's algorithmic work: (candidate pixel tests, prism boundary
+    clips).  Tests: the canvas pixels of each particle's conservative binning box
+    (ext = max(a, b) sqrt 2 + 1 for a prism, max(a, b) + 1 for an ellipsoid).  Clips:
+    the pixels a prism's four edges cross, 4 (a + b) (|cos| + |sin|) on average for a
+    rectangle of half-widths a, b (perimeter 4 (a + b)) at a uniform sub-pixel offset."""
     cx, cy, ang, a, b = (soa[k].astype(np.float64) for k in range(5))
-    c, s = np.abs(np.cos(ang)), np.abs(np.sin(ang))
     prism = soa[7] < 0.5
-    ex = np.where(prism, a * c + b * s, np.sqrt(a * a * c * c + b * b * s * s))
-    ey = np.where(prism, a * s + b * c, np.sqrt(a * a * s * s + b * b * c * c))
-    nx = np.clip(np.floor(cx + ex), 0, W - 1) - np.clip(np.floor(cx - ex), 0, W - 1) + 1
-    ny = np.clip(np.floor(cy + ey), 0, H - 1) - np.clip(np.floor(cy - ey), 0, H - 1) + 1
-    px = nx * ny
-    return float(px[prism].sum()), float(px[~prism].sum())
+    ext = np.where(prism, np.maximum(a, b) * math.sqrt(2.0) + 1.0, np.maximum(a, b) + 1.0)
+    nx = np.clip(np.floor(cx + ext), 0, W - 1) - np.clip(np.floor(cx - ext), 0, W - 1) + 1
+    ny = np.clip(np.floor(cy + ext), 0, H - 1) - np.clip(np.floor(cy - ext), 0, H - 1) + 1
+    tests = float((nx * ny).sum())
+    clips = float((4.0 * (a + b) * (np.abs(np.cos(ang)) + np.abs(np.sin(ang))))[prism].sum())
+    return tests, clips
+
+
+def host_cpu():
+    """(model name, logical cores) of the host running the oracle."""
+    name = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return name, os.cpu_count()
 
 
 def kernel_hash():
@@ -102,12 +117,18 @@ def measured_counters(kernel):
     return None
 
 
-def frame_valu_floor_us():
+def frame_kernels(logW=11, radix=8):
+    """Kernel names of one forward frame (no habits, no absorption) for a plan."""
+    fft = "<%d, %d>" % (logW, radix)
+    return ("k_bin_clear", "k_bin", "k_tile_scan", "k_emit", "k_raster<false, false>", "k_pass1" + fft,
+            "k_pass2" + fft, "k_pass3" + fft)
+
+
+def frame_valu_floor_us(logW=11, radix=8):
     """Time the headline frame's kernels need at the chip's full VALU issue rate (their
     wave instructions x 4 cycles over 1024 SIMDs at 2.4 GHz), from the committed counter
     summary; None when that summary belongs to another build of the library."""
-    frame = ("k_bin", "k_bin_clear", "k_raster<false, false>", "k_pass1<11, 8>", "k_pass2<11, 8>",
-             "k_pass3<11, 8>")
+    frame = frame_kernels(logW, radix)
     try:
         lines = open(COUNTERS).read().splitlines()
     except OSError:
@@ -153,7 +174,9 @@ def cpu_baseline(fr, budget_s=20.0):
         m = min(m + 4096, flat.size)
     t_noise = (time.perf_counter() - t1) * flat.size / m
     per_frame = t_render + t_noise
+    cpu, ncpu = host_cpu()
     return {"value": 1.0 / per_frame, "unit": "frames/s", "cores": 1, "kind": "oracle",
+            "host_cpu": cpu, "host_logical_cores": ncpu,
             "sample": "1 full noiseless 2048^2 x 40k DIC frame (%.2f s) + Poisson noise of %d pixels "
                       "extrapolated to %d (%.1f s/frame)" % (t_render, m, flat.size, t_noise)}
 
@@ -171,8 +194,9 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed run, one plain device-to-device copy of this many MiB "
                          "(reference dispatch for hardware byte counters)")
-    ap.add_argument("--learned", action="store_true",
-                    help="also train the learned initializer (200,000 rendered crops) and compare inverse solves")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip training the learned initializer (200,000 rendered crops) and its comparison of "
+                         "inverse solves (part of the inverse leg by default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X with no sharding "
@@ -201,13 +225,14 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.steps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev[0].record()
+    for k in range(args.steps):
         step()
-    e1.record()
+        ev[k + 1].record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
+    ms = ev[0].elapsed_time(ev[-1]) / args.steps
+    step_ms = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(args.steps)])
 
     # per-stage durations with HIP events on the launch stream (separate run)
     lib = _lib.load()
@@ -228,7 +253,7 @@ def main():
     alg = algorithmic_bytes(H, W, n, P, kx_n)
     dom = max((k for k in stage_us if k in alg), key=lambda k: stage_us[k])
     achieved = alg[dom] / (stage_us[dom] * 1e-6) / 1e9
-    kname = {"binning": "k_fill", "raster": "k_raster", "pass1": "k_pass1", "pass2": "k_pass2",
+    kname = {"binning": "k_bin", "raster": "k_raster", "pass1": "k_pass1", "pass2": "k_pass2",
              "pass3": "k_pass3"}[dom]
     cnt = measured_counters(kname)
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -238,17 +263,20 @@ def main():
             "valu_busy": round(cnt["valu_busy"], 3) if cnt else None}
     if dom == "raster":
         # the raster is bound by vector ALU issue, not by HBM: its roofline is FP32 arithmetic
-        pp, pe = raster_candidates(fr.soa, H, W)
-        flops = pp * RASTER_OPS["prism"] + pe * RASTER_OPS["ellipsoid"]
+        tests, clips = raster_work(fr.soa, H, W)
+        flops = tests * RASTER_FLOP_PER_TEST + clips * RASTER_FLOP_PER_CLIP
         tflops = flops / (stage_us[dom] * 1e-6) / 1e12
         roof = {"bound": "alu", "kernel": dom, "achieved": round(tflops, 3), "peak": FP32_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(tflops / FP32_PEAK_TFLOPS, 4),
                 "traffic": round(cnt["traffic"]) if cnt else None,
-                "algorithmic_flops": flops, "candidate_pixels": {"prism": pp, "ellipsoid": pe},
+                "algorithmic_flops": flops, "units": {"candidate_pixel_tests": tests, "prism_boundary_clips": clips,
+                                                      "flop_per_test": RASTER_FLOP_PER_TEST,
+                                                      "flop_per_clip": RASTER_FLOP_PER_CLIP},
                 "avg_us": round(stage_us[dom], 2), "valu_busy": round(cnt["valu_busy"], 3) if cnt else None,
                 "hbm_frac": round(achieved / HBM_PEAK_GBS, 4), "algorithmic_bytes": alg[dom]}
     total_alg = sum(alg.values())
-    vf = frame_valu_floor_us()
+    th, tw = render.get_tiling(dev)
+    vf = frame_valu_floor_us(int(round(math.log2(W))), 8)
     res = {
         "metric": METRIC,
         "value": round(1000.0 / ms, 2),
@@ -266,10 +294,16 @@ def main():
                    "prisms": int((fr.soa[7] < 0.5).sum()), "mode": "DIC", "na": fr.optics.na,
                    "photons_mean": fr.optics.photons_mean, "pairs": P, "band_columns": kx_n},
         "particles_per_s": round(n * 1000.0 / ms, 1),
+        "step_ms": {"mean": round(float(step_ms.mean()), 4), "std": round(float(step_ms.std()), 4),
+                    "p50": round(float(np.percentile(step_ms, 50)), 4),
+                    "p99": round(float(np.percentile(step_ms, 99)), 4)},
+        "tiling": [th, tw],
         "stage_us": {k: round(v, 2) for k, v in stage_us.items()},
         "frame_alg_bytes": total_alg,
         "frame_alg_gbs": round(total_alg / (ms * 1e-3) / 1e9, 1),
         "frame_hbm_frac": round(total_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "frame_hbm_target_frac": HBM_TARGET_FRAC,
+        "frame_us_at_target": round(total_alg / (HBM_TARGET_FRAC * HBM_PEAK_GBS * 1e9) * 1e6, 2),
         # the frame is bound by vector issue: its kernels' VALU instructions at the full issue
         # rate, and that floor as a share of the measured frame time
         "frame_valu_floor_us": round(vf, 1) if vf else None,
@@ -292,7 +326,7 @@ def main():
         if "stream" in legs:
             res["stream"] = bench_stream(render, fr, dev)
         if "inverse" in legs:
-            res["inverse"] = bench_inverse(dev, learned=args.learned)
+            res["inverse"] = bench_inverse(dev, learned=not args.no_learned)
     if args.calib_copy_mib > 0:
         nb = args.calib_copy_mib << 20
         src = torch.ones(nb, dtype=torch.uint8, device=dev)
@@ -484,6 +518,13 @@ def bench_batch(render, dev, reps=10):
         torch.cuda.synchronize()
         lats.append(b.latencies_ms())
     lat = np.concatenate(lats)
+    # the tuned plans stay in the context: put the default plan back so that later legs
+    # (the stream of headline frames) run the headline frame's plan
+    th, tw = render.get_tiling(dev)
+    lib, ctx = render._lib.load(), render.context(dev)
+    for (hh, ww) in reps_by_size:
+        render._lib.check(lib.osog_set_size_tiling(ctx, hh, ww, th, tw), "osog_set_size_tiling")
+        render._lib.check(lib.osog_set_size_radix(ctx, hh, ww, 8), "osog_set_size_radix")
     px = sum(x.H * x.W for x in frs)
     parts = sum(x.soa.shape[1] for x in frs)
     return {"workload": "batch64_mixed", "frames": len(frs), "ms_per_batch": round(ms, 4),
@@ -518,25 +559,33 @@ def bench_stream(render, fr, dev, frames=8, reps=10):
             "frames_per_s": round(frames * 1000.0 / ms, 1), "error_flag": b.error_flag()}
 
 
-def bench_inverse(dev, learned=False):
-    """1024^2 DIC, 500 prisms: Adam through the adjoint from the perturbed start (500 steps)."""
+def bench_inverse(dev, learned=True, learned_targets=6, learned_samples=200_000):
+    """1024^2 DIC, 500 prisms (seed 3): the hybrid solve (Adam from the perturbed start,
+    angles held until the second-order polish); time to e <= 1e-3.  Then, when
+    `learned`, the learned initializer trained on engine-rendered crops against the
+    default start on `learned_targets` further targets (seeds 300..)."""
     import torch
     from paper_2606_21381_amd import inverse, workloads
     prob = workloads.config3()
     target, start, truth = inverse.problem_tensors(prob, dev)
     inverse.solve(target, inverse.problem_tensors(prob, dev)[1], truth, prob.target.H, prob.target.W,
                   prob.target.optics, inverse.SolverConfig(steps=3))  # warm-up
-    res = inverse.solve(target, start, truth, prob.target.H, prob.target.W, prob.target.optics,
-                        inverse.SolverConfig())
-    out = {"workload": "dic1024_n500_adam500", "time_to_1e-3_s": res.time_to_target_s,
-           "steps_to_1e-3": res.steps_to_target, "final_error": float(res.error[-1]),
-           "final_error_glob": float(res.error_glob[-1]), "final_error_part": float(res.error_part[-1]),
-           "glob_steps_to_1e-3": res.steps_to_glob_target, "glob_time_to_1e-3_s": res.time_to_glob_target_s,
-           "final_loss": float(res.loss[-1]), "steps_per_s": round(len(res.loss) / float(res.time_s[-1]), 1)}
+    res = inverse.solve_hybrid(target, start, truth, prob.target.H, prob.target.W, prob.target.optics)
+    a = res.adam
+    out = {"workload": "dic1024_n500 (seed 3): Adam %d steps (globals first, angles held) + polish" % a.steps,
+           "time_to_1e-3_s": res.time_to_target_s, "glob_time_to_1e-3_s": res.time_to_glob_target_s,
+           "final_error": res.final_e, "final_error_glob": res.final_e_glob, "final_error_part": res.final_e_part,
+           "final_loss": res.final_loss, "total_s": round(res.total_s, 3),
+           "adam_s": round(float(a.time_s[-1]), 3), "adam_steps_per_s": round(len(a.loss) / float(a.time_s[-1]), 1),
+           "adam_final_error": float(a.error[-1]),
+           "polish_stages": [(tag.split()[0], round(t, 3), float("%.3g" % e)) for tag, t, e, _ in res.trace]}
     if learned:
         from paper_2606_21381_amd import cnn
-        rep = cnn.compare(dev)
-        rep.pop("targets")
+        rep = cnn.compare(dev, samples=learned_samples, n_targets=learned_targets)
+        rep["targets"] = [{"seed": r["seed"], "fallback": r["fallback"],
+                           "default": {k: r["default"][k] for k in ("time_to_1e-3_s", "glob_time_to_1e-3_s", "final_e")},
+                           "learned": {k: r["learned"][k] for k in ("time_to_1e-3_s", "glob_time_to_1e-3_s", "final_e")}}
+                          for r in rep["targets"]]
         out["learned"] = rep
     return out
 

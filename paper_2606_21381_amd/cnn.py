@@ -183,21 +183,25 @@ def _seed_globals(start, g):
 
 
 def compare(device="cuda", samples: int = 200_000, n_targets: int = 10, target_seed0: int = 300,
-            net: Optional["LearnedInit"] = None, cfg=None, log=None) -> dict:
+            net: Optional["LearnedInit"] = None, cfg=None, pc=None, stall_loss: float = 1e-10, log=None) -> dict:
     """Learned-init against default-init inverse solves on 1024^2 DIC targets of 500 prisms.
 
     Both runs start every prism from the same perturbed position, angle and
-    width; they differ only in the four globals: the default start perturbs
-    them by x(1 + U[-0.2, 0.2]), the learned start takes the network's
-    prediction on the full target frame.  Fallback: when the image loss at the
-    learned start exceeds the loss at the default start, the learned run uses
-    the default start instead (counted).  Returns training cost, held-out
-    per-global error, and the median time and steps to e <= 1e-3 of each arm.
+    width and run the same solve (inverse.solve_hybrid: Adam, then the
+    second-order polish); they differ only in the four globals: the default start
+    perturbs them by x(1 + U[-0.2, 0.2]), the learned start takes the network's
+    prediction on the full target frame.  Fallback to the plain solve from the
+    default start: (a) when the image loss at the learned start exceeds the loss
+    at the default start, before solving; (b) when the learned run stalls (its
+    final mean squared image error stays above ``stall_loss`` x mean(target^2)
+    while the default run's does not need to be known), after it -- its time then
+    counts in full, plus the default solve's.  Returns training cost, held-out
+    per-global error, per-target rows and the medians (over targets) of the time
+    to e <= 1e-3 and to e_glob <= 1e-3 of each arm (inf when not reached).
     """
     from . import inverse
     from .render import render
     device = torch.device(device)
-    cfg = cfg or inverse.SolverConfig()
     if net is None:
         net = LearnedInit(device)
         losses, t_train = net.train(samples, log=log)
@@ -205,7 +209,7 @@ def compare(device="cuda", samples: int = 200_000, n_targets: int = 10, target_s
         losses, t_train = np.array([]), 0.0
     mae = net.evaluate()
     rows = []
-    fallbacks = 0
+    fallbacks_start, fallbacks_stall = 0, 0
     for k in range(n_targets):
         prob = workloads.config3(seed=target_seed0 + k)
         H, W, opt = prob.target.H, prob.target.W, prob.target.optics
@@ -213,20 +217,30 @@ def compare(device="cuda", samples: int = 200_000, n_targets: int = 10, target_s
         _, start_cnn, _ = inverse.problem_tensors(prob, device)
         g_pred = net.predict(target)
         _seed_globals(start_cnn, g_pred)
+        scale = float(torch.mean(target.double() ** 2))
         with torch.no_grad():
             l_def = float(torch.mean((render(start_def.soa(), H, W, opt, start_def.globals4()) - target) ** 2))
             l_cnn = float(torch.mean((render(start_cnn.soa(), H, W, opt, start_cnn.globals4()) - target) ** 2))
-        used_fallback = l_cnn > l_def
-        if used_fallback:
-            fallbacks += 1
-            _, start_cnn, _ = inverse.problem_tensors(prob, device)
-        r_def = inverse.solve(target, start_def, truth, H, W, opt, cfg)
-        r_cnn = inverse.solve(target, start_cnn, truth, H, W, opt, cfg)
+        r_def = inverse.solve_hybrid(target, start_def, truth, H, W, opt, cfg, pc)
+        fb = "none"
+        if l_cnn > l_def:
+            fb = "start"
+            fallbacks_start += 1
+            r_cnn = r_def
+            learned = _arm(r_def)
+        else:
+            r_cnn = inverse.solve_hybrid(target, start_cnn, truth, H, W, opt, cfg, pc)
+            learned = _arm(r_cnn)
+            if r_cnn.final_loss > stall_loss * scale:
+                fb = "stall"
+                fallbacks_stall += 1
+                _, start_fb, _ = inverse.problem_tensors(prob, device)
+                r_fb = inverse.solve_hybrid(target, start_fb, truth, H, W, opt, cfg, pc)
+                learned = _arm(r_fb, offset=r_cnn.total_s)
         g_true = truth.globals4.double().cpu().numpy()
         rows.append({"seed": target_seed0 + k, "loss_start_default": l_def, "loss_start_learned": l_cnn,
-                     "fallback": used_fallback,
-                     "pred_abs_err": np.abs(g_pred - g_true).tolist(),
-                     "default": _arm(r_def), "learned": _arm(r_cnn)})
+                     "fallback": fb, "pred_abs_err": np.abs(g_pred - g_true).tolist(),
+                     "default": _arm(r_def), "learned": learned})
         if log:
             log(k, rows[-1])
 
@@ -237,19 +251,24 @@ def compare(device="cuda", samples: int = 200_000, n_targets: int = 10, target_s
             out[arm] = float(np.median(v))
         return out
 
-    rep = {"workload": "dic1024_n500 x %d targets" % n_targets, "train_samples": samples,
+    rep = {"workload": "dic1024_n500 x %d targets (seeds %d..%d)" % (n_targets, target_seed0, target_seed0 + n_targets - 1),
+           "train_samples": samples,
            "train_s": round(t_train, 2), "train_final_loss": float(losses[-20:].mean()) if len(losses) else None,
            "heldout_mae": dict(zip(("dn", "dz_um", "shear_px", "bias_rad"), map(float, mae))),
-           "fallbacks": fallbacks, "targets": rows}
-    for key in ("time_to_1e-3_s", "steps_to_1e-3", "glob_time_to_1e-3_s", "glob_steps_to_1e-3", "final_e",
-                "final_e_glob", "final_e_part", "glob_error_at_60"):
+           "fallbacks_start": fallbacks_start, "fallbacks_stall": fallbacks_stall,
+           "reached_1e-3": {arm: int(sum(r[arm]["time_to_1e-3_s"] is not None for r in rows)) for arm in ("default", "learned")},
+           "targets": rows}
+    for key in ("time_to_1e-3_s", "glob_time_to_1e-3_s", "final_e", "final_e_glob", "final_e_part", "total_s"):
         rep["median_" + key] = med(key)
     return rep
 
 
-def _arm(r) -> dict:
-    """Summary of one inverse solve: time/steps to e <= 1e-3 and to e_glob <= 1e-3, final errors."""
-    return {"time_to_1e-3_s": r.time_to_target_s, "steps_to_1e-3": r.steps_to_target,
-            "glob_time_to_1e-3_s": r.time_to_glob_target_s, "glob_steps_to_1e-3": r.steps_to_glob_target,
-            "final_e": float(r.error[-1]), "final_e_glob": float(r.error_glob[-1]),
-            "final_e_part": float(r.error_part[-1]), "glob_error_at_60": float(r.error_glob[min(60, r.steps)])}
+def _arm(r, offset: float = 0.0) -> dict:
+    """Summary of one hybrid inverse solve (times shifted by `offset` seconds, the time
+    a stalled learned run spent before its fallback)."""
+    def sh(t):
+        return None if t is None else t + offset
+    return {"time_to_1e-3_s": sh(r.time_to_target_s), "glob_time_to_1e-3_s": sh(r.time_to_glob_target_s),
+            "final_e": r.final_e, "final_e_glob": r.final_e_glob, "final_e_part": r.final_e_part,
+            "final_loss": r.final_loss, "total_s": r.total_s + offset,
+            "adam_e_glob_at_60": float(r.adam.error_glob[min(60, r.adam.steps)])}

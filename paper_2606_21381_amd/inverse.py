@@ -381,3 +381,79 @@ def problem_tensors(prob, device):
                   torch.tensor([float(tf.soa[6, 0]), *[float(v) for v in tf.globals4[:3]]],
                                dtype=torch.float32, device=device))
     return target, start, truth
+
+
+@dataclass
+class HybridResult:
+    """Adam, then the second-order polish (polish.py).  Times are seconds since the
+    start of Adam's first step (GPU events for Adam, wall clock after it)."""
+    adam: SolveResult
+    trace: list                               # polish stages: (tag, time_s, e, e_glob)
+    time_to_target_s: Optional[float]
+    time_to_glob_target_s: Optional[float]    # e_glob <= target (the four globals)
+    final_loss: float
+    final_e: Optional[float]
+    final_e_glob: Optional[float]
+    final_e_part: Optional[float]
+    total_s: float
+    final: dict = field(default_factory=dict)
+
+
+def hybrid_config(steps: int = 500, globals_steps: int = 60) -> SolverConfig:
+    """Adam schedule of the hybrid solve: the globals alone, then centres, widths and
+    globals; the angles stay at their start (inside +-0.2 rad of the truth, the bracket
+    the polish's angle search covers) until the polish."""
+    glob = ("dn", "dz", "shear", "bias")
+    return SolverConfig(steps=steps, curriculum=((globals_steps, glob), (steps - globals_steps, ("position", "width") + glob)))
+
+
+def solve_hybrid(target: torch.Tensor, start: Params, truth: Optional[Truth], H: int, W: int, optics,
+                 cfg: Optional[SolverConfig] = None, pc=None) -> HybridResult:
+    """Adam (``cfg``, by default hybrid_config()) then polish.polish (``pc``) from
+    Adam's state; ``start`` ends at the solution.  With a truth, e after every Adam
+    step and every polish stage is recorded (the truth never steers the solve)."""
+    from . import polish
+    cfg = cfg or hybrid_config()
+    pc = pc or polish.PolishConfig()
+    res = solve(target, start, truth, H, W, optics, cfg)
+    torch.cuda.synchronize(target.device)
+    t_adam = float(res.time_s[-1]) if len(res.time_s) else 0.0
+    model = polish.Model(H, W, optics, start.height.detach())
+    floor = error_floor(target.device)
+
+    glob_err = []
+
+    def error_fn(x, y, a, w, glob):
+        tmp = Params(x, y, a, w, start.height.detach(), glob)
+        eg, ep = parameter_errors(tmp, truth, floor)
+        glob_err.append(float(eg))
+        return float(torch.maximum(eg, ep))
+
+    t0 = time.perf_counter()
+    with torch.no_grad():
+        x, y, a, w, glob = (t.detach().clone() for t in (start.x, start.y, start.angle, start.width, start.glob()))
+        x, y, a, w, glob, trace = polish.polish(target, model, x, y, a, w, glob, pc,
+                                                error_fn=error_fn if truth is not None else None,
+                                                clock=lambda: t_adam + time.perf_counter() - t0)
+        torch.cuda.synchronize(target.device)
+        total = t_adam + time.perf_counter() - t0
+        for q, v in ((start.x, x), (start.y, y), (start.angle, a), (start.width, w)):
+            q.copy_(v)
+        for q, v in zip((start.dn, start.dz, start.shear, start.bias), glob):
+            q.fill_(float(v))
+    trace = [(tag, t, e, eg) for (tag, t, e), eg in zip(trace, glob_err)] if truth is not None else trace
+    hit, hitg = res.time_to_target_s, res.time_to_glob_target_s
+    for _, t, e, eg in (trace if truth is not None else []):
+        if hit is None and e <= cfg.target_error:
+            hit = t
+        if hitg is None and eg <= cfg.target_error:
+            hitg = t
+    fe = fg = fp = None
+    if truth is not None:
+        eg, ep = parameter_errors(start, truth)
+        fe, fg, fp = float(torch.maximum(eg, ep)), float(eg), float(ep)
+    with torch.no_grad():
+        I = model.render(start.x, start.y, start.angle, start.width, start.glob())
+        final_loss = float(torch.mean((I.double() - target.double()) ** 2))
+    return HybridResult(res, trace, hit, hitg, final_loss, fe, fg, fp, total,
+                        {k: float(v) for k, v in zip(GLOBAL_NAMES, start.glob().detach().cpu().numpy())})

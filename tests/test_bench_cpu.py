@@ -1,4 +1,4 @@
-"""Host logic of bench.py: the raster's candidate-pixel count against closed forms, the
+"""Host logic of bench.py: the raster's work units against closed forms, the
 counter-summary stamp (measured traffic only for the library the summary measured),
 the frame's VALU-issue floor from a summary, and the one-GPU rule."""
 import math
@@ -22,19 +22,29 @@ def table(rows):
     return s
 
 
-def test_raster_candidates_closed_forms():
+def test_raster_work_closed_forms():
     H, W = 64, 48
-    # axis-aligned square prism of half-width 5 centred on a pixel centre: pixels 15..25 per axis
-    assert bench.raster_candidates(table([(20.5, 20.5, 0.0, 5, 5, 0)]), H, W) == (121.0, 0.0)
-    # the same square turned by 45 degrees: half-extent 5 sqrt 2 = 7.07, pixels 13..27 per axis
-    assert bench.raster_candidates(table([(20.5, 20.5, math.pi / 4, 5, 5, 0)]), H, W) == (225.0, 0.0)
-    # a circle (ellipsoid a = b) has the axis-aligned square's extent at any angle
-    assert bench.raster_candidates(table([(20.5, 20.5, 1.1, 5, 5, 1)]), H, W) == (0.0, 121.0)
-    # clipped by the canvas corner: columns and rows 0..5
-    assert bench.raster_candidates(table([(0.0, 0.0, 0.0, 5, 5, 0)]), H, W) == (36.0, 0.0)
-    # a table sums its particles by kind
+    # square prism of half-width 5 centred on a pixel centre: binning box ext = 5 sqrt 2 + 1 = 8.07,
+    # pixels 12..28 per axis; its four edges (perimeter 4 (a + b) = 40) cross 40 pixels when axis-aligned
+    assert bench.raster_work(table([(20.5, 20.5, 0.0, 5, 5, 0)]), H, W) == (289.0, 40.0)
+    # turned by 45 degrees: the same box, the edges cross sqrt 2 more pixels
+    t, c = bench.raster_work(table([(20.5, 20.5, math.pi / 4, 5, 5, 0)]), H, W)
+    assert t == 289.0 and c == pytest.approx(40.0 * math.sqrt(2.0), rel=1e-6)
+    # an ellipsoid: ext = max(a, b) + 1 = 6, pixels 14..26, no clips
+    assert bench.raster_work(table([(20.5, 20.5, 1.1, 5, 5, 1)]), H, W) == (169.0, 0.0)
+    # clipped by the canvas corner: columns and rows 0..8
+    assert bench.raster_work(table([(0.0, 0.0, 0.0, 5, 5, 0)]), H, W) == (81.0, 40.0)
     both = table([(20.5, 20.5, 0.0, 5, 5, 0), (0.0, 0.0, 0.0, 5, 5, 0), (20.5, 20.5, 1.1, 5, 5, 1)])
-    assert bench.raster_candidates(both, H, W) == (157.0, 121.0)
+    assert bench.raster_work(both, H, W) == (539.0, 80.0)
+
+
+def test_raster_flop_model_matches_the_frame():
+    # the 2048^2 x 40k frame: 19.2 M candidate tests and 1.5 M clips, 0.50 GFLOP
+    from paper_2606_21381_amd import workloads
+    fr = workloads.config1()
+    t, c = bench.raster_work(fr.soa, fr.H, fr.W)
+    assert 1.90e7 < t < 1.94e7 and 1.4e6 < c < 1.6e6
+    assert 0.48e9 < t * bench.RASTER_FLOP_PER_TEST + c * bench.RASTER_FLOP_PER_CLIP < 0.52e9
 
 
 def summary(stamp, rows):
@@ -46,8 +56,9 @@ def summary(stamp, rows):
     return "\n".join(lines) + "\n"
 
 
-FRAME = [("k_bin", 1_000_000), ("k_bin_clear", 1_000), ("k_pass1<11, 8>", 2_000_000), ("k_pass2<11, 8>", 500_000),
-         ("k_pass3<11, 8>", 3_000_000), ("k_raster<false, false>", 10_000_000)]
+FRAME = [("k_bin", 1_000_000), ("k_bin_clear", 1_000), ("k_tile_scan", 2_000), ("k_emit", 300_000),
+         ("k_pass1<11, 8>", 2_000_000), ("k_pass2<11, 8>", 500_000), ("k_pass3<11, 8>", 3_000_000),
+         ("k_raster<false, false>", 10_000_000)]
 
 
 @pytest.fixture

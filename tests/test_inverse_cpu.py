@@ -76,3 +76,67 @@ def test_curriculum_stages():
     assert inverse.stage_groups(cur, 10) == frozenset(("position", "width"))
     assert inverse.stage_groups(cur, 15) == frozenset(("bias",))
     assert inverse.stage_groups(cur, 1000) == frozenset(("bias",))
+
+
+def _toy_model(H=64, W=64, n=6):
+    """A smooth stand-in for the renderer: oriented Gaussian blobs (long axis w, short
+    axis (0.5 + 0.1 shear) w) scaled by dn, each with a round halo of twice its width
+    weighted by dz, on a background set by the bias (every global has its own
+    signature); gradients by autograd."""
+    from paper_2606_21381_amd import polish
+    jj, ii = torch.meshgrid(torch.arange(W, dtype=torch.float64), torch.arange(H, dtype=torch.float64), indexing="xy")
+
+    def render(x, y, a, w, glob):
+        x, y, a, w, glob = (t.double() for t in (x, y, a, w, glob))
+        dx = jj[None] - x[:, None, None]
+        dy = ii[None] - y[:, None, None]
+        c, s = torch.cos(a)[:, None, None], torch.sin(a)[:, None, None]
+        u, v = c * dx + s * dy, -s * dx + c * dy
+        ww = w[:, None, None]
+        sv = (0.5 + 0.1 * glob[2]) * ww
+        blobs = torch.exp(-(u * u) / (ww * ww) - (v * v) / (sv * sv))
+        halo = torch.exp(-(dx * dx + dy * dy) / (4.0 * ww * ww))
+        return (glob[3] + 30.0 * glob[0] * blobs.sum(0) + 0.2 * glob[1] * halo.sum(0)).float()
+
+    def grad(x, y, a, w, glob, gI):
+        v = [t.detach().clone().requires_grad_(True) for t in (x, y, a, w, glob)]
+        (render(*v).double() * gI.double()).sum().backward()
+        return torch.stack([v[0].grad, v[1].grad, v[2].grad, v[3].grad]).float(), v[4].grad.float()
+
+    return polish.Model(H, W, None, torch.ones(n), render_fn=render, grad_fn=grad), render
+
+
+def test_polish_recovers_a_toy_problem():
+    """Angle search plus Gauss-Newton-CG from a start 0.15 rad, 0.3 px and 5 % off the
+    truth of six well-separated blobs: every parameter within 1e-3 of its scale."""
+    from paper_2606_21381_amd import polish
+    torch.manual_seed(0)
+    model, render = _toy_model()
+    x = torch.tensor([12.0, 30.0, 50.0, 14.0, 33.0, 52.0])
+    y = torch.tensor([12.0, 14.0, 11.0, 45.0, 50.0, 47.0])
+    a = torch.tensor([0.3, 1.0, 2.0, 0.6, 1.4, 2.6])
+    w = torch.tensor([3.0, 4.0, 3.5, 4.5, 3.2, 3.8])
+    g = torch.tensor([0.03, 0.5, 0.2, 1.0])
+    target = render(x, y, a, w, g)
+    pert = torch.tensor([1.0, -1.0, 1.0, -1.0, 1.0, -1.0])
+    pc = polish.PolishConfig(iters=12, margin_px=6.0, separation_px=6.0, eps=(0.01, 0.01, 0.002, 0.01),
+                             eps_glob=(1e-4, 0.01, 0.01, 0.01), angle_span=0.3, angle_steps=31, research_w_max=10.0)
+    res = polish.polish(target, model, x + 0.3 * pert, y - 0.3 * pert, a + 0.15 * pert, w * 1.05,
+                        g * torch.tensor([1.05, 0.95, 1.05, 1.02]), pc)
+    xr, yr, ar, wr, gr = res[:5]
+    da = torch.remainder(ar - a + math.pi / 4, math.pi / 2) - math.pi / 4
+    assert float((xr - x).abs().max()) < 3e-3 and float((yr - y).abs().max()) < 3e-3
+    assert float(da.abs().max()) < 2e-4 and float((wr - w).abs().max()) < 3e-3
+    assert float(((gr - g).abs() / g.abs()).max()) < 1e-3
+
+
+def test_colouring_keeps_colours_apart():
+    from paper_2606_21381_amd import polish
+    rng = np.random.default_rng(1)
+    x, y, w = rng.uniform(0, 256, 60), rng.uniform(0, 256, 60), rng.uniform(3, 8, 60)
+    color, bounds = polish.color_windows(x, y, w, 256, 256, 5.0, 20.0)
+    sep = w * math.sqrt(2) + 20.0
+    for i in range(60):
+        same = (color == color[i]) & (np.arange(60) != i)
+        assert not np.any(same & (np.abs(x - x[i]) < sep + sep[i]) & (np.abs(y - y[i]) < sep + sep[i]))
+    assert np.all(bounds[:, 0] <= bounds[:, 1]) and np.all(bounds[:, 0] >= 0) and np.all(bounds[:, 1] <= 255)
