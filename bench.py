@@ -446,11 +446,16 @@ def bench_variants(render, fr, g, dev, reps=20):
     soa_h = torch.from_numpy(workloads.f32(hab)).to(dev)
     habits = [workloads.habit_octahedron(), workloads.habit_tetragonal(0.5),
               workloads.habit_tetragonal(0.3, topo_amplitude_um=0.15, topo_cell_px=4.0)]
+    frc = workloads.config1_clustered()
+    soa_c = torch.from_numpy(frc.soa).to(dev)
     cases = {"absorbing_dic": (soa9, replace(fr.optics, absorption=1)),
              "incoherent_dic": (soa8, replace(fr.optics, mode=workloads.DIC_INCOHERENT)),
-             "habits_dic": (soa_h, fr.optics)}
+             "habits_dic": (soa_h, fr.optics),
+             "uniform_dic": (soa8, fr.optics),
+             "clustered_dic": (soa_c, frc.optics)}
     res = {"workload": "dic2048_n40000 (absorbing: dmu ~ U[0, 0.4] 1/um; habits: a third of the particles "
-                       "as octahedra / tetragonal bipyramids, one habit with micro-topography)"}
+                       "as octahedra / tetragonal bipyramids, one habit with micro-topography; clustered: the "
+                       "40,000 centres in 64 Gaussian clusters of sigma 25 px)"}
     for name, (s, o) in cases.items():
         if name == "habits_dic":
             render.set_habits(habits, 7)
@@ -468,6 +473,17 @@ def bench_variants(render, fr, g, dev, reps=20):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         res[name] = {"ms_per_frame": round(ms, 4), "frames_per_s": round(1000.0 / ms, 1)}
+        if name in ("uniform_dic", "clustered_dic"):  # per-stage times: does crowding slow the raster?
+            import ctypes
+            from paper_2606_21381_amd import _lib
+            lib, ctx = _lib.load(), render.context(dev)
+            _lib.check(lib.osog_profile_enable(ctx, 1), "profile_enable")
+            for _ in range(reps):
+                render.render(s, fr.H, fr.W, o, g, out=out, workspace=ws)
+            st_ms, st_n = (ctypes.c_double * 10)(), (ctypes.c_int64 * 10)()
+            _lib.check(lib.osog_profile_read(ctx, st_ms, st_n), "profile_read")
+            _lib.check(lib.osog_profile_enable(ctx, 0), "profile_disable")
+            res[name]["stage_us"] = {_lib.STAGES[k]: round(1000.0 * st_ms[k] / st_n[k], 2) for k in range(5) if st_n[k]}
         if name == "habits_dic":
             render.set_habits([], 0)
     return res

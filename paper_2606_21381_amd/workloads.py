@@ -91,6 +91,28 @@ def mixed(rng: np.random.Generator, n: int, H: int, W: int) -> np.ndarray:
     return s[:, rng.permutation(n)] if n else s
 
 
+def clustered(rng: np.random.Generator, n: int, H: int, W: int, clusters: int = 64, sigma_px: float = 25.0) -> np.ndarray:
+    """The mixed table with its centres drawn in clusters (a suspension whose crystals
+    aggregate): cluster centres uniform over the canvas, each particle's centre
+    Gaussian (sigma_px) around a uniformly chosen cluster, wrapped onto the canvas."""
+    s = mixed(rng, n, H, W)
+    cc = np.stack([rng.uniform(0, W, clusters), rng.uniform(0, H, clusters)])
+    k = rng.integers(0, clusters, n)
+    s[0] = np.mod(cc[0, k] + rng.normal(0.0, sigma_px, n), W)
+    s[1] = np.mod(cc[1, k] + rng.normal(0.0, sigma_px, n), H)
+    return s
+
+
+def config1_clustered(seed: int = 1, n: int = 40000, size: int = 2048, photons: float = 1000.0) -> Frame:
+    """The 2048x2048 DIC frame of config1 with its 40,000 particles in 64 Gaussian
+    clusters of sigma 25 px (tiles at the cluster cores hold hundreds of particles)."""
+    rng = np.random.Generator(np.random.PCG64(seed + 7000))
+    soa = f32(clustered(rng, n, size, size))
+    dz = rng.uniform(-2.0, 2.0)
+    g = np.array([dz, 1.0, math.pi / 2, 0.0], np.float32)
+    return Frame(size, size, soa, dic_optics(photons, seed), g, "dic%d_n%d_clustered" % (size, n))
+
+
 def with_absorption(rng: np.random.Generator, s: np.ndarray, lo: float = 0.0, hi: float = 0.4) -> np.ndarray:
     """The table with a ninth row, dmu ~ U[lo, hi] 1/um, appended."""
     dmu = rng.uniform(lo, hi, s.shape[1])
