@@ -195,7 +195,7 @@ def main():
                     help="after the timed run, one plain device-to-device copy of this many MiB "
                          "(reference dispatch for hardware byte counters)")
     ap.add_argument("--no-learned", action="store_true",
-                    help="skip training the learned initializer (200,000 rendered crops) and its comparison of "
+                    help="skip training the learned initializer (600,000 rendered crops) and its comparison of "
                          "inverse solves (part of the inverse leg by default)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -575,7 +575,7 @@ def bench_stream(render, fr, dev, frames=8, reps=10):
             "frames_per_s": round(frames * 1000.0 / ms, 1), "error_flag": b.error_flag()}
 
 
-def bench_inverse(dev, learned=True, learned_targets=6, learned_samples=200_000):
+def bench_inverse(dev, learned=True, learned_targets=6, learned_samples=600_000):
     """1024^2 DIC, 500 prisms (seed 3): the hybrid solve (Adam from the perturbed start,
     angles held until the second-order polish); time to e <= 1e-3.  Then, when
     `learned`, the learned initializer trained on engine-rendered crops against the

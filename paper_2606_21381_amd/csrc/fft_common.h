@@ -345,7 +345,10 @@ __device__ inline void band_chord(const OpticsArgs& o, int kx, int* lo_out, int*
 // log(V inv_alpha / (a/us^2 + b)) with -mu + k log(mu) - log(k!), log(k!) from a
 // table for k < 10 and from Stirling's series
 // (x - 1/2) ln x - x + ln(2 pi)/2 + 1/(12x) - 1/(360 x^3), x = k + 1, above.
-// Every operation is a separately rounded FP32 operation.
+// Every operation is a separately rounded FP32 operation; square roots and
+// quotients use the hardware square root and reciprocal (within 1 ulp), so a
+// decision can differ from an exactly rounded evaluation only for a variate
+// within an ulp or two of a threshold.
 __device__ __forceinline__ float log_factorial(float k) {
 #pragma clang fp contract(off)
   const float table[10] = {0.000000000e+00f, 0.000000000e+00f, 6.931471825e-01f, 1.791759491e+00f,
@@ -353,7 +356,8 @@ __device__ __forceinline__ float log_factorial(float k) {
                            1.060460281e+01f, 1.280182743e+01f};
   if (k < 10.0f) return table[(int)k];
   const float x = k + 1.0f;
-  return (x - 0.5f) * logf(x) - x + 0.918938533f + 1.0f / (12.0f * x) - 1.0f / (360.0f * x * x * x);
+  const float rx = __builtin_amdgcn_rcpf(x);
+  return (x - 0.5f) * logf(x) - x + 0.918938533f + rx * (1.0f / 12.0f) - (rx * rx * rx) * (1.0f / 360.0f);
 }
 
 // PTRS constants for one mean (mu >= 10).
@@ -364,12 +368,12 @@ struct PtrsConst {
 __device__ __forceinline__ PtrsConst ptrs_const(float mu) {
 #pragma clang fp contract(off)
   PtrsConst c;
-  const float smu = sqrtf(mu);
+  const float smu = __builtin_amdgcn_sqrtf(mu);  // mu >= 10: no denormal scaling needed
   c.log_mu = logf(mu);
   c.b = 0.931f + 2.53f * smu;
   c.a = -0.059f + 0.02483f * c.b;
-  c.inv_alpha = 1.1239f + 1.1328f / (c.b - 3.4f);
-  c.vr = 0.9277f - 3.6224f / (c.b - 2.0f);
+  c.inv_alpha = 1.1239f + 1.1328f * __builtin_amdgcn_rcpf(c.b - 3.4f);
+  c.vr = 0.9277f - 3.6224f * __builtin_amdgcn_rcpf(c.b - 2.0f);
   return c;
 }
 
@@ -381,7 +385,7 @@ __device__ __forceinline__ bool ptrs_quick(uint32_t wu, uint32_t wv, float mu, f
   const float U = u01(wu) - 0.5f;
   const float V = u01(wv);
   const float us = 0.5f - fabsf(U);
-  const float kf = floorf((((2.0f * a) / us) + b) * U + (mu + 0.43f));
+  const float kf = floorf((((2.0f * a) * __builtin_amdgcn_rcpf(us)) + b) * U + (mu + 0.43f));
   *U_out = U; *V_out = V; *us_out = us; *kf_out = kf;
   return us >= 0.07f && V <= vr;
 }
@@ -392,7 +396,7 @@ __device__ __forceinline__ int ptrs_attempt(uint32_t wu, uint32_t wv, float mu, 
   float U, V, us, kf;
   if (ptrs_quick(wu, wv, mu, c.a, c.b, c.vr, &U, &V, &us, &kf)) return (int)kf;
   if (kf < 0.0f || (us < 0.013f && V > us)) return -1;
-  const float lhs = logf(V * c.inv_alpha / (c.a / (us * us) + c.b));
+  const float lhs = logf(V * c.inv_alpha * __builtin_amdgcn_rcpf(c.a * __builtin_amdgcn_rcpf(us * us) + c.b));
   const float rhs = (-mu + kf * c.log_mu) - log_factorial(kf);
   return lhs <= rhs ? (int)kf : -1;
 }
@@ -406,7 +410,7 @@ __device__ __forceinline__ int poisson_small(float mu, uint32_t w0) {
   int k = 0;
   while (u > F && k < 40) {
     ++k;
-    p = p * (mu / (float)k);
+    p = p * (mu * __builtin_amdgcn_rcpf((float)k));
     F = F + p;
   }
   return k;

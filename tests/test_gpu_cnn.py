@@ -113,19 +113,31 @@ def test_training_on_engine_crops_reduces_loss():
 
 
 def test_trained_network_beats_the_default_start():
-    """Trained on 400,000 engine-rendered crops, the network's held-out error on the
-    four globals is compared with the default start of the inverse problem, which
-    multiplies each true global by 1 + U[-0.2, 0.2]: its mean absolute error is
-    0.1 E|g| over the training distribution of the globals (dn ~ U[0.01, 0.05],
-    dz ~ U[-2, 2] um, shear ~ U[0.8, 1.2] px, bias ~ pi/2 U[0.8, 1.2])."""
+    """Trained on 600,000 engine-rendered 256^2 crops, the network predicts the four
+    globals of held-out 1024^2 frames (500 prisms each, globals drawn from the training
+    distribution; the network runs fully convolutionally with a global pool, as the
+    inverse solve uses it) with a smaller mean absolute error than the inverse
+    problem's default start, which multiplies each true global by 1 + U[-0.2, 0.2]:
+    0.1 E|g| over that distribution (dn ~ U[0.01, 0.05], dz ~ U[-2, 2] um, shear ~
+    U[0.8, 1.2] px, bias ~ pi/2 U[0.8, 1.2]) -- on every global."""
     need_gpu()
-    from paper_2606_21381_amd import cnn
+    from paper_2606_21381_amd import cnn, render, workloads
     net = cnn.LearnedInit()
-    losses, secs = net.train(samples=400_000, lr=1e-3)
-    mae = net.evaluate(1024, seed=5)
+    losses, secs = net.train(samples=600_000, lr=1e-3)
+    crop_mae = net.evaluate(1024, seed=5)
+    rng = np.random.Generator(np.random.PCG64(6))
+    errs = []
+    for _ in range(16):
+        dn, dz, sh, th = workloads.crop_globals(rng)
+        t = workloads.prisms(rng, 500, 1024, 1024)
+        t[6] = dn
+        g = torch.tensor([dz, sh, th, 0.0], dtype=torch.float32, device="cuda")
+        I = render.render(torch.from_numpy(workloads.f32(t)).cuda(), 1024, 1024, workloads.dic_optics(0.0), g)
+        errs.append(np.abs(net.predict(I) - np.array([dn, dz, sh, th])))
+    mae = np.mean(errs, axis=0)
     default = np.array([0.1 * 0.03, 0.1 * 1.0, 0.1 * 1.0, 0.1 * math.pi / 2])
-    say("trained 400k crops in %.1f s (loss %.4f); held-out MAE dn %.4f dz %.3f um shear %.3f px bias %.4f rad; "
-        "default start %s" % (secs, losses[-50:].mean(), *mae, np.array2string(default, precision=4)))
+    say("trained 600k crops in %.1f s (loss %.4f); held-out 256^2 crop MAE %s; 1024^2 frame MAE dn %.4f dz %.3f um "
+        "shear %.3f px bias %.4f rad; default start %s" % (secs, losses[-50:].mean(), np.array2string(crop_mae, precision=4),
+                                                          *mae, np.array2string(default, precision=4)))
     assert np.isfinite(losses).all()
-    assert mae[3] < 0.5 * default[3]      # the bias is read well from the background level and contrast
-    assert mae[0] < default[0] and mae[1] < 1.5 * default[1]
+    assert np.all(mae < default)
