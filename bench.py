@@ -109,8 +109,11 @@ def measured_counters(kernel):
     cols = head[0][1:]
     for l in lines:
         f = l.split()
-        if f and not l.startswith("#") and f[0].startswith(kernel):
-            # the kernel name may contain spaces ("k_pass1<11, 8>"): the numbers are the last fields
+        if not f or l.startswith("#") or l.startswith("kernel ") or len(f) <= len(cols):
+            continue
+        # the kernel name may contain spaces ("k_pass1<11, 8>"): the numbers are the last fields
+        name = " ".join(f[:-len(cols)])
+        if name == kernel or name.startswith(kernel + "<"):
             v = dict(zip(cols, map(float, f[-len(cols):])))
             return {"traffic": v["total_MB"] * 1e6, "fetch": v["fetch_MB"] * 1e6, "write": v["write_MB"] * 1e6,
                     "valu_winst": v["valu_winst"], "valu_busy": v["valu%"] / 100.0}

@@ -108,7 +108,7 @@ typedef struct {
 typedef struct osog_context osog_context;
 
 /* Create a context on HIP device `device`: uploads the FFT twiddle table and
- * sets the default tiling (16 x 16 pixel tiles).  Allocates device memory. */
+ * sets the default tiling (32 x 16 pixel tiles: 32 rows by 16 columns).  Allocates device memory. */
 osog_status osog_context_create(osog_context** out, int device);
 osog_status osog_context_destroy(osog_context* ctx);
 

@@ -23,7 +23,7 @@
 struct osog_context {
   int device = 0;
   float2* twiddle = nullptr;  // kTwN entries: (cos, sin)(2 pi m / kTwN)
-  int tile_h = 16, tile_w = 16;
+  int tile_h = 32, tile_w = 16;
   std::map<std::pair<int, int>, std::pair<int, int>> size_tiling;  // per canvas size (autotuner)
   std::map<std::pair<int, int>, int> size_radix;                   // per canvas size (autotuner)
   int fft_radix = 8;

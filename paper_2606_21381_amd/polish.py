@@ -59,6 +59,7 @@ class PolishConfig:
     cg_iters: int = 20            # conjugate-gradient iterations per Gauss-Newton step
     search_every: int = 3         # repeat the angle search every this many steps (0: only at the start)
     research_span: float = 0.3    # bracket of the repeated searches
+    research_refine: int = 0      # further repeated searches, each over a bracket 1/10 as wide
     research_w_max: float = 5.0   # the repeated searches turn only prisms narrower than this [px]
     # parameter scales of the CG's unknowns: x, y [px], angle [rad], width [px]; dn, dz, shear, bias
     scale: tuple = (1.0, 1.0, 0.1, 1.0)
@@ -343,8 +344,11 @@ def polish(target: torch.Tensor, model: Model, x, y, a, w, glob, pc: PolishConfi
     n = model.n
     for it in range(pc.iters):
         if pc.search_every and it > 0 and it % pc.search_every == 0:
-            a = angle_search(model, target, x, y, a, w, glob, win, pc.research_span, pc.angle_steps,
-                             only=w < pc.research_w_max)
+            span = pc.research_span
+            for r in range(1 + pc.research_refine):
+                a = angle_search(model, target, x, y, a, w, glob, win, span, pc.angle_steps,
+                                 only=w < pc.research_w_max)
+                span /= 10.0
             I = model.render(x, y, a, w, glob)
             L = _loss(I, target)
         if pc.method == "cg":

@@ -61,6 +61,7 @@ def mid_frame(seed, size, n, mode):
 def test_binning_bit_exact(tiling):
     r = R()
     fr = workloads.config1(n=5000, size=1024)
+    th0, tw0 = r.get_tiling()
     r.set_tiling(*tiling)
     try:
         keys, pids, ts, counts, P = r.bin_pairs(dev_soa(fr.soa), fr.H, fr.W)
@@ -72,15 +73,15 @@ def test_binning_bit_exact(tiling):
         assert np.array_equal(ts.cpu().numpy(), ref["tile_start"])
         assert np.array_equal(counts.cpu().numpy(), ref["counts"])
     finally:
-        r.set_tiling(16, 16)
+        r.set_tiling(th0, tw0)
 
 
 def test_binning_bit_exact_full_size():
     r = R()
     fr = workloads.config1()
     keys, pids, ts, counts, P = r.bin_pairs(dev_soa(fr.soa), fr.H, fr.W)
-    ref = oracle.binning.bin_pairs(fr.soa, fr.H, fr.W, 16, 16)
-    say("binning 2048^2 x 40000 pairs", P)
+    ref = oracle.binning.bin_pairs(fr.soa, fr.H, fr.W, *r.get_tiling())
+    say("binning 2048^2 x 40000 pairs (tiles %s)" % (r.get_tiling(),), P)
     assert np.array_equal(keys.cpu().numpy(), ref["keys"])
     assert np.array_equal(pids.cpu().numpy(), ref["pids"])
     assert np.array_equal(ts.cpu().numpy(), ref["tile_start"])
@@ -125,12 +126,13 @@ def test_deterministic_and_tiling_invariant():
     a_opd, a_I = gpu_frame(fr)
     b_opd, b_I = gpu_frame(fr)
     assert np.array_equal(a_opd, b_opd) and np.array_equal(a_I, b_I)
-    for tl in [(8, 32), (32, 8), (64, 4), (32, 32), (32, 16), (4, 256)]:
+    th0, tw0 = r.get_tiling()
+    for tl in [(16, 16), (8, 32), (32, 8), (64, 4), (32, 32), (32, 16), (4, 256)]:
         r.set_tiling(*tl)
         try:
             c_opd, c_I = gpu_frame(fr)
         finally:
-            r.set_tiling(16, 16)
+            r.set_tiling(th0, tw0)
         assert np.array_equal(a_opd, c_opd), tl
         assert np.array_equal(a_I, c_I), tl
 
@@ -171,7 +173,12 @@ def test_crowded_tiles_sorted_and_scanned_paths():
     r = R()
     fr = crowded_frame()
     soa, g = dev_soa(fr.soa), dev_globals(fr.globals4)
-    keys, pids, ts, counts, P = r.bin_pairs(soa, fr.H, fr.W)
+    th0, tw0 = r.get_tiling()
+    r.set_tiling(16, 16)  # the frame's crowding is laid out for 16 x 16 tiles
+    try:
+        keys, pids, ts, counts, P = r.bin_pairs(soa, fr.H, fr.W)
+    finally:
+        r.set_tiling(th0, tw0)
     ref = oracle.binning.bin_pairs(fr.soa, fr.H, fr.W, 16, 16)
     per_tile = np.diff(ref["tile_start"])
     say("crowded: pairs %d, max per tile %d, tiles over 64: %d, over 512: %d" % (
@@ -195,7 +202,7 @@ def test_crowded_tiles_sorted_and_scanned_paths():
         I2, opd2 = r.render(soa, fr.H, fr.W, fr.optics, g, want_opd=True)
         torch.cuda.synchronize()
     finally:
-        r.set_tiling(16, 16)
+        r.set_tiling(th0, tw0)
     assert torch.equal(opd, opd2) and torch.equal(I, I2)
 
 
@@ -303,5 +310,5 @@ def test_radix4_plan_and_autotuner():
     assert (choice["tile_h"], choice["tile_w"]) in [(16, 16), (32, 32), (32, 16), (16, 32), (64, 16)]
     assert choice["fft_radix"] in (4, 8)
     # back to the defaults for the other tests
-    render._lib.check(lib.osog_set_size_tiling(render.context(), 512, 512, 16, 16), "tiling")
+    render._lib.check(lib.osog_set_size_tiling(render.context(), 512, 512, *render.get_tiling()), "tiling")
     render._lib.check(lib.osog_set_size_radix(render.context(), 512, 512, 8), "radix")

@@ -76,7 +76,7 @@ def test_habit_binning_bit_exact(habits):
     keys, pids, ts, counts, P = render.bin_pairs(dev_soa(soa), 512, 512)
     torch.cuda.synchronize()
     radii = np.array([h.radius for h in HABITS], np.float32)
-    ref = oracle.binning.bin_pairs(soa, 512, 512, 16, 16, habit_radius=radii)
+    ref = oracle.binning.bin_pairs(soa, 512, 512, *render.get_tiling(), habit_radius=radii)
     assert P == len(ref["keys"])
     assert np.array_equal(keys.cpu().numpy(), ref["keys"]) and np.array_equal(pids.cpu().numpy(), ref["pids"])
     assert np.array_equal(ts.cpu().numpy(), ref["tile_start"])

@@ -65,7 +65,7 @@ def test_habit_binning_4096():
         soa = workloads.f32(s)
         keys, pids, ts, counts, P = render.bin_pairs(dev_soa(soa), N, N)
         torch.cuda.synchronize()
-        ref = oracle.binning.bin_pairs(soa, N, N, 16, 16, habit_radius=np.array([h.radius for h in habits], np.float32))
+        ref = oracle.binning.bin_pairs(soa, N, N, *render.get_tiling(), habit_radius=np.array([h.radius for h in habits], np.float32))
         say("habit binning 4096^2: %d pairs" % P)
         assert P == len(ref["keys"]) and np.array_equal(keys.cpu().numpy(), ref["keys"])
         assert np.array_equal(pids.cpu().numpy(), ref["pids"])
