@@ -113,7 +113,10 @@ def measured_counters(kernel):
             continue
         # the kernel name may contain spaces ("k_pass1<11, 8>"): the numbers are the last fields
         name = " ".join(f[:-len(cols)])
-        if name == kernel or name.startswith(kernel + "<"):
+        # a whole name, or a prefix that does not stop inside an identifier ("k_bin" is
+        # not "k_bin_clear"; "k_pass1<11" is "k_pass1<11, 8>")
+        nxt = name[len(kernel):len(kernel) + 1]
+        if name.startswith(kernel) and not (nxt.isalnum() or nxt == "_"):
             v = dict(zip(cols, map(float, f[-len(cols):])))
             return {"traffic": v["total_MB"] * 1e6, "fetch": v["fetch_MB"] * 1e6, "write": v["write_MB"] * 1e6,
                     "valu_winst": v["valu_winst"], "valu_busy": v["valu%"] / 100.0}
@@ -578,7 +581,7 @@ def bench_stream(render, fr, dev, frames=8, reps=10):
             "frames_per_s": round(frames * 1000.0 / ms, 1), "error_flag": b.error_flag()}
 
 
-def bench_inverse(dev, learned=True, learned_targets=6, learned_samples=600_000):
+def bench_inverse(dev, learned=True, learned_targets=10, learned_samples=600_000):
     """1024^2 DIC, 500 prisms (seed 3): the hybrid solve (Adam from the perturbed start,
     angles held until the second-order polish); time to e <= 1e-3.  Then, when
     `learned`, the learned initializer trained on engine-rendered crops against the

@@ -53,7 +53,8 @@ __global__ void __launch_bounds__(64) k_sort_segments(FrameDev F, int* __restric
   if (lane == 0) tile_start[tile] = start;
   if ((int64_t)F.tile_start[F.n_tiles] > capacity) return;  // the lists would not fit: left untouched
   int base = start;
-  for_tile_ids(F, tile, lane, seg, [&](int mine, int m) {
+  const TileIds T = tile_ids(F, tile, lane, seg);
+  visit_tile_ids(F, tile, lane, T, [&](int mine, int m) {
     if (lane < m) {
       out_pids[base + lane] = mine;
       out_keys[base + lane] = tile;

@@ -228,10 +228,13 @@ __device__ __forceinline__ void emit_body(const FrameDev& F, int64_t gid) {
 
 // ---- F4: a segment's particle ids in ascending order, for one 64-lane wave ------
 // Up to 64 ids are sorted in registers (bitonic network over the lanes), up to
-// kSegSort in LDS.  A longer segment, or one cut short by the list's capacity, is
-// not sorted: the reader visits all particles in id order and keeps those whose
-// box meets the tile (the same ids in the same order).
+// kSegSort in LDS and then held in registers, kSegRegs per lane, so that the LDS
+// used for the sort is free again while the ids are visited.  A longer segment,
+// or one cut short by the list's capacity, is not sorted: the reader visits all
+// particles in id order and keeps those whose box meets the tile (the same ids in
+// the same order).
 constexpr int kSegSort = 512;
+constexpr int kSegRegs = kSegSort / 64;
 
 __device__ __forceinline__ int wave_sort64(int v, int lane) {
 #pragma unroll
@@ -269,48 +272,77 @@ __device__ __forceinline__ bool box_meets(const FrameDev& F, int64_t p, int x0, 
   return !(b.x > b.y || b.x > x1 || b.y < x0 || b.z > y1 || b.w < y0);
 }
 
-// Visits the ids of tile `tile` in ascending order, up to 64 at a time: visit(ids
-// held by the lanes, count).  `seg`: kSegSort ints of LDS.  Returns true when the
-// segment was read by the id-ordered scan.  (It writes no global memory, so the
-// records it reads stay provably unclobbered and load through the scalar cache.)
-template <class Visit>
-__device__ __forceinline__ bool for_tile_ids(const FrameDev& F, int tile, int lane, int* seg, Visit&& visit) {
+// A tile's sorted segment as the lanes hold it: id c * 64 + lane in v[c].
+struct TileIds {
+  int v[kSegRegs];
+  int cnt;    // ids in the segment
+  bool scan;  // not stored or too long: read by the id-ordered scan instead
+};
+
+// Reads and sorts tile `tile`'s segment.  `seg`: kSegSort ints of LDS, free again
+// on return (the workgroup is one wave).
+__device__ __forceinline__ TileIds tile_ids(const FrameDev& F, int tile, int lane, int* seg) {
+  TileIds T;
   const int start = F.tile_start[tile], end = F.tile_start[tile + 1];
-  const int cnt = end - start;
-  const bool stored = end <= F.pair_cap;
+  T.cnt = end - start;
+  T.scan = !(end <= F.pair_cap && T.cnt <= kSegSort);
+#pragma unroll
+  for (int c = 0; c < kSegRegs; ++c) T.v[c] = 0;
+  if (T.scan || T.cnt == 0) return T;
   const int* __restrict__ pids = F.pids + start;
-  if (stored && cnt <= 64) {
-    if (cnt > 0) visit(wave_sort64(lane < cnt ? pids[lane] : INT_MAX, lane), cnt);
-  } else if (stored && cnt <= kSegSort) {
+  if (T.cnt <= 64) {
+    T.v[0] = wave_sort64(lane < T.cnt ? pids[lane] : INT_MAX, lane);
+  } else {
     int n2 = 128;
-    while (n2 < cnt) n2 <<= 1;
-    for (int i = lane; i < n2; i += 64) seg[i] = i < cnt ? pids[i] : INT_MAX;
+    while (n2 < T.cnt) n2 <<= 1;
+    for (int i = lane; i < n2; i += 64) seg[i] = i < T.cnt ? pids[i] : INT_MAX;
     __syncthreads();
     lds_sort(seg, n2, lane);
-    for (int c0 = 0; c0 < cnt; c0 += 64) {
-      const int m = min(64, cnt - c0);
-      visit(lane < m ? seg[c0 + lane] : 0, m);
-    }
-  } else {
-    const int ty = tile / F.ntx, tx = tile - ty * F.ntx;
-    const int x0 = tx * F.tile_w, x1 = x0 + F.tile_w - 1, y0 = ty * F.tile_h, y1 = y0 + F.tile_h - 1;
-    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
-    for (int64_t p0 = 0; p0 < F.n; p0 += 64) {
-      const int64_t p = p0 + lane;
-      const bool hit = p < F.n && box_meets(F, p, x0, x1, y0, y1);
-      const uint64_t m = __ballot(hit);
-      if (!m) continue;
-      // compact the hits into the low lanes, keeping their order
-      if (hit) seg[__popcll(m & below)] = (int)p;
-      __syncthreads();
-      const int c = __popcll(m);
-      const int mine = lane < c ? seg[lane] : 0;
-      __syncthreads();
-      visit(mine, c);
-    }
-    return true;
+#pragma unroll
+    for (int c = 0; c < kSegRegs; ++c)
+      if (c * 64 < T.cnt) T.v[c] = seg[c * 64 + lane];  // c * 64 + lane < n2
+    __syncthreads();
   }
-  return false;
+  return T;
+}
+
+// Visits the ids of T in ascending order, up to 64 at a time: visit(ids held by
+// the lanes, count).  The scan path compacts each 64-particle window's hits into
+// the low lanes with a lane permutation (no LDS).  Returns true when the segment
+// was read by the scan.  (It writes no global memory, so the records the visitor
+// reads stay provably unclobbered and load through the scalar cache.)
+template <class Visit>
+__device__ __forceinline__ bool visit_tile_ids(const FrameDev& F, int tile, int lane, const TileIds& T,
+                                               Visit&& visit) {
+  if (!T.scan) {
+    // one visit site (the visitor is inlined once): the chunks shift down through v
+    int v[kSegRegs];
+#pragma unroll
+    for (int c = 0; c < kSegRegs; ++c) v[c] = T.v[c];
+#pragma unroll 1
+    for (int c0 = 0; c0 < T.cnt; c0 += 64) {
+      visit(v[0], min(64, T.cnt - c0));
+#pragma unroll
+      for (int c = 0; c + 1 < kSegRegs; ++c) v[c] = v[c + 1];
+    }
+    return false;
+  }
+  const int ty = tile / F.ntx, tx = tile - ty * F.ntx;
+  const int x0 = tx * F.tile_w, x1 = x0 + F.tile_w - 1, y0 = ty * F.tile_h, y1 = y0 + F.tile_h - 1;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (int64_t p0 = 0; p0 < F.n; p0 += 64) {
+    const int64_t p = p0 + lane;
+    const bool hit = p < F.n && box_meets(F, p, x0, x1, y0, y1);
+    const uint64_t m = __ballot(hit);
+    if (!m) continue;
+    // hits to lanes [0, c) in order, the others to [c, 64): a permutation
+    const int c = __popcll(m);
+    const int hb = __popcll(m & below);
+    const int dst = hit ? hb : c + (lane - hb);
+    const int mine = __builtin_amdgcn_ds_permute(dst << 2, (int)p);
+    visit(mine, c);
+  }
+  return true;
 }
 
 // ---- F5: rasterise one tile with one 64-lane wave ------------------------------
@@ -339,18 +371,20 @@ constexpr int kQueue = 128;  // queued costly pixels per wave: 64 plus one batch
 
 // LDS of one raster wave, for a tile of `area` pixels (layout of raster_lds_bytes)
 struct RasterLds {
+  __device__ int* acc_ids() const { return reinterpret_cast<int*>(acc); }  // sort space (acc, cacc)
   float* acc;   // [area] terms in ascending particle id
   float* cacc;  // [area] costly terms in ascending particle id
   float* tacc;  // [area] absorbance (ABS)
   float* ctacc; // [area]
   int* qpix;    // [kQueue] tile pixel index of a queued pixel
   int* qpid;    // [kQueue] its particle
-  int* seg;     // [kSegSort] a long segment's ids
 };
 
+// (A segment is sorted in the sums' space before they are cleared: 2 * area >= kSegSort.)
 __host__ __device__ constexpr int raster_lds_bytes(int area, bool abs) {
-  return 4 * area * (abs ? 4 : 2) + 8 * kQueue + 4 * kSegSort;
+  return 4 * area * (abs ? 4 : 2) + 8 * kQueue;
 }
+static_assert(2 * kMinTile >= kSegSort, "a segment sorts in the space of two tile sums");
 
 __device__ __forceinline__ RasterLds raster_lds(char* base, int area, bool abs) {
   RasterLds L;
@@ -362,7 +396,6 @@ __device__ __forceinline__ RasterLds raster_lds(char* base, int area, bool abs) 
   int* q = reinterpret_cast<int*>(f + area * (abs ? 4 : 2));
   L.qpix = q;
   L.qpid = q + kQueue;
-  L.seg = q + 2 * kQueue;
   return L;
 }
 
@@ -609,6 +642,8 @@ __device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int lan
   G.topo_hi = F.topo_hi;
   const int area = G.tw * G.th;
   const RasterLds L = raster_lds(lds, area, ABS);
+  // the segment is sorted in the space of the sums, which are cleared afterwards
+  const TileIds T = tile_ids(F, tile, lane, L.acc_ids());
   for (int q = lane; q < area; q += 64) {
     L.acc[q] = 0.0f;
     L.cacc[q] = 0.0f;
@@ -620,7 +655,7 @@ __device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int lan
   __syncthreads();
   int qn = 0;
   const PRec* __restrict__ recs = F.recs;
-  const bool scanned = for_tile_ids(F, tile, lane, L.seg, [&](int mine, int m) {
+  const bool scanned = visit_tile_ids(F, tile, lane, T, [&](int mine, int m) {
     // wave-uniform records through the scalar cache, the next one requested
     // before the current one is rasterised
     int pid = __builtin_amdgcn_readlane(mine, 0);

@@ -28,6 +28,9 @@ library's forward render and hand-written adjoint:
   disjoint the neighbours' changes dominated a small prism's window loss.
   Repeated searches turn only prisms narrower than ``research_w_max``: the large
   ones' angles are well determined, and turning them leaves far-reaching residuals.
+  They scan a whole period of the square's angle (+-pi/4), since a small prism's
+  first search, made while the positions were still off, can end in a side minimum
+  more than the first bracket away from the truth.
 
 Nothing here computes an image: every render and gradient goes through libosog
 (or the injected functions the CPU tests use).
@@ -58,8 +61,8 @@ class PolishConfig:
     method: str = "cg"            # "cg": Gauss-Newton by preconditioned CG; "block": block steps only
     cg_iters: int = 20            # conjugate-gradient iterations per Gauss-Newton step
     search_every: int = 3         # repeat the angle search every this many steps (0: only at the start)
-    research_span: float = 0.3    # bracket of the repeated searches
-    research_refine: int = 0      # further repeated searches, each over a bracket 1/10 as wide
+    research_span: float = math.pi / 4  # bracket of the repeated searches (a full period of a square)
+    research_refine: int = 1      # further repeated searches, each over a bracket 1/10 as wide
     research_w_max: float = 5.0   # the repeated searches turn only prisms narrower than this [px]
     # parameter scales of the CG's unknowns: x, y [px], angle [rad], width [px]; dn, dz, shear, bias
     scale: tuple = (1.0, 1.0, 0.1, 1.0)
