@@ -159,7 +159,8 @@ __global__ void __launch_bounds__(kThreads) k_adj_pass1(const float2* __restrict
                                                         const float* __restrict__ opd,
                                                         const float* __restrict__ tau,
                                                         const float* __restrict__ grad_opd,
-                                                        float phase_k, const float2* __restrict__ tw,
+                                                        float phase_k, float inv_lambda,
+                                                        const float2* __restrict__ tw,
                                                         float* __restrict__ gopd, float* __restrict__ gtau,
                                                         int64_t plane) {
   constexpr int W = 1 << LOGW, RB = rows_per_block(W);
@@ -193,7 +194,7 @@ __global__ void __launch_bounds__(kThreads) k_adj_pass1(const float2* __restrict
       const int idx = i0 + u * kThreads;
       if (idx >= NP) continue;
       float s, c;
-      sincosf(phase_k * ov[u], &s, &c);
+      phase_sincos(ov[u], inv_lambda, &s, &c);
       if (tau) {  // U = e^{-tau} (c + i s), as pass 1 forms it
         const float am = expf(-tv[u]);
         c = am * c;
@@ -491,7 +492,7 @@ hipError_t launch_adj_pass1(const FramePlan& p, const float* opd, const float* t
   const float* ta = p.absorb ? tau : nullptr;
   const int64_t plane = (int64_t)p.H * p.W;
 #define K(LG) hipLaunchKernelGGL(k_adj_pass1<LG>, dim3(p.H / p.rb), dim3(kThreads), 0, s, b.band2, o, opd, ta, \
-                                 grad_opd, p.phase_k, tw, b.gopd, b.gtau, plane)
+                                 grad_opd, p.phase_k, p.inv_lambda, tw, b.gopd, b.gtau, plane)
   OSOG_SIZE_SWITCH(p.logW, K)
 #undef K
   return hipGetLastError();

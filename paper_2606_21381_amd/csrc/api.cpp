@@ -288,6 +288,7 @@ FramePlan make_plan(const osog_context* ctx, int H, int W, int64_t n, int64_t ld
   p.n = n; p.ld = ld; p.pair_cap = pair_cap;
   p.mode = o.mode;
   p.phase_k = (float)(2.0 * M_PI / o.wavelength_um);
+  p.inv_lambda = (float)(1.0 / o.wavelength_um);
   p.inv_wdx = (float)(1.0 / ((double)W * o.pixel_um));
   p.inv_hdx = (float)(1.0 / ((double)H * o.pixel_um));
   p.kn = (float)(o.n_medium / o.wavelength_um);

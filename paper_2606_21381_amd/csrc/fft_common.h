@@ -234,6 +234,17 @@ struct Stages<N, ROWS, DIR, NS, 0, MAXR, QIN> {
   static __device__ __forceinline__ void run(float2*, const float2* __restrict__, const Tw&) {}
 };
 
+// ---- object field ------------------------------------------------------------
+// sin and cos of the phase 2 pi opd / lambda (Eq. 2): the phase in turns, reduced
+// exactly to [-1/2, 1/2] (the subtraction of the nearest integer is exact), then the
+// hardware sine and cosine, which take their argument in turns.
+__device__ __forceinline__ void phase_sincos(float opd, float inv_lambda, float* s, float* c) {
+  const float turns = opd * inv_lambda;
+  const float r = turns - __builtin_rintf(turns);
+  *s = __builtin_amdgcn_sinf(r);
+  *c = __builtin_amdgcn_cosf(r);
+}
+
 // ---- transfer function ------------------------------------------------------
 // P(f) = exp(i dz (kz - k0)) inside the pupil (the piston exp(i dz k0) of Eq. 3 is
 // dropped: it multiplies the whole field by one phase and leaves |E|^2 unchanged);

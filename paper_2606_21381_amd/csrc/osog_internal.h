@@ -57,6 +57,7 @@ struct FramePlan {
   // optics in the precision the kernels use
   int mode;
   float phase_k;         // 2 pi / lambda  [rad/um]
+  float inv_lambda;      // 1 / lambda  [turns/um]
   float inv_wdx, inv_hdx;// 1/(W dx), 1/(H dx)  [cycles/um per bin]
   float kn;              // n_medium / lambda [cycles/um]
   float tfx, tfy;        // oblique tilt [cycles/um] (0 unless oblique)

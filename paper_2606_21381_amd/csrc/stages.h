@@ -25,6 +25,7 @@ struct FrameDev {
   int64_t pair_cap;                // entries of the pair list
   OpticsArgs o;
   float phase_k;
+  float inv_lambda;                // 1 / lambda [turns/um]
   const float* soa;
   const float* globals;
   float* opd;                      // caller's or workspace OPD canvas
@@ -692,7 +693,7 @@ __device__ __forceinline__ void pass1_body(const FrameDev& F, int g, const float
   float2* buf = reinterpret_cast<float2*>(lds);
   const int t = threadIdx.x;
   const float* src = F.opd + (size_t)g * RPB * W;
-  const float pk = F.phase_k;
+  const float il = F.inv_lambda;
   // every load of the row block is issued before the first is used, so the
   // workgroup waits on memory once rather than once per point it handles
   constexpr int PER = RPB * W / kThreads;
@@ -708,7 +709,7 @@ __device__ __forceinline__ void pass1_body(const FrameDev& F, int g, const float
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       float s, c;
-      sincosf(pk * ph[u], &s, &c);
+      phase_sincos(ph[u], il, &s, &c);
       const float am = expf(-tv[u]);
       buf[t + u * kThreads] = make_float2(am * c, am * s);
     }
@@ -716,7 +717,7 @@ __device__ __forceinline__ void pass1_body(const FrameDev& F, int g, const float
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       float s, c;
-      sincosf(pk * ph[u], &s, &c);
+      phase_sincos(ph[u], il, &s, &c);
       buf[t + u * kThreads] = make_float2(c, s);
     }
   }
@@ -986,6 +987,7 @@ inline FrameDev make_dev(const FramePlan& p, const FrameBufs& b) {
   F.n = p.n; F.ld = p.ld; F.pair_cap = p.pair_cap;
   F.o = optics_args(p);
   F.phase_k = p.phase_k;
+  F.inv_lambda = p.inv_lambda;
   F.recs = b.recs; F.boxes = b.boxes; F.counts = b.counts; F.scal = b.scal;
   F.tile_count = b.tile_count; F.tile_start = b.tile_start; F.cursor = b.cursor;
   F.pids = b.pids;
