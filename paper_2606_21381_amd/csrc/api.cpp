@@ -98,6 +98,8 @@ int64_t pair_capacity(int64_t n, int n_tiles, int ppp) {
   return c < 1 ? 1 : (c > INT_MAX ? INT_MAX : c);
 }
 
+int64_t extra_capacity(int64_t pair_cap) { return (pair_cap / 32 + 1 + 7) / 8 * 8; }
+
 static FrameBufs carve_impl(Carver& c, int H, int W, int64_t n, int tile_h, int tile_w, int ppp,
                             bool backward, int64_t* pair_cap_out) {
   const int n_tiles = (H / tile_h) * (W / tile_w);
@@ -111,6 +113,7 @@ static FrameBufs carve_impl(Carver& c, int H, int W, int64_t n, int tile_h, int 
   b.tile_count = c.take<int>(n_tiles);
   b.tile_start = c.take<int>(n_tiles + 1);
   b.cursor = c.take<int>(n_tiles);
+  b.items = c.take<int>((size_t)extra_capacity(pcap));
   b.pids = c.take<int>((size_t)pcap);
   b.opd = c.take<float>(hw);
   b.tau = c.take<float>(hw);
@@ -155,6 +158,7 @@ static FrameBufs carve_compact(Carver& c, const FramePlan& p, int64_t pair_cap, 
   b.tile_count = c.take<int>(p.n_tiles);
   b.tile_start = c.take<int>(p.n_tiles + 1);
   b.cursor = c.take<int>(p.n_tiles);
+  b.items = c.take<int>((size_t)extra_capacity(pair_cap));
   b.pids = c.take<int>((size_t)pair_cap);
   if (own_opd) {
     b.opd = c.take<float>(hw);

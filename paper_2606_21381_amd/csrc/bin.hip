@@ -46,14 +46,14 @@ __global__ void __launch_bounds__(kThreads) k_emit(FrameDev F) {
 __global__ void __launch_bounds__(64) k_sort_segments(FrameDev F, int* __restrict__ out_keys,
                                                       int* __restrict__ out_pids, int64_t capacity,
                                                       int* __restrict__ tile_start) {
-  __shared__ int seg[kSegSort];
+  __shared__ int seg[kSegSort];  // 4 KB
   const int tile = blockIdx.x, lane = threadIdx.x;
   const int start = F.tile_start[tile];
   if (tile == 0 && lane == 0) tile_start[F.n_tiles] = F.tile_start[F.n_tiles];
   if (lane == 0) tile_start[tile] = start;
   if ((int64_t)F.tile_start[F.n_tiles] > capacity) return;  // the lists would not fit: left untouched
   int base = start;
-  const TileIds T = tile_ids(F, tile, lane, seg);
+  const TileIds T = tile_ids(F, tile, lane, seg, kSegSort);
   visit_tile_ids(F, tile, lane, T, [&](int mine, int m) {
     if (lane < m) {
       out_pids[base + lane] = mine;

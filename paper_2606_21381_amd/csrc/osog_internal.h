@@ -85,10 +85,11 @@ struct FrameBufs {
   PRec* recs;
   int4* boxes;
   int* counts;            // pairs per particle
-  int* scal;              // [1] tiles rasterised by the id-ordered scan, [3] total pairs
+  int* scal;              // [1] tiles rasterised by the id-ordered scan, [2] row parts after the first, [3] total pairs
   int* tile_count;        // n_tiles: pairs per tile (histogram)
   int* tile_start;        // n_tiles + 1: exclusive prefix of the tile counts
   int* cursor;            // n_tiles: next free entry of each tile's segment (emit)
+  int* items;             // extra_capacity(pair_cap): (tile << 3 | part) of every part after the first
   int* pids;              // pair_cap: particle ids, grouped by tile (segments at tile_start)
   float* opd;             // H*W (used when the caller passes no opd_out)
   float* tau;             // H*W absorbance (absorbing frames without opd_out)
@@ -109,6 +110,9 @@ FrameBufs carve(void* ws, int H, int W, int64_t n, int tile_h, int tile_w, int p
                 int64_t* pair_cap_out);
 // entries of the pair list: ppp pairs per particle plus one per tile
 int64_t pair_capacity(int64_t n, int n_tiles, int ppp);
+// entries of the part list: a stored tile of c pairs adds fewer than c / 32 parts, so
+// pair_cap / 32 bounds them (rounded up to a multiple of 8, the XCD count)
+int64_t extra_capacity(int64_t pair_cap);
 
 // launchers (return hipError_t of the last launch)
 hipError_t launch_binning(const FramePlan& p, const float* soa, FrameBufs& b, hipStream_t s);

@@ -45,6 +45,8 @@ struct FrameDev {
   int* tile_count;                 // pairs per tile (histogram)
   int* tile_start;                 // n_tiles + 1: first pair of each tile's segment
   int* cursor;                     // next free entry of each segment (emit)
+  int* items;                      // (tile << 3 | part) of the parts after the first
+  int extra_cap;                   // entries of items
   int* pids;                       // the pair list: particle ids grouped by tile
   float2* band;
   double* colsum;
@@ -111,14 +113,23 @@ __device__ __forceinline__ void bin_body(const FrameDev& F, int64_t gid) {
 
 // ---- F2: exclusive prefix of the tile histogram (one workgroup) -----------------
 // tile_start[t] = pairs of tiles 0..t-1, tile_start[n_tiles] = all pairs (also
-// scal[3]), and the emit cursors start at tile_start.  The counts pass through LDS
-// in chunks of kScanChunk, read and written coalesced; each thread sums
-// kScanChunk / kScanThreads consecutive counts, the threads' sums are scanned
-// across the wave with shuffles and across the waves in LDS.  Integer sums: the
-// result is exact in any order.
+// scal[3]), and the emit cursors start at tile_start.  The counts pass through
+// registers in chunks of kScanChunk, read and written coalesced; each thread sums
+// kScanPer consecutive counts, the threads' sums are scanned across the wave with
+// shuffles and across the waves in LDS.  Integer sums: the result is exact in any
+// order.
+// The same pass plans the raster's row parts: a stored segment of more than 64
+// particles splits its tile's rows into P = 2, 4 or 8 parts (64 or more particles
+// per part), each rasterised by its own workgroup, so that a crowded tile is not
+// one long serial wave.  The parts after the first are listed in items
+// (tile << 3 | part), scal[2] of them; the raster derives P from the segment.  A
+// part's pixels still sum their particles in ascending id, so the canvas does not
+// depend on P.
 constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 16;                         // counts per thread and chunk
 constexpr int kScanChunk = kScanThreads * kScanPer;  // 16384 tiles per pass
+constexpr int kMaxParts = 8;
+constexpr int kPartPairs = 64;
 
 __device__ __forceinline__ long long wave_incl_scan(long long v, int lane) {
 #pragma unroll
@@ -129,13 +140,46 @@ __device__ __forceinline__ long long wave_incl_scan(long long v, int lane) {
   return v;
 }
 
-// Each thread holds kScanPer consecutive counts in registers (read as int4), so a
-// chunk costs one round trip to memory.  wsum: 2 * kScanThreads / 64 + 1 long longs of LDS.
-__device__ __forceinline__ void tile_scan_body(const FrameDev& F, long long* wsum) {
+// Row parts of a tile of th rows holding cnt particles.
+__host__ __device__ __forceinline__ int tile_parts_for(int cnt, int th) {
+  int P = 1;
+  while (P < kMaxParts && 2 * P <= th && cnt > kPartPairs * P) P <<= 1;
+  return P;
+}
+
+// Row parts of tile `tile` after the scan: split only when its segment is stored.
+__device__ __forceinline__ int segment_parts(const FrameDev& F, int tile) {
+  const int start = F.tile_start[tile], end = F.tile_start[tile + 1];
+  return end <= F.pair_cap ? tile_parts_for(end - start, F.tile_h) : 1;
+}
+
+// Exclusive prefix of s over the workgroup's threads (in thread order) plus the
+// workgroup total.  wsum: 2 * kScanThreads / 64 + 1 long longs of LDS.
+__device__ __forceinline__ long long block_excl_scan(long long s, long long* wsum, long long* total) {
   constexpr int NW = kScanThreads / 64;
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const long long incl = wave_incl_scan(s, lane);
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  if (wv == 0) {
+    const long long w = lane < NW ? wsum[lane] : 0;
+    const long long wi = wave_incl_scan(w, lane);
+    if (lane < NW) wsum[NW + lane] = wi - w;  // exclusive per wave
+    if (lane == NW - 1) wsum[2 * NW] = wi;    // workgroup total
+  }
+  __syncthreads();
+  const long long ex = wsum[NW + wv] + incl - s;
+  *total = wsum[2 * NW];
+  __syncthreads();  // wsum is reused by the next scan
+  return ex;
+}
+
+// Each thread holds kScanPer consecutive counts in registers (read as int4), so a
+// chunk costs one round trip to memory.
+__device__ __forceinline__ void tile_scan_body(const FrameDev& F, long long* wsum) {
+  const int t = threadIdx.x;
   const int nt = F.n_tiles;
-  long long carry = 0;
+  long long carry = 0, ecarry = 0;
   for (int c0 = 0; c0 < nt; c0 += kScanChunk) {
     const int i0 = c0 + t * kScanPer;
     int loc[kScanPer];
@@ -153,23 +197,19 @@ __device__ __forceinline__ void tile_scan_body(const FrameDev& F, long long* wsu
     long long s = 0;
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) s += loc[k];
-    const long long incl = wave_incl_scan(s, lane);
-    if (lane == 63) wsum[wv] = incl;
-    __syncthreads();
-    if (wv == 0) {
-      const long long w = lane < NW ? wsum[lane] : 0;
-      const long long wi = wave_incl_scan(w, lane);
-      if (lane < NW) wsum[NW + lane] = wi - w;  // exclusive per wave
-      if (lane == NW - 1) wsum[2 * NW] = wi;    // chunk total
-    }
-    __syncthreads();
-    long long run = carry + wsum[NW + wv] + incl - s;
-    carry += wsum[2 * NW];
-    int out[kScanPer];
+    long long tot;
+    long long run = carry + block_excl_scan(s, wsum, &tot);
+    carry += tot;
+    int out[kScanPer], parts[kScanPer];
+    int es = 0;
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
       out[k] = run < INT_MAX ? (int)run : INT_MAX;
       run += loc[k];
+      // only stored segments are split: their pairs bound the part list (the
+      // raster derives the same P from the segment, segment_parts)
+      parts[k] = (i0 + k < nt && run <= (long long)F.pair_cap) ? tile_parts_for(loc[k], F.tile_h) : 1;
+      es += parts[k] - 1;
     }
     if (i0 + kScanPer <= nt) {
       int4* d0 = reinterpret_cast<int4*>(F.tile_start + i0);  // tile_start is 16-byte aligned
@@ -188,15 +228,22 @@ __device__ __forceinline__ void tile_scan_body(const FrameDev& F, long long* wsu
           F.cursor[i0 + k] = out[k];
         }
     }
-    __syncthreads();  // wsum is rewritten by the next chunk
+    if (__syncthreads_or(es)) {  // some tile of the chunk is split: list its parts
+      long long etot;
+      int e = (int)(ecarry + block_excl_scan(es, wsum, &etot));
+      ecarry += etot;
+#pragma unroll
+      for (int k = 0; k < kScanPer; ++k)
+        for (int j = 1; j < parts[k]; ++j) F.items[e++] = ((i0 + k) << 3) | j;  // e < extra_cap
+    }
   }
   if (t == 0) {
     const int tot = carry < INT_MAX ? (int)carry : INT_MAX;
     F.tile_start[nt] = tot;
     F.scal[3] = tot;
+    F.scal[2] = (int)ecarry;
   }
 }
-
 // ---- F3: emit each pair into its tile's segment -----------------------------------
 // A group of kBinGroup lanes shares one particle and deals its tiles round robin;
 // every pair takes the next entry of its tile's segment through the tile's
@@ -234,7 +281,7 @@ __device__ __forceinline__ void emit_body(const FrameDev& F, int64_t gid) {
 // or one cut short by the list's capacity, is not sorted: the reader visits all
 // particles in id order and keeps those whose box meets the tile (the same ids in
 // the same order).
-constexpr int kSegSort = 512;
+constexpr int kSegSort = 1024;
 constexpr int kSegRegs = kSegSort / 64;
 
 __device__ __forceinline__ int wave_sort64(int v, int lane) {
@@ -280,13 +327,13 @@ struct TileIds {
   bool scan;  // not stored or too long: read by the id-ordered scan instead
 };
 
-// Reads and sorts tile `tile`'s segment.  `seg`: kSegSort ints of LDS, free again
-// on return (the workgroup is one wave).
-__device__ __forceinline__ TileIds tile_ids(const FrameDev& F, int tile, int lane, int* seg) {
+// Reads and sorts tile `tile`'s segment.  `seg`: seg_cap ints of LDS (a power of
+// two, 128 <= seg_cap <= kSegSort), free again on return (the workgroup is one wave).
+__device__ __forceinline__ TileIds tile_ids(const FrameDev& F, int tile, int lane, int* seg, int seg_cap) {
   TileIds T;
   const int start = F.tile_start[tile], end = F.tile_start[tile + 1];
   T.cnt = end - start;
-  T.scan = !(end <= F.pair_cap && T.cnt <= kSegSort);
+  T.scan = !(end <= F.pair_cap && T.cnt <= seg_cap);
 #pragma unroll
   for (int c = 0; c < kSegRegs; ++c) T.v[c] = 0;
   if (T.scan || T.cnt == 0) return T;
@@ -381,11 +428,12 @@ struct RasterLds {
   int* qpid;    // [kQueue] its particle
 };
 
-// (A segment is sorted in the sums' space before they are cleared: 2 * area >= kSegSort.)
+// (A segment is sorted in the sums' space before they are cleared: up to
+// min(kSegSort, 2 * area) ids, at least 512 since area >= kMinTile.)
 __host__ __device__ constexpr int raster_lds_bytes(int area, bool abs) {
   return 4 * area * (abs ? 4 : 2) + 8 * kQueue;
 }
-static_assert(2 * kMinTile >= kSegSort, "a segment sorts in the space of two tile sums");
+static_assert(2 * kMinTile >= 512 && kSegSort % 64 == 0, "a segment sorts in the space of two tile sums");
 
 __device__ __forceinline__ RasterLds raster_lds(char* base, int area, bool abs) {
   RasterLds L;
@@ -627,24 +675,27 @@ __device__ __forceinline__ void raster_particle(const FrameDev& F, const TileGeo
   }
 }
 
+// Part `part` of tile `tile` (rows [part, part + 1) * tile_h / P of the tile, P =
+// segment_parts); every part sorts and visits the whole segment.
 template <bool ABS, bool HAB>
-__device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int lane, char* lds) {
+__device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int part, int lane, char* lds) {
 #pragma clang fp contract(off)
   TileGeom G;
+  const int P = segment_parts(F, tile);
   G.tw = F.tile_w;
-  G.th = F.tile_h;
+  G.th = F.tile_h / P;
   const int ty = tile / F.ntx, tx = tile - ty * F.ntx;
   G.X0 = tx * G.tw;
-  G.Y0 = ty * G.th;
+  G.Y0 = ty * F.tile_h + part * G.th;
   G.hab_enc = F.hab_enc;
   G.hab_raw = F.hab_raw;
   G.hab_info = F.hab_info;
   G.topo_lo = F.topo_lo;
   G.topo_hi = F.topo_hi;
-  const int area = G.tw * G.th;
-  const RasterLds L = raster_lds(lds, area, ABS);
+  const int full = G.tw * F.tile_h, area = G.tw * G.th;
+  const RasterLds L = raster_lds(lds, full, ABS);
   // the segment is sorted in the space of the sums, which are cleared afterwards
-  const TileIds T = tile_ids(F, tile, lane, L.acc_ids());
+  const TileIds T = tile_ids(F, tile, lane, L.acc_ids(), min(kSegSort, 2 * full));
   for (int q = lane; q < area; q += 64) {
     L.acc[q] = 0.0f;
     L.cacc[q] = 0.0f;
@@ -680,7 +731,7 @@ __device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int lan
     F.opd[o] = L.acc[q] + L.cacc[q];
     if (ABS) F.tau[o] = L.tacc[q] + L.ctacc[q];
   }
-  if (scanned && lane == 0) atomicAdd(&F.scal[1], 1);
+  if (scanned && lane == 0 && part == 0) atomicAdd(&F.scal[1], 1);
 }
 
 // ---- F6: pass 1, rows --------------------------------------------------------
@@ -990,6 +1041,7 @@ inline FrameDev make_dev(const FramePlan& p, const FrameBufs& b) {
   F.inv_lambda = p.inv_lambda;
   F.recs = b.recs; F.boxes = b.boxes; F.counts = b.counts; F.scal = b.scal;
   F.tile_count = b.tile_count; F.tile_start = b.tile_start; F.cursor = b.cursor;
+  F.items = b.items; F.extra_cap = (int)extra_capacity(p.pair_cap);
   F.pids = b.pids;
   F.band = b.band; F.colsum = b.colsum;
   F.band_in = b.band; F.in_kx_lo = p.kx_lo; F.in_kx_n = p.kx_n;

@@ -150,9 +150,9 @@ def test_pair_overflow_fallback_is_bitwise_identical():
 
 def crowded_frame(seed=11):
     """256^2 brightfield frame whose particles crowd into a few tiles: 700 small
-    prisms and ellipsoids in a 48x48 px patch (tiles of 65-512 particles: the
-    LDS sort) and 700 more centred in one 16x16 tile (a segment of more than 512
-    ids: the id-ordered scan)."""
+    prisms and ellipsoids in a 48x48 px patch (16x16 tiles of 65-512 particles:
+    the LDS sort, rows split into parts) and 700 more centred in one 16x16 tile
+    (a segment of more than 512 ids: the id-ordered scan, also in parts)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     a = workloads.mixed(rng, 700, 256, 256)
     a[0] = rng.uniform(100, 148, 700)
@@ -188,22 +188,28 @@ def test_crowded_tiles_sorted_and_scanned_paths():
     assert np.array_equal(keys.cpu().numpy(), ref["keys"])
     assert np.array_equal(pids.cpu().numpy(), ref["pids"])
     assert np.array_equal(ts.cpu().numpy(), ref["tile_start"])
-    I, opd = r.render(soa, fr.H, fr.W, fr.optics, g, want_opd=True)
-    torch.cuda.synchronize()
+    r.set_tiling(16, 16)
+    try:
+        I, opd = r.render(soa, fr.H, fr.W, fr.optics, g, want_opd=True)
+        torch.cuda.synchronize()
+    finally:
+        r.set_tiling(th0, tw0)
     ref_opd = oracle.raster.opd(fr.soa, fr.H, fr.W)
     e = float(np.abs(opd.cpu().numpy() - ref_opd).max())
     ref_I = oracle.optics.intensity(ref_opd, oracle_optics(fr.optics), 1.0, 0.0, 0.0)
     e_i = rel_l2(I.cpu().numpy(), ref_I)
     say("crowded: OPD max abs %.3e um, I rel L2 %.3e" % (e, e_i))
     assert e <= 1e-5 and e_i <= 1e-4
-    # a tiling whose tiles hold everything differently must give the same canvas
-    r.set_tiling(8, 32)
-    try:
-        I2, opd2 = r.render(soa, fr.H, fr.W, fr.optics, g, want_opd=True)
-        torch.cuda.synchronize()
-    finally:
-        r.set_tiling(th0, tw0)
-    assert torch.equal(opd, opd2) and torch.equal(I, I2)
+    # tilings whose tiles hold everything differently (other sorted, scanned and
+    # row-split tiles) must give the same canvas
+    for tl in [(8, 32), (32, 16), (32, 32)]:
+        r.set_tiling(*tl)
+        try:
+            I2, opd2 = r.render(soa, fr.H, fr.W, fr.optics, g, want_opd=True)
+            torch.cuda.synchronize()
+        finally:
+            r.set_tiling(th0, tw0)
+        assert torch.equal(opd, opd2) and torch.equal(I, I2), tl
 
 
 @pytest.mark.parametrize("mode", [0, 1, 2])
