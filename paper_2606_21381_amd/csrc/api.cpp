@@ -93,12 +93,16 @@ struct Carver {
 
 // Entries of the pair list: ppp pairs per particle plus one per tile (the
 // tile-aligned part of every particle's box), at least one.
+int plane_count(int64_t pair_cap) {
+  const int64_t c = pair_cap / 64 + 1;
+  return c < kPlaneCap ? (int)c : kPlaneCap;
+}
+
 int64_t pair_capacity(int64_t n, int n_tiles, int ppp) {
   const int64_t c = n * (int64_t)ppp + n_tiles;
   return c < 1 ? 1 : (c > INT_MAX ? INT_MAX : c);
 }
 
-int64_t extra_capacity(int64_t pair_cap) { return (pair_cap / 32 + 1 + 7) / 8 * 8; }
 
 static FrameBufs carve_impl(Carver& c, int H, int W, int64_t n, int tile_h, int tile_w, int ppp,
                             bool backward, int64_t* pair_cap_out) {
@@ -113,7 +117,10 @@ static FrameBufs carve_impl(Carver& c, int H, int W, int64_t n, int tile_h, int 
   b.tile_count = c.take<int>(n_tiles);
   b.tile_start = c.take<int>(n_tiles + 1);
   b.cursor = c.take<int>(n_tiles);
-  b.items = c.take<int>((size_t)extra_capacity(pcap));
+  b.items = c.take<int>(plane_count(pcap));
+  b.tile_plane = c.take<int>(n_tiles);
+  b.tile_done = c.take<int>(n_tiles);
+  b.planes = c.take<unsigned long long>((size_t)plane_count(pcap) * 2 * tile_h * tile_w);
   b.pids = c.take<int>((size_t)pcap);
   b.opd = c.take<float>(hw);
   b.tau = c.take<float>(hw);
@@ -158,7 +165,10 @@ static FrameBufs carve_compact(Carver& c, const FramePlan& p, int64_t pair_cap, 
   b.tile_count = c.take<int>(p.n_tiles);
   b.tile_start = c.take<int>(p.n_tiles + 1);
   b.cursor = c.take<int>(p.n_tiles);
-  b.items = c.take<int>((size_t)extra_capacity(pair_cap));
+  b.items = c.take<int>(plane_count(pair_cap));
+  b.tile_plane = c.take<int>(p.n_tiles);
+  b.tile_done = c.take<int>(p.n_tiles);
+  b.planes = c.take<unsigned long long>((size_t)plane_count(pair_cap) * (p.absorb ? 2 : 1) * p.tile_h * p.tile_w);
   b.pids = c.take<int>((size_t)pair_cap);
   if (own_opd) {
     b.opd = c.take<float>(hw);

@@ -2,15 +2,16 @@
 // the (tile key, particle id) pairs on the tile key, with exact segment offsets.
 // The paper composes particle patches with an atomic scatter-add (Sec. III.C,
 // Eq. 7); grouping the pairs by tile instead lets every tile sum its particles in
-// ascending id with no float atomics, so the canvas is bitwise reproducible.
+// LDS, in fixed point, with no global float atomics, so the canvas is bitwise
+// reproducible.
 //
-//   k_bin_clear  tile histogram and flags = 0
+//   k_bin_clear  tile histogram, slice counters and flags = 0
 //   k_bin        F1: records, boxes, pairs per particle; tile histogram
 //   k_tile_scan  F2: exclusive prefix of the histogram = each tile's segment start
 //                (and the emit cursors); total pairs
 //   k_emit       F3: every pair takes the next entry of its tile's segment
-// F4, ascending id inside a segment, is restored by the segment's reader
-// (raster_tile; k_sort_segments for the inspection API), which sorts it.
+// The raster's fixed-point sums do not depend on the order inside a segment;
+// k_sort_segments restores ascending id for the inspection API (F4).
 // Integer atomics only form order-independent results (counts) or entries
 // inside a tile's segment.  The pair list holds pair_cap entries: a tile whose
 // segment does not fit is read by an id-ordered scan of all particles' boxes.
@@ -23,7 +24,10 @@ namespace osog {
 
 __global__ void __launch_bounds__(kThreads) k_bin_clear(FrameDev F) {
   const int t = blockIdx.x * kThreads + threadIdx.x;
-  if (t < F.n_tiles) F.tile_count[t] = 0;
+  if (t < F.n_tiles) {
+    F.tile_count[t] = 0;
+    F.tile_done[t] = 0;
+  }
   if (t < 4) F.scal[t] = 0;
 }
 

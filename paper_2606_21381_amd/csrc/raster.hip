@@ -21,25 +21,26 @@ namespace osog {
 // tiles: a particle spanning neighbouring tiles is then fetched into one L2.
 // HAB: the frame's context defines polyhedral habits (a separate build of the
 // kernel, so frames without them keep the smaller register footprint).
-// The first kPartGrid workgroups take the listed parts after the first of crowded
-// tiles, in turn (so that they start early; a frame without crowded tiles costs
-// kPartGrid empty workgroups), the rest part 0 of every tile.
-constexpr int kPartGrid = 2048;  // a multiple of kXcds
+// The first kSliceGrid workgroups take, in turn, the slices after the first of
+// crowded tiles (so that they start early; a frame without crowded tiles costs
+// kSliceGrid empty workgroups), the rest slice 0 of every tile.
+constexpr int kSliceGrid = 2048;  // a multiple of kXcds
 
 template <bool ABS, bool HAB>
 __global__ void __launch_bounds__(64) k_raster(FrameDev F, int per_xcd) {
   extern __shared__ char lds_raster[];
   const int g = (int)blockIdx.x;
-  if (g < kPartGrid) {
+  if (g < kSliceGrid) {
     const int ne = F.scal[2];
-    for (int e = g; e < ne; e += kPartGrid) {
+    for (int e = g; e < ne; e += kSliceGrid) {
       const int it = F.items[e];
-      raster_tile<ABS, HAB>(F, it >> 3, it & 7, threadIdx.x, lds_raster);
-      __syncthreads();  // the next part reuses the LDS
+      if ((it & 15) == 0) continue;  // slice 0: the tile's own workgroup
+      raster_tile<ABS, HAB>(F, it >> 4, it & 15, threadIdx.x, lds_raster);
+      __syncthreads();  // the next slice reuses the LDS
     }
     return;
   }
-  const int h = g - kPartGrid;  // kPartGrid is a multiple of kXcds: h mod 8 is still the XCD
+  const int h = g - kSliceGrid;  // kSliceGrid is a multiple of kXcds: h mod 8 is still the XCD
   const int tile = (h % kXcds) * per_xcd + h / kXcds;
   if (tile < F.n_tiles) raster_tile<ABS, HAB>(F, tile, 0, threadIdx.x, lds_raster);
 }
@@ -49,7 +50,7 @@ hipError_t launch_raster(const FramePlan& p, FrameBufs& b, float* opd, float* ta
   F.opd = opd;
   F.tau = tau;
   const int per = (p.n_tiles + kXcds - 1) / kXcds;
-  const dim3 g((unsigned)(kPartGrid + per * kXcds)), wg(64);
+  const dim3 g((unsigned)(kSliceGrid + per * kXcds)), wg(64);
   const int area = p.tile_h * p.tile_w;
   const size_t lds = (size_t)raster_lds_bytes(area, p.absorb != 0);
   if (p.n_habits > 0) {

@@ -45,8 +45,11 @@ struct FrameDev {
   int* tile_count;                 // pairs per tile (histogram)
   int* tile_start;                 // n_tiles + 1: first pair of each tile's segment
   int* cursor;                     // next free entry of each segment (emit)
-  int* items;                      // (tile << 3 | part) of the parts after the first
-  int extra_cap;                   // entries of items
+  int* items;                      // (tile << 4 | slice) of every plane in use
+  int* tile_plane;                 // first plane of a sliced tile (-1: none left)
+  int* tile_done;                  // slices of each tile finished (cleared per frame)
+  unsigned long long* planes;      // plane_cap planes of tile sums
+  int plane_cap;
   int* pids;                       // the pair list: particle ids grouped by tile
   float2* band;
   double* colsum;
@@ -118,18 +121,17 @@ __device__ __forceinline__ void bin_body(const FrameDev& F, int64_t gid) {
 // kScanPer consecutive counts, the threads' sums are scanned across the wave with
 // shuffles and across the waves in LDS.  Integer sums: the result is exact in any
 // order.
-// The same pass plans the raster's row parts: a stored segment of more than 64
-// particles splits its tile's rows into P = 2, 4 or 8 parts (64 or more particles
-// per part), each rasterised by its own workgroup, so that a crowded tile is not
-// one long serial wave.  The parts after the first are listed in items
-// (tile << 3 | part), scal[2] of them; the raster derives P from the segment.  A
-// part's pixels still sum their particles in ascending id, so the canvas does not
-// depend on P.
+// The same pass plans the slices of crowded tiles: a stored segment of more than
+// kSlicePairs particles is split into S = ceil(count / kSlicePairs) slices (at
+// most kMaxSlices), each rasterised by its own workgroup into its own plane of
+// tile sums; tiles take consecutive planes in tile order while plane_cap lasts
+// (tile_plane[t], -1 once they run out), and items lists (tile << 4 | slice) for
+// every plane in use, scal[2] of them.
 constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 16;                         // counts per thread and chunk
 constexpr int kScanChunk = kScanThreads * kScanPer;  // 16384 tiles per pass
-constexpr int kMaxParts = 8;
-constexpr int kPartPairs = 64;
+constexpr int kSlicePairs = 128;  // particles per slice of a crowded tile
+constexpr int kMaxSlices = 16;
 
 __device__ __forceinline__ long long wave_incl_scan(long long v, int lane) {
 #pragma unroll
@@ -140,17 +142,9 @@ __device__ __forceinline__ long long wave_incl_scan(long long v, int lane) {
   return v;
 }
 
-// Row parts of a tile of th rows holding cnt particles.
-__host__ __device__ __forceinline__ int tile_parts_for(int cnt, int th) {
-  int P = 1;
-  while (P < kMaxParts && 2 * P <= th && cnt > kPartPairs * P) P <<= 1;
-  return P;
-}
-
-// Row parts of tile `tile` after the scan: split only when its segment is stored.
-__device__ __forceinline__ int segment_parts(const FrameDev& F, int tile) {
-  const int start = F.tile_start[tile], end = F.tile_start[tile + 1];
-  return end <= F.pair_cap ? tile_parts_for(end - start, F.tile_h) : 1;
+// Slices of a stored segment of cnt particles.
+__host__ __device__ __forceinline__ int tile_slices(int cnt) {
+  return cnt > kSlicePairs ? min(kMaxSlices, (cnt + kSlicePairs - 1) / kSlicePairs) : 1;
 }
 
 // Exclusive prefix of s over the workgroup's threads (in thread order) plus the
@@ -200,16 +194,16 @@ __device__ __forceinline__ void tile_scan_body(const FrameDev& F, long long* wsu
     long long tot;
     long long run = carry + block_excl_scan(s, wsum, &tot);
     carry += tot;
-    int out[kScanPer], parts[kScanPer];
+    int out[kScanPer], planes[kScanPer];
     int es = 0;
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
       out[k] = run < INT_MAX ? (int)run : INT_MAX;
       run += loc[k];
-      // only stored segments are split: their pairs bound the part list (the
-      // raster derives the same P from the segment, segment_parts)
-      parts[k] = (i0 + k < nt && run <= (long long)F.pair_cap) ? tile_parts_for(loc[k], F.tile_h) : 1;
-      es += parts[k] - 1;
+      // only stored segments are sliced
+      const int S = (i0 + k < nt && run <= (long long)F.pair_cap) ? tile_slices(loc[k]) : 1;
+      planes[k] = S > 1 ? S : 0;
+      es += planes[k];
     }
     if (i0 + kScanPer <= nt) {
       int4* d0 = reinterpret_cast<int4*>(F.tile_start + i0);  // tile_start is 16-byte aligned
@@ -228,20 +222,28 @@ __device__ __forceinline__ void tile_scan_body(const FrameDev& F, long long* wsu
           F.cursor[i0 + k] = out[k];
         }
     }
-    if (__syncthreads_or(es)) {  // some tile of the chunk is split: list its parts
+    if (__syncthreads_or(es)) {  // some tile of the chunk is sliced: give it planes
       long long etot;
-      int e = (int)(ecarry + block_excl_scan(es, wsum, &etot));
+      int pp = (int)min(ecarry + block_excl_scan(es, wsum, &etot), (long long)INT_MAX);
       ecarry += etot;
 #pragma unroll
-      for (int k = 0; k < kScanPer; ++k)
-        for (int j = 1; j < parts[k]; ++j) F.items[e++] = ((i0 + k) << 3) | j;  // e < extra_cap
+      for (int k = 0; k < kScanPer; ++k) {
+        if (planes[k] == 0) continue;
+        if (pp + planes[k] <= F.plane_cap) {
+          F.tile_plane[i0 + k] = pp;
+          for (int j = 0; j < planes[k]; ++j) F.items[pp + j] = ((i0 + k) << 4) | j;
+          atomicMax(&F.scal[2], pp + planes[k]);
+        } else {
+          F.tile_plane[i0 + k] = -1;
+        }
+        pp += planes[k];
+      }
     }
   }
   if (t == 0) {
     const int tot = carry < INT_MAX ? (int)carry : INT_MAX;
     F.tile_start[nt] = tot;
     F.scal[3] = tot;
-    F.scal[2] = (int)ecarry;
   }
 }
 // ---- F3: emit each pair into its tile's segment -----------------------------------
@@ -394,21 +396,28 @@ __device__ __forceinline__ bool visit_tile_ids(const FrameDev& F, int tile, int 
 }
 
 // ---- F5: rasterise one tile with one 64-lane wave ------------------------------
-// The tile's pixel sums live in LDS.  Each particle of the tile, in ascending id,
-// deals its candidate pixels (the pixels of its record's candidate rectangle that
-// lie in the tile) to the 64 lanes, 64 at a time; each lane evaluates its pixel
-// without branching for the common cases -- outside, inside, one edge (the
-// half-plane box filter) for a prism; the centre sample for an ellipsoid; the
-// vertical chord for a habit -- and adds dn * thickness to the pixel's LDS sum.  A
-// particle's candidates are distinct pixels and its adds complete before the next
-// particle's, so every pixel sums its terms in ascending particle id.
+// The tile's pixel sums live in LDS as 64-bit fixed-point integers (units of
+// 2^-32 um of OPD; of 2^-32 for the absorbance).  Each particle of the tile deals
+// its candidate pixels (the pixels of its record's candidate rectangle that lie in
+// the tile) to the 64 lanes, 64 at a time; each lane evaluates its pixel without
+// branching for the common cases -- outside, inside, one edge (the half-plane box
+// filter) for a prism; the centre sample for an ellipsoid; the vertical chord for
+// a habit -- and adds dn * thickness, rounded down to the fixed-point grid, to the
+// pixel's LDS sum (ds_add_u64).  Integer sums do not depend on their order, so the
+// canvas value -- the pixel's sum converted back to FP32 once -- is a function of
+// the pixel and the particles that reach it alone: bitwise the same under every
+// tiling, launch order and split of the tile's particles between workgroups.
+// Each term carries at most 2^-32 of rounding (FP32 accumulation would carry
+// ~1e-7 relative per add).
 // The costly pixels -- a prism pixel two edges reach (the clipped-polygon area),
 // an ellipsoid pixel within 2e-3 of the rim and a habit pixel next to a vertical
-// face (both FP64) -- are queued as (pixel, particle) in particle order and
-// evaluated 64 at a time with every lane busy; their terms go to a second LDS sum
-// per pixel, again in ascending particle id.  The canvas value is the first sum
-// plus the second: a function of the pixel and of the particles that reach it
-// alone, so it is bitwise the same under every tiling.
+// face (both FP64) -- are queued as (pixel, particle) and evaluated 64 at a time
+// with every lane busy, then added like the others.
+// A crowded tile (a stored segment of more than kSlicePairs particles) is split
+// into up to kMaxSlices slices of its segment, each rasterised by its own
+// workgroup into its own sums; each slice stores its sums in a plane of the
+// workspace, and the last slice to finish (a counter per tile, no waiting) adds
+// the planes and writes the tile.
 // The offset of a pixel centre from the particle centre is exact in FP32 (both
 // are multiples of the centre's ulp and the difference is small), so the rotated
 // offsets u, v carry ~1e-6 px of rounding and depend on the pixel and the
@@ -419,33 +428,39 @@ constexpr int kQueue = 128;  // queued costly pixels per wave: 64 plus one batch
 
 // LDS of one raster wave, for a tile of `area` pixels (layout of raster_lds_bytes)
 struct RasterLds {
-  __device__ int* acc_ids() const { return reinterpret_cast<int*>(acc); }  // sort space (acc, cacc)
-  float* acc;   // [area] terms in ascending particle id
-  float* cacc;  // [area] costly terms in ascending particle id
-  float* tacc;  // [area] absorbance (ABS)
-  float* ctacc; // [area]
-  int* qpix;    // [kQueue] tile pixel index of a queued pixel
-  int* qpid;    // [kQueue] its particle
+  unsigned long long* acc;   // [area] OPD, fixed point
+  unsigned long long* tacc;  // [area] absorbance (ABS), fixed point
+  int* qpix;                 // [kQueue] tile pixel index of a queued pixel
+  int* qpid;                 // [kQueue] its particle
 };
 
-// (A segment is sorted in the sums' space before they are cleared: up to
-// min(kSegSort, 2 * area) ids, at least 512 since area >= kMinTile.)
 __host__ __device__ constexpr int raster_lds_bytes(int area, bool abs) {
-  return 4 * area * (abs ? 4 : 2) + 8 * kQueue;
+  return 8 * area * (abs ? 2 : 1) + 8 * kQueue;
 }
-static_assert(2 * kMinTile >= 512 && kSegSort % 64 == 0, "a segment sorts in the space of two tile sums");
 
 __device__ __forceinline__ RasterLds raster_lds(char* base, int area, bool abs) {
   RasterLds L;
-  float* f = reinterpret_cast<float*>(base);
+  unsigned long long* f = reinterpret_cast<unsigned long long*>(base);
   L.acc = f;
-  L.cacc = f + area;
-  L.tacc = f + 2 * area;
-  L.ctacc = f + 3 * area;
-  int* q = reinterpret_cast<int*>(f + area * (abs ? 4 : 2));
+  L.tacc = f + area;
+  int* q = reinterpret_cast<int*>(f + area * (abs ? 2 : 1));
   L.qpix = q;
   L.qpid = q + kQueue;
   return L;
+}
+
+// v rounded down to a multiple of 2^-32, as a two's-complement 64-bit count of
+// 2^-32: the integer part floor(v) in the high word, the fraction v - floor(v)
+// (exact in FP64) times 2^32, truncated, in the low word.  |v| < 2^31.
+__device__ __forceinline__ unsigned long long to_fixed(float v) {
+  const float fl = floorf(v);
+  const unsigned lo = (unsigned)(((double)v - (double)fl) * 4294967296.0);
+  return ((unsigned long long)(unsigned)(int)fl << 32) | lo;
+}
+
+// A fixed-point sum back to FP32 (via FP64: one rounding to double, one to float).
+__device__ __forceinline__ float from_fixed(unsigned long long q) {
+  return (float)((double)(long long)q * (1.0 / 4294967296.0));
 }
 
 struct TileGeom {
@@ -473,14 +488,12 @@ __device__ __forceinline__ PRec const_load(const PRec* p) {
   return r;
 }
 
-__device__ __forceinline__ void lds_add(float* p, float v) {
-  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+__device__ __forceinline__ void lds_add(unsigned long long* p, float v) {
+  __hip_atomic_fetch_add(p, to_fixed(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // Evaluates the first `count` queued costly pixels, one per lane, and adds their
-// terms to the costly sums in queue (= particle) order: the entries are sorted by
-// (pixel, queue position) and added in rounds, round r adding the r-th term of
-// every pixel, so a pixel queued twice in one batch still sums in particle order.
+// terms to the sums.
 template <bool ABS, bool HAB>
 __device__ __forceinline__ void flush_costly(const FrameDev& F, const TileGeom& G, const RasterLds& L, int count,
                                           int lane) {
@@ -515,26 +528,9 @@ __device__ __forceinline__ void flush_costly(const FrameDev& F, const TileGeom& 
       if (ABS) tval = (float)((double)F.absr[pid].y * t);
     }
   }
-  const int key = valid ? (pix << 6) | lane : INT_MAX;
-  const int sk = wave_sort64(key, lane);
-  const bool sv = sk != INT_MAX;
-  const int src = sk & 63, spix = sk >> 6;
-  const float sval = __shfl(val, src, 64);
-  const float stval = ABS ? __shfl(tval, src, 64) : 0.0f;
-  const int prev = __shfl_up(spix, 1, 64);
-  const bool first = sv && (lane == 0 || prev != spix);
-  const uint64_t fm = __ballot(first);
-  const uint64_t upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-  const uint64_t mine = fm & upto;
-  const int rank = mine ? lane - (63 - __clzll((long long)mine)) : 0;
-  for (int rd = 0;; ++rd) {
-    const bool act = sv && rank == rd;
-    if (!__ballot(act)) break;
-    if (act) {  // distinct pixels within a round
-      L.cacc[spix] += sval;
-      if (ABS) L.ctacc[spix] += stval;
-    }
-    __syncthreads();
+  if (valid) {  // integer sums: pixels queued twice in one batch need no ordering
+    lds_add(L.acc + pix, val);
+    if (ABS) lds_add(L.tacc + pix, tval);
   }
 }
 
@@ -675,39 +671,39 @@ __device__ __forceinline__ void raster_particle(const FrameDev& F, const TileGeo
   }
 }
 
-// Part `part` of tile `tile` (rows [part, part + 1) * tile_h / P of the tile, P =
-// segment_parts); every part sorts and visits the whole segment.
+// Slice `slice` of tile `tile`: particles [slice, slice + 1) * cnt / S of its
+// segment (S = tile_slices; 1 unless the scan gave the tile planes), or, for a
+// segment the pair list does not hold, every particle whose box meets the tile.
 template <bool ABS, bool HAB>
-__device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int part, int lane, char* lds) {
+__device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int slice, int lane, char* lds) {
 #pragma clang fp contract(off)
   TileGeom G;
-  const int P = segment_parts(F, tile);
   G.tw = F.tile_w;
-  G.th = F.tile_h / P;
+  G.th = F.tile_h;
   const int ty = tile / F.ntx, tx = tile - ty * F.ntx;
   G.X0 = tx * G.tw;
-  G.Y0 = ty * F.tile_h + part * G.th;
+  G.Y0 = ty * G.th;
   G.hab_enc = F.hab_enc;
   G.hab_raw = F.hab_raw;
   G.hab_info = F.hab_info;
   G.topo_lo = F.topo_lo;
   G.topo_hi = F.topo_hi;
-  const int full = G.tw * F.tile_h, area = G.tw * G.th;
-  const RasterLds L = raster_lds(lds, full, ABS);
-  // the segment is sorted in the space of the sums, which are cleared afterwards
-  const TileIds T = tile_ids(F, tile, lane, L.acc_ids(), min(kSegSort, 2 * full));
-  for (int q = lane; q < area; q += 64) {
-    L.acc[q] = 0.0f;
-    L.cacc[q] = 0.0f;
-    if (ABS) {
-      L.tacc[q] = 0.0f;
-      L.ctacc[q] = 0.0f;
-    }
+  const int area = G.tw * G.th;
+  const RasterLds L = raster_lds(lds, area, ABS);
+  const int start = F.tile_start[tile], end = F.tile_start[tile + 1];
+  const bool stored = end <= F.pair_cap;
+  int S = 1, plane = 0;
+  if (stored && tile_slices(end - start) > 1) {
+    plane = F.tile_plane[tile];  // -1: no planes were left for this tile
+    if (plane >= 0) S = tile_slices(end - start);
   }
-  __syncthreads();
+  for (int q = lane; q < area; q += 64) {
+    L.acc[q] = 0ull;
+    if (ABS) L.tacc[q] = 0ull;
+  }
   int qn = 0;
   const PRec* __restrict__ recs = F.recs;
-  const bool scanned = visit_tile_ids(F, tile, lane, T, [&](int mine, int m) {
+  auto visit = [&](int mine, int m) {
     // wave-uniform records through the scalar cache, the next one requested
     // before the current one is rasterised
     int pid = __builtin_amdgcn_readlane(mine, 0);
@@ -721,17 +717,66 @@ __device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int par
       }
       raster_particle<ABS, HAB>(F, G, L, cur, cpid, lane, qn);
     }
-  });
-  __syncthreads();
+  };
+  if (stored) {
+    const int cnt = end - start;
+    const int a0 = start + (int)((long long)cnt * slice / S), a1 = start + (int)((long long)cnt * (slice + 1) / S);
+    const int* __restrict__ pids = F.pids;
+    for (int c0 = a0; c0 < a1; c0 += 64) {
+      const int m = min(64, a1 - c0);
+      visit(lane < m ? pids[c0 + lane] : 0, m);
+    }
+  } else {
+    // every particle whose box meets the tile, compacted to the low lanes by a lane permutation
+    const int x0 = G.X0, x1 = x0 + G.tw - 1, y0 = G.Y0, y1 = y0 + G.th - 1;
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    for (int64_t p0 = 0; p0 < F.n; p0 += 64) {
+      const int64_t p = p0 + lane;
+      const bool hit = p < F.n && box_meets(F, p, x0, x1, y0, y1);
+      const uint64_t mk = __ballot(hit);
+      if (!mk) continue;
+      const int c = __popcll(mk);
+      const int hb = __popcll(mk & below);
+      visit(__builtin_amdgcn_ds_permute((hit ? hb : c + (lane - hb)) << 2, (int)p), c);
+    }
+  }
   if (qn > 0) flush_costly<ABS, HAB>(F, G, L, qn, lane);
   __syncthreads();
-  for (int q = lane; q < area; q += 64) {
-    const int i = q / G.tw, j = q - i * G.tw;
-    const int64_t o = (int64_t)(G.Y0 + i) * F.W + G.X0 + j;
-    F.opd[o] = L.acc[q] + L.cacc[q];
-    if (ABS) F.tau[o] = L.tacc[q] + L.ctacc[q];
+  if (S == 1) {
+    for (int q = lane; q < area; q += 64) {
+      const int i = q / G.tw, j = q - i * G.tw;
+      const int64_t o = (int64_t)(G.Y0 + i) * F.W + G.X0 + j;
+      F.opd[o] = from_fixed(L.acc[q]);
+      if (ABS) F.tau[o] = from_fixed(L.tacc[q]);
+    }
+  } else {
+    // this slice's sums to its plane; the last slice of the tile adds the S planes
+    const size_t pl = (size_t)area * (ABS ? 2 : 1);
+    unsigned long long* mine = F.planes + (size_t)(plane + slice) * pl;
+    for (int q = lane; q < area; q += 64) {
+      mine[q] = L.acc[q];
+      if (ABS) mine[area + q] = L.tacc[q];
+    }
+    __threadfence();  // the plane before the count
+    int last = 0;
+    if (lane == 0) last = atomicAdd(&F.tile_done[tile], 1) == S - 1;
+    if (__builtin_amdgcn_readfirstlane(last)) {
+      __threadfence();  // every other slice's plane after its count
+      const unsigned long long* base = F.planes + (size_t)plane * pl;
+      for (int q = lane; q < area; q += 64) {
+        unsigned long long a = 0ull, t = 0ull;
+        for (int k = 0; k < S; ++k) {
+          a += base[(size_t)k * pl + q];
+          if (ABS) t += base[(size_t)k * pl + area + q];
+        }
+        const int i = q / G.tw, j = q - i * G.tw;
+        const int64_t o = (int64_t)(G.Y0 + i) * F.W + G.X0 + j;
+        F.opd[o] = from_fixed(a);
+        if (ABS) F.tau[o] = from_fixed(t);
+      }
+    }
   }
-  if (scanned && lane == 0 && part == 0) atomicAdd(&F.scal[1], 1);
+  if (!stored && lane == 0) atomicAdd(&F.scal[1], 1);
 }
 
 // ---- F6: pass 1, rows --------------------------------------------------------
@@ -1041,7 +1086,8 @@ inline FrameDev make_dev(const FramePlan& p, const FrameBufs& b) {
   F.inv_lambda = p.inv_lambda;
   F.recs = b.recs; F.boxes = b.boxes; F.counts = b.counts; F.scal = b.scal;
   F.tile_count = b.tile_count; F.tile_start = b.tile_start; F.cursor = b.cursor;
-  F.items = b.items; F.extra_cap = (int)extra_capacity(p.pair_cap);
+  F.items = b.items; F.tile_plane = b.tile_plane; F.tile_done = b.tile_done;
+  F.planes = b.planes; F.plane_cap = plane_count(p.pair_cap);
   F.pids = b.pids;
   F.band = b.band; F.colsum = b.colsum;
   F.band_in = b.band; F.in_kx_lo = p.kx_lo; F.in_kx_n = p.kx_n;

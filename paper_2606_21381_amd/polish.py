@@ -53,7 +53,7 @@ class PolishConfig:
     eps: tuple = (0.02, 0.02, 0.004, 0.02)          # forward-difference steps: x, y [px], angle [rad], width [px]
     eps_glob: tuple = (1e-5, 0.004, 0.002, 0.002)   # dn, dz [um], shear [px], bias [rad]
     angle_span: float = 0.3       # angle search over [-span, +span] around the current angle
-    angle_steps: int = 31
+    angle_steps: int = 61
     angle_refine: int = 2         # further searches, each over a bracket 1/10 as wide
     lam0: float = 1e-3            # initial damping (relative to the block diagonal)
     target_error: float = 1e-3
