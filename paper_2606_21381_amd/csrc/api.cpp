@@ -93,9 +93,9 @@ struct Carver {
 
 // Entries of the pair list: ppp pairs per particle plus one per tile (the
 // tile-aligned part of every particle's box), at least one.
-int plane_count(int64_t pair_cap) {
-  const int64_t c = pair_cap / 64 + 1;
-  return c < kPlaneCap ? (int)c : kPlaneCap;
+int plane_count(int64_t pair_cap, int area) {
+  const int64_t c = pair_cap / 24 + 1, cap = kPlaneBytes / (16 * (int64_t)area);
+  return (int)(c < cap ? c : cap);
 }
 
 int64_t pair_capacity(int64_t n, int n_tiles, int ppp) {
@@ -117,10 +117,11 @@ static FrameBufs carve_impl(Carver& c, int H, int W, int64_t n, int tile_h, int 
   b.tile_count = c.take<int>(n_tiles);
   b.tile_start = c.take<int>(n_tiles + 1);
   b.cursor = c.take<int>(n_tiles);
-  b.items = c.take<int>(plane_count(pcap));
+  const int npl = plane_count(pcap, tile_h * tile_w);
+  b.items = c.take<int>(npl);
   b.tile_plane = c.take<int>(n_tiles);
   b.tile_done = c.take<int>(n_tiles);
-  b.planes = c.take<unsigned long long>((size_t)plane_count(pcap) * 2 * tile_h * tile_w);
+  b.planes = c.take<unsigned long long>((size_t)npl * 2 * tile_h * tile_w);
   b.pids = c.take<int>((size_t)pcap);
   b.opd = c.take<float>(hw);
   b.tau = c.take<float>(hw);
@@ -165,10 +166,11 @@ static FrameBufs carve_compact(Carver& c, const FramePlan& p, int64_t pair_cap, 
   b.tile_count = c.take<int>(p.n_tiles);
   b.tile_start = c.take<int>(p.n_tiles + 1);
   b.cursor = c.take<int>(p.n_tiles);
-  b.items = c.take<int>(plane_count(pair_cap));
+  const int npl = plane_count(pair_cap, p.tile_h * p.tile_w);
+  b.items = c.take<int>(npl);
   b.tile_plane = c.take<int>(p.n_tiles);
   b.tile_done = c.take<int>(p.n_tiles);
-  b.planes = c.take<unsigned long long>((size_t)plane_count(pair_cap) * (p.absorb ? 2 : 1) * p.tile_h * p.tile_w);
+  b.planes = c.take<unsigned long long>((size_t)npl * (p.absorb ? 2 : 1) * p.tile_h * p.tile_w);
   b.pids = c.take<int>((size_t)pair_cap);
   if (own_opd) {
     b.opd = c.take<float>(hw);

@@ -89,10 +89,10 @@ struct FrameBufs {
   int* tile_count;        // n_tiles: pairs per tile (histogram)
   int* tile_start;        // n_tiles + 1: exclusive prefix of the tile counts
   int* cursor;            // n_tiles: next free entry of each tile's segment (emit)
-  int* items;             // plane_count(pair_cap): (tile << 4 | slice) of every plane in use
+  int* items;             // plane_count: (tile << 4 | slice) of every plane in use
   int* tile_plane;        // n_tiles: first plane of a sliced tile
   int* tile_done;         // n_tiles: slices finished (cleared per frame)
-  unsigned long long* planes;  // plane_count(pair_cap) planes of 2 * tile area: slices' fixed-point tile sums
+  unsigned long long* planes;  // plane_count planes of 2 * tile area: slices' fixed-point tile sums
   int* pids;              // pair_cap: particle ids, grouped by tile (segments at tile_start)
   float* opd;             // H*W (used when the caller passes no opd_out)
   float* tau;             // H*W absorbance (absorbing frames without opd_out)
@@ -114,10 +114,11 @@ FrameBufs carve(void* ws, int H, int W, int64_t n, int tile_h, int tile_w, int p
 // entries of the pair list: ppp pairs per particle plus one per tile
 int64_t pair_capacity(int64_t n, int n_tiles, int ppp);
 // planes of tile sums for the slices of crowded tiles (tiles past them are not
-// sliced): a sliced tile of c stored pairs takes at most c / 64 planes, so
-// pair_cap / 64 + 1 bounds them; at most kPlaneCap
-constexpr int kPlaneCap = 1024;
-int plane_count(int64_t pair_cap);
+// sliced): a sliced tile of c > 48 stored pairs takes ceil(c / 48) <= c / 24 planes,
+// so pair_cap / 24 + 1 bounds them; at most kPlaneBytes of planes (2 * area
+// 64-bit sums each)
+constexpr int64_t kPlaneBytes = int64_t(32) << 20;
+int plane_count(int64_t pair_cap, int area);
 
 // launchers (return hipError_t of the last launch)
 hipError_t launch_binning(const FramePlan& p, const float* soa, FrameBufs& b, hipStream_t s);

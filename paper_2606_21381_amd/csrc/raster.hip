@@ -24,7 +24,7 @@ namespace osog {
 // The first kSliceGrid workgroups take, in turn, the slices after the first of
 // crowded tiles (so that they start early; a frame without crowded tiles costs
 // kSliceGrid empty workgroups), the rest slice 0 of every tile.
-constexpr int kSliceGrid = 2048;  // a multiple of kXcds
+constexpr int kSliceGrid = 4096;  // a multiple of kXcds
 
 template <bool ABS, bool HAB>
 __global__ void __launch_bounds__(64) k_raster(FrameDev F, int per_xcd) {

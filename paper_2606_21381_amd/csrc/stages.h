@@ -130,7 +130,7 @@ __device__ __forceinline__ void bin_body(const FrameDev& F, int64_t gid) {
 constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 16;                         // counts per thread and chunk
 constexpr int kScanChunk = kScanThreads * kScanPer;  // 16384 tiles per pass
-constexpr int kSlicePairs = 128;  // particles per slice of a crowded tile
+constexpr int kSlicePairs = 48;  // particles per slice of a crowded tile
 constexpr int kMaxSlices = 16;
 
 __device__ __forceinline__ long long wave_incl_scan(long long v, int lane) {
@@ -753,21 +753,30 @@ __device__ __forceinline__ void raster_tile(const FrameDev& F, int tile, int sli
     // this slice's sums to its plane; the last slice of the tile adds the S planes
     const size_t pl = (size_t)area * (ABS ? 2 : 1);
     unsigned long long* mine = F.planes + (size_t)(plane + slice) * pl;
+    // The planes are written and read with agent-scope atomic stores and loads,
+    // which the GPU keeps coherent across its XCDs without a write-back of the
+    // issuing L2; the stores have completed (s_waitcnt 0) before the count is
+    // raised, and the last slice reads the planes after its own count.  (A
+    // release/acquire fence pair here writes back and invalidates the XCD's whole
+    // L2 once per slice, which cost more than slicing saved.)
     for (int q = lane; q < area; q += 64) {
-      mine[q] = L.acc[q];
-      if (ABS) mine[area + q] = L.tacc[q];
+      __hip_atomic_store(mine + q, L.acc[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (ABS) __hip_atomic_store(mine + area + q, L.tacc[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __threadfence();  // the plane before the count
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     int last = 0;
-    if (lane == 0) last = atomicAdd(&F.tile_done[tile], 1) == S - 1;
+    if (lane == 0)
+      last = __hip_atomic_fetch_add(&F.tile_done[tile], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == S - 1;
     if (__builtin_amdgcn_readfirstlane(last)) {
-      __threadfence();  // every other slice's plane after its count
-      const unsigned long long* base = F.planes + (size_t)plane * pl;
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      unsigned long long* base = F.planes + (size_t)plane * pl;
       for (int q = lane; q < area; q += 64) {
         unsigned long long a = 0ull, t = 0ull;
         for (int k = 0; k < S; ++k) {
-          a += base[(size_t)k * pl + q];
-          if (ABS) t += base[(size_t)k * pl + area + q];
+          a += __hip_atomic_load(base + (size_t)k * pl + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (ABS) t += __hip_atomic_load(base + (size_t)k * pl + area + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         const int i = q / G.tw, j = q - i * G.tw;
         const int64_t o = (int64_t)(G.Y0 + i) * F.W + G.X0 + j;
@@ -1087,7 +1096,7 @@ inline FrameDev make_dev(const FramePlan& p, const FrameBufs& b) {
   F.recs = b.recs; F.boxes = b.boxes; F.counts = b.counts; F.scal = b.scal;
   F.tile_count = b.tile_count; F.tile_start = b.tile_start; F.cursor = b.cursor;
   F.items = b.items; F.tile_plane = b.tile_plane; F.tile_done = b.tile_done;
-  F.planes = b.planes; F.plane_cap = plane_count(p.pair_cap);
+  F.planes = b.planes; F.plane_cap = plane_count(p.pair_cap, p.tile_h * p.tile_w);
   F.pids = b.pids;
   F.band = b.band; F.colsum = b.colsum;
   F.band_in = b.band; F.in_kx_lo = p.kx_lo; F.in_kx_n = p.kx_n;

@@ -108,8 +108,12 @@ def test_incoherent_dic_is_forward_only():
     with pytest.raises(_lib.OsogError) as e:
         render.render_multi(s, 64, 64, [inc_optics()], gl.view(1, 4))
     assert e.value.status == 2
-    # the small (forward) workspace is refused with a clear error
-    small = torch.empty(render.workspace_size(64, 64, 10, False), dtype=torch.uint8, device="cuda")
+    # the small (forward) workspace is refused with a clear error (at 512^2 the
+    # incoherent mode's full-width spectra need megabytes more than the forward
+    # carve holds, whatever pair capacity it is given)
+    soa5, g5 = frame(5, 512, 10)
+    s5, gl5 = dev_soa(soa5), dev_globals(g5)
+    small = torch.empty(render.workspace_size(512, 512, 10, False), dtype=torch.uint8, device="cuda")
     with pytest.raises(_lib.OsogError) as e:
-        render.render(s, 64, 64, inc_optics(), gl, workspace=small)
+        render.render(s5, 512, 512, inc_optics(), gl5, workspace=small)
     assert e.value.status == 3  # OSOG_ERR_WORKSPACE
