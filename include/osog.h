@@ -125,7 +125,11 @@ osog_status osog_get_tiling(const osog_context* ctx, int32_t* tile_h, int32_t* t
  * + tiles entries (0 selects 32).  The list is grouped by tile with exact
  * offsets, so a crowded tile costs only its own pairs.  A frame whose pairs
  * exceed the list stays correct and bitwise identical: the tiles whose segments
- * do not fit are rasterised by a slower id-ordered scan of all particles. */
+ * do not fit are rasterised by a slower id-ordered scan of all particles.  The
+ * workspace also holds up to 32 MiB of planes in which the slices of crowded
+ * tiles (more than 48 pairs) keep their partial sums; a frame that needs more
+ * leaves its last crowded tiles unsliced (slower, same result).  The workspace
+ * holds no state between calls and may be reused for anything in between. */
 osog_status osog_workspace_size(const osog_context* ctx, int32_t height, int32_t width, int64_t n,
                                 int32_t pairs_per_particle, int32_t with_backward, size_t* bytes);
 
