@@ -1,12 +1,13 @@
 // OPD rasterisation (step F5): one 64-lane wave per tile, the tile's pixel sums
 // in LDS.  Absorbing frames also build the absorbance canvas tau = sum of
-// dmu * thickness from the same coverage values, in the same order (the
-// Beer-Lambert exponent of Eq. 4).
-// Each particle of the tile, in ascending id, deals the candidate pixels of its
-// record that lie in the tile to the lanes, 64 at a time; the costly pixels (two
-// prism edges, ellipse rim, habit face) are queued and evaluated 64 at a time.
-// Every pixel's value depends only on the pixel and the particles that reach it,
-// so the canvas is bitwise the same under every tiling, launch order and GPU.
+// dmu * thickness from the same coverage values (the Beer-Lambert exponent of
+// Eq. 4).
+// Each particle of the tile's segment deals the candidate pixels of its record
+// that lie in the tile to the lanes, 64 at a time; the costly pixels (two prism
+// edges, ellipse rim, habit face) are queued and evaluated 64 at a time.  The
+// sums are 64-bit fixed point, so their order does not matter: every pixel's
+// value depends only on the pixel and the particles that reach it, and the canvas
+// is bitwise the same under every tiling, launch order and GPU.
 // This replaces the paper's atomic scatter-add (Sec. III.C, Eq. 7) by a gather
 // over the tile-sorted pair list.  Body: raster_tile (stages.h).
 #include <hip/hip_runtime.h>

@@ -249,9 +249,10 @@ __device__ __forceinline__ void tile_scan_body(const FrameDev& F, long long* wsu
 // ---- F3: emit each pair into its tile's segment -----------------------------------
 // A group of kBinGroup lanes shares one particle and deals its tiles round robin;
 // every pair takes the next entry of its tile's segment through the tile's
-// cursor.  The order inside a segment depends on the atomics; the reader restores
-// ascending id.  Pairs past the list's capacity are not stored (their tiles are
-// rasterised by the id-ordered scan instead).
+// cursor.  The order inside a segment depends on the atomics and does not matter
+// to the raster, whose sums are exact integers; only the inspection copy
+// (k_sort_segments) is put in ascending id.  Pairs past the list's capacity are not
+// stored (their tiles are rasterised by the scan over all particles instead).
 constexpr int kFillBatch = 4;
 
 __device__ __forceinline__ void emit_body(const FrameDev& F, int64_t gid) {
@@ -276,7 +277,7 @@ __device__ __forceinline__ void emit_body(const FrameDev& F, int64_t gid) {
   }
 }
 
-// ---- F4: a segment's particle ids in ascending order, for one 64-lane wave ------
+// ---- F4 (inspection): a segment's particle ids in ascending order, one wave ------
 // Up to 64 ids are sorted in registers (bitonic network over the lanes), up to
 // kSegSort in LDS and then held in registers, kSegRegs per lane, so that the LDS
 // used for the sort is free again while the ids are visited.  A longer segment,
