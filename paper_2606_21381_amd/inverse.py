@@ -10,7 +10,8 @@ Schedule (a curriculum of stages, each naming the parameter groups that move):
 by default for the first ``globals_first`` steps only the four globals move (the
 per-particle parameters would otherwise drift to compensate for 20 % errors in
 dn, defocus, shear and bias, and some settle in other basins); then everything
-moves, with a cosine decay of every rate over the last part of the run.
+moves, with a cosine decay of every rate over the last part of the run.  Optionally
+the first ``blur_steps`` steps compare blurred residuals (a coarse start).
 
 Losses: the mean squared image error for a pixel-aligned target, or the
 spectral loss of Eq. 8 (log amplitudes of the 2-D DFT, eps = ``spectral_eps``
@@ -66,6 +67,12 @@ class SolverConfig:
     curriculum: Optional[tuple] = None
     loss: str = "mse"          # "mse" (pixel-aligned target) or "spectral" (Eq. 8)
     spectral_eps: float = 1e-4 # eps of the spectral loss, relative to the target's DC term
+    # coarse start: for the first blur_steps steps the pixel loss compares the residual
+    # I - target after two box blurs of radius r = blur_radius px (close to a Gaussian of
+    # sigma = sqrt(((2 r + 1)^2 - 1) / 6) px, 5.3 px for r = 6), which widens each
+    # particle's basin of attraction
+    blur_steps: int = 0
+    blur_radius: int = 0
     # replay each step as one captured HIP graph (one per curriculum stage) when the
     # target is on the GPU; the eager loop issues ~50 launches per step and is bound by
     # the host.  The steps compute the same values either way.
@@ -230,6 +237,8 @@ def solve(target: torch.Tensor, start: Params, truth: Optional[Truth], H: int, W
     is undone; the rates of the cosine decay live in a device tensor that each
     step rewrites.  If a captured graph holds a memset node the solve runs eager.
     """
+    if cfg.blur_steps > 0 and (cfg.loss != "mse" or cfg.blur_radius < 1):
+        raise ValueError("blur_steps needs the mse loss and blur_radius >= 1")
     if render_fn is None:
         from .render import render_diff
 
@@ -245,9 +254,16 @@ def solve(target: torch.Tensor, start: Params, truth: Optional[Truth], H: int, W
             return spectral_loss_diff(I, tl, eps)
     elif cfg.loss == "mse":
         inv_n = 1.0 / target.numel()
+        rb = cfg.blur_radius
 
-        def loss_fn(I):  # row sums, then their sum: no grid-wide reduction
-            return torch.sum(torch.sum((I - target) ** 2, dim=-1)) * inv_n
+        def loss_fn(I, blurred=False):  # row sums, then their sum: no grid-wide reduction
+            r = I - target
+            if blurred:
+                q = r.reshape(1, 1, *r.shape[-2:])
+                for _ in range(2):
+                    q = torch.nn.functional.avg_pool2d(q, 2 * rb + 1, stride=1, padding=rb)
+                r = q.reshape(r.shape)
+            return torch.sum(torch.sum(r ** 2, dim=-1)) * inv_n
     else:
         raise ValueError("loss must be 'mse' or 'spectral'")
     dev = target.device
@@ -283,10 +299,10 @@ def solve(target: torch.Tensor, start: Params, truth: Optional[Truth], H: int, W
             for g, b in zip(opt.param_groups, base):
                 g["lr"] = b * m
 
-    def body(moving):
+    def body(moving, blurred=False):
         opt.zero_grad(set_to_none=True)
         I = render_fn(start.soa(), start.globals4())
-        loss = loss_fn(I)
+        loss = loss_fn(I, blurred) if blurred else loss_fn(I)
         loss.backward()
         for grp in GROUPS:  # frozen groups keep their values (and Adam state)
             if grp not in moving:
@@ -300,26 +316,29 @@ def solve(target: torch.Tensor, start: Params, truth: Optional[Truth], H: int, W
                 static_err.copy_(torch.stack(parameter_errors(start, truth, floor)))
 
     graphs = None
-    stages = sorted({stage_groups(cfg, k) for k in range(cfg.steps)}, key=lambda f: sorted(f))
+    def key(k):  # what one step does: the groups that move and whether the loss is blurred
+        return stage_groups(cfg, k), k < cfg.blur_steps
+
+    stages = sorted({key(k) for k in range(cfg.steps)}, key=lambda f: (sorted(f[0]), f[1]))
     if on_gpu and cfg.graph and cfg.steps > 0:
         saved = [q.detach().clone() for q in start.parameters()]
         side = _warmup_stream(dev)
         side.wait_stream(torch.cuda.current_stream(dev))
         with torch.cuda.stream(side):  # warm-up: creates Adam's state and the allocator's blocks
-            for _ in range(3):
-                body(frozenset(GROUPS))
+            for i in range(3):
+                body(frozenset(GROUPS), i == 0 and cfg.blur_steps > 0)
         torch.cuda.current_stream(dev).wait_stream(side)
         graphs, pool = {}, None
-        for moving in stages:
+        for st in stages:
             g = torch.cuda.CUDAGraph(keep_graph=True)
             with torch.cuda.graph(g, pool=pool):
-                body(moving)
+                body(*st)
             pool = g.pool()
             g.instantiate()
             if _graph_memsets(g):
                 graphs = None
                 break
-            graphs[moving] = g
+            graphs[st] = g
         with torch.no_grad():  # undo the warm-up and capture steps
             for q, v in zip(start.parameters(), saved):
                 q.copy_(v)
@@ -340,9 +359,9 @@ def solve(target: torch.Tensor, start: Params, truth: Optional[Truth], H: int, W
         if k >= k0 or k == 0:
             set_rates(k)
         if graphs is not None:
-            graphs[stage_groups(cfg, k)].replay()
+            graphs[key(k)].replay()
         else:
-            body(stage_groups(cfg, k))
+            body(*key(k))
         losses[k].copy_(static_loss)
         if truth is not None:
             errors[k + 1].copy_(static_err)

@@ -31,6 +31,13 @@ library's forward render and hand-written adjoint:
   They scan a whole period of the square's angle (+-pi/4), since a small prism's
   first search, made while the positions were still off, can end in a side minimum
   more than the first bracket away from the truth.
+* Re-seeding.  When the Gauss-Newton steps end above the loss floor, the
+  particles whose window loss exceeds ``reseed_factor`` times the median are
+  moved, colour by colour, to the best point of a grid around their state
+  (centre offsets of whole pixels up to ``reseed_px``, half-width offsets
+  ``reseed_dw``, the angle as it is or turned by pi/4), scored by the window loss;
+  then the polish starts again from there.  This lets a particle that Adam left a
+  few pixels from its truth, in a side minimum of its window, leave it.
 
 Nothing here computes an image: every render and gradient goes through libosog
 (or the injected functions the CPU tests use).
@@ -38,7 +45,7 @@ Nothing here computes an image: every render and gradient goes through libosog
 from __future__ import annotations
 
 import math
-from dataclasses import dataclass
+from dataclasses import dataclass, replace
 from typing import Callable, Optional
 
 import numpy as np
@@ -68,6 +75,10 @@ class PolishConfig:
     scale: tuple = (1.0, 1.0, 0.1, 1.0)
     scale_glob: tuple = (1e-3, 0.1, 0.05, 0.05)
     jvp_eps: float = 0.01         # forward-difference step of J v along the scaled unit direction
+    reseed_rounds: int = 1        # re-seed and polish again at most this many times
+    reseed_factor: float = 10.0   # re-seed particles whose window loss exceeds this times the median
+    reseed_px: int = 3            # centre offsets -reseed_px .. reseed_px px in x and y
+    reseed_dw: tuple = (-1.5, 0.0, 1.5)  # half-width offsets [px]
 
 
 class Model:
@@ -202,6 +213,47 @@ def angle_search(model: Model, target, x, y, a, w, glob, win: Windows, span: flo
     return best_a
 
 
+def reseed(model: Model, target, x, y, a, w, glob, pc: PolishConfig):
+    """Moves every particle whose window loss exceeds pc.reseed_factor times the
+    median to the best point of its grid (centre offsets in whole pixels up to
+    pc.reseed_px, half-width offsets pc.reseed_dw, angle offsets 0 and pi/4), scored
+    by the window loss with the other particles of its colour moved alike; keeps a
+    particle where no grid point lowers its window loss.  Returns (x, y, a, w, moved)."""
+    color, bounds = color_windows(x.detach().cpu().numpy(), y.detach().cpu().numpy(),
+                                  w.detach().cpu().numpy(), model.H, model.W, pc.margin_px, pc.separation_px)
+    win = Windows(color, bounds, model.H, model.W, x.device)
+    tf = target.reshape(-1)
+    r = model.render(x, y, a, w, glob).reshape(-1) - tf
+    s = torch.zeros(model.n, dtype=torch.float64, device=x.device)
+    for c in range(len(win.colors)):
+        s += win.sums(c, r * r)
+    bad = s > float(torch.median(s)) * pc.reseed_factor
+    R = pc.reseed_px
+    grid = [(dx, dy, dw, da) for dx in range(-R, R + 1) for dy in range(-R, R + 1)
+            for dw in pc.reseed_dw for da in (0.0, math.pi / 4)]
+    best = s.clone()
+    bx, by, ba, bw = x.clone(), y.clone(), a.clone(), w.clone()
+    for c, (members, _, _) in enumerate(win.colors):
+        m = members[bad[members]]
+        if m.numel() == 0:
+            continue
+        for dx, dy, dw, da in grid:
+            xc, yc, ac, wc = x.clone(), y.clone(), a.clone(), w.clone()
+            xc[m] += dx
+            yc[m] += dy
+            ac[m] += da
+            wc[m] = torch.clamp(wc[m] + dw, min=1.0)
+            rc = model.render(xc, yc, ac, wc, glob).reshape(-1) - tf
+            sc = win.sums(c, rc * rc)
+            better = torch.zeros_like(bad)
+            better[m] = sc[m] < best[m]
+            best = torch.where(better, sc, best)
+            bx, by = torch.where(better, xc, bx), torch.where(better, yc, by)
+            ba, bw = torch.where(better, ac, ba), torch.where(better, wc, bw)
+    moved = int(((bx != x) | (by != y) | (ba != a) | (bw != w)).sum())
+    return bx, by, ba, bw, moved
+
+
 def particle_blocks(model: Model, I, x, y, a, w, glob, win: Windows, eps):
     """Gauss-Newton blocks J_i^T J_i [n, 4, 4] (sum of squared-residual convention:
     the curvature of sum r^2 / 2) from forward differences, one render per colour
@@ -323,7 +375,8 @@ def polish(target: torch.Tensor, model: Model, x, y, a, w, glob, pc: PolishConfi
     """Angle search, then Gauss-Newton steps (with the small prisms' angle search
     repeated every ``search_every`` steps) from (x, y, a, w, glob) (device tensors,
     returned updated), until the loss falls below ``loss_tol`` x mean(target^2) or
-    after ``iters`` steps.  error_fn(x, y, a, w, glob) -> e (float) is recorded after
+    after ``iters`` steps; then, above that floor, up to ``reseed_rounds`` times a
+    re-seed (``reseed``) and the whole polish again.  error_fn(x, y, a, w, glob) -> e (float) is recorded after
     every stage when given (it only records; the loss alone decides when to stop);
     clock() -> seconds since the solve started.  Returns (x, y, a, w, glob, trace)."""
     N = target.numel()
@@ -398,4 +451,11 @@ def polish(target: torch.Tensor, model: Model, x, y, a, w, glob, pc: PolishConfi
         record("lm%d loss %.3e" % (it, L))
         if L <= pc.loss_tol * float(torch.mean(target.double() ** 2)):
             break
+    if pc.reseed_rounds > 0 and L > pc.loss_tol * float(torch.mean(target.double() ** 2)):
+        x, y, a, w, moved = reseed(model, target, x, y, a, w, glob, pc)
+        if moved:
+            record("reseed %d" % moved)
+            x, y, a, w, glob, more = polish(target, model, x, y, a, w, glob,
+                                            replace(pc, reseed_rounds=pc.reseed_rounds - 1), error_fn, clock)
+            trace += more
     return x, y, a, w, glob, trace

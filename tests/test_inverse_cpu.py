@@ -140,3 +140,60 @@ def test_colouring_keeps_colours_apart():
         same = (color == color[i]) & (np.arange(60) != i)
         assert not np.any(same & (np.abs(x - x[i]) < sep + sep[i]) & (np.abs(y - y[i]) < sep + sep[i]))
     assert np.all(bounds[:, 0] <= bounds[:, 1]) and np.all(bounds[:, 0] >= 0) and np.all(bounds[:, 1] <= 255)
+
+
+def test_reseed_returns_a_displaced_particle():
+    """A blob left 2 px and 3 px off in x and y, its width 1.5 px too large, is moved
+    back onto its truth by one re-seed (a grid point), and the particles already at
+    their truth stay where they are."""
+    from paper_2606_21381_amd import polish
+    model, render = _toy_model()
+    x = torch.tensor([12.0, 30.0, 50.0, 14.0, 33.0, 52.0])
+    y = torch.tensor([12.0, 14.0, 11.0, 45.0, 50.0, 47.0])
+    a = torch.tensor([0.3, 1.0, 2.0, 0.6, 1.4, 2.6])
+    w = torch.tensor([3.0, 4.0, 3.5, 4.5, 3.2, 3.8])
+    g = torch.tensor([0.03, 0.5, 0.2, 1.0])
+    target = render(x, y, a, w, g)
+    xs, ys, ws = x.clone(), y.clone(), w.clone()
+    xs[1] += 2.0
+    ys[1] -= 3.0
+    ws[1] += 1.5
+    pc = polish.PolishConfig(margin_px=6.0, separation_px=6.0)
+    xr, yr, ar, wr, moved = polish.reseed(model, target, xs, ys, a.clone(), ws, g, pc)
+    assert moved == 1
+    assert torch.equal(xr, x) and torch.equal(yr, y) and torch.equal(wr, w) and torch.equal(ar, a)
+    # at the truth nothing is selected or moved
+    assert polish.reseed(model, target, x, y, a, w, g, pc)[4] == 0
+
+
+def test_blurred_start_runs_and_converges():
+    """The optional coarse start (blurred residuals for the first steps) moves blobs
+    4 px off back onto their truth; it needs the pixel loss."""
+    H = W = 48
+    ii = torch.arange(H, dtype=torch.float32)[:, None]
+    jj = torch.arange(W, dtype=torch.float32)[None, :]
+
+    def blobs(soa, g):
+        I = torch.zeros(H, W)
+        for k in range(soa.shape[1]):
+            I = I + torch.exp(-((ii - soa[1, k]) ** 2 + (jj - soa[0, k]) ** 2) / 8.0)
+        return I * g[0] * 30
+
+    x, y = torch.tensor([10.0, 25.0, 38.0]), torch.tensor([12.0, 30.0, 20.0])
+    a, w, h = torch.zeros(3), torch.full((3,), 3.0), torch.ones(3)
+    glob = torch.tensor([0.03, -0.8, 1.0, math.pi / 2])
+    truth = inverse.Truth(x, y, a, w, glob)
+    p = inverse.Params(x, y, a, w, h, glob)
+    target = blobs(p.soa(), p.globals4()).detach()
+    start = inverse.Params(x + 4.5, y - 4.0, a, w, h, glob)
+    cfg = inverse.SolverConfig(steps=300, lr_pos=0.2, curriculum=((300, ("position",)),),
+                               blur_steps=150, blur_radius=4, target_error=1e-2)
+    res = inverse.solve(target, start, truth, H, W, None, cfg, render_fn=blobs)
+    assert res.steps_to_target is not None and res.error[-1] < 1e-3
+    bad = inverse.SolverConfig(steps=3, loss="spectral", blur_steps=2, blur_radius=2)
+    try:
+        inverse.solve(target, inverse.Params(x, y, a, w, h, glob), truth, H, W, None, bad, render_fn=blobs)
+    except ValueError:
+        pass
+    else:
+        raise AssertionError("a blurred start with the spectral loss must be refused")
