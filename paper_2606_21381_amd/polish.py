@@ -37,7 +37,11 @@ library's forward render and hand-written adjoint:
   (centre offsets of whole pixels up to ``reseed_px``, half-width offsets
   ``reseed_dw``, the angle as it is or turned by pi/4), scored by the window loss;
   then the polish starts again from there.  This lets a particle that Adam left a
-  few pixels from its truth, in a side minimum of its window, leave it.
+  few pixels from its truth, in a side minimum of its window, leave it.  The same
+  stage tries exchanging the centres (or centres, angles and half-widths) of
+  neighbouring particles closer than 1.5 times the larger half-width: their
+  heights differ, so a pair that Adam crossed over fits the image nearly but not
+  exactly, and no small step uncrosses it.
 
 Nothing here computes an image: every render and gradient goes through libosog
 (or the injected functions the CPU tests use).
@@ -218,7 +222,10 @@ def reseed(model: Model, target, x, y, a, w, glob, pc: PolishConfig):
     median to the best point of its grid (centre offsets in whole pixels up to
     pc.reseed_px, half-width offsets pc.reseed_dw, angle offsets 0 and pi/4), scored
     by the window loss with the other particles of its colour moved alike; keeps a
-    particle where no grid point lowers its window loss.  Returns (x, y, a, w, moved)."""
+    particle where no grid point lowers its window loss.  Then, for every pair of
+    particles closer than 1.5 times the larger half-width, keeps the exchange of their
+    centres (or of centres, angles and half-widths) if it lowers the loss over the
+    pair's joint window.  Returns (x, y, a, w, moved)."""
     color, bounds = color_windows(x.detach().cpu().numpy(), y.detach().cpu().numpy(),
                                   w.detach().cpu().numpy(), model.H, model.W, pc.margin_px, pc.separation_px)
     win = Windows(color, bounds, model.H, model.W, x.device)
@@ -251,7 +258,39 @@ def reseed(model: Model, target, x, y, a, w, glob, pc: PolishConfig):
             bx, by = torch.where(better, xc, bx), torch.where(better, yc, by)
             ba, bw = torch.where(better, ac, ba), torch.where(better, wc, bw)
     moved = int(((bx != x) | (by != y) | (ba != a) | (bw != w)).sum())
-    return bx, by, ba, bw, moved
+    x, y, a, w = bx, by, ba, bw
+    # exchanges within close pairs, scored by the loss over the pair's joint window
+    xn, yn, wn = (v.detach().cpu().numpy().astype(np.float64) for v in (x, y, w))
+    dist = np.hypot(xn[:, None] - xn[None], yn[:, None] - yn[None])
+    close = (dist < 1.5 * np.maximum(wn[:, None], wn[None])) & np.triu(np.ones_like(dist, dtype=bool), 1)
+    tg = target.reshape(model.H, model.W).double()
+    I = model.render(x, y, a, w, glob).reshape(model.H, model.W)
+    for i, j in np.argwhere(close).tolist():
+        ext = pc.margin_px + 1.5 * max(wn[i], wn[j])
+        x0 = max(0, math.floor(min(xn[i], xn[j]) - ext))
+        x1 = min(model.W - 1, math.ceil(max(xn[i], xn[j]) + ext))
+        y0 = max(0, math.floor(min(yn[i], yn[j]) - ext))
+        y1 = min(model.H - 1, math.ceil(max(yn[i], yn[j]) + ext))
+
+        def pair_loss(img):
+            r = img[y0:y1 + 1, x0:x1 + 1].double() - tg[y0:y1 + 1, x0:x1 + 1]
+            return float((r * r).sum())
+
+        best_l, best_s = pair_loss(I), None
+        for whole in (False, True):
+            xc, yc, ac, wc = x.clone(), y.clone(), a.clone(), w.clone()
+            xc[[i, j]], yc[[i, j]] = x[[j, i]], y[[j, i]]
+            if whole:
+                ac[[i, j]], wc[[i, j]] = a[[j, i]], w[[j, i]]
+            Ic = model.render(xc, yc, ac, wc, glob).reshape(model.H, model.W)
+            lc = pair_loss(Ic)
+            if lc < best_l:
+                best_l, best_s = lc, (xc, yc, ac, wc, Ic)
+        if best_s is not None:
+            x, y, a, w, I = best_s
+            xn, yn, wn = (v.detach().cpu().numpy().astype(np.float64) for v in (x, y, w))
+            moved += 2
+    return x, y, a, w, moved
 
 
 def particle_blocks(model: Model, I, x, y, a, w, glob, win: Windows, eps):

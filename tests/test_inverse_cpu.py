@@ -197,3 +197,32 @@ def test_blurred_start_runs_and_converges():
         pass
     else:
         raise AssertionError("a blurred start with the spectral loss must be refused")
+
+
+def test_reseed_uncrosses_a_swapped_pair():
+    """Two overlapping blobs of different heights whose centres were exchanged are
+    put back by the re-seed's pair exchange."""
+    from paper_2606_21381_amd import polish
+    H = W = 64
+    jj, ii = torch.meshgrid(torch.arange(W, dtype=torch.float64), torch.arange(H, dtype=torch.float64), indexing="xy")
+    height = torch.tensor([1.0, 2.5, 1.0])
+
+    def render(x, y, a, w, glob):
+        x, y, w = (t.double() for t in (x, y, w))
+        dx = jj[None] - x[:, None, None]
+        dy = ii[None] - y[:, None, None]
+        ww = w[:, None, None]
+        return (height.double()[:, None, None] * torch.exp(-(dx * dx + dy * dy) / (ww * ww))).sum(0).float()
+
+    model = polish.Model(H, W, None, height, render_fn=render, grad_fn=lambda *args: None)
+    x = torch.tensor([30.0, 33.0, 10.0])
+    y = torch.tensor([30.0, 32.0, 50.0])
+    a = torch.zeros(3)
+    w = torch.tensor([4.0, 4.0, 3.0])
+    g = torch.zeros(4)
+    target = render(x, y, a, w, g)
+    xs, ys = x[[1, 0, 2]], y[[1, 0, 2]]
+    pc = polish.PolishConfig(margin_px=6.0, separation_px=6.0, reseed_px=0, reseed_dw=(0.0,))
+    xr, yr, ar, wr, moved = polish.reseed(model, target, xs, ys, a.clone(), w.clone(), g, pc)
+    assert moved >= 2
+    assert torch.equal(xr, x) and torch.equal(yr, y)
