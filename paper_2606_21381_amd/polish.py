@@ -31,6 +31,10 @@ library's forward render and hand-written adjoint:
   They scan a whole period of the square's angle (+-pi/4), since a small prism's
   first search, made while the positions were still off, can end in a side minimum
   more than the first bracket away from the truth.
+* Closing angle search.  The repeated searches leave the small prisms' angles on a
+  grid of a few 1e-3 rad, and the Gauss-Newton steps barely move them; when the
+  steps end above the loss floor, those angles are searched once more over
+  brackets of +-``final_span`` and a tenth of it.
 * Re-seeding.  When the Gauss-Newton steps end above the loss floor, the
   particles whose window loss exceeds ``reseed_factor`` times the median are
   moved, colour by colour, to the best point of a grid around their state
@@ -75,6 +79,8 @@ class PolishConfig:
     research_span: float = math.pi / 4  # bracket of the repeated searches (a full period of a square)
     research_refine: int = 1      # further repeated searches, each over a bracket 1/10 as wide
     research_w_max: float = 5.0   # the repeated searches turn only prisms narrower than this [px]
+    final_span: float = 3e-3      # closing search of those prisms' angles over +-final_span [rad]
+    final_refine: int = 1         # further closing searches, each over a bracket 1/10 as wide
     # parameter scales of the CG's unknowns: x, y [px], angle [rad], width [px]; dn, dz, shear, bias
     scale: tuple = (1.0, 1.0, 0.1, 1.0)
     scale_glob: tuple = (1e-3, 0.1, 0.05, 0.05)
@@ -414,8 +420,9 @@ def polish(target: torch.Tensor, model: Model, x, y, a, w, glob, pc: PolishConfi
     """Angle search, then Gauss-Newton steps (with the small prisms' angle search
     repeated every ``search_every`` steps) from (x, y, a, w, glob) (device tensors,
     returned updated), until the loss falls below ``loss_tol`` x mean(target^2) or
-    after ``iters`` steps; then, above that floor, up to ``reseed_rounds`` times a
-    re-seed (``reseed``) and the whole polish again.  error_fn(x, y, a, w, glob) -> e (float) is recorded after
+    after ``iters`` steps; then, above that floor, a closing fine search of the small
+    prisms' angles and up to ``reseed_rounds`` times a re-seed (``reseed``) and the
+    whole polish again.  error_fn(x, y, a, w, glob) -> e (float) is recorded after
     every stage when given (it only records; the loss alone decides when to stop);
     clock() -> seconds since the solve started.  Returns (x, y, a, w, glob, trace)."""
     N = target.numel()
@@ -490,6 +497,18 @@ def polish(target: torch.Tensor, model: Model, x, y, a, w, glob, pc: PolishConfi
         record("lm%d loss %.3e" % (it, L))
         if L <= pc.loss_tol * float(torch.mean(target.double() ** 2)):
             break
+    if pc.final_span > 0.0 and L > pc.loss_tol * float(torch.mean(target.double() ** 2)):
+        # the repeated searches leave the small prisms' angles on a grid of
+        # 2 research_span / ((angle_steps - 1) 10^research_refine), and the Gauss-Newton
+        # steps barely move them; close with finer brackets
+        span = pc.final_span
+        for r in range(1 + pc.final_refine):
+            a = angle_search(model, target, x, y, a, w, glob, win, span, pc.angle_steps,
+                             only=w < pc.research_w_max)
+            span /= 10.0
+        I = model.render(x, y, a, w, glob)
+        L = _loss(I, target)
+        record("fine angles loss %.3e" % L)
     if pc.reseed_rounds > 0 and L > pc.loss_tol * float(torch.mean(target.double() ** 2)):
         x, y, a, w, moved = reseed(model, target, x, y, a, w, glob, pc)
         if moved:
