@@ -319,20 +319,28 @@ def main():
     }
     if not args.no_extras:
         legs = set(args.legs.split(","))
+        progress("headline frame done: %.4f ms per frame" % ms)
         if "fft_vs_rocfft" in legs:
             res["fft_vs_rocfft"] = bench_fft_vs_rocfft(render, lib, ctx, soa, fr, g, dev)
+            progress("leg fft_vs_rocfft done")
         if "multimodal" in legs:
             res["multimodal"] = bench_multimodal(render, soa, fr, dev)
+            progress("leg multimodal done")
         if "variants" in legs:
             res["variants"] = bench_variants(render, fr, g, dev)
+            progress("leg variants done")
         if "backward" in legs:
             res["backward"] = bench_backward(render, soa, g, fr, dev)
+            progress("leg backward done")
         if "batch" in legs:
             res["batch"] = bench_batch(render, dev)
+            progress("leg batch done")
         if "stream" in legs:
             res["stream"] = bench_stream(render, fr, dev)
+            progress("leg stream done")
         if "inverse" in legs:
             res["inverse"] = bench_inverse(dev, learned=not args.no_learned)
+            progress("leg inverse done")
     if args.calib_copy_mib > 0:
         nb = args.calib_copy_mib << 20
         src = torch.ones(nb, dtype=torch.uint8, device=dev)
@@ -581,6 +589,11 @@ def bench_stream(render, fr, dev, frames=8, reps=10):
             "frames_per_s": round(frames * 1000.0 / ms, 1), "error_flag": b.error_flag()}
 
 
+def progress(*parts):
+    """One line on stderr when a leg (or one of its targets) is done."""
+    print("bench:", *parts, file=sys.stderr, flush=True)
+
+
 def bench_inverse(dev, learned=True, learned_targets=10, learned_samples=600_000):
     """1024^2 DIC, 500 prisms (seed 3): the hybrid solve (Adam from the perturbed start,
     angles held until the second-order polish); time to e <= 1e-3.  Then, when
@@ -603,7 +616,15 @@ def bench_inverse(dev, learned=True, learned_targets=10, learned_samples=600_000
            "polish_stages": [(tag.split()[0], round(t, 3), float("%.3g" % e)) for tag, t, e, _ in res.trace]}
     if learned:
         from paper_2606_21381_amd import cnn
-        rep = cnn.compare(dev, samples=learned_samples, n_targets=learned_targets)
+        def log(k, info):
+            if isinstance(info, dict) and "seed" in info:
+                progress("learned vs default, target seed %d: fallback %s, time to 1e-3 %s / %s s" % (
+                    info["seed"], info["fallback"], info["default"]["time_to_1e-3_s"],
+                    info["learned"]["time_to_1e-3_s"]))
+            elif k % 500 == 0:
+                progress("learned initializer training step", k)
+
+        rep = cnn.compare(dev, samples=learned_samples, n_targets=learned_targets, log=log)
         rep["targets"] = [{"seed": r["seed"], "fallback": r["fallback"],
                            "default": {k: r["default"][k] for k in ("time_to_1e-3_s", "glob_time_to_1e-3_s", "final_e")},
                            "learned": {k: r["learned"][k] for k in ("time_to_1e-3_s", "glob_time_to_1e-3_s", "final_e")}}
