@@ -389,7 +389,7 @@ osog_status osog_philox4x32_10(void* stream, const uint32_t* ctr, int64_t count,
  * launches into launches[OSOG_NSTAGES] (both host arrays, overwritten), and
  * forgets them. */
 enum {
-  OSOG_STAGE_BINNING = 0,   /* F1-F4: boxes, scan, emit, radix sort, tile offsets */
+  OSOG_STAGE_BINNING = 0,   /* F1-F4: boxes and counts, scan (tile offsets), emit */
   OSOG_STAGE_RASTER = 1,    /* F5: per-tile OPD accumulation                      */
   OSOG_STAGE_PASS1 = 2,     /* F6: exp(i phi), row FFT, band store                */
   OSOG_STAGE_PASS2 = 3,     /* F7: column FFT, transfer function, column IFFT     */
