@@ -8,7 +8,7 @@
 //   global average pool, dense 128 -> 64 (ReLU), dense 64 -> 4.
 // Every convolution -- forward, input gradient (dgrad) and weight gradient
 // (wgrad) -- is an implicit GEMM whose operand tiles are gathered from the
-// activations into LDS as BF16 and multiplied with v_mfma_f32_16x16x16_bf16:
+// activations into LDS as BF16 and multiplied with v_mfma_f32_16x16x32_bf16:
 //   forward  C[pix][co]  = sum_k  im2col(x)[pix][k]            W[k][co],  k = (ky,kx,ci)
 //   dgrad    C[pix][ci]  = sum_k  col(gz)[pix][k]              W^T[k][ci], k = (ky,kx,co)
 //   wgrad    C[k][co]    = sum_pix im2col(x)[pix][k]^T         gz[pix][co]  (split over pix)
@@ -24,7 +24,7 @@
 
 namespace osog {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
@@ -223,15 +223,17 @@ __device__ __forceinline__ void load_b_vec(const ConvArgs& a, uint16_t (*Bs)[16]
 }
 
 // One workgroup computes a BM x BN tile of C with 4 waves (2 x 2), each wave a
-// (BM/2) x (BN/2) block of 16 x 16 MFMA tiles.  K advances 16 at a time through
-// LDS tiles stored [row][16] so every MFMA operand is one 8-byte LDS read:
-// A lane l reads row l%16, k 4(l/16)..+3; B lane l reads column l%16 likewise;
-// C lane l holds rows 4(l/16)..+3 of column l%16 (v_mfma_f32_16x16x16_bf16).
+// (BM/2) x (BN/2) block of 16 x 16 MFMA tiles.  K advances 32 at a time, as two
+// LDS sub-tiles of 16 stored [sub][row][16], so every MFMA operand is one 16-byte
+// LDS read: A lane l reads row l%16 of sub-tile l/32, k 8((l/16)%2)..+7; B lane l
+// reads column l%16 likewise (A and B agree on which k each lane holds, which is
+// all the product needs); C lane l holds rows 4(l/16)..+3 of column l%16
+// (v_mfma_f32_16x16x32_bf16, gfx950's BF16 shape with 32 products per lane group).
 template <int MODE, int BM, int BN, bool VA, bool VB>
 __global__ void __launch_bounds__(256) k_conv_gemm(ConvArgs a) {
   constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 16, TN = WN / 16;
-  __shared__ __align__(16) uint16_t As[BM][16];
-  __shared__ __align__(16) uint16_t Bs[BN][16];
+  __shared__ __align__(16) uint16_t As[2][BM][16];
+  __shared__ __align__(16) uint16_t Bs[2][BN][16];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
@@ -245,31 +247,41 @@ __global__ void __launch_bounds__(256) k_conv_gemm(ConvArgs a) {
   for (int i = 0; i < TM; ++i)
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = kbeg; k0 < kend; k0 += 16) {
-    if constexpr (VA) {
-      load_a_vec<MODE, BM>(a, As, m0, k0, kend, t);
-    } else {
-      for (int e = t; e < BM * 16; e += 256) {
-        const int r = e >> 4, kk = e & 15, m = m0 + r, k = k0 + kk;
-        As[r][kk] = (m < a.M && k < kend) ? gather_a<MODE>(a, m, k) : (uint16_t)0;
+  const int sub = lane >> 5, kq = 8 * ((lane >> 4) & 1);
+  for (int k0 = kbeg; k0 < kend; k0 += 32) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int ks = k0 + 16 * s;
+      if (ks >= kend) {  // (workgroup-uniform) past the end: a zero sub-tile
+        for (int e = t; e < BM * 16; e += 256) As[s][e >> 4][e & 15] = 0;
+        for (int e = t; e < BN * 16; e += 256) Bs[s][e >> 4][e & 15] = 0;
+        continue;
       }
-    }
-    if constexpr (VB) {
-      load_b_vec<MODE, BN>(a, Bs, n0, k0, kend, t);
-    } else {
-      for (int e = t; e < BN * 16; e += 256) {
-        const int c = e >> 4, kk = e & 15, n = n0 + c, k = k0 + kk;
-        Bs[c][kk] = (n < a.N && k < kend) ? gather_b<MODE>(a, k, n) : (uint16_t)0;
+      if constexpr (VA) {
+        load_a_vec<MODE, BM>(a, As[s], m0, ks, kend, t);
+      } else {
+        for (int e = t; e < BM * 16; e += 256) {
+          const int r = e >> 4, kk = e & 15, m = m0 + r, k = ks + kk;
+          As[s][r][kk] = (m < a.M && k < kend) ? gather_a<MODE>(a, m, k) : (uint16_t)0;
+        }
+      }
+      if constexpr (VB) {
+        load_b_vec<MODE, BN>(a, Bs[s], n0, ks, kend, t);
+      } else {
+        for (int e = t; e < BN * 16; e += 256) {
+          const int c = e >> 4, kk = e & 15, n = n0 + c, k = ks + kk;
+          Bs[s][c][kk] = (n < a.N && k < kend) ? gather_b<MODE>(a, k, n) : (uint16_t)0;
+        }
       }
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
-      const bf16x4 av = *reinterpret_cast<const bf16x4*>(&As[wm * WM + i * 16 + (lane & 15)][4 * (lane >> 4)]);
+      const bf16x8 av = *reinterpret_cast<const bf16x8*>(&As[sub][wm * WM + i * 16 + (lane & 15)][kq]);
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
-        const bf16x4 bv = *reinterpret_cast<const bf16x4*>(&Bs[wn * WN + j * 16 + (lane & 15)][4 * (lane >> 4)]);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[i][j], 0, 0, 0);
+        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(&Bs[sub][wn * WN + j * 16 + (lane & 15)][kq]);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[i][j], 0, 0, 0);
       }
     }
     __syncthreads();
@@ -690,7 +702,7 @@ static hipError_t cnn_run(const CnnPlan& P, const CnnBufs& b, const float* image
     a.M = 9 * kLayers[l].Ci;
     a.N = kLayers[l].Co;
     a.K = (int)npix;
-    a.k_chunk = (int)((wgrad_chunk(P, l) + 15) / 16 * 16);
+    a.k_chunk = (int)((wgrad_chunk(P, l) + 31) / 32 * 32);  // whole 32-wide k steps
     const int nsplit = (a.K + a.k_chunk - 1) / a.k_chunk;
     hipError_t e = launch_conv<CONV_WGRAD>(a, s);
     if (e != hipSuccess) return e;
@@ -765,7 +777,7 @@ hipError_t conv3x3(int mode, int B, int Hi, int Wi, int Ci, int Co, int stride, 
   }
   a.M = 9 * Ci; a.N = Co; a.K = B * a.g.Ho * a.g.Wo;
   const int nsplit = std::max(1, std::min(64, a.K / 4096));
-  a.k_chunk = ((a.K + nsplit - 1) / nsplit + 15) / 16 * 16;
+  a.k_chunk = ((a.K + nsplit - 1) / nsplit + 31) / 32 * 32;
   const int ns = (a.K + a.k_chunk - 1) / a.k_chunk;
   a.out_f32 = static_cast<float*>(ws);
   hipError_t e = launch_conv<CONV_WGRAD>(a, s);
