@@ -1,7 +1,7 @@
 """ctypes binding of libosog.so: structures mirroring include/osog.h and the loader.
 
 Argument marshalling only; every step of the renderer runs in the library's HIP
-kernels.  Importing this module loads the library and raises if it is missing.
+kernels.  ``load()`` loads the library on first use and raises if it is missing.
 """
 from __future__ import annotations
 
@@ -76,6 +76,10 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError("libosog.so is not built (%s); run python -m paper_2606_21381_amd.build" % path)
+    # torch first: the library links libamdhip64.so.7 and binds to the HIP runtime
+    # already in the process, torch's; with the library loaded first the process
+    # takes the system runtime instead, and torch then finds no GPU
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
     sz = ctypes.c_size_t

@@ -280,3 +280,62 @@ def _arm(r, offset: float = 0.0) -> dict:
             "final_e": r.final_e, "final_e_glob": r.final_e_glob, "final_e_part": r.final_e_part,
             "final_loss": r.final_loss, "total_s": r.total_s + offset,
             "adam_e_glob_at_60": float(r.adam.error_glob[min(60, r.adam.steps)])}
+
+
+STRIDES = (2, 1, 2, 1, 2, 2)  # stride of each layer of LAYERS
+
+
+def conv_flops(crop: int) -> float:
+    """Multiply-add FLOPs (2 per product) of one crop's training step in the
+    convolutions: forward, input gradient (every layer but the first) and weight
+    gradient, each one implicit GEMM of (pixels) x (9 Ci) x (Co)."""
+    side, fwd, dgrad = crop, 0.0, 0.0
+    for k, ((ci, co), s) in enumerate(zip(LAYERS, STRIDES)):
+        side //= s
+        f = 2.0 * side * side * 9 * ci * co
+        fwd += f
+        dgrad += f if k > 0 else 0.0
+    return 2.0 * fwd + dgrad  # forward + weight gradient + input gradient
+
+
+def main(argv=None) -> int:
+    """Train the initializer on engine-rendered crops, or time its forward + backward."""
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--samples", type=int, default=200_000, help="crops to train on (0: skip training)")
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--crop", type=int, default=256)
+    ap.add_argument("--time-steps", type=int, default=0,
+                    help="also time this many forward + backward passes of one rendered batch "
+                         "(no rendering and no parameter update in the loop)")
+    args = ap.parse_args(argv)
+    dev = torch.device("cuda", 0)
+    net = LearnedInit(dev, batch=args.batch, crop=args.crop)
+    out = {"batch": args.batch, "crop": args.crop}
+    if args.samples > 0:
+        losses, secs = net.train(args.samples)
+        out.update(samples=args.samples, train_s=round(secs, 2), final_loss=float(losses[-20:].mean()))
+    if args.time_steps > 0:
+        rng = np.random.Generator(np.random.PCG64(net.seed))
+        if not hasattr(net, "batch_renderer"):
+            net._crop_source()
+        tgt = net.render_crops(rng)
+        for _ in range(3):
+            net.train_step(net.images, tgt, 0.0, update=False)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.time_steps):
+            net.train_step(net.images, tgt, 0.0, update=False)
+        e1.record()
+        torch.cuda.synchronize(dev)
+        ms = e0.elapsed_time(e1) / args.time_steps
+        fl = conv_flops(args.crop) * args.batch
+        out.update(fwd_bwd_ms=round(ms, 3), conv_gflop_per_batch=round(fl / 1e9, 1),
+                   conv_tflops_over_fwd_bwd=round(fl / (ms * 1e-3) / 1e12, 1))
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
