@@ -82,9 +82,12 @@ __device__ __forceinline__ uint16_t gather_a(const ConvArgs& a, int m, int k) {
     if (oy >= g.Ho || ox >= g.Wo) return 0;
     return f2bf(relu_mask_grad(a, ((int64_t)b * g.Ho + oy) * g.Wo + ox, co));
   } else {
-    // wgrad: A[m = tap-channel k'][k = pixel] = im2col(x)[pixel][k']
+    // wgrad: A[m = tap-channel k'][k = pixel] = im2col(x)[pixel][k']; row 9 Ci
+    // (present when the caller sets M = 9 Ci + 1) is all ones, so that row of the
+    // product is the bias gradient, the sum of the masked output gradient
     const int kk = m;
-    if (kk >= 9 * g.Ci) return 0;
+    if (kk == 9 * g.Ci) return k < g.B * g.Ho * g.Wo ? (uint16_t)0x3F80u : (uint16_t)0;
+    if (kk > 9 * g.Ci) return 0;
     const int tap = kk / g.Ci, ci = kk - tap * g.Ci, ky = tap / 3, kx = tap - ky * 3;
     const int hw = g.Ho * g.Wo, b = k / hw, r = k - b * hw, oy = r / g.Wo, ox = r - oy * g.Wo;
     if (b >= g.B) return 0;
@@ -180,7 +183,9 @@ __device__ __forceinline__ void load_a_vec(const ConvArgs& a, uint16_t (*As)[16]
     for (int e = t; e < (BM / 8) * 16; e += 256) {
       const int kk = e & 15, gi = e >> 4, m = m0 + 8 * gi, k = k0 + kk;
       uint4 v = z;
-      if (m < a.M && k < kend) {
+      if (m == 9 * g.Ci && m < a.M && k < kend) {
+        v = make_uint4(0x3F80u, 0u, 0u, 0u);  // the ones row (bias gradient), then zero rows
+      } else if (m < a.M && k < kend) {
         const int tap = m / g.Ci, ci0 = m - tap * g.Ci, ky = tap / 3, kx = tap - 3 * (tap / 3);
         const int b = k / hw, rr = k - b * hw, oy = rr / g.Wo, ox = rr - oy * g.Wo;
         const int iy = oy * g.stride - 1 + ky, ix = ox * g.stride - 1 + kx;
@@ -427,36 +432,14 @@ __global__ void __launch_bounds__(256) k_cnn_unpool(const float* __restrict__ gp
   gy[e] = f2bf(gp[b * C + c] / (float)hw);
 }
 
-// Bias-gradient partials: part[blk][c] = sum over the block's pixels of the
-// ReLU-masked output gradient of channel c.  C divides 256: the 256 / C threads
-// of one channel take every (256 / C)-th pixel and are then summed in order.
-__global__ void __launch_bounds__(256) k_cnn_bias_partials(const uint16_t* __restrict__ y,
-                                                           const uint16_t* __restrict__ gy, int64_t npix,
-                                                           int C, int64_t chunk, float* __restrict__ part) {
-  __shared__ float red[256];
-  const int t = threadIdx.x, c = t % C, r = t / C, R = 256 / C;
-  const int64_t p0 = (int64_t)blockIdx.x * chunk, p1 = min(npix, p0 + chunk);
-  float s = 0.0f;
-  for (int64_t p = p0 + r; p < p1; p += R) {
-    const uint16_t yv = y[p * C + c];
-    if (yv != 0 && !(yv & 0x8000u)) s += bf2f(gy[p * C + c]);
-  }
-  red[t] = s;
-  __syncthreads();
-  if (t < C) {
-    float tot = 0.0f;
-    for (int k = 0; k < R; ++k) tot += red[k * C + t];
-    part[(int64_t)blockIdx.x * C + t] = tot;
-  }
-}
-
 // out[i] = sum over s of part[s][i], in order of s.
 __global__ void __launch_bounds__(256) k_cnn_reduce(const float* __restrict__ part, int nsplit, int64_t n,
                                                     float* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
   float s = 0.0f;
-  for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * n + i];
+#pragma unroll 8
+  for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * n + i];  // loads batched, adds in order
   out[i] = s;
 }
 
@@ -519,7 +502,6 @@ struct CnnPlan {
   int split[6];
 };
 
-constexpr int kBiasBlocks = 1024;  // bias-gradient partial sums per layer (at most)
 
 static int64_t wgrad_chunk(const CnnPlan& P, int l) {
   const int64_t K = (int64_t)P.B * P.hs[l + 1] * P.ws[l + 1];
@@ -554,7 +536,7 @@ static CnnPlan cnn_plan(int B, int H, int W) {
     const int64_t K = (int64_t)B * P.hs[l + 1] * P.ws[l + 1];
     // split the pixel reduction so that the weight-gradient GEMM has about 2048
     // workgroups (at most 512 splits, at least 256 pixels each)
-    const int M = 9 * kLayers[l].Ci, N = kLayers[l].Co;
+    const int M = 9 * kLayers[l].Ci + 1, N = kLayers[l].Co;  // weights and the bias row
     const int bm = N <= 32 ? 128 : 64, bn = N <= 32 ? 32 : 64;
     const int64_t tiles = (int64_t)((M + bm - 1) / bm) * ((N + bn - 1) / bn);
     int64_t sp = (2048 + tiles - 1) / tiles;
@@ -563,7 +545,6 @@ static CnnPlan cnn_plan(int B, int H, int W) {
     P.split[l] = s;
     part = std::max(part, (size_t)s * M * N);
   }
-  part = std::max(part, (size_t)kBiasBlocks * 128);
   P.part_elems = part;
   return P;
 }
@@ -697,9 +678,12 @@ static hipError_t cnn_run(const CnnPlan& P, const CnnBufs& b, const float* image
     a.gy = gy;
     a.w = b.wbf + P.wbf_off[l];
     const int64_t npix = (int64_t)P.B * P.hs[l + 1] * P.ws[l + 1];
-    // weight gradient: split over pixels, reduced in order
+    // weight and bias gradient in one GEMM: rows 0 .. 9 Ci - 1 the weights, row 9 Ci
+    // (a row of ones in the im2col operand) the bias, which the parameter layout keeps
+    // right after the weights; split over pixels, reduced in order
+    if (O.b[l] != O.w[l] + 9LL * kLayers[l].Ci * kLayers[l].Co) return hipErrorInvalidValue;
     a.out_f32 = b.part;
-    a.M = 9 * kLayers[l].Ci;
+    a.M = 9 * kLayers[l].Ci + 1;
     a.N = kLayers[l].Co;
     a.K = (int)npix;
     a.k_chunk = (int)((wgrad_chunk(P, l) + 31) / 32 * 32);  // whole 32-wide k steps
@@ -708,13 +692,6 @@ static hipError_t cnn_run(const CnnPlan& P, const CnnBufs& b, const float* image
     if (e != hipSuccess) return e;
     const int64_t nw = (int64_t)a.M * a.N;
     hipLaunchKernelGGL(k_cnn_reduce, dim3(blocks(nw)), dim3(256), 0, s, b.part, nsplit, nw, b.grads + O.w[l]);
-    // bias gradient
-    const int64_t chunk = std::max<int64_t>(256, (npix + kBiasBlocks - 1) / kBiasBlocks);
-    const int nbb = (int)((npix + chunk - 1) / chunk);
-    hipLaunchKernelGGL(k_cnn_bias_partials, dim3((unsigned)nbb), dim3(256), 0, s, a.y, gy, npix, kLayers[l].Co,
-                       chunk, b.part);
-    hipLaunchKernelGGL(k_cnn_reduce, dim3(blocks(kLayers[l].Co)), dim3(256), 0, s, b.part, nbb,
-                       (int64_t)kLayers[l].Co, b.grads + O.b[l]);
     if (l > 0) {  // input gradient
       ConvArgs d = a;
       d.out_bf16 = gx;

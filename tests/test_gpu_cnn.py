@@ -101,6 +101,17 @@ def test_network_gradients_vs_float64_autograd():
     cos = float(torch.dot(gg, ref_grad) / (gg.norm() * ref_grad.norm()))
     say("cnn: pred rel %.2e, loss %.6f vs %.6f, grad cosine %.6f" % (e_pred, float(loss.item()), float(ref_loss), cos))
     assert e_pred < 3e-2 and abs(float(loss.item()) - float(ref_loss)) < 3e-2 * float(ref_loss) and cos > 0.995
+    # each convolution's bias gradient on its own (the weight-gradient GEMM's row of ones)
+    off = 0
+    for ci, co in cnn.LAYERS:
+        off += 9 * ci * co
+        gb, rb = gg[off:off + co], ref_grad[off:off + co]
+        off += co
+        if float(rb.norm()) < 1e-6 * float(ref_grad.norm()):
+            continue
+        cb = float(torch.dot(gb, rb) / (gb.norm() * rb.norm()))
+        say("cnn: bias gradient %d->%d cosine %.5f" % (ci, co, cb))
+        assert cb > 0.99
 
 
 def test_training_on_engine_crops_reduces_loss():
