@@ -432,6 +432,19 @@ __global__ void __launch_bounds__(256) k_cnn_unpool(const float* __restrict__ gp
   gy[e] = f2bf(gp[b * C + c] / (float)hw);
 }
 
+// out[c][i] = sum over s in [c group, (c + 1) group) of part[s][i], in order of s:
+// the first level of a two-level reduce over many splits (grid.y = chunks).
+__global__ void __launch_bounds__(256) k_cnn_reduce_chunks(const float* __restrict__ part, int nsplit,
+                                                           int group, int64_t n, float* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int k0 = (int)blockIdx.y * group, k1 = min(nsplit, k0 + group);
+  float s = 0.0f;
+#pragma unroll 8
+  for (int k = k0; k < k1; ++k) s += part[(int64_t)k * n + i];
+  out[(int64_t)blockIdx.y * n + i] = s;
+}
+
 // out[i] = sum over s of part[s][i], in order of s.
 __global__ void __launch_bounds__(256) k_cnn_reduce(const float* __restrict__ part, int nsplit, int64_t n,
                                                     float* __restrict__ out) {
@@ -470,6 +483,8 @@ struct CnnLayer {
 };
 static const CnnLayer kLayers[6] = {{1, 32, 2}, {32, 32, 1}, {32, 64, 2}, {64, 64, 1}, {64, 128, 2}, {128, 128, 2}};
 constexpr int kHead1 = 64, kOut = 4;
+constexpr int64_t kSmallGrad = 4096;  // weight + bias gradients this small split their pixels finer
+constexpr int kReduceGroup = 64;      // splits per first-level sum of a two-level reduce
 
 struct CnnOffsets {
   int64_t w[6], b[6], w7, b7, w8, b8, total;
@@ -535,15 +550,19 @@ static CnnPlan cnn_plan(int B, int H, int W) {
   for (int l = 0; l < 6; ++l) {
     const int64_t K = (int64_t)B * P.hs[l + 1] * P.ws[l + 1];
     // split the pixel reduction so that the weight-gradient GEMM has about 2048
-    // workgroups (at most 512 splits, at least 256 pixels each)
+    // workgroups (at most 512 splits, at least 256 pixels each); a small gradient
+    // (at most kSmallGrad entries: the first layer's) gets about 4096 workgroups and up
+    // to 4096 splits, whose sums are then reduced in two levels
     const int M = 9 * kLayers[l].Ci + 1, N = kLayers[l].Co;  // weights and the bias row
     const int bm = N <= 32 ? 128 : 64, bn = N <= 32 ? 32 : 64;
     const int64_t tiles = (int64_t)((M + bm - 1) / bm) * ((N + bn - 1) / bn);
-    int64_t sp = (2048 + tiles - 1) / tiles;
+    const bool small = (int64_t)M * N <= kSmallGrad;
+    int64_t sp = ((small ? 4096 : 2048) + tiles - 1) / tiles;
     sp = std::min<int64_t>(sp, std::max<int64_t>(1, K / 256));
-    int s = (int)std::min<int64_t>(512, std::max<int64_t>(1, sp));
+    int s = (int)std::min<int64_t>(small ? 4096 : 512, std::max<int64_t>(1, sp));
     P.split[l] = s;
-    part = std::max(part, (size_t)s * M * N);
+    const size_t level1 = small ? (size_t)((s + kReduceGroup - 1) / kReduceGroup) * M * N : 0;
+    part = std::max(part, (size_t)s * M * N + level1);
   }
   P.part_elems = part;
   return P;
@@ -691,7 +710,15 @@ static hipError_t cnn_run(const CnnPlan& P, const CnnBufs& b, const float* image
     hipError_t e = launch_conv<CONV_WGRAD>(a, s);
     if (e != hipSuccess) return e;
     const int64_t nw = (int64_t)a.M * a.N;
-    hipLaunchKernelGGL(k_cnn_reduce, dim3(blocks(nw)), dim3(256), 0, s, b.part, nsplit, nw, b.grads + O.w[l]);
+    if (nw <= kSmallGrad && nsplit > kReduceGroup) {  // two levels: chunks of kReduceGroup splits, then the chunks
+      const int chunks = (nsplit + kReduceGroup - 1) / kReduceGroup;
+      float* level1 = b.part + (int64_t)nsplit * nw;
+      hipLaunchKernelGGL(k_cnn_reduce_chunks, dim3(blocks(nw), chunks), dim3(256), 0, s, b.part, nsplit,
+                         kReduceGroup, nw, level1);
+      hipLaunchKernelGGL(k_cnn_reduce, dim3(blocks(nw)), dim3(256), 0, s, level1, chunks, nw, b.grads + O.w[l]);
+    } else {
+      hipLaunchKernelGGL(k_cnn_reduce, dim3(blocks(nw)), dim3(256), 0, s, b.part, nsplit, nw, b.grads + O.w[l]);
+    }
     if (l > 0) {  // input gradient
       ConvArgs d = a;
       d.out_bf16 = gx;

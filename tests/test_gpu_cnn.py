@@ -81,12 +81,16 @@ def test_conv_modes_vs_float64(B, H, W, Ci, Co, s):
     assert e_f < 1e-2 and e_dx < 1e-2 and e_dw < 1e-2
 
 
-def test_network_gradients_vs_float64_autograd():
+@pytest.mark.parametrize("crop", [64, 256])
+def test_network_gradients_vs_float64_autograd(crop):
+    """Loss, prediction and every gradient against float64 autograd of the oracle's
+    network.  At 256^2 the first layer's weight gradient is split over 256 pixel
+    ranges and summed in two levels."""
     need_gpu()
     from paper_2606_21381_amd import cnn
-    net = cnn.LearnedInit(batch=4, crop=64)
+    net = cnn.LearnedInit(batch=4, crop=crop)
     g = torch.Generator().manual_seed(3)
-    images = (4.0 + torch.randn(4, 64, 64, generator=g)).float()
+    images = (4.0 + torch.randn(4, crop, crop, generator=g)).float()
     targets = torch.randn(4, 4, generator=g).float()
     grads = torch.empty_like(net.params)
     loss = net.train_step(images.cuda(), targets.cuda(), 0.0, grads_out=grads, update=False)
