@@ -12,8 +12,10 @@
 //   forward  C[pix][co]  = sum_k  im2col(x)[pix][k]            W[k][co],  k = (ky,kx,ci)
 //   dgrad    C[pix][ci]  = sum_k  col(gz)[pix][k]              W^T[k][ci], k = (ky,kx,co)
 //   wgrad    C[k][co]    = sum_pix im2col(x)[pix][k]^T         gz[pix][co]  (split over pix)
-// with gz = dL/d(output) masked by ReLU (output > 0).  The wgrad's split-K
-// partial sums are reduced in a fixed order, so training is deterministic.
+// with gz = dL/d(output) masked by ReLU (output > 0).  In training the wgrad GEMM
+// has one more row, of ones in im2col(x)^T, whose product row is the bias gradient
+// sum_pix gz[pix][co].  The wgrad's split-K partial sums are reduced in a fixed
+// order, so training is deterministic.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
