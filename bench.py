@@ -268,7 +268,8 @@ def main():
             "algorithmic_bytes": alg[dom], "avg_us": round(stage_us[dom], 2),
             "valu_busy": round(cnt["valu_busy"], 3) if cnt else None}
     if dom == "raster":
-        # the raster is bound by vector ALU issue, not by HBM: its roofline is FP32 arithmetic
+        # the raster's time is set by its arithmetic pipeline, not by HBM: its roofline is FP32
+        # arithmetic
         tests, clips = raster_work(fr.soa, H, W)
         flops = tests * RASTER_FLOP_PER_TEST + clips * RASTER_FLOP_PER_CLIP
         tflops = flops / (stage_us[dom] * 1e-6) / 1e12
@@ -310,8 +311,8 @@ def main():
         "frame_hbm_frac": round(total_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "frame_hbm_target_frac": HBM_TARGET_FRAC,
         "frame_us_at_target": round(total_alg / (HBM_TARGET_FRAC * HBM_PEAK_GBS * 1e9) * 1e6, 2),
-        # the frame is bound by vector issue: its kernels' VALU instructions at the full issue
-        # rate, and that floor as a share of the measured frame time
+        # a floor from vector issue alone: the frame's kernels' VALU instructions at the full
+        # issue rate, and that floor as a share of the measured frame time
         "frame_valu_floor_us": round(vf, 1) if vf else None,
         "frame_valu_frac": round(vf / (ms * 1e3), 4) if vf else None,
         "roofline": roof,
